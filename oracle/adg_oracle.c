@@ -796,6 +796,19 @@ static void sc_alloc(const or_solver *S, sc_work *W) {
 }
 static void sc_free(sc_work *W) { free(W->halo); free(W->tr); free(W->have); free(W->F); }
 
+/* 1 if every point of q[v*npts + i] has finite values, rho > 0 and p > 0 */
+static int all_physical(int d, double g, const double *q, int npts) {
+    for (int i = 0; i < npts; i++) {
+        double Q[5];
+        for (int v = 0; v < d + 2; v++) {
+            Q[v] = q[v * npts + i];
+            if (!isfinite(Q[v])) return 0;
+        }
+        if (!(Q[0] > 0.0) || !(pressure(d, g, Q) > 0.0)) return 0;
+    }
+    return 1;
+}
+
 static int floordiv(int a, int b) { return (a >= 0) ? a / b : -((-a + b - 1) / b); }
 
 /* Operator A of eq. (aderweno) for troubled cell c:
@@ -915,40 +928,54 @@ static void subcell_update(const or_solver *S, const double *vn, long c, double 
                 if (f == Ns && !W->have[iR]) bside = 1;
                 const double *trL = W->tr + (long)iL * trsz + (long)(2 * k + 1) * nv * nfn3 * 3;
                 const double *trR = W->tr + (long)iR * trsz + (long)(2 * k + 0) * nv * nfn3 * 3;
-                double Fbar[5] = {0, 0, 0, 0, 0};
-                for (int s = 0; s < 3; s++)
-                    for (int ap = 0; ap < nfn3; ap++) {
-                        double qL[5], qR[5], G[5];
-                        int ma[3] = {0, 0, 0};
-                        unflat(ap, 3, d - 1, ma);
-                        double wt = S->B3.w[s];
-                        double x[3];
-                        int j3 = 0;
-                        for (int j = 0; j < d; j++) {
-                            if (j == k) x[j] = S->c.lo[j] + S->h[j] * (ci[j] + (double)f / Ns);
-                            else {
-                                int sj = mp[j3];
-                                wt *= S->B3.w[ma[j3]];
-                                x[j] = S->c.lo[j] + S->h[j] * (ci[j] + (sj + S->B3.xi[ma[j3]]) / Ns);
-                                j3++;
-                            }
-                        }
-                        double tn = t + S->B3.xi[s] * dt;
-                        if (bside == 0) {
-                            for (int v = 0; v < nv; v++) qR[v] = trR[v * nfn3 * 3 + ap + nfn3 * s];
-                            bc_ghost(S, k, 0, qR, x, tn, qL);
-                        } else if (bside == 1) {
-                            for (int v = 0; v < nv; v++) qL[v] = trL[v * nfn3 * 3 + ap + nfn3 * s];
-                            bc_ghost(S, k, 1, qL, x, tn, qR);
-                        } else {
-                            for (int v = 0; v < nv; v++) {
-                                qL[v] = trL[v * nfn3 * 3 + ap + nfn3 * s];
-                                qR[v] = trR[v * nfn3 * 3 + ap + nfn3 * s];
-                            }
-                        }
-                        rusanov(d, k, g, qL, qR, G);
-                        for (int v = 0; v < nv; v++) Fbar[v] += wt * G[v];
+                /* subcell averages on both sides (halo coordinates) */
+                double avL[5], avR[5];
+                {
+                    int hL[3], hR[3];
+                    for (int j = 0; j < d; j++) { hL[j] = pL[j] - 1 + 3; hR[j] = pR[j] - 1 + 3; }
+                    for (int v = 0; v < nv; v++) {
+                        avL[v] = W->halo[v * hsz + flat(hL, HN, d)];
+                        avR[v] = W->halo[v * hsz + flat(hR, HN, d)];
                     }
+                }
+                /* reading (positivity safeguard; the paper leaves the subcell scheme to its
+                 * references and notes that WENO3 may fail positivity): if any predictor
+                 * trace on either side of the sub-face is not a physical state, the
+                 * sub-face takes the first-order flux of the two subcell averages. */
+                double Fbar[5] = {0, 0, 0, 0, 0};
+                for (int pass = 0; pass < 2; pass++) {
+                    int ok = 1;
+                    for (int v = 0; v < nv; v++) Fbar[v] = 0.0;
+                    for (int s = 0; s < 3 && ok; s++)
+                        for (int ap = 0; ap < nfn3; ap++) {
+                            double qL[5], qR[5], G[5];
+                            int ma[3] = {0, 0, 0};
+                            unflat(ap, 3, d - 1, ma);
+                            double wt = S->B3.w[s];
+                            double x[3];
+                            int j3 = 0;
+                            for (int j = 0; j < d; j++) {
+                                if (j == k) x[j] = S->c.lo[j] + S->h[j] * (ci[j] + (double)f / Ns);
+                                else {
+                                    int sj = mp[j3];
+                                    wt *= S->B3.w[ma[j3]];
+                                    x[j] = S->c.lo[j] + S->h[j] * (ci[j] + (sj + S->B3.xi[ma[j3]]) / Ns);
+                                    j3++;
+                                }
+                            }
+                            double tn = t + S->B3.xi[s] * dt;
+                            for (int v = 0; v < nv; v++) {
+                                qL[v] = pass ? avL[v] : trL[v * nfn3 * 3 + ap + nfn3 * s];
+                                qR[v] = pass ? avR[v] : trR[v * nfn3 * 3 + ap + nfn3 * s];
+                            }
+                            if (bside == 0) bc_ghost(S, k, 0, qR, x, tn, qL);
+                            else if (bside == 1) bc_ghost(S, k, 1, qL, x, tn, qR);
+                            if (!pass && !(all_physical(d, g, qL, 1) && all_physical(d, g, qR, 1))) { ok = 0; break; }
+                            rusanov(d, k, g, qL, qR, G);
+                            for (int v = 0; v < nv; v++) Fbar[v] += wt * G[v];
+                        }
+                    if (ok) break;
+                }
                 for (int v = 0; v < nv; v++) W->F[(((long)k * (Ns + 1) + f) * nsf + sp) * nv + v] = Fbar[v];
             }
     /* 5. FV update */

@@ -188,7 +188,10 @@ def _cons_tuple(gamma, prim):
     return (rho, rho * u, rho * v, p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v), 0.0)
 
 
-def double_mach(nx: int = 400, ny: int = 100, N: int = 5, gamma: float = 1.4) -> Workload:
+def double_mach(nx: int = 400, ny: int = 100, N: int = 5, gamma: float = 1.4, Lx: float = 4.0,
+                Ly: float = 1.0) -> Workload:
+    """Domain [0, Lx] x [0, Ly]; the top boundary carries the exact moving oblique shock
+    at y = Ly (a smaller window of the same problem keeps the paper's mesh size)."""
     pre, post = dmr_states(gamma)
     x0 = 1.0 / 6.0
     cpre, cpost = _cons_tuple(gamma, pre), _cons_tuple(gamma, post)
@@ -207,10 +210,10 @@ def double_mach(nx: int = 400, ny: int = 100, N: int = 5, gamma: float = 1.4) ->
     right = BC.simple(TRANSMISSIVE)
     # bottom: post-shock inflow for x < 1/6, reflecting wall after
     bottom = BC((DIRICHLET, REFLECTIVE), (cpost, cpost), split_axis=0, split0=x0, split_speed=0.0)
-    # top: exact moving shock, x_s(t) = 1/6 + (1 + 20 t)/sqrt(3)
+    # top: exact moving shock, x_s(t) = 1/6 + (Ly + 20 t)/sqrt(3)
     top = BC((DIRICHLET, DIRICHLET), (cpost, cpre), split_axis=0,
-             split0=x0 + 1.0 / math.sqrt(3.0), split_speed=20.0 / math.sqrt(3.0))
-    return Workload("double_mach", 2, N, (nx, ny), (0.0, 0.0), (4.0, 1.0),
+             split0=x0 + Ly / math.sqrt(3.0), split_speed=20.0 / math.sqrt(3.0))
+    return Workload("double_mach", 2, N, (nx, ny), (0.0, 0.0), (Lx, Ly),
                     [(left, right), (bottom, top)], ic, t_end=0.2)
 
 

@@ -1,0 +1,174 @@
+#!/usr/bin/env python3
+"""Benchmark of one full ADER-DG step with the a-posteriori subcell limiter on one MI355X.
+
+Workload: the smooth isentropic vortex of Sec. 5 (beta = 5, rho = p = 1, u = v = 1
+background, periodic [0,10]^2) with N = 9 on 64 x 64 cells, limiter active (detection
+runs every step; the resolved vortex triggers no troubled cell).  One step = Delta t
+reduction (eq. (cfl)) + old-time bounds + space-time predictor + face fluxes + corrector
++ scatter/detection + compaction (+ subcell recompute and flux correction when cells are
+flagged).  Metric: space-time degrees of freedom updated per second, counted per
+conserved variable as the paper does ((N+1)^(d+1) per cell and step).
+
+Prints one JSON line.  With --gpus above 1 it exits: this build runs on one GPU.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X published peaks used for the roofline fraction
+PEAK_FP64_VALU_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+
+
+def predictor_flops_per_cell(d: int, N: int) -> float:
+    """Algorithmic flops of the local space-time predictor per cell: n Picard sweeps,
+    each with d + 1 length-n contractions (d spatial, one in time) of nu * n^(d+1)
+    values and one flux evaluation per axis and space-time node ((10 + 8 d) flops per
+    node for the d fluxes)."""
+    n, nv = N + 1, d + 2
+    return n * (2.0 * (d + 1) * nv * n ** (d + 2) + (10 + 8 * d) * n ** (d + 1))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--grid", type=int, default=64)
+    ap.add_argument("--N", type=int, default=9)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="bounded CPU-baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1406_7416_amd import adg
+    from paper_1406_7416_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+
+    wl = W.vortex(args.grid, args.N)
+    d, N = wl.dim, wl.N
+    st_dof_step = wl.st_dof_per_step()
+
+    prob = adg.Problem(wl)
+    u0, _ = prob.project(wl.ic, 0)      # nodal values of the initial condition
+    prob.set_state(u0)
+    print(f"# workload vortex N={N} grid={args.grid}^2 cells={wl.num_cells} cfl={wl.cfl}", file=sys.stderr,
+          flush=True)
+
+    for _ in range(args.warmup):
+        prob.step_cfl()
+    torch.cuda.synchronize()
+
+    prob.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        prob.step_cfl()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = prob.profile_read()
+    prob.profile(False)
+    elapsed = t1 - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = st_dof_step * args.steps / elapsed
+    stats = prob.stats()
+    t_sim = prob.time
+
+    # accuracy of the GPU run against the exact (translated) vortex at its final time
+    u = prob.state()
+    ue, _ = prob.project(lambda x, t: wl.ic(x, t_sim), 0)
+    linf_rho = float(np.abs(u[0] - ue[0]).max())
+
+    # roofline of the dominant kernel (the predictor)
+    pred_ms, pred_n = prof["predictor"]
+    pred_avg_s = pred_ms * 1e-3 / max(1, pred_n)
+    flops_launch = predictor_flops_per_cell(d, N) * wl.num_cells
+    achieved_tflops = flops_launch / pred_avg_s / 1e12
+    kernels = {g: {"ms_total": round(ms, 4), "launches": n, "avg_us": round(1e3 * ms / n, 3) if n else None}
+               for g, (ms, n) in prof.items()}
+
+    out = {
+        "metric": "space-time dof-updates/s",
+        "value": value,
+        "unit": "st-dof/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (analytic initial condition)",
+        "config": {
+            "workload": f"isentropic vortex (Sec. 5), N={N}, {args.grid}x{args.grid} cells, periodic [0,10]^2, "
+                        f"limiter on, CFL factor {wl.cfl}, Ns={2 * N + 1}",
+            "cells": wl.num_cells,
+            "st_dof_per_step": st_dof_step,
+            "form": "FP64 GPU",
+        },
+        "roofline": {
+            "bound": "alu",
+            "kernel": "k_predictor (space-time predictor + volume term + face traces)",
+            "achieved": achieved_tflops,
+            "peak": PEAK_FP64_VALU_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved_tflops / PEAK_FP64_VALU_TFLOPS,
+            "traffic": None,
+            "flops_per_launch": flops_launch,
+            "avg_launch_us": pred_avg_s * 1e6,
+        },
+        "kernels": kernels,
+        "troubled_last_step": stats["troubled"],
+        "t_simulated": t_sim,
+        "linf_rho_vs_exact": linf_rho,
+    }
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, u0, args.cpu_seconds)
+
+    print(json.dumps(out), flush=True)
+    prob.close()
+
+
+def cpu_baseline(wl, u0, budget_s):
+    """The FP64 CPU oracle, as it stands, on the same workload: whole steps until the
+    time budget is used (at least one)."""
+    from oracle import oracle as O
+    o = O.Oracle(wl)
+    o.set_state(u0)
+    threads = O.get_threads()
+    steps, t0 = 0, time.perf_counter()
+    while True:
+        o.step(o.cfl_dt())
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or steps >= 50:
+            break
+    return {
+        "value": wl.st_dof_per_step() * steps / el,
+        "unit": "st-dof/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"{steps} full steps of the same workload ({wl.num_cells} cells, N={wl.N}), {el:.1f} s, "
+                  f"OpenMP threads={threads}",
+    }
+
+
+if __name__ == "__main__":
+    main()

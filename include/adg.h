@@ -1,0 +1,168 @@
+/*
+ * adg.h -- C ABI of the MI355X (gfx950) ADER-DG step with the a-posteriori subcell
+ * limiter for the compressible Euler equations on uniform Cartesian grids.
+ *
+ * Method: Dumbser, Zanotti, Loubere, Diot, "A posteriori subcell limiting of the
+ * discontinuous Galerkin finite element method for hyperbolic conservation laws",
+ * J. Comput. Phys. 2014 (arXiv 1406.7416).  One call of adg_step performs the five
+ * steps of Sec. 4.4: unlimited ADER-DG candidate (Sec. 2.2 predictor eq. (pde.nc.dg2),
+ * Sec. 2.3 corrector eq. (pde.nc.gw2) with the Rusanov flux), scatter onto Ns^d
+ * subcells (eq. (subcell.p)), detection by PAD + relaxed DMP (eqs. (positivity),
+ * (relax), (dmp)), subcell ADER-WENO3 recompute of troubled cells (eqs. (aderweno),
+ * (ader.icbc)) with flux correction of their unlimited neighbours, and gather
+ * (eq. (subcell.r)).
+ *
+ * Conventions
+ *  - Every function returns ADG_OK (0) or a negative error code; adg_last_error()
+ *    gives a thread-local message for the last failure.  Nothing throws or exits.
+ *  - State layout (device or host, double): [var][cell][node] with var = (rho, rho u,
+ *    rho v, [rho w], rho E); cells row-major with x fastest; nodes the tensor
+ *    Gauss-Legendre points of the cell (N+1 per axis), x fastest.  Nodal values are the
+ *    DG degrees of freedom (Sec. 2.1).
+ *  - Subcell layout: [var][cell][subcell], Ns per axis, x fastest.
+ *  - Memory: the caller owns all device memory and the stream.  adg_workspace_bytes
+ *    says how much one problem needs; adg_bind hands in one device allocation of at
+ *    least that size (256-byte aligned) and a hipStream_t.  The library keeps only host
+ *    tables and the plan; adg_destroy frees host memory only.
+ *  - Calls on one problem are not thread-safe; work is enqueued on the bound stream.
+ *    Functions marked "synchronising" wait for that stream.
+ */
+#ifndef ADG_H
+#define ADG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    ADG_OK = 0,
+    ADG_EINVAL = -1,      /* bad argument or unsupported configuration */
+    ADG_ENOMEM = -2,      /* host allocation failed or workspace too small */
+    ADG_EDEVICE = -3,     /* a HIP call failed (message names it) */
+    ADG_ECAPACITY = -4,   /* more troubled cells than the subcell pool holds */
+    ADG_ENONPHYSICAL = -5,/* a subcell recompute produced rho <= 0 or p <= 0 (count via stats) */
+    ADG_ESTATE = -6       /* call order (e.g. step before bind/set_state) */
+};
+
+enum { ADG_PERIODIC = 0, ADG_TRANSMISSIVE = 1, ADG_REFLECTIVE = 2, ADG_DIRICHLET = 3 };
+enum { ADG_FP64 = 0, ADG_MIXED = 1 };
+
+/* One side of one axis.  Where the coordinate along split_axis is below
+ * split0 + split_speed * t, (kind[0], state[0]) applies, else (kind[1], state[1]);
+ * split_axis = -1: no split.  States are conserved variables (unused entries ignored).
+ * Ghost states (the paper names its boundary conditions without formulas): transmissive
+ * copies the interior state, reflective negates the normal momentum, Dirichlet takes
+ * the prescribed state; subcell ghosts mirror the interior subcells first.  Periodic
+ * must be set on both sides of an axis. */
+typedef struct {
+    int kind[2];
+    int split_axis;
+    double split0, split_speed;
+    double state[2][5];
+} adg_bc;
+
+/* Uniform Cartesian grid on [lo, hi] with n[k] cells along axis k (k < dim). */
+typedef struct {
+    int dim;              /* 2 or 3 */
+    int64_t n[3];
+    double lo[3], hi[3];
+    adg_bc bc[3][2];      /* [axis][0: low side, 1: high side] */
+} adg_grid_desc;
+
+typedef struct {
+    int Ns;               /* subcells per axis; 0 -> 2N+1 (Sec. 4.5); only 2N+1 accepted */
+    int picard_iters;     /* 0 -> N+1 sweeps of the predictor (reading: fixed count) */
+    int precision;        /* ADG_FP64 or ADG_MIXED */
+    int limiter;          /* 1: subcell limiter on (default), 0: unlimited ADER-DG */
+    double eps;           /* eq. (relax) epsilon; 0 -> 1e-3 */
+    double delta0;        /* absolute floor of delta; 0 -> 1e-4 (reading: not in the paper) */
+    int64_t pool_capacity;/* troubled cells the subcell pool holds; 0 -> all cells */
+} adg_params;
+
+typedef struct adg_problem adg_problem;
+
+const char *adg_last_error(void);
+
+/* Creates a problem (host side only).  N in 1..9; gamma > 1.  p may be NULL for
+ * defaults.  Errors: ADG_EINVAL. */
+int adg_create(const adg_grid_desc *g, int N, double gamma, const adg_params *p, adg_problem **out);
+int adg_destroy(adg_problem *pb);
+
+/* Bytes of device workspace (including the state) this problem needs. */
+size_t adg_workspace_bytes(const adg_problem *pb);
+
+/* Binds a caller-owned device allocation (>= adg_workspace_bytes, 256-byte aligned) and
+ * a hipStream_t (NULL: the null stream), uploads the operator tables.  Errors:
+ * ADG_ENOMEM (too small), ADG_EDEVICE. */
+int adg_bind(adg_problem *pb, void *dev_workspace, size_t bytes, void *hip_stream);
+
+/* Physical coordinates along `axis` of the points where initial data is sampled:
+ * m = 0: the DG nodes, out[(i*(N+1) + a)] for cell i, node a;
+ * m > 0: m-point Gauss-Legendre points of every subcell, out[(i*Ns + s)*m + q].
+ * Host memory, n[axis]*(N+1) or n[axis]*Ns*m doubles. */
+int adg_axis_points(const adg_problem *pb, int axis, int m, double *out);
+
+/* Host-side projection of samples taken on the tensor grid of adg_axis_points(m):
+ * samples[var][z][y][x].  m = 0: nodal interpolation (u only).  m > 0: L2 projection
+ * onto the DG basis by the composite m-point rule on every subcell, and (if v != NULL)
+ * the subcell averages of the samples.  u, v: host, state / subcell layouts. */
+int adg_project_samples(const adg_problem *pb, const double *samples, int m, double *u, double *v);
+
+/* Sets the DG state u (layout above; device pointer if on_device, else host) and time 0.
+ * If v_exact (host, subcell layout) is given, applies the initial detection of Sec. 4.4:
+ * PAD + DMP of P(u) against the bounds of v_exact over each cell's neighbourhood;
+ * troubled cells start from v_exact and u := R(v_exact).  Synchronising. */
+int adg_set_state(adg_problem *pb, const double *u, int on_device, const double *v_exact);
+
+/* Copies the DG state out (device pointer if to_device).  Synchronising for host copies. */
+int adg_get_state(const adg_problem *pb, double *u, int to_device);
+
+/* Eq. (cfl): dt = cfl * min_k h_k / (d (2N+1) max |v_k| + c) from the current state.
+ * Synchronising. */
+int adg_cfl_dt(adg_problem *pb, double cfl, double *dt_out);
+
+/* One full step with the given dt.  Enqueued on the bound stream; one host wait for the
+ * troubled-cell count is taken inside.  Errors: ADG_ESTATE, ADG_EDEVICE, ADG_ECAPACITY. */
+int adg_step(adg_problem *pb, double dt);
+
+/* As adg_step with dt from eq. (cfl) computed on the device from the current state. */
+int adg_step_cfl(adg_problem *pb, double cfl);
+
+/* Current time (synchronising). */
+int adg_time(const adg_problem *pb, double *t);
+
+/* Troubled-cell map beta of the last step (or of the initial detection), 1 byte per
+ * cell, host memory; *count = number of troubled cells.  Synchronising. */
+int adg_get_troubled(const adg_problem *pb, uint8_t *beta, int64_t *count);
+
+/* Signed normalised detection margin per cell of the last detection (negative: a test
+ * failed).  Host memory, float per cell.  Synchronising. */
+int adg_get_margin(const adg_problem *pb, float *margin);
+
+/* Subcell data v of troubled cells (subcell layout, host; entries of untroubled cells
+ * are left untouched).  Synchronising. */
+int adg_get_subcells(const adg_problem *pb, double *v);
+
+/* Statistics of the last step: out[0] troubled cells, out[1] corrected neighbours,
+ * out[2] cumulative subcell results failing PAD, out[3] steps taken.  Synchronising. */
+int adg_get_stats(const adg_problem *pb, int64_t *out4);
+
+/* Per-kernel timing with hipEvents recorded on the bound stream around each kernel
+ * group.  Groups: 0 old-time bounds, 1 predictor, 2 face fluxes, 3 corrector + detection,
+ * 4 compaction, 5 subcell ADER-WENO3, 6 flux correction, 7 time-step reduction.
+ * adg_profile(pb, 1) starts (and clears), 0 stops.  adg_profile_read fills ms[g] (total
+ * milliseconds) and launches[g] for g < ngroups (<= 8).  Synchronising. */
+int adg_profile(adg_problem *pb, int enable);
+int adg_profile_read(adg_problem *pb, double *ms, int64_t *launches, int ngroups);
+
+/* Debug hook: cells with mask[c] != 0 are flagged troubled at every following detection
+ * (NULL clears).  Host memory, one byte per cell. */
+int adg_debug_force_troubled(adg_problem *pb, const uint8_t *mask);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,260 @@
+"""Python binding of the C ABI in include/adg.h (libadg.so, built for gfx950).
+
+Argument marshalling only: every step of the method runs in the library's HIP kernels.
+PyTorch supplies the device workspace and the stream.  Importing works without a GPU;
+creating a Problem needs the built library and fails loudly if it is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libadg.so")
+
+ADG_PERIODIC, ADG_TRANSMISSIVE, ADG_REFLECTIVE, ADG_DIRICHLET = 0, 1, 2, 3
+ADG_FP64, ADG_MIXED = 0, 1
+
+EXPORTS = [
+    "adg_last_error", "adg_create", "adg_destroy", "adg_workspace_bytes", "adg_bind", "adg_axis_points",
+    "adg_project_samples", "adg_set_state", "adg_get_state", "adg_cfl_dt", "adg_step", "adg_step_cfl",
+    "adg_time", "adg_get_troubled", "adg_get_margin", "adg_get_subcells", "adg_get_stats",
+    "adg_profile", "adg_profile_read", "adg_debug_force_troubled",
+]
+
+KERNEL_GROUPS = ["bounds", "predictor", "faces", "corrector_detect", "compact", "subcell", "fluxcorr", "dt"]
+
+
+class AdgError(RuntimeError):
+    pass
+
+
+class _BC(C.Structure):
+    _fields_ = [("kind", C.c_int * 2), ("split_axis", C.c_int), ("split0", C.c_double),
+                ("split_speed", C.c_double), ("state", (C.c_double * 5) * 2)]
+
+
+class _Grid(C.Structure):
+    _fields_ = [("dim", C.c_int), ("n", C.c_int64 * 3), ("lo", C.c_double * 3), ("hi", C.c_double * 3),
+                ("bc", (_BC * 2) * 3)]
+
+
+class _Params(C.Structure):
+    _fields_ = [("Ns", C.c_int), ("picard_iters", C.c_int), ("precision", C.c_int), ("limiter", C.c_int),
+                ("eps", C.c_double), ("delta0", C.c_double), ("pool_capacity", C.c_int64)]
+
+
+_lib = None
+
+
+def load():
+    """Loads libadg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise AdgError(f"{LIB_PATH} not built: run __graft_entry__.build()")
+    L = C.CDLL(LIB_PATH)
+    vp, dp, i64 = C.c_void_p, C.POINTER(C.c_double), C.c_int64
+    L.adg_last_error.restype = C.c_char_p
+    L.adg_create.argtypes = [C.POINTER(_Grid), C.c_int, C.c_double, C.POINTER(_Params), C.POINTER(vp)]
+    L.adg_destroy.argtypes = [vp]
+    L.adg_workspace_bytes.restype = C.c_size_t
+    L.adg_workspace_bytes.argtypes = [vp]
+    L.adg_bind.argtypes = [vp, vp, C.c_size_t, vp]
+    L.adg_axis_points.argtypes = [vp, C.c_int, C.c_int, dp]
+    L.adg_project_samples.argtypes = [vp, dp, C.c_int, dp, dp]
+    L.adg_set_state.argtypes = [vp, vp, C.c_int, dp]
+    L.adg_get_state.argtypes = [vp, vp, C.c_int]
+    L.adg_cfl_dt.argtypes = [vp, C.c_double, dp]
+    L.adg_step.argtypes = [vp, C.c_double]
+    L.adg_step_cfl.argtypes = [vp, C.c_double]
+    L.adg_time.argtypes = [vp, dp]
+    L.adg_get_troubled.argtypes = [vp, C.POINTER(C.c_uint8), C.POINTER(i64)]
+    L.adg_get_margin.argtypes = [vp, C.POINTER(C.c_float)]
+    L.adg_get_subcells.argtypes = [vp, dp]
+    L.adg_get_stats.argtypes = [vp, C.POINTER(i64)]
+    L.adg_debug_force_troubled.argtypes = [vp, C.POINTER(C.c_uint8)]
+    L.adg_profile.argtypes = [vp, C.c_int]
+    L.adg_profile_read.argtypes = [vp, dp, C.POINTER(i64), C.c_int]
+    for name in EXPORTS[1:]:
+        if name != "adg_workspace_bytes":
+            getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise AdgError(f"adg error {rc}: {load().adg_last_error().decode()}")
+
+
+def _dp(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _grid(wl) -> _Grid:
+    g = _Grid()
+    g.dim = wl.dim
+    for k in range(3):
+        g.n[k] = wl.ncell[k] if k < wl.dim else 1
+        g.lo[k] = wl.lo[k] if k < wl.dim else 0.0
+        g.hi[k] = wl.hi[k] if k < wl.dim else 1.0
+    for k in range(wl.dim):
+        for side in range(2):
+            b = wl.bcs[k][side]
+            cb = g.bc[k][side]
+            cb.kind[0], cb.kind[1] = b.kind
+            cb.split_axis, cb.split0, cb.split_speed = b.split_axis, b.split0, b.split_speed
+            for w in range(2):
+                for v in range(5):
+                    cb.state[w][v] = b.states[w][v] if v < len(b.states[w]) else 0.0
+    return g
+
+
+class Problem:
+    """One problem on one GPU: owns a torch workspace, drives the C ABI."""
+
+    def __init__(self, wl, precision: int = ADG_FP64, limiter: bool = True, pool_capacity: int = 0,
+                 picard_iters: int = 0, device: str = "cuda:0", stream=None):
+        import torch
+        L = load()
+        self.wl = wl
+        self.dim, self.nv, self.n = wl.dim, wl.dim + 2, wl.N + 1
+        self.Ns = wl.Ns if wl.Ns else 2 * wl.N + 1
+        self.ncell = wl.num_cells
+        self.nn = self.n ** self.dim
+        self.nsub = self.Ns ** self.dim
+        prm = _Params()
+        prm.Ns = self.Ns
+        prm.picard_iters = picard_iters
+        prm.precision = precision
+        prm.limiter = 1 if limiter else 0
+        prm.eps, prm.delta0 = wl.eps, wl.delta0
+        prm.pool_capacity = pool_capacity
+        self._grid = _grid(wl)
+        h = C.c_void_p()
+        _check(L.adg_create(C.byref(self._grid), wl.N, wl.gamma, C.byref(prm), C.byref(h)))
+        self.h = h
+        self.device = torch.device(device)
+        nbytes = L.adg_workspace_bytes(self.h)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) & ~255
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        _check(L.adg_bind(self.h, C.c_void_p(aligned), nbytes, C.c_void_p(self.stream.cuda_stream)))
+        self.workspace_bytes = nbytes
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().adg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- initial data
+    def axis_points(self, axis: int, m: int) -> np.ndarray:
+        per = self.n if m == 0 else self.Ns * m
+        out = np.zeros(self.wl.ncell[axis] * per)
+        _check(load().adg_axis_points(self.h, axis, m, _dp(out)))
+        return out
+
+    def project(self, ic, m: int, t: float = 0.0):
+        from .workloads import sample_grid
+        axes = [self.axis_points(k, m) for k in range(self.dim)]
+        samples = np.ascontiguousarray(sample_grid(ic, axes, t))
+        u = np.zeros((self.nv, self.ncell, self.nn))
+        v = np.zeros((self.nv, self.ncell, self.nsub)) if m > 0 else None
+        _check(load().adg_project_samples(self.h, _dp(samples), m, _dp(u), _dp(v) if v is not None else None))
+        return u, v
+
+    def set_state(self, u, v_exact: Optional[np.ndarray] = None):
+        ve = None if v_exact is None else np.ascontiguousarray(v_exact, dtype=np.float64)
+        vptr = _dp(ve) if ve is not None else None
+        if hasattr(u, "is_cuda") and u.is_cuda:
+            assert u.dtype.is_floating_point and u.is_contiguous()
+            _check(load().adg_set_state(self.h, C.c_void_p(u.data_ptr()), 1, vptr))
+        else:
+            uh = np.ascontiguousarray(u, dtype=np.float64)
+            _check(load().adg_set_state(self.h, uh.ctypes.data_as(C.c_void_p), 0, vptr))
+
+    def init(self, m: Optional[int] = None, detect: bool = True):
+        if m is None:
+            m = self.n
+        u, v = self.project(self.wl.ic, m)
+        self.set_state(u, v if detect else None)
+
+    # ---- stepping
+    def cfl_dt(self, cfl: Optional[float] = None) -> float:
+        dt = C.c_double()
+        _check(load().adg_cfl_dt(self.h, self.wl.cfl if cfl is None else cfl, C.byref(dt)))
+        return dt.value
+
+    def step(self, dt: float):
+        _check(load().adg_step(self.h, dt))
+
+    def step_cfl(self, cfl: Optional[float] = None):
+        _check(load().adg_step_cfl(self.h, self.wl.cfl if cfl is None else cfl))
+
+    def force_troubled(self, mask: Optional[np.ndarray]):
+        if mask is None:
+            _check(load().adg_debug_force_troubled(self.h, None))
+        else:
+            m = np.ascontiguousarray(mask, dtype=np.uint8)
+            _check(load().adg_debug_force_troubled(self.h, m.ctypes.data_as(C.POINTER(C.c_uint8))))
+
+    # ---- outputs
+    @property
+    def time(self) -> float:
+        t = C.c_double()
+        _check(load().adg_time(self.h, C.byref(t)))
+        return t.value
+
+    def state(self) -> np.ndarray:
+        u = np.zeros((self.nv, self.ncell, self.nn))
+        _check(load().adg_get_state(self.h, u.ctypes.data_as(C.c_void_p), 0))
+        return u
+
+    def state_tensor(self):
+        import torch
+        u = torch.empty((self.nv, self.ncell, self.nn), dtype=torch.float64, device=self.device)
+        _check(load().adg_get_state(self.h, C.c_void_p(u.data_ptr()), 1))
+        return u
+
+    def troubled(self) -> np.ndarray:
+        b = np.zeros(self.ncell, dtype=np.uint8)
+        cnt = C.c_int64()
+        _check(load().adg_get_troubled(self.h, b.ctypes.data_as(C.POINTER(C.c_uint8)), C.byref(cnt)))
+        return b
+
+    def margin(self) -> np.ndarray:
+        m = np.zeros(self.ncell, dtype=np.float32)
+        _check(load().adg_get_margin(self.h, m.ctypes.data_as(C.POINTER(C.c_float))))
+        return m
+
+    def subcells(self) -> np.ndarray:
+        v = np.zeros((self.nv, self.ncell, self.nsub))
+        _check(load().adg_get_subcells(self.h, _dp(v)))
+        return v
+
+    def profile(self, enable: bool):
+        _check(load().adg_profile(self.h, 1 if enable else 0))
+
+    def profile_read(self) -> dict:
+        ms = np.zeros(8)
+        n = (C.c_int64 * 8)()
+        _check(load().adg_profile_read(self.h, _dp(ms), n, 8))
+        return {g: (float(ms[i]), int(n[i])) for i, g in enumerate(KERNEL_GROUPS)}
+
+    def stats(self) -> dict:
+        out = (C.c_int64 * 4)()
+        _check(load().adg_get_stats(self.h, out))
+        return {"troubled": out[0], "corrected": out[1], "nonphysical": out[2], "steps": out[3]}

@@ -1,0 +1,801 @@
+// C ABI: problem plan, workspace carving, step sequence, state I/O.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+#include "adg_kernels.h"
+
+using namespace adg;
+
+static thread_local std::string g_err;
+
+static int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+static int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(call)                                                                                 \
+    do {                                                                                             \
+        hipError_t e_ = (call);                                                                      \
+        if (e_ != hipSuccess) return fail(ADG_EDEVICE, "%s: %s", #call, hipGetErrorString(e_));      \
+    } while (0)
+
+struct adg_problem {
+    Prob P;
+    adg_params prm;
+    Tables tab_host;
+    int64_t cap;            // pool slots
+    int chunk;              // troubled cells per subcell chunk
+    int npos;               // subcell positions per troubled cell
+    int lam_blocks;
+    size_t ws_bytes;
+    // offsets into the workspace
+    struct Off {
+        size_t tab, u0, u1, emin, emax, bmin, bmax, trace, gbar, beta0, beta1, force, margin, tlist, clist, slot0,
+            slot1, pool0, pool1, sflux, blk, counts, scal, lampart, halo, Y, strace, end;
+    } off;
+    // bound state
+    char *ws = nullptr;
+    hipStream_t stream = nullptr;
+    Bufs B;
+    Tables *tab_dev = nullptr;
+    int cur = 0;
+    bool bound = false, has_state = false;
+    int *pinned = nullptr;    // host-pinned copy of the counters
+    int64_t last_troubled = 0, last_corrected = 0, steps = 0;
+    // kernel-group timing
+    bool profiling = false;
+    struct Mark { int group; hipEvent_t a, b; };
+    std::vector<Mark> pending;
+    std::vector<hipEvent_t> spare;
+    double prof_ms[8] = {0};
+    int64_t prof_n[8] = {0};
+};
+
+static hipEvent_t take_event(adg_problem *pb) {
+    if (!pb->spare.empty()) {
+        hipEvent_t e = pb->spare.back();
+        pb->spare.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Records events around one kernel group when profiling is on.
+struct GroupTimer {
+    adg_problem *pb;
+    int group;
+    hipEvent_t a = nullptr, b = nullptr;
+    GroupTimer(adg_problem *p, int g) : pb(p), group(g) {
+        if (!pb->profiling) return;
+        a = take_event(pb);
+        b = take_event(pb);
+        if (a) (void)hipEventRecord(a, pb->stream);
+    }
+    ~GroupTimer() {
+        if (!pb->profiling || !a || !b) return;
+        (void)hipEventRecord(b, pb->stream);
+        pb->pending.push_back({group, a, b});
+    }
+};
+
+// Accumulates completed marks (the stream must have been synchronised).
+static void harvest(adg_problem *pb) {
+    for (auto &m : pb->pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, m.a, m.b) == hipSuccess) {
+            pb->prof_ms[m.group] += ms;
+            pb->prof_n[m.group] += 1;
+        }
+        pb->spare.push_back(m.a);
+        pb->spare.push_back(m.b);
+    }
+    pb->pending.clear();
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static void plan(adg_problem *pb) {
+    const Prob &P = pb->P;
+    const int d = P.dim, nv = P.nv, n = P.n, Ns = P.Ns;
+    const int64_t nn = ipow64(n, d), nfn = ipow64(n, d - 1), nsub = ipow64(Ns, d), nsf = ipow64(Ns, d - 1);
+    int64_t next = 1;
+    for (int j = 0; j < d; j++) next *= P.nc[j] + 2;
+    const int64_t nc = P.ncell;
+    const int64_t nblk = (nc + 255) / 256;
+    const int64_t hsz = ipow64(Ns + 6, d), n3 = ipow64(3, d), nf3 = ipow64(3, d - 1);
+    const int64_t per_chunk_cell = (nv * hsz + pb->npos * nv * n3 + pb->npos * 2 * d * nv * nf3 * 3) * 8;
+    int64_t chunk = std::max<int64_t>(16, (int64_t)(512ll << 20) / per_chunk_cell);
+    chunk = std::min<int64_t>(chunk, std::max<int64_t>(1, pb->cap));
+    chunk = std::min<int64_t>(chunk, 65535);
+    pb->chunk = (int)chunk;
+    pb->lam_blocks = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (nc * nn + 255) / 256));
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t r = o;
+        o = align256(o + bytes);
+        return r;
+    };
+    auto &f = pb->off;
+    f.tab = take(sizeof(Tables));
+    f.u0 = take(8ull * nv * nc * nn);
+    f.u1 = take(8ull * nv * nc * nn);
+    f.emin = take(8ull * nv * next);
+    f.emax = take(8ull * nv * next);
+    f.bmin = take(8ull * nv * nc);
+    f.bmax = take(8ull * nv * nc);
+    f.trace = take(8ull * nc * 2 * d * nv * nfn * n);
+    f.gbar = take(8ull * nc * 2 * d * nv * nfn);
+    f.beta0 = take(nc);
+    f.beta1 = take(nc);
+    f.force = take(nc);
+    f.margin = take(4ull * nc);
+    f.tlist = take(4ull * nc);
+    f.clist = take(4ull * nc);
+    f.slot0 = take(4ull * nc);
+    f.slot1 = take(4ull * nc);
+    f.pool0 = take(8ull * pb->cap * nv * nsub);
+    f.pool1 = take(8ull * pb->cap * nv * nsub);
+    f.sflux = take(8ull * pb->cap * 2 * d * nv * nsf);
+    f.blk = take(4ull * 2 * nblk);
+    f.counts = take(4ull * 8);
+    f.scal = take(8ull * 8);
+    f.lampart = take(8ull * 1024);
+    f.halo = take(8ull * chunk * nv * hsz);
+    f.Y = take(8ull * chunk * pb->npos * nv * n3);
+    f.strace = take(8ull * chunk * pb->npos * 2 * d * nv * nf3 * 3);
+    f.end = o;
+    pb->ws_bytes = o;
+}
+
+static void carve(adg_problem *pb) {
+    char *w = pb->ws;
+    auto &f = pb->off;
+    Bufs &B = pb->B;
+    B.tab = (Tables *)(w + f.tab);
+    B.u[0] = (double *)(w + f.u0);
+    B.u[1] = (double *)(w + f.u1);
+    B.ext_min = (double *)(w + f.emin);
+    B.ext_max = (double *)(w + f.emax);
+    B.bmin = (double *)(w + f.bmin);
+    B.bmax = (double *)(w + f.bmax);
+    B.trace = (double *)(w + f.trace);
+    B.gbar = (double *)(w + f.gbar);
+    B.beta[0] = (uint8_t *)(w + f.beta0);
+    B.beta[1] = (uint8_t *)(w + f.beta1);
+    B.force = (uint8_t *)(w + f.force);
+    B.margin = (float *)(w + f.margin);
+    B.tlist = (int *)(w + f.tlist);
+    B.clist = (int *)(w + f.clist);
+    B.slot[0] = (int *)(w + f.slot0);
+    B.slot[1] = (int *)(w + f.slot1);
+    B.pool[0] = (double *)(w + f.pool0);
+    B.pool[1] = (double *)(w + f.pool1);
+    B.sflux = (double *)(w + f.sflux);
+    B.blk = (int *)(w + f.blk);
+    B.counts = (int *)(w + f.counts);
+    B.scal = (double *)(w + f.scal);
+    B.lam_part = (double *)(w + f.lampart);
+    B.halo = (double *)(w + f.halo);
+    B.Y = (double *)(w + f.Y);
+    B.strace = (double *)(w + f.strace);
+    pb->tab_dev = B.tab;
+}
+
+static StepCtx ctx(const adg_problem *pb) {
+    StepCtx C;
+    C.P = pb->P;
+    C.B = pb->B;
+    C.tab = pb->tab_dev;
+    C.stream = pb->stream;
+    C.cur = pb->cur;
+    C.limiter = pb->prm.limiter;
+    C.picard_iters = pb->prm.picard_iters;
+    C.capacity = pb->cap;
+    C.lam_blocks = pb->lam_blocks;
+    return C;
+}
+
+extern "C" {
+
+const char *adg_last_error(void) { return g_err.c_str(); }
+
+int adg_create(const adg_grid_desc *g, int N, double gamma, const adg_params *p, adg_problem **out) {
+    if (!g || !out) return fail(ADG_EINVAL, "null argument");
+    *out = nullptr;
+    if (g->dim != 2 && g->dim != 3) return fail(ADG_EINVAL, "dim must be 2 or 3");
+    if (!supported(g->dim, N)) return fail(ADG_EINVAL, "N=%d not built for dim=%d", N, g->dim);
+    if (!(gamma > 1.0)) return fail(ADG_EINVAL, "gamma must exceed 1");
+    adg_params prm{};
+    if (p) prm = *p;
+    else prm.limiter = 1;
+    if (prm.Ns == 0) prm.Ns = 2 * N + 1;
+    if (prm.Ns != 2 * N + 1) return fail(ADG_EINVAL, "only Ns = 2N+1 is built");
+    if (prm.picard_iters <= 0) prm.picard_iters = N + 1;
+    if (prm.eps == 0) prm.eps = 1e-3;
+    if (prm.delta0 == 0) prm.delta0 = 1e-4;
+    if (prm.precision != ADG_FP64) return fail(ADG_EINVAL, "precision mode not built");
+    adg_problem *pb = new (std::nothrow) adg_problem();
+    if (!pb) return fail(ADG_ENOMEM, "host allocation failed");
+    Prob &P = pb->P;
+    std::memset(&P, 0, sizeof P);
+    P.dim = g->dim;
+    P.N = N;
+    P.n = N + 1;
+    P.nv = g->dim + 2;
+    P.Ns = prm.Ns;
+    P.ncell = 1;
+    for (int k = 0; k < 3; k++) {
+        if (k < g->dim) {
+            if (g->n[k] < 1 || g->n[k] > (1 << 30) || !(g->hi[k] > g->lo[k])) {
+                delete pb;
+                return fail(ADG_EINVAL, "bad extent on axis %d", k);
+            }
+            P.nc[k] = (int)g->n[k];
+            P.lo[k] = g->lo[k];
+            P.h[k] = (g->hi[k] - g->lo[k]) / g->n[k];
+        } else {
+            P.nc[k] = 1;
+            P.lo[k] = 0;
+            P.h[k] = 1;
+        }
+        P.ncell *= P.nc[k];
+    }
+    if (P.ncell > (int64_t)1 << 31) {
+        delete pb;
+        return fail(ADG_EINVAL, "too many cells");
+    }
+    P.gamma = gamma;
+    P.eps = prm.eps;
+    P.delta0 = prm.delta0;
+    for (int k = 0; k < g->dim; k++) {
+        const int p0 = g->bc[k][0].kind[0] == ADG_PERIODIC, p1 = g->bc[k][1].kind[0] == ADG_PERIODIC;
+        if (p0 != p1) {
+            delete pb;
+            return fail(ADG_EINVAL, "periodic must be set on both sides of axis %d", k);
+        }
+        P.periodic[k] = p0;
+        for (int s = 0; s < 2; s++) {
+            const adg_bc &b = g->bc[k][s];
+            BCDev &d = P.bc[k][s];
+            for (int w = 0; w < 2; w++) {
+                if (b.kind[w] < 0 || b.kind[w] > ADG_DIRICHLET) {
+                    delete pb;
+                    return fail(ADG_EINVAL, "bad boundary kind");
+                }
+                d.kind[w] = b.kind[w];
+                for (int v = 0; v < 5; v++) d.state[w][v] = b.state[w][v];
+            }
+            if (b.split_axis >= g->dim || b.split_axis == k) {
+                delete pb;
+                return fail(ADG_EINVAL, "split axis must be a tangential axis");
+            }
+            d.split_axis = b.split_axis < 0 ? -1 : b.split_axis;
+            d.split0 = b.split0;
+            d.split_speed = b.split_speed;
+        }
+    }
+    pb->prm = prm;
+    pb->cap = prm.pool_capacity > 0 ? std::min<int64_t>(prm.pool_capacity, P.ncell) : P.ncell;
+    pb->npos = positions_per_cell(P.dim, N);
+    build_tables(N, P.Ns, &pb->tab_host);
+    plan(pb);
+    *out = pb;
+    return ADG_OK;
+}
+
+int adg_destroy(adg_problem *pb) {
+    if (!pb) return ADG_OK;
+    if (pb->stream || pb->bound) (void)hipStreamSynchronize(pb->stream);
+    for (auto &m : pb->pending) {
+        (void)hipEventDestroy(m.a);
+        (void)hipEventDestroy(m.b);
+    }
+    for (auto e : pb->spare) (void)hipEventDestroy(e);
+    if (pb->pinned) (void)hipHostFree(pb->pinned);
+    delete pb;
+    return ADG_OK;
+}
+
+size_t adg_workspace_bytes(const adg_problem *pb) { return pb ? pb->ws_bytes : 0; }
+
+int adg_bind(adg_problem *pb, void *dev_workspace, size_t bytes, void *hip_stream) {
+    if (!pb || !dev_workspace) return fail(ADG_EINVAL, "null argument");
+    if (bytes < pb->ws_bytes) return fail(ADG_ENOMEM, "workspace %zu bytes < %zu needed", bytes, pb->ws_bytes);
+    if (((uintptr_t)dev_workspace) & 255) return fail(ADG_EINVAL, "workspace must be 256-byte aligned");
+    pb->ws = (char *)dev_workspace;
+    pb->stream = (hipStream_t)hip_stream;
+    carve(pb);
+    if (!pb->pinned) HIPCHK(hipHostMalloc((void **)&pb->pinned, 64, hipHostMallocDefault));
+    HIPCHK(hipMemcpyAsync(pb->tab_dev, &pb->tab_host, sizeof(Tables), hipMemcpyHostToDevice, pb->stream));
+    HIPCHK(hipMemsetAsync(pb->B.counts, 0, 32, pb->stream));
+    HIPCHK(hipMemsetAsync(pb->B.scal, 0, 64, pb->stream));
+    HIPCHK(hipMemsetAsync(pb->B.force, 0, pb->P.ncell, pb->stream));
+    HIPCHK(hipMemsetAsync(pb->B.beta[0], 0, pb->P.ncell, pb->stream));
+    HIPCHK(hipMemsetAsync(pb->B.beta[1], 0, pb->P.ncell, pb->stream));
+    HIPCHK(hipMemsetAsync(pb->B.margin, 0, 4 * pb->P.ncell, pb->stream));
+    HIPCHK(hipStreamSynchronize(pb->stream));
+    pb->bound = true;
+    pb->has_state = false;
+    pb->cur = 0;
+    return ADG_OK;
+}
+
+int adg_axis_points(const adg_problem *pb, int axis, int m, double *out) {
+    if (!pb || !out || axis < 0 || axis >= pb->P.dim || m < 0 || m > 16) return fail(ADG_EINVAL, "bad argument");
+    const Prob &P = pb->P;
+    if (m == 0) {
+        for (int i = 0; i < P.nc[axis]; i++)
+            for (int a = 0; a < P.n; a++) out[(int64_t)i * P.n + a] = P.lo[axis] + P.h[axis] * (i + pb->tab_host.xi[a]);
+        return ADG_OK;
+    }
+    double xq[16], wq[16];
+    gl_nodes(m, xq, wq);
+    for (int i = 0; i < P.nc[axis]; i++)
+        for (int s = 0; s < P.Ns; s++)
+            for (int q = 0; q < m; q++)
+                out[((int64_t)i * P.Ns + s) * m + q] = P.lo[axis] + P.h[axis] * (i + (s + xq[q]) / P.Ns);
+    return ADG_OK;
+}
+
+int adg_project_samples(const adg_problem *pb, const double *samples, int m, double *u, double *v) {
+    if (!pb || !samples || !u || m < 0 || m > 16) return fail(ADG_EINVAL, "bad argument");
+    const Prob &P = pb->P;
+    const int d = P.dim, n = P.n, Ns = P.Ns, nv = P.nv;
+    const int64_t nn = ipow64(n, d), nsub = ipow64(Ns, d), nc = P.ncell;
+    const int per = m == 0 ? n : Ns * m;
+    int64_t ext[3] = {1, 1, 1};
+    for (int k = 0; k < d; k++) ext[k] = (int64_t)P.nc[k] * per;
+    const int64_t npts = ext[0] * ext[1] * ext[2];
+    if (m == 0) {
+        for (int64_t c = 0; c < nc; c++) {
+            int ci[3] = {(int)(c % P.nc[0]), (int)((c / P.nc[0]) % P.nc[1]), (int)(c / ((int64_t)P.nc[0] * P.nc[1]))};
+            for (int64_t a = 0; a < nn; a++) {
+                int ma[3] = {(int)(a % n), (int)((a / n) % n), (int)(a / (n * n))};
+                int64_t gi[3] = {0, 0, 0};
+                for (int k = 0; k < d; k++) gi[k] = (int64_t)ci[k] * per + ma[k];
+                const int64_t pidx = gi[0] + ext[0] * (gi[1] + ext[1] * gi[2]);
+                for (int vv = 0; vv < nv; vv++) u[((int64_t)vv * nc + c) * nn + a] = samples[vv * npts + pidx];
+            }
+        }
+        return ADG_OK;
+    }
+    // composite m-point rule on every subcell; per-axis basis values at the points
+    double xq[16], wq[16];
+    gl_nodes(m, xq, wq);
+    std::vector<double> phi((size_t)Ns * m * n);
+    for (int s = 0; s < Ns; s++)
+        for (int q = 0; q < m; q++) lagrange_values(n, pb->tab_host.xi, (s + xq[q]) / Ns, &phi[((size_t)s * m + q) * n]);
+    const int64_t nq = ipow64(m, d);
+    std::vector<double> acc((size_t)nv * nn);
+    for (int64_t c = 0; c < nc; c++) {
+        int ci[3] = {(int)(c % P.nc[0]), (int)((c / P.nc[0]) % P.nc[1]), (int)(c / ((int64_t)P.nc[0] * P.nc[1]))};
+        std::fill(acc.begin(), acc.end(), 0.0);
+        for (int64_t sg = 0; sg < nsub; sg++) {
+            int ms[3] = {(int)(sg % Ns), (int)((sg / Ns) % Ns), (int)(sg / (Ns * Ns))};
+            double avg[5] = {0, 0, 0, 0, 0};
+            for (int64_t qi = 0; qi < nq; qi++) {
+                int mq[3] = {(int)(qi % m), (int)((qi / m) % m), (int)(qi / (m * m))};
+                int64_t gi[3] = {0, 0, 0};
+                double w = 1.0;
+                for (int k = 0; k < d; k++) {
+                    gi[k] = ((int64_t)ci[k] * Ns + ms[k]) * m + mq[k];
+                    w *= wq[mq[k]];
+                }
+                const int64_t pidx = gi[0] + ext[0] * (gi[1] + ext[1] * gi[2]);
+                double f[5];
+                for (int vv = 0; vv < nv; vv++) {
+                    f[vv] = samples[vv * npts + pidx];
+                    avg[vv] += w * f[vv];
+                }
+                for (int64_t a = 0; a < nn; a++) {
+                    int ma[3] = {(int)(a % n), (int)((a / n) % n), (int)(a / (n * n))};
+                    double ph = w;
+                    for (int k = 0; k < d; k++) ph *= phi[((size_t)ms[k] * m + mq[k]) * n + ma[k]];
+                    for (int vv = 0; vv < nv; vv++) acc[vv * nn + a] += ph * f[vv];
+                }
+            }
+            if (v)
+                for (int vv = 0; vv < nv; vv++) v[((int64_t)vv * nc + c) * nsub + sg] = avg[vv];
+        }
+        for (int64_t a = 0; a < nn; a++) {
+            int ma[3] = {(int)(a % n), (int)((a / n) % n), (int)(a / (n * n))};
+            double W = 1.0;
+            for (int k = 0; k < d; k++) W *= pb->tab_host.w[ma[k]];
+            for (int vv = 0; vv < nv; vv++) u[((int64_t)vv * nc + c) * nn + a] = acc[vv * nn + a] / (W * nsub);
+        }
+    }
+    return ADG_OK;
+}
+
+// Host-side initial detection (Sec. 4.4, last paragraph): P(u0) against the bounds of
+// the exact subcell averages over each cell's neighbourhood.
+static int initial_detection(adg_problem *pb, std::vector<double> &u, const double *vex, std::vector<uint8_t> &beta,
+                             std::vector<int> &slot, std::vector<double> &pool, int64_t &count) {
+    const Prob &P = pb->P;
+    const Tables &T = pb->tab_host;
+    const int d = P.dim, n = P.n, Ns = P.Ns, nv = P.nv;
+    const int64_t nn = ipow64(n, d), nsub = ipow64(Ns, d), nc = P.ncell;
+    beta.assign(nc, 0);
+    slot.assign(nc, -1);
+    count = 0;
+    // per (possibly ghost) subcell value of the exact data
+    auto value = [&](const int *gci, const int *gs, double *q) {
+        int src[3] = {0, 0, 0}, ss[3] = {0, 0, 0}, gside[3] = {-1, -1, -1};
+        for (int j = 0; j < d; j++) {
+            src[j] = gci[j];
+            ss[j] = gs[j];
+            if (gci[j] < 0 || gci[j] >= P.nc[j]) {
+                const int side = gci[j] >= P.nc[j];
+                if (P.periodic[j]) src[j] = (gci[j] + P.nc[j]) % P.nc[j];
+                else {
+                    src[j] = side ? 2 * P.nc[j] - 1 - gci[j] : -1 - gci[j];
+                    ss[j] = Ns - 1 - gs[j];
+                    gside[j] = side;
+                }
+            }
+        }
+        const int64_t cs = src[0] + (int64_t)P.nc[0] * (src[1] + (int64_t)P.nc[1] * src[2]);
+        int sidx = 0;
+        for (int j = d - 1; j >= 0; j--) sidx = sidx * Ns + ss[j];
+        for (int vv = 0; vv < nv; vv++) q[vv] = vex[((int64_t)vv * nc + cs) * nsub + sidx];
+        double x[3] = {0, 0, 0};
+        for (int j = 0; j < d; j++) x[j] = P.lo[j] + P.h[j] * (gci[j] + (gs[j] + 0.5) / Ns);
+        for (int j = 0; j < d; j++) {
+            if (gside[j] < 0) continue;
+            const BCDev &b = P.bc[j][gside[j]];
+            int which = 0;
+            if (b.split_axis >= 0) which = (x[b.split_axis] < b.split0) ? 0 : 1;
+            if (b.kind[which] == ADG_DIRICHLET) {
+                for (int vv = 0; vv < nv; vv++) q[vv] = b.state[which][vv];
+            } else if (b.kind[which] == ADG_REFLECTIVE) {
+                q[1 + j] = -q[1 + j];
+            }
+        }
+    };
+    std::vector<double> vstar((size_t)nv * nsub);
+    for (int64_t c = 0; c < nc; c++) {
+        int ci[3] = {(int)(c % P.nc[0]), (int)((c / P.nc[0]) % P.nc[1]), (int)(c / ((int64_t)P.nc[0] * P.nc[1]))};
+        double lo[5], hi[5];
+        for (int vv = 0; vv < nv; vv++) {
+            lo[vv] = INFINITY;
+            hi[vv] = -INFINITY;
+        }
+        const int nb = (int)ipow64(3, d);
+        for (int o = 0; o < nb; o++) {
+            int gci[3] = {ci[0], ci[1], ci[2]};
+            int off[3] = {o % 3, (o / 3) % 3, o / 9};
+            for (int j = 0; j < d; j++) gci[j] += off[j] - 1;
+            for (int64_t sg = 0; sg < nsub; sg++) {
+                int gs[3] = {(int)(sg % Ns), (int)((sg / Ns) % Ns), (int)(sg / (Ns * Ns))};
+                double q[5];
+                value(gci, gs, q);
+                for (int vv = 0; vv < nv; vv++) {
+                    lo[vv] = std::fmin(lo[vv], q[vv]);
+                    hi[vv] = std::fmax(hi[vv], q[vv]);
+                }
+            }
+        }
+        // candidate subcell averages P(u0)
+        for (int vv = 0; vv < nv; vv++)
+            for (int64_t sg = 0; sg < nsub; sg++) {
+                int ms[3] = {(int)(sg % Ns), (int)((sg / Ns) % Ns), (int)(sg / (Ns * Ns))};
+                double acc = 0;
+                for (int64_t a = 0; a < nn; a++) {
+                    int ma[3] = {(int)(a % n), (int)((a / n) % n), (int)(a / (n * n))};
+                    double wgt = 1;
+                    for (int j = 0; j < d; j++) wgt *= T.P[ms[j]][ma[j]];
+                    acc += wgt * u[((int64_t)vv * nc + c) * nn + a];
+                }
+                vstar[vv * nsub + sg] = acc;
+            }
+        bool bad = false;
+        for (int64_t sg = 0; sg < nsub && !bad; sg++) {
+            double q[5];
+            bool finite = true;
+            for (int vv = 0; vv < nv; vv++) {
+                q[vv] = vstar[vv * nsub + sg];
+                finite = finite && std::isfinite(q[vv]);
+            }
+            if (!finite) { bad = true; break; }
+            double ke = 0;
+            for (int j = 0; j < d; j++) ke += q[1 + j] * q[1 + j];
+            const double p = (P.gamma - 1.0) * (q[d + 1] - 0.5 * ke / q[0]);
+            if (!(q[0] > 0) || !(p > 0)) bad = true;
+            for (int vv = 0; vv < nv; vv++) {
+                const double delta = std::fmax(P.delta0, P.eps * (hi[vv] - lo[vv]));
+                if (q[vv] < lo[vv] - delta || q[vv] > hi[vv] + delta) bad = true;
+            }
+        }
+        if (bad) {
+            if (count >= pb->cap) return fail(ADG_ECAPACITY, "initial detection flags more cells than the pool holds");
+            beta[c] = 1;
+            slot[c] = (int)count;
+            for (int vv = 0; vv < nv; vv++)
+                for (int64_t sg = 0; sg < nsub; sg++)
+                    pool[((size_t)count * nv + vv) * nsub + sg] = vex[((int64_t)vv * nc + c) * nsub + sg];
+            // u := R(v_exact)
+            for (int vv = 0; vv < nv; vv++)
+                for (int64_t a = 0; a < nn; a++) {
+                    int ma[3] = {(int)(a % n), (int)((a / n) % n), (int)(a / (n * n))};
+                    double acc = 0;
+                    for (int64_t sg = 0; sg < nsub; sg++) {
+                        int ms[3] = {(int)(sg % Ns), (int)((sg / Ns) % Ns), (int)(sg / (Ns * Ns))};
+                        double wgt = 1;
+                        for (int j = 0; j < d; j++) wgt *= T.Rg[ma[j]][ms[j]];
+                        acc += wgt * vex[((int64_t)vv * nc + c) * nsub + sg];
+                    }
+                    u[((int64_t)vv * nc + c) * nn + a] = acc;
+                }
+            count++;
+        }
+    }
+    return ADG_OK;
+}
+
+int adg_set_state(adg_problem *pb, const double *u, int on_device, const double *v_exact) {
+    if (!pb || !u) return fail(ADG_EINVAL, "null argument");
+    if (!pb->bound) return fail(ADG_ESTATE, "adg_bind first");
+    const Prob &P = pb->P;
+    const int64_t nn = ipow64(P.n, P.dim), nsub = ipow64(P.Ns, P.dim);
+    const size_t ubytes = 8ull * P.nv * P.ncell * nn;
+    pb->cur = 0;
+    std::vector<uint8_t> beta(P.ncell, 0);
+    std::vector<int> slot(P.ncell, -1);
+    int64_t count = 0;
+    if (v_exact && pb->prm.limiter) {
+        std::vector<double> uh((size_t)P.nv * P.ncell * nn);
+        if (on_device) {
+            HIPCHK(hipMemcpyAsync(uh.data(), u, ubytes, hipMemcpyDeviceToHost, pb->stream));
+            HIPCHK(hipStreamSynchronize(pb->stream));
+        } else {
+            std::memcpy(uh.data(), u, ubytes);
+        }
+        std::vector<double> pool;
+        pool.resize((size_t)pb->cap * P.nv * nsub);
+        int rc = initial_detection(pb, uh, v_exact, beta, slot, pool, count);
+        if (rc != ADG_OK) return rc;
+        HIPCHK(hipMemcpyAsync(pb->B.u[0], uh.data(), ubytes, hipMemcpyHostToDevice, pb->stream));
+        if (count)
+            HIPCHK(hipMemcpyAsync(pb->B.pool[0], pool.data(), 8ull * count * P.nv * nsub, hipMemcpyHostToDevice,
+                                  pb->stream));
+        HIPCHK(hipStreamSynchronize(pb->stream));
+    } else {
+        HIPCHK(hipMemcpyAsync(pb->B.u[0], u, ubytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                              pb->stream));
+    }
+    HIPCHK(hipMemcpyAsync(pb->B.beta[0], beta.data(), P.ncell, hipMemcpyHostToDevice, pb->stream));
+    HIPCHK(hipMemcpyAsync(pb->B.slot[0], slot.data(), 4ull * P.ncell, hipMemcpyHostToDevice, pb->stream));
+    HIPCHK(hipMemsetAsync(pb->B.scal, 0, 64, pb->stream));
+    HIPCHK(hipMemsetAsync(pb->B.counts, 0, 32, pb->stream));
+    HIPCHK(hipStreamSynchronize(pb->stream));
+    pb->has_state = true;
+    pb->last_troubled = count;
+    pb->last_corrected = 0;
+    pb->steps = 0;
+    return ADG_OK;
+}
+
+int adg_get_state(const adg_problem *pb, double *u, int to_device) {
+    if (!pb || !u) return fail(ADG_EINVAL, "null argument");
+    if (!pb->has_state) return fail(ADG_ESTATE, "no state");
+    const size_t ubytes = 8ull * pb->P.nv * pb->P.ncell * ipow64(pb->P.n, pb->P.dim);
+    HIPCHK(hipMemcpyAsync(u, pb->B.u[pb->cur], ubytes, to_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                          pb->stream));
+    if (!to_device) HIPCHK(hipStreamSynchronize(pb->stream));
+    return ADG_OK;
+}
+
+static double dt_factor(const adg_problem *pb, double cfl) {
+    double h = pb->P.h[0];
+    for (int k = 1; k < pb->P.dim; k++) h = std::fmin(h, pb->P.h[k]);
+    return cfl * h / (pb->P.dim * (2.0 * pb->P.N + 1.0));
+}
+
+int adg_cfl_dt(adg_problem *pb, double cfl, double *dt_out) {
+    if (!pb || !dt_out || !(cfl > 0)) return fail(ADG_EINVAL, "bad argument");
+    if (!pb->has_state) return fail(ADG_ESTATE, "no state");
+    StepCtx C = ctx(pb);
+    launch_lambda(C, pb->B.u[pb->cur], dt_factor(pb, cfl));
+    HIPCHK(hipGetLastError());
+    double s[3];
+    HIPCHK(hipMemcpyAsync(s, pb->B.scal, sizeof s, hipMemcpyDeviceToHost, pb->stream));
+    HIPCHK(hipStreamSynchronize(pb->stream));
+    *dt_out = s[0];
+    return ADG_OK;
+}
+
+static int do_step(adg_problem *pb) {
+    StepCtx C = ctx(pb);
+    Bufs &B = pb->B;
+    if (pb->prm.limiter) {
+        GroupTimer g(pb, 0);
+        launch_bounds(C);
+    }
+    {
+        GroupTimer g(pb, 1);
+        launch_predictor(C);
+    }
+    {
+        GroupTimer g(pb, 2);
+        launch_faces(C);
+    }
+    {
+        GroupTimer g(pb, 3);
+        launch_corrector_detect(C);
+    }
+    HIPCHK(hipGetLastError());
+    int64_t troubled = 0, corrected = 0;
+    int rc = ADG_OK;
+    if (pb->prm.limiter) {
+        {
+            GroupTimer g(pb, 4);
+            launch_compact(C);
+        }
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(pb->pinned, B.counts, 16, hipMemcpyDeviceToHost, pb->stream));
+        HIPCHK(hipStreamSynchronize(pb->stream));
+        if (pb->profiling) harvest(pb);
+        troubled = pb->pinned[0];
+        corrected = pb->pinned[1];
+        if (troubled > pb->cap) rc = fail(ADG_ECAPACITY, "%lld troubled cells exceed pool capacity %lld",
+                                          (long long)troubled, (long long)pb->cap);
+        const int64_t todo = std::min<int64_t>(troubled, pb->cap);
+        if (todo > 0) {
+            GroupTimer g(pb, 5);
+            for (int64_t first = 0; first < todo; first += pb->chunk) {
+                const int cnt = (int)std::min<int64_t>(pb->chunk, todo - first);
+                launch_subcell_chunk(C, (int)first, cnt);
+            }
+        }
+        if (corrected > 0) {
+            GroupTimer g(pb, 6);
+            launch_fluxcorr(C, (int)corrected);
+        }
+        HIPCHK(hipGetLastError());
+        std::swap(B.beta[0], B.beta[1]);
+        std::swap(B.slot[0], B.slot[1]);
+        std::swap(B.pool[0], B.pool[1]);
+    }
+    launch_advance_time(C);
+    HIPCHK(hipGetLastError());
+    pb->cur ^= 1;
+    pb->last_troubled = troubled;
+    pb->last_corrected = corrected;
+    pb->steps++;
+    return rc;
+}
+
+int adg_step(adg_problem *pb, double dt) {
+    if (!pb) return fail(ADG_EINVAL, "null argument");
+    if (!pb->has_state) return fail(ADG_ESTATE, "no state");
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(ADG_EINVAL, "dt must be positive");
+    StepCtx C = ctx(pb);
+    launch_set_scalar(C, 0, dt);
+    return do_step(pb);
+}
+
+int adg_step_cfl(adg_problem *pb, double cfl) {
+    if (!pb) return fail(ADG_EINVAL, "null argument");
+    if (!pb->has_state) return fail(ADG_ESTATE, "no state");
+    if (!(cfl > 0)) return fail(ADG_EINVAL, "cfl must be positive");
+    StepCtx C = ctx(pb);
+    {
+        GroupTimer g(pb, 7);
+        launch_lambda(C, pb->B.u[pb->cur], dt_factor(pb, cfl));
+    }
+    return do_step(pb);
+}
+
+int adg_time(const adg_problem *pb, double *t) {
+    if (!pb || !t) return fail(ADG_EINVAL, "null argument");
+    if (!pb->bound) return fail(ADG_ESTATE, "not bound");
+    double s[2];
+    HIPCHK(hipMemcpyAsync(s, pb->B.scal, sizeof s, hipMemcpyDeviceToHost, pb->stream));
+    HIPCHK(hipStreamSynchronize(pb->stream));
+    *t = s[1];
+    return ADG_OK;
+}
+
+int adg_get_troubled(const adg_problem *pb, uint8_t *beta, int64_t *count) {
+    if (!pb || !beta) return fail(ADG_EINVAL, "null argument");
+    if (!pb->has_state) return fail(ADG_ESTATE, "no state");
+    HIPCHK(hipMemcpyAsync(beta, pb->B.beta[0], pb->P.ncell, hipMemcpyDeviceToHost, pb->stream));
+    HIPCHK(hipStreamSynchronize(pb->stream));
+    if (count) {
+        int64_t s = 0;
+        for (int64_t c = 0; c < pb->P.ncell; c++) s += beta[c] != 0;
+        *count = s;
+    }
+    return ADG_OK;
+}
+
+int adg_get_margin(const adg_problem *pb, float *margin) {
+    if (!pb || !margin) return fail(ADG_EINVAL, "null argument");
+    HIPCHK(hipMemcpyAsync(margin, pb->B.margin, 4ull * pb->P.ncell, hipMemcpyDeviceToHost, pb->stream));
+    HIPCHK(hipStreamSynchronize(pb->stream));
+    return ADG_OK;
+}
+
+int adg_get_subcells(const adg_problem *pb, double *v) {
+    if (!pb || !v) return fail(ADG_EINVAL, "null argument");
+    if (!pb->has_state) return fail(ADG_ESTATE, "no state");
+    const Prob &P = pb->P;
+    const int64_t nsub = ipow64(P.Ns, P.dim), nc = P.ncell;
+    std::vector<uint8_t> beta(nc);
+    std::vector<int> slot(nc);
+    HIPCHK(hipMemcpyAsync(beta.data(), pb->B.beta[0], nc, hipMemcpyDeviceToHost, pb->stream));
+    HIPCHK(hipMemcpyAsync(slot.data(), pb->B.slot[0], 4ull * nc, hipMemcpyDeviceToHost, pb->stream));
+    HIPCHK(hipStreamSynchronize(pb->stream));
+    std::vector<double> buf((size_t)P.nv * nsub);
+    for (int64_t c = 0; c < nc; c++) {
+        if (!beta[c] || slot[c] < 0) continue;
+        HIPCHK(hipMemcpyAsync(buf.data(), pb->B.pool[0] + (size_t)slot[c] * P.nv * nsub, 8ull * P.nv * nsub,
+                              hipMemcpyDeviceToHost, pb->stream));
+        HIPCHK(hipStreamSynchronize(pb->stream));
+        for (int vv = 0; vv < P.nv; vv++)
+            std::memcpy(v + ((int64_t)vv * nc + c) * nsub, buf.data() + (size_t)vv * nsub, 8ull * nsub);
+    }
+    return ADG_OK;
+}
+
+int adg_get_stats(const adg_problem *pb, int64_t *out4) {
+    if (!pb || !out4) return fail(ADG_EINVAL, "null argument");
+    int cnt[4];
+    HIPCHK(hipMemcpyAsync(cnt, pb->B.counts, sizeof cnt, hipMemcpyDeviceToHost, pb->stream));
+    HIPCHK(hipStreamSynchronize(pb->stream));
+    out4[0] = pb->last_troubled;
+    out4[1] = pb->last_corrected;
+    out4[2] = cnt[2];
+    out4[3] = pb->steps;
+    return ADG_OK;
+}
+
+int adg_profile(adg_problem *pb, int enable) {
+    if (!pb) return fail(ADG_EINVAL, "null argument");
+    if (!pb->bound) return fail(ADG_ESTATE, "not bound");
+    HIPCHK(hipStreamSynchronize(pb->stream));
+    harvest(pb);
+    if (enable) {
+        for (int g = 0; g < 8; g++) {
+            pb->prof_ms[g] = 0;
+            pb->prof_n[g] = 0;
+        }
+    }
+    pb->profiling = enable != 0;
+    return ADG_OK;
+}
+
+int adg_profile_read(adg_problem *pb, double *ms, int64_t *launches, int ngroups) {
+    if (!pb || ngroups < 0 || ngroups > 8) return fail(ADG_EINVAL, "bad argument");
+    if (!pb->bound) return fail(ADG_ESTATE, "not bound");
+    HIPCHK(hipStreamSynchronize(pb->stream));
+    harvest(pb);
+    for (int g = 0; g < ngroups; g++) {
+        if (ms) ms[g] = pb->prof_ms[g];
+        if (launches) launches[g] = pb->prof_n[g];
+    }
+    return ADG_OK;
+}
+
+int adg_debug_force_troubled(adg_problem *pb, const uint8_t *mask) {
+    if (!pb) return fail(ADG_EINVAL, "null argument");
+    if (!pb->bound) return fail(ADG_ESTATE, "not bound");
+    if (mask) HIPCHK(hipMemcpyAsync(pb->B.force, mask, pb->P.ncell, hipMemcpyHostToDevice, pb->stream));
+    else HIPCHK(hipMemsetAsync(pb->B.force, 0, pb->P.ncell, pb->stream));
+    HIPCHK(hipStreamSynchronize(pb->stream));
+    return ADG_OK;
+}
+
+}  // extern "C"

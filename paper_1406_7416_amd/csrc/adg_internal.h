@@ -1,0 +1,74 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include "adg.h"
+
+namespace adg {
+
+constexpr int MAXN = 10;     // nodes per axis (N <= 9)
+constexpr int MAXNS = 19;    // subcells per axis (2N+1)
+
+// Operator tables, built on the host in FP64 (Newton Gauss-Legendre, barycentric
+// Lagrange) and uploaded once per problem.
+struct Tables {
+    double xi[MAXN], w[MAXN];
+    double D[MAXN][MAXN];        // D[a][b] = phi_b'(xi_a)
+    double L[MAXN], R[MAXN];     // phi_b(0), phi_b(1)
+    double Kw[MAXN][MAXN];       // K1^{-1} diag(w), time operator of the predictor
+    double Dvol[MAXN][MAXN];     // w_b D[b][a] / w_a : volume-term operator
+    double P[MAXNS][MAXN];       // subcell projection, eq. (subcell.p)
+    double Rg[MAXN][MAXNS];      // subcell reconstruction (gather), eq. (subcell.r)
+    double Pt[MAXNS][MAXN];      // P[s][a] / (Ns w_a): sub-face integral of phi_a over face w_a
+    // degree-2 subcell scheme (3 Gauss-Legendre nodes)
+    double xi3[3], w3[3];
+    double D3[MAXN][MAXN], L3[MAXN], R3[MAXN], Kw3[MAXN][MAXN];
+    double weno[3][3][3];        // [stencil][monomial][cell]: averages -> coefficients
+};
+
+struct BCDev {
+    int kind[2];
+    int split_axis;
+    double split0, split_speed;
+    double state[2][5];
+};
+
+// Everything a kernel needs to know about one problem.
+struct Prob {
+    int dim, N, n, nv, Ns;
+    int nc[3];
+    int64_t ncell;
+    double lo[3], h[3];
+    double gamma, eps, delta0;
+    BCDev bc[3][2];
+    int periodic[3];
+};
+
+// Device buffers of one problem, carved out of the caller's workspace.
+struct Bufs {
+    Tables *tab;
+    double *u[2];          // [v][cell][node] current / next
+    double *ext_min, *ext_max;   // [v][ext cell] per-cell subcell min/max incl. ghost ring
+    double *bmin, *bmax;   // [v][cell] neighbourhood bounds
+    double *trace;         // [cell][2d][v][nfn*n]
+    double *gbar;          // [cell][2d][v][nfn]
+    uint8_t *beta[2];      // [cell] old / new
+    uint8_t *force;        // [cell] forced troubled mask
+    float *margin;         // [cell]
+    int *tlist, *clist;    // troubled cells, corrected cells
+    int *slot[2];          // cell -> pool slot (old / new), -1 if none
+    double *pool[2];       // [slot][v][sub]
+    double *sflux;         // [slot][2d][v][subf]
+    int *blk;              // block partial counts for compaction [2][nblk]
+    int *counts;           // [0] troubled [1] corrected [2] nonphysical cumulative [3] capacity overflow
+    double *scal;          // [0] dt [1] t [2] lambda_max ...
+    double *lam_part;      // per-block lambda partials
+    // subcell chunk scratch
+    double *halo;          // [chunk][v][(Ns+6)^d]
+    double *Y;             // [chunk][pos][v][3^d]
+    double *strace;        // [chunk][pos][2d][v][3^(d-1)*3]
+};
+
+int64_t ipow64(int64_t b, int e);
+
+}  // namespace adg

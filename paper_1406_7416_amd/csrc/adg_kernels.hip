@@ -1,0 +1,1421 @@
+// HIP kernels for gfx950: one ADER-DG step with the a-posteriori subcell limiter.
+//
+// Data layout in HBM (FP64):
+//   u[v][cell][node]           nodal DG state, node = tensor GL index (x fastest)
+//   trace[cell][2d][v][nfn*n]  predictor face traces, nfn = n^(d-1) tangential nodes x n time nodes
+//   gbar[cell][2d][v][nfn]     time-integrated Rusanov face flux, one copy per adjacent cell
+//   pool[slot][v][sub]         subcell data of troubled cells (sparse), slot = worklist index
+//
+// Parallel mapping: every kernel is element-local or face-local and writes each output
+// from exactly one thread (no atomics on data), so results are bitwise reproducible.
+#include <cmath>
+#include "adg_internal.h"
+#include "adg_kernels.h"
+
+namespace adg {
+
+// ------------------------------------------------------------------ small helpers
+template <int B, int E> struct Pow { static constexpr int v = B * Pow<B, E - 1>::v; };
+template <int B> struct Pow<B, 0> { static constexpr int v = 1; };
+
+__host__ __device__ constexpr int cpow(int b, int e) { return e == 0 ? 1 : b * cpow(b, e - 1); }
+
+template <int DIM>
+__device__ __forceinline__ double pressure(const double *q, double g) {
+    double ke = 0.0;
+#pragma unroll
+    for (int j = 0; j < DIM; j++) ke += q[1 + j] * q[1 + j];
+    return (g - 1.0) * (q[DIM + 1] - 0.5 * ke / q[0]);
+}
+
+// Euler flux along axis k (Sec. 5).
+template <int DIM>
+__device__ __forceinline__ void euler_flux(int k, const double *q, double *F, double g) {
+    const double p = pressure<DIM>(q, g);
+    const double un = q[1 + k] / q[0];
+    F[0] = q[1 + k];
+#pragma unroll
+    for (int j = 0; j < DIM; j++) F[1 + j] = q[1 + j] * un + (j == k ? p : 0.0);
+    F[DIM + 1] = un * (q[DIM + 1] + p);
+}
+
+// Rusanov flux; wave speed per quadrature node: max over both sides of |u_n| + c.
+template <int DIM>
+__device__ __forceinline__ void rusanov(int k, const double *qL, const double *qR, double *G, double g) {
+    constexpr int NV = DIM + 2;
+    double FL[NV], FR[NV];
+    euler_flux<DIM>(k, qL, FL, g);
+    euler_flux<DIM>(k, qR, FR, g);
+    const double sL = fabs(qL[1 + k] / qL[0]) + sqrt(g * pressure<DIM>(qL, g) / qL[0]);
+    const double sR = fabs(qR[1 + k] / qR[0]) + sqrt(g * pressure<DIM>(qR, g) / qR[0]);
+    const double s = fmax(sL, sR);
+#pragma unroll
+    for (int v = 0; v < NV; v++) G[v] = 0.5 * (FL[v] + FR[v]) - 0.5 * s * (qR[v] - qL[v]);
+}
+
+template <int DIM>
+__device__ __forceinline__ bool physical(const double *q, double g) {
+#pragma unroll
+    for (int v = 0; v < DIM + 2; v++)
+        if (!isfinite(q[v])) return false;
+    return q[0] > 0.0 && pressure<DIM>(q, g) > 0.0;
+}
+
+// Ghost state of one boundary side (transmissive / reflective / Dirichlet with split).
+template <int DIM>
+__device__ __forceinline__ void bc_ghost(const Prob &P, int k, int side, const double *qin, const double *x,
+                                         double t, double *qout) {
+    constexpr int NV = DIM + 2;
+    const BCDev &b = P.bc[k][side];
+    int which = 0;
+    if (b.split_axis >= 0) which = (x[b.split_axis] < b.split0 + b.split_speed * t) ? 0 : 1;
+    const int kind = b.kind[which];
+    if (kind == ADG_DIRICHLET) {
+#pragma unroll
+        for (int v = 0; v < NV; v++) qout[v] = b.state[which][v];
+        return;
+    }
+#pragma unroll
+    for (int v = 0; v < NV; v++) qout[v] = qin[v];
+    if (kind == ADG_REFLECTIVE) qout[1 + k] = -qout[1 + k];
+}
+
+__device__ __forceinline__ int64_t cell_of(const Prob &P, const int *ci) {
+    return ci[0] + (int64_t)P.nc[0] * (ci[1] + (int64_t)P.nc[1] * ci[2]);
+}
+__device__ __forceinline__ void coords_of(const Prob &P, int64_t c, int *ci) {
+    ci[0] = (int)(c % P.nc[0]);
+    ci[1] = (int)((c / P.nc[0]) % P.nc[1]);
+    ci[2] = (int)(c / ((int64_t)P.nc[0] * P.nc[1]));
+}
+
+// ------------------------------------------------------------- space-time predictor
+// Eq. (pde.nc.dg2) in nodal form (spatial weights divided out, K1^{-1} L = 1):
+//   q^{r+1}(a,s) = u(a) - sum_t Kw[s][t] S(a,t),
+//   S(a,t) = sum_k (dt/h_k) sum_b D[a_k][b] F_k(q^r(a|b, t))
+// Thread mapping: a "point owner" thread holds one spatial node of one cell with its
+// whole time pencil (NV x n values) in registers.  It evaluates the fluxes of the pencil
+// and stores them in LDS; "line owner" threads do the length-n spatial contractions
+// (n loads -> n outputs each, in place); the point owner accumulates S over the d axes
+// and applies the time contraction in registers: d + 1 contractions per sweep.
+template <int DIM, int N>
+struct PredShape {
+    static constexpr int n = N + 1;
+    static constexpr int NV = DIM + 2;
+    static constexpr int NN = cpow(n, DIM);
+    static constexpr int NST = NN * n;
+    static constexpr int NFN = cpow(n, DIM - 1);
+    static constexpr int CPB = NN <= 256 ? 256 / NN : 1;
+    static constexpr int ACT = CPB * NN;                           // active point owners
+    static constexpr int BS = ((ACT + 63) / 64) * 64;
+    static constexpr int VCMAX = 65536 / (CPB * NST * 8);
+    static constexpr int VC = VCMAX < 1 ? 1 : (VCMAX > NV ? NV : VCMAX);  // vars per LDS chunk
+};
+
+struct PredArgs {
+    const double *in;      // input nodal values
+    int64_t in_cstride;    // stride between cells
+    int64_t in_vstride;    // stride between variables
+    double *trace;         // [cell][2d][v][nfn*n]
+    double *vol_out;       // candidate with volume term [v][cell][node] (main scheme only)
+    int64_t ncell;         // cells (or subcell positions) in this launch
+    int64_t cell0;         // first cell index (for vol_out addressing)
+    int iters;
+    double dth[3];         // dt/h_k multipliers (without dt)
+    const double *dt;      // device scalar
+    // operators of the n-node basis used by this launch (row stride MAXN)
+    const double *D, *Kw, *Lb, *Rb, *w, *Dvol;
+};
+
+// Contraction along axis k of every line held in LDS: line[i] <- c * sum_b M[i][b] line[b].
+template <int DIM, int N, int CPB, int VC, int BS>
+__device__ __forceinline__ void lds_lines(double *X, int k, int nlines_per_var, int lstride_s, const double (*M)[MAXN],
+                                          double c, int tid) {
+    constexpr int n = N + 1, NN = cpow(n, DIM), NST = NN * n;
+    const int st = (k == 0) ? 1 : (k == 1 ? n : n * n);
+    const int nitems = CPB * VC * nlines_per_var;
+    for (int it = tid; it < nitems; it += BS) {
+        const int lcl = it / (VC * nlines_per_var);
+        const int vv = (it / nlines_per_var) % VC;
+        const int j = it % nlines_per_var;          // (a_perp, s) flattened, a_perp fastest
+        const int s = j / (NN / n), ap = j % (NN / n);
+        int base = 0, rem = ap, mul = 1;
+#pragma unroll
+        for (int jj = 0; jj < DIM; jj++) {
+            if (jj == k) { mul *= n; continue; }
+            base += (rem % n) * mul;
+            rem /= n;
+            mul *= n;
+        }
+        double *line = &X[(lcl * VC + vv) * NST + lstride_s * s + base];
+        double xb[n];
+#pragma unroll
+        for (int b = 0; b < n; b++) xb[b] = line[b * st];
+#pragma unroll
+        for (int i = 0; i < n; i++) {
+            double acc = 0.0;
+#pragma unroll
+            for (int b = 0; b < n; b++) acc += M[i][b] * xb[b];
+            line[i * st] = c * acc;
+        }
+    }
+}
+
+template <int DIM, int N, bool VOL>
+__global__ __launch_bounds__((PredShape<DIM, N>::BS)) void k_predictor(const Tables *__restrict__ T, PredArgs A,
+                                                                      double gamma) {
+    using S = PredShape<DIM, N>;
+    constexpr int n = S::n, NV = S::NV, NN = S::NN, NST = S::NST, NFN = S::NFN, CPB = S::CPB, VC = S::VC;
+    __shared__ double X[CPB * VC * NST];
+
+    const int tid = threadIdx.x;
+    const int lc = tid / NN, a = tid % NN;
+    const int64_t c = (int64_t)blockIdx.x * CPB + lc;
+    const bool owner = (tid < S::ACT) && (c < A.ncell);
+    const double dt = *A.dt;
+
+    // operators on the hot path (wave-uniform loads)
+    const double(*D)[MAXN] = reinterpret_cast<const double(*)[MAXN]>(A.D);
+    const double(*Kw)[MAXN] = reinterpret_cast<const double(*)[MAXN]>(A.Kw);
+    const double(*Dvol)[MAXN] = reinterpret_cast<const double(*)[MAXN]>(A.Dvol);
+    (void)T;
+
+    double u0[NV], q[NV][n], Sacc[NV][n];
+    if (owner) {
+#pragma unroll
+        for (int v = 0; v < NV; v++) u0[v] = A.in[c * A.in_cstride + v * A.in_vstride + a];
+    } else {
+        // idle lanes carry a valid constant state so that they never produce NaN
+#pragma unroll
+        for (int v = 0; v < NV; v++) u0[v] = (v == 0) ? 1.0 : 0.0;
+        u0[NV - 1] = 2.5;
+    }
+#pragma unroll
+    for (int v = 0; v < NV; v++)
+#pragma unroll
+        for (int s = 0; s < n; s++) q[v][s] = u0[v];
+
+    for (int r = 0; r < A.iters; r++) {
+#pragma unroll
+        for (int v = 0; v < NV; v++)
+#pragma unroll
+            for (int s = 0; s < n; s++) Sacc[v][s] = 0.0;
+#pragma unroll
+        for (int k = 0; k < DIM; k++) {
+            const double ck = dt * A.dth[k];
+            for (int v0 = 0; v0 < NV; v0 += VC) {
+                // point phase: fluxes of the time pencil straight into LDS
+                if (tid < S::ACT) {
+#pragma unroll
+                    for (int t = 0; t < n; t++) {
+                        double qt[NV], F[NV];
+#pragma unroll
+                        for (int v = 0; v < NV; v++) qt[v] = q[v][t];
+                        euler_flux<DIM>(k, qt, F, gamma);
+#pragma unroll
+                        for (int vv = 0; vv < VC; vv++)
+                            if (v0 + vv < NV) X[(lc * VC + vv) * NST + a + NN * t] = F[v0 + vv];
+                    }
+                }
+                __syncthreads();
+                lds_lines<DIM, N, CPB, VC, S::BS>(X, k, NN, NN, D, ck, tid);
+                __syncthreads();
+                if (tid < S::ACT) {
+#pragma unroll
+                    for (int vv = 0; vv < VC; vv++)
+                        if (v0 + vv < NV)
+#pragma unroll
+                            for (int t = 0; t < n; t++) Sacc[v0 + vv][t] += X[(lc * VC + vv) * NST + a + NN * t];
+                }
+                __syncthreads();
+            }
+        }
+        // time contraction in registers
+#pragma unroll
+        for (int v = 0; v < NV; v++)
+#pragma unroll
+            for (int s = 0; s < n; s++) {
+                double acc = 0.0;
+#pragma unroll
+                for (int t = 0; t < n; t++) acc += Kw[s][t] * Sacc[v][t];
+                q[v][s] = u0[v] - acc;
+            }
+    }
+
+    // ---- volume term of eq. (pde.nc.gw2), divided by the diagonal mass:
+    //   (dt/h_k) sum_b [w_b D[b][a_k] / w_{a_k}] sum_s w_s F_k(q(a|b, s))
+    if constexpr (VOL) {
+        double vol[NV];
+#pragma unroll
+        for (int v = 0; v < NV; v++) vol[v] = 0.0;
+#pragma unroll
+        for (int k = 0; k < DIM; k++) {
+            const double ck = dt * A.dth[k];
+            double Fi[NV];
+#pragma unroll
+            for (int v = 0; v < NV; v++) Fi[v] = 0.0;
+#pragma unroll
+            for (int t = 0; t < n; t++) {
+                double qt[NV], F[NV];
+#pragma unroll
+                for (int v = 0; v < NV; v++) qt[v] = q[v][t];
+                euler_flux<DIM>(k, qt, F, gamma);
+#pragma unroll
+                for (int v = 0; v < NV; v++) Fi[v] += A.w[t] * F[v];
+            }
+            for (int v0 = 0; v0 < NV; v0 += VC) {
+                if (tid < S::ACT) {
+#pragma unroll
+                    for (int vv = 0; vv < VC; vv++)
+                        if (v0 + vv < NV) X[(lc * VC + vv) * NST + a] = Fi[v0 + vv];
+                }
+                __syncthreads();
+                lds_lines<DIM, N, CPB, VC, S::BS>(X, k, NN / n, 0, Dvol, ck, tid);
+                __syncthreads();
+                if (tid < S::ACT) {
+#pragma unroll
+                    for (int vv = 0; vv < VC; vv++)
+                        if (v0 + vv < NV) vol[v0 + vv] += X[(lc * VC + vv) * NST + a];
+                }
+                __syncthreads();
+            }
+        }
+        if (owner) {
+#pragma unroll
+            for (int v = 0; v < NV; v++)
+                A.vol_out[(A.cell0 + c) * NN + (int64_t)v * A.in_vstride + a] = u0[v] + vol[v];
+        }
+    }
+
+    // ---- face traces: q at xi_k = 0 / 1 per tangential node and time node
+    for (int v0 = 0; v0 < NV; v0 += VC) {
+        if (tid < S::ACT) {
+#pragma unroll
+            for (int vv = 0; vv < VC; vv++)
+                if (v0 + vv < NV)
+#pragma unroll
+                    for (int s = 0; s < n; s++) X[(lc * VC + vv) * NST + a + NN * s] = q[v0 + vv][s];
+        }
+        __syncthreads();
+        const int nitems = CPB * VC * 2 * DIM * NFN * n;
+        for (int it = tid; it < nitems; it += S::BS) {
+            const int lcl = it / (VC * 2 * DIM * NFN * n);
+            int rem0 = it % (VC * 2 * DIM * NFN * n);
+            const int vv = rem0 / (2 * DIM * NFN * n);
+            rem0 %= 2 * DIM * NFN * n;
+            const int face = rem0 / (NFN * n);
+            const int j = rem0 % (NFN * n);   // ap + NFN*s
+            const int s = j / NFN, ap = j % NFN;
+            const int k = face >> 1, side = face & 1;
+            const int64_t cc = (int64_t)blockIdx.x * CPB + lcl;
+            if (cc >= A.ncell || v0 + vv >= NV) continue;
+            int base = 0, rem = ap, mul = 1;
+#pragma unroll
+            for (int jj = 0; jj < DIM; jj++) {
+                if (jj == k) { mul *= n; continue; }
+                base += (rem % n) * mul;
+                rem /= n;
+                mul *= n;
+            }
+            const double *line = &X[(lcl * VC + vv) * NST + NN * s + base];
+            const int st = (k == 0) ? 1 : (k == 1 ? n : n * n);
+            const double *Bv = side ? A.Rb : A.Lb;
+            double acc = 0.0;
+#pragma unroll
+            for (int b = 0; b < n; b++) acc += Bv[b] * line[b * st];
+            A.trace[((cc * 2 * DIM + face) * NV + v0 + vv) * (NFN * n) + j] = acc;
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------- face fluxes
+// One thread per (face, tangential node): time-integrated Rusanov flux, written into
+// the slot of both adjacent cells.
+template <int DIM, int N>
+__global__ void k_face(const Tables *__restrict__ T, Prob P, const double *__restrict__ trace,
+                       double *__restrict__ gbar, const double *__restrict__ scal, int k) {
+    constexpr int n = N + 1, NV = DIM + 2, NFN = cpow(n, DIM - 1);
+    const int nk = P.nc[k];
+    const int nfk = P.periodic[k] ? nk : nk + 1;           // faces along k per line
+    int64_t nlines = 1;
+    for (int j = 0; j < DIM; j++)
+        if (j != k) nlines *= P.nc[j];
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t total = nlines * nfk * NFN;
+    if (gid >= total) return;
+    const int ap = (int)(gid % NFN);
+    const int64_t fidx = gid / NFN;
+    const int fk = (int)(fidx % nfk);
+    int64_t line = fidx / nfk;
+    int ci[3] = {0, 0, 0};
+    for (int j = 0; j < DIM; j++) {
+        if (j == k) continue;
+        ci[j] = (int)(line % P.nc[j]);
+        line /= P.nc[j];
+    }
+    // left cell index fk-1, right cell fk (wrapping when periodic)
+    int cl[3] = {ci[0], ci[1], ci[2]}, cr[3] = {ci[0], ci[1], ci[2]};
+    cl[k] = fk - 1;
+    cr[k] = fk;
+    bool hasL = true, hasR = true;
+    if (cl[k] < 0) {
+        if (P.periodic[k]) cl[k] += nk; else hasL = false;
+    }
+    if (cr[k] >= nk) hasR = false;
+    const int64_t cL = hasL ? cell_of(P, cl) : -1, cR = hasR ? cell_of(P, cr) : -1;
+    const double dt = scal[0], t0 = scal[1];
+    // node position on the face (for boundary states)
+    double x[3] = {0, 0, 0};
+    {
+        int rem = ap;
+        for (int j = 0; j < DIM; j++) {
+            if (j == k) {
+                x[j] = P.lo[j] + P.h[j] * fk;
+                continue;
+            }
+            x[j] = P.lo[j] + P.h[j] * (ci[j] + T->xi[rem % n]);
+            rem /= n;
+        }
+    }
+    double acc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; v++) acc[v] = 0.0;
+    for (int s = 0; s < n; s++) {
+        double qL[NV], qR[NV], G[NV];
+        if (hasL) {
+#pragma unroll
+            for (int v = 0; v < NV; v++) qL[v] = trace[((cL * 2 * DIM + 2 * k + 1) * NV + v) * (NFN * n) + ap + NFN * s];
+        }
+        if (hasR) {
+#pragma unroll
+            for (int v = 0; v < NV; v++) qR[v] = trace[((cR * 2 * DIM + 2 * k) * NV + v) * (NFN * n) + ap + NFN * s];
+        }
+        const double ts = t0 + T->xi[s] * dt;
+        if (!hasL) bc_ghost<DIM>(P, k, 0, qR, x, ts, qL);
+        if (!hasR) bc_ghost<DIM>(P, k, 1, qL, x, ts, qR);
+        rusanov<DIM>(k, qL, qR, G, P.gamma);
+#pragma unroll
+        for (int v = 0; v < NV; v++) acc[v] += T->w[s] * G[v];
+    }
+    if (hasL) {
+#pragma unroll
+        for (int v = 0; v < NV; v++) gbar[((cL * 2 * DIM + 2 * k + 1) * NV + v) * NFN + ap] = acc[v];
+    }
+    if (hasR) {
+#pragma unroll
+        for (int v = 0; v < NV; v++) gbar[((cR * 2 * DIM + 2 * k) * NV + v) * NFN + ap] = acc[v];
+    }
+}
+
+// --------------------------------------------------- tensor application in LDS
+// out[v][...] = sum over axis k of M[i][b] in[...b...], applied axis by axis.  Shapes:
+// before stage k axes < k have size m (output), axes >= k have size n (input).
+template <int DIM>
+__device__ void tensor_apply(const double *Mbase, int mstride, int m, int n, int nvars, const double *in, double *out,
+                             double *tmp, int tid, int bs) {
+    // in: [v][n^DIM] ; out: [v][m^DIM] ; tmp: scratch of nvars*max(m,n)^DIM
+    const double *src = in;
+    for (int k = 0; k < DIM; k++) {
+        // alternate between the two buffers so that the last stage lands in `out`
+        double *dst = ((DIM - 1 - k) % 2 == 0) ? out : tmp;
+        // sizes before: dims j<k: m, j>=k: n ; after: j<=k: m
+        int szb = 1, sza = 1;
+        for (int j = 0; j < DIM; j++) {
+            szb *= (j < k) ? m : n;
+            sza *= (j <= k) ? m : n;
+        }
+        const int total = nvars * sza;
+        for (int it = tid; it < total; it += bs) {
+            const int v = it / sza;
+            int e = it % sza;
+            int idx[3] = {0, 0, 0};
+            for (int j = 0; j < DIM; j++) {
+                const int dj = (j <= k) ? m : n;
+                idx[j] = e % dj;
+                e /= dj;
+            }
+            const int i = idx[k];
+            double acc = 0.0;
+            for (int b = 0; b < n; b++) {
+                idx[k] = b;
+                int ib = 0;
+                for (int j = DIM - 1; j >= 0; j--) ib = ib * ((j < k) ? m : n) + idx[j];
+                acc += Mbase[i * mstride + b] * src[v * szb + ib];
+            }
+            dst[it] = acc;
+        }
+        __syncthreads();
+        src = dst;
+    }
+}
+
+// ------------------------------------------- corrector + scatter + detection
+// Candidate of eq. (pde.nc.gw2) (face terms added to the volume-term candidate), then
+// v* = P(u*) (eq. (subcell.p)) and the PAD / relaxed-DMP tests of Sec. 4.3.
+template <int DIM, int N>
+__global__ __launch_bounds__(128) void k_corrector_detect(const Tables *__restrict__ T, Prob P, Bufs B, int cur,
+                                                          int limiter) {
+    constexpr int n = N + 1, NV = DIM + 2, NN = cpow(n, DIM), NFN = cpow(n, DIM - 1);
+    constexpr int NS = 2 * N + 1, NSUB = cpow(NS, DIM);
+    constexpr int BIG = cpow(NS, DIM) > cpow(n, DIM) ? cpow(NS, DIM) : cpow(n, DIM);
+    __shared__ double us[NV * NN];
+    __shared__ double vs[NV * BIG];
+    __shared__ double tmp[NV * BIG];
+    __shared__ int bad_s[128];
+    __shared__ float mg_s[128];
+    const int64_t c = blockIdx.x;
+    const int tid = threadIdx.x;
+    const double dt = B.scal[0];
+    double *un = B.u[cur ^ 1];
+    for (int it = tid; it < NV * NN; it += 128) {
+        const int v = it / NN, a = it % NN;
+        int m[3] = {a % n, (a / n) % n, a / (n * n)};
+        double val = un[((int64_t)v * P.ncell + c) * NN + a];
+#pragma unroll
+        for (int k = 0; k < DIM; k++) {
+            int ap = 0, mul = 1;
+            for (int j = 0; j < DIM; j++) {
+                if (j == k) continue;
+                ap += m[j] * mul;
+                mul *= n;
+            }
+            const int ak = m[k];
+            const double Gm = B.gbar[((c * 2 * DIM + 2 * k) * NV + v) * NFN + ap];
+            const double Gp = B.gbar[((c * 2 * DIM + 2 * k + 1) * NV + v) * NFN + ap];
+            val += dt / P.h[k] / T->w[ak] * (T->L[ak] * Gm - T->R[ak] * Gp);
+        }
+        un[((int64_t)v * P.ncell + c) * NN + a] = val;
+        us[it] = val;
+    }
+    if (!limiter) return;
+    __syncthreads();
+    tensor_apply<DIM>(&T->P[0][0], MAXN, NS, n, NV, us, vs, tmp, tid, 128);
+    // detection on the NSUB candidate subcell averages
+    double m_[NV], M_[NV];
+#pragma unroll
+    for (int v = 0; v < NV; v++) {
+        m_[v] = B.bmin[(int64_t)v * P.ncell + c];
+        M_[v] = B.bmax[(int64_t)v * P.ncell + c];
+    }
+    int bad = 0;
+    float mg = INFINITY;
+    double sr = fmax(fabs(M_[0]), fabs(m_[0]));
+    double se = fmax(fabs(M_[DIM + 1]), fabs(m_[DIM + 1]));
+    if (!(sr > 0)) sr = 1.0;
+    if (!(se > 0)) se = 1.0;
+    for (int sg = tid; sg < NSUB; sg += 128) {
+        double q[NV];
+        bool finite = true;
+#pragma unroll
+        for (int v = 0; v < NV; v++) {
+            q[v] = vs[v * NSUB + sg];
+            if (!isfinite(q[v])) finite = false;
+        }
+        if (!finite) {
+            bad = 1;
+            mg = -INFINITY;
+            continue;
+        }
+        const double p = pressure<DIM>(q, P.gamma);
+        if (!(q[0] > 0.0) || !(p > 0.0)) bad = 1;
+        double lmg = fmin(q[0] / sr, p / se);
+#pragma unroll
+        for (int v = 0; v < NV; v++) {
+            const double delta = fmax(P.delta0, P.eps * (M_[v] - m_[v]));
+            const double lo = m_[v] - delta, hi = M_[v] + delta;
+            if (q[v] < lo || q[v] > hi) bad = 1;
+            double sc = fmax(fabs(M_[v]), fabs(m_[v]));
+            if (!(sc > 0)) sc = 1.0;
+            lmg = fmin(lmg, fmin(q[v] - lo, hi - q[v]) / sc);
+        }
+        mg = fminf(mg, (float)lmg);
+    }
+    bad_s[tid] = bad;
+    mg_s[tid] = mg;
+    __syncthreads();
+    for (int off = 64; off > 0; off >>= 1) {
+        if (tid < off) {
+            bad_s[tid] |= bad_s[tid + off];
+            mg_s[tid] = fminf(mg_s[tid], mg_s[tid + off]);
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        B.beta[1][c] = (uint8_t)((bad_s[0] || B.force[c]) ? 1 : 0);
+        B.margin[c] = mg_s[0];
+    }
+}
+
+// --------------------------------------------------------- old-time bounds
+// Subcell data v^n of eq. (ader.icbc) for one (possibly ghost) cell: the stored
+// ADER-WENO result when the cell was troubled at the previous step, else P(u^n).
+// Ghost cells (outside a non-periodic boundary) mirror the interior subcells and apply
+// the boundary rule at the ghost subcell centre.  Output: per-variable min / max over
+// the cell's subcells, for the extended grid with a one-cell ghost ring.
+template <int DIM, int N>
+__global__ __launch_bounds__(128) void k_cell_bounds(const Tables *__restrict__ T, Prob P, Bufs B, int cur) {
+    constexpr int n = N + 1, NV = DIM + 2, NN = cpow(n, DIM);
+    constexpr int NS = 2 * N + 1, NSUB = cpow(NS, DIM);
+    constexpr int BIG = NSUB > NN ? NSUB : NN;
+    __shared__ double us[NV * NN];
+    __shared__ double vs[NV * BIG];
+    __shared__ double tmp[NV * BIG];
+    __shared__ double red[2][NV][128];
+    const int tid = threadIdx.x;
+    const int64_t e = blockIdx.x;
+    int ei[3] = {0, 0, 0}, ne[3] = {1, 1, 1};
+    for (int j = 0; j < DIM; j++) ne[j] = P.nc[j] + 2;
+    {
+        int64_t r = e;
+        for (int j = 0; j < DIM; j++) {
+            ei[j] = (int)(r % ne[j]) - 1;
+            r /= ne[j];
+        }
+    }
+    int src[3] = {0, 0, 0}, mir[3] = {0, 0, 0}, gside[3] = {-1, -1, -1};
+    for (int j = 0; j < DIM; j++) {
+        src[j] = ei[j];
+        if (ei[j] < 0 || ei[j] >= P.nc[j]) {
+            const int side = ei[j] >= P.nc[j];
+            if (P.periodic[j]) {
+                src[j] = (ei[j] + P.nc[j]) % P.nc[j];
+            } else {
+                src[j] = side ? 2 * P.nc[j] - 1 - ei[j] : -1 - ei[j];
+                mir[j] = 1;
+                gside[j] = side;
+            }
+        }
+    }
+    const int64_t cs = cell_of(P, src);
+    const double *uo = B.u[cur];
+    const int oslot = B.slot[0][cs];
+    // a cell flagged beyond the pool capacity has no stored data: fall back to P(u)
+    const bool bo = B.beta[0][cs] && oslot >= 0;
+    if (bo) {
+        const int slot = oslot;
+        for (int it = tid; it < NV * NSUB; it += 128) vs[it] = B.pool[0][(int64_t)slot * NV * NSUB + it];
+        __syncthreads();
+    } else {
+        for (int it = tid; it < NV * NN; it += 128) {
+            const int v = it / NN, a = it % NN;
+            us[it] = uo[((int64_t)v * P.ncell + cs) * NN + a];
+        }
+        __syncthreads();
+        tensor_apply<DIM>(&T->P[0][0], MAXN, NS, n, NV, us, vs, tmp, tid, 128);
+    }
+    const double t0 = B.scal[1];
+    double lo[NV], hi[NV];
+#pragma unroll
+    for (int v = 0; v < NV; v++) {
+        lo[v] = INFINITY;
+        hi[v] = -INFINITY;
+    }
+    for (int sg = tid; sg < NSUB; sg += 128) {
+        int gs[3] = {sg % NS, (sg / NS) % NS, sg / (NS * NS)};
+        int ss[3] = {gs[0], gs[1], gs[2]};
+        for (int j = 0; j < DIM; j++)
+            if (mir[j]) ss[j] = NS - 1 - gs[j];
+        int sidx = 0;
+        for (int j = DIM - 1; j >= 0; j--) sidx = sidx * NS + ss[j];
+        double q[NV];
+#pragma unroll
+        for (int v = 0; v < NV; v++) q[v] = vs[v * NSUB + sidx];
+        double x[3] = {0, 0, 0};
+        for (int j = 0; j < DIM; j++) x[j] = P.lo[j] + P.h[j] * (ei[j] + (gs[j] + 0.5) / NS);
+        for (int j = 0; j < DIM; j++) {
+            if (gside[j] < 0) continue;
+            double qo[NV];
+            bc_ghost<DIM>(P, j, gside[j], q, x, t0, qo);
+#pragma unroll
+            for (int v = 0; v < NV; v++) q[v] = qo[v];
+        }
+#pragma unroll
+        for (int v = 0; v < NV; v++) {
+            lo[v] = fmin(lo[v], q[v]);
+            hi[v] = fmax(hi[v], q[v]);
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < NV; v++) {
+        red[0][v][tid] = lo[v];
+        red[1][v][tid] = hi[v];
+    }
+    __syncthreads();
+    for (int off = 64; off > 0; off >>= 1) {
+        if (tid < off) {
+#pragma unroll
+            for (int v = 0; v < NV; v++) {
+                red[0][v][tid] = fmin(red[0][v][tid], red[0][v][tid + off]);
+                red[1][v][tid] = fmax(red[1][v][tid], red[1][v][tid + off]);
+            }
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        int64_t next = 1;
+        for (int j = 0; j < DIM; j++) next *= ne[j];
+        for (int v = 0; v < NV; v++) {
+            B.ext_min[(int64_t)v * next + e] = red[0][v][0];
+            B.ext_max[(int64_t)v * next + e] = red[1][v][0];
+        }
+    }
+}
+
+// min / max over the 3^d block V_i of the extended per-cell bounds (eq. (dmp)).
+template <int DIM>
+__global__ void k_neigh_bounds(Prob P, Bufs B) {
+    constexpr int NV = DIM + 2;
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= P.ncell) return;
+    int ci[3];
+    coords_of(P, c, ci);
+    int ne[3] = {1, 1, 1};
+    int64_t next = 1;
+    for (int j = 0; j < DIM; j++) {
+        ne[j] = P.nc[j] + 2;
+        next *= ne[j];
+    }
+    double lo[NV], hi[NV];
+#pragma unroll
+    for (int v = 0; v < NV; v++) {
+        lo[v] = INFINITY;
+        hi[v] = -INFINITY;
+    }
+    constexpr int NB = cpow(3, DIM);
+    for (int o = 0; o < NB; o++) {
+        int off[3] = {o % 3, (o / 3) % 3, o / 9};
+        int64_t e = 0;
+        for (int j = DIM - 1; j >= 0; j--) e = e * ne[j] + (ci[j] + off[j]);  // ext index = ci + 1 + (off - 1)
+#pragma unroll
+        for (int v = 0; v < NV; v++) {
+            lo[v] = fmin(lo[v], B.ext_min[(int64_t)v * next + e]);
+            hi[v] = fmax(hi[v], B.ext_max[(int64_t)v * next + e]);
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < NV; v++) {
+        B.bmin[(int64_t)v * P.ncell + c] = lo[v];
+        B.bmax[(int64_t)v * P.ncell + c] = hi[v];
+    }
+}
+
+// ------------------------------------------------------------------ compaction
+// Troubled cells and unlimited neighbours of troubled cells, compacted in cell order
+// with wavefront ballots and a block prefix; three passes (count, scan, scatter).
+__device__ __forceinline__ bool corr_flag(const Prob &P, const uint8_t *beta, int64_t c) {
+    if (beta[c]) return false;
+    int ci[3];
+    coords_of(P, c, ci);
+    for (int k = 0; k < P.dim; k++)
+        for (int side = 0; side < 2; side++) {
+            int nb[3] = {ci[0], ci[1], ci[2]};
+            nb[k] += side ? 1 : -1;
+            if (nb[k] < 0 || nb[k] >= P.nc[k]) {
+                if (!P.periodic[k]) continue;
+                nb[k] = (nb[k] + P.nc[k]) % P.nc[k];
+            }
+            if (beta[cell_of(P, nb)]) return true;
+        }
+    return false;
+}
+
+constexpr int CBS = 256;   // compaction block size
+
+__global__ __launch_bounds__(CBS) void k_compact_count(Prob P, Bufs B) {
+    __shared__ int cnt[2][CBS / 64];
+    const int64_t c = (int64_t)blockIdx.x * CBS + threadIdx.x;
+    const bool t = c < P.ncell && B.beta[1][c];
+    const bool f = c < P.ncell && corr_flag(P, B.beta[1], c);
+    const uint64_t bt = __ballot(t), bf = __ballot(f);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) {
+        cnt[0][wv] = __popcll(bt);
+        cnt[1][wv] = __popcll(bf);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int s0 = 0, s1 = 0;
+        for (int w = 0; w < CBS / 64; w++) { s0 += cnt[0][w]; s1 += cnt[1][w]; }
+        B.blk[blockIdx.x] = s0;
+        B.blk[gridDim.x + blockIdx.x] = s1;
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_compact_scan(Bufs B, int nblk, int64_t cap) {
+    // exclusive scan of both block-count arrays, single block, sequential chunks
+    __shared__ int part[2][1024];
+    __shared__ int carry[2];
+    if (threadIdx.x == 0) { carry[0] = 0; carry[1] = 0; }
+    __syncthreads();
+    for (int base = 0; base < nblk; base += 1024) {
+        const int i = base + threadIdx.x;
+        for (int a = 0; a < 2; a++) part[a][threadIdx.x] = (i < nblk) ? B.blk[a * nblk + i] : 0;
+        __syncthreads();
+        // Hillis-Steele inclusive scan
+        for (int off = 1; off < 1024; off <<= 1) {
+            int v0 = 0, v1 = 0;
+            if (threadIdx.x >= off) { v0 = part[0][threadIdx.x - off]; v1 = part[1][threadIdx.x - off]; }
+            __syncthreads();
+            part[0][threadIdx.x] += v0;
+            part[1][threadIdx.x] += v1;
+            __syncthreads();
+        }
+        if (i < nblk) {
+            const int in0 = B.blk[i], in1 = B.blk[nblk + i];
+            B.blk[i] = carry[0] + part[0][threadIdx.x] - in0;
+            B.blk[nblk + i] = carry[1] + part[1][threadIdx.x] - in1;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) { carry[0] += part[0][1023]; carry[1] += part[1][1023]; }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        B.counts[0] = carry[0];
+        B.counts[1] = carry[1];
+        if (carry[0] > cap) B.counts[3] = 1;
+    }
+}
+
+__global__ __launch_bounds__(CBS) void k_compact_scatter(Prob P, Bufs B, int64_t cap) {
+    __shared__ int woff[2][CBS / 64];
+    const int64_t c = (int64_t)blockIdx.x * CBS + threadIdx.x;
+    const bool t = c < P.ncell && B.beta[1][c];
+    const bool f = c < P.ncell && corr_flag(P, B.beta[1], c);
+    const uint64_t bt = __ballot(t), bf = __ballot(f);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    if (lane == 0) {
+        woff[0][wv] = __popcll(bt);
+        woff[1][wv] = __popcll(bf);
+    }
+    __syncthreads();
+    int o0 = B.blk[blockIdx.x], o1 = B.blk[gridDim.x + blockIdx.x];
+    for (int w = 0; w < wv; w++) { o0 += woff[0][w]; o1 += woff[1][w]; }
+    if (c < P.ncell) {
+        int slot = -1;
+        if (t) {
+            const int idx = o0 + __popcll(bt & below);
+            if (idx < cap) {
+                B.tlist[idx] = (int)c;
+                slot = idx;
+            }
+        }
+        B.slot[1][c] = slot;
+        if (f) B.clist[o1 + __popcll(bf & below)] = (int)c;
+    }
+}
+
+// ------------------------------------------------------ subcell ADER-WENO3
+// Positions of one troubled cell's subcell scheme: the Ns^d own subcells first, then
+// for each axis k and side the Ns^(d-1) face-adjacent subcells of the neighbour.
+template <int DIM>
+__device__ __forceinline__ void position_coords(int pos, int Ns, int *L) {
+    const int nsub = (DIM == 2) ? Ns * Ns : Ns * Ns * Ns;
+    const int nsf = (DIM == 2) ? Ns : Ns * Ns;
+    if (pos < nsub) {
+        L[0] = pos % Ns;
+        L[1] = (pos / Ns) % Ns;
+        L[2] = (DIM == 3) ? pos / (Ns * Ns) : 0;
+        return;
+    }
+    const int r = pos - nsub;
+    const int face = r / nsf, sp = r % nsf;
+    const int k = face >> 1, side = face & 1;
+    int tmp = sp;
+    for (int j = 0; j < DIM; j++) {
+        if (j == k) {
+            L[j] = side ? Ns : -1;
+            continue;
+        }
+        L[j] = tmp % Ns;
+        tmp /= Ns;
+    }
+    if (DIM == 2) L[2] = 0;
+}
+
+// S1: halo of subcell data v^n (eq. (ader.icbc)) 3 subcells deep around the cell.
+template <int DIM, int N>
+__global__ __launch_bounds__(256) void k_sub_halo(const Tables *__restrict__ T, Prob P, Bufs B, int cur, int first) {
+    constexpr int n = N + 1, NV = DIM + 2, NN = cpow(n, DIM);
+    constexpr int NS = 2 * N + 1, NSUB = cpow(NS, DIM), HN = NS + 6, HSZ = cpow(HN, DIM);
+    const int w = first + blockIdx.x;
+    const int64_t c = B.tlist[w];
+    int ci[3];
+    coords_of(P, c, ci);
+    const double t0 = B.scal[1];
+    double *halo = B.halo + (int64_t)blockIdx.x * NV * HSZ;
+    for (int hidx = threadIdx.x; hidx < HSZ; hidx += 256) {
+        int hl[3] = {hidx % HN, (hidx / HN) % HN, hidx / (HN * HN)};
+        int gci[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, src[3] = {0, 0, 0}, ss[3] = {0, 0, 0}, gside[3] = {-1, -1, -1};
+        for (int j = 0; j < DIM; j++) {
+            const int Lj = hl[j] - 3;
+            const int off = Lj < 0 ? -1 : (Lj >= NS ? 1 : 0);
+            gci[j] = ci[j] + off;
+            gs[j] = Lj - off * NS;
+            src[j] = gci[j];
+            ss[j] = gs[j];
+            if (gci[j] < 0 || gci[j] >= P.nc[j]) {
+                const int side = gci[j] >= P.nc[j];
+                if (P.periodic[j]) {
+                    src[j] = (gci[j] + P.nc[j]) % P.nc[j];
+                } else {
+                    src[j] = side ? 2 * P.nc[j] - 1 - gci[j] : -1 - gci[j];
+                    ss[j] = NS - 1 - gs[j];
+                    gside[j] = side;
+                }
+            }
+        }
+        const int64_t cs = cell_of(P, src);
+        int sidx = 0;
+        for (int j = DIM - 1; j >= 0; j--) sidx = sidx * NS + ss[j];
+        double q[NV];
+        const int slot = B.slot[0][cs];
+        if (B.beta[0][cs] && slot >= 0) {
+#pragma unroll
+            for (int v = 0; v < NV; v++) q[v] = B.pool[0][((int64_t)slot * NV + v) * NSUB + sidx];
+        } else {
+            // P(u^n) at one subcell: plain tensor sum over the nodes
+#pragma unroll
+            for (int v = 0; v < NV; v++) q[v] = 0.0;
+            for (int a = 0; a < NN; a++) {
+                int m[3] = {a % n, (a / n) % n, a / (n * n)};
+                double wgt = 1.0;
+                for (int j = 0; j < DIM; j++) wgt *= T->P[ss[j]][m[j]];
+#pragma unroll
+                for (int v = 0; v < NV; v++) q[v] += wgt * B.u[cur][((int64_t)v * P.ncell + cs) * NN + a];
+            }
+        }
+        double x[3] = {0, 0, 0};
+        for (int j = 0; j < DIM; j++) x[j] = P.lo[j] + P.h[j] * (gci[j] + (gs[j] + 0.5) / NS);
+        for (int j = 0; j < DIM; j++) {
+            if (gside[j] < 0) continue;
+            double qo[NV];
+            bc_ghost<DIM>(P, j, gside[j], q, x, t0, qo);
+#pragma unroll
+            for (int v = 0; v < NV; v++) q[v] = qo[v];
+        }
+#pragma unroll
+        for (int v = 0; v < NV; v++) halo[v * HSZ + hidx] = q[v];
+    }
+}
+
+// One-dimensional WENO3 (degree 2, three stencils, lambda = 1, 1e5, 1, eps 1e-14, r 8):
+// five averages at offsets -2..2 -> values at the three GL nodes of the central subcell.
+__device__ __forceinline__ void weno3(const Tables *__restrict__ T, const double *a, double *out) {
+    double c[3][3], wt[3], sum = 0.0;
+    const double lam[3] = {1.0, 1.0e5, 1.0};
+#pragma unroll
+    for (int st = 0; st < 3; st++) {
+#pragma unroll
+        for (int p = 0; p < 3; p++) {
+            double acc = 0.0;
+#pragma unroll
+            for (int m = 0; m < 3; m++) acc += T->weno[st][p][m] * a[st + m];
+            c[st][p] = acc;
+        }
+        const double sig = c[st][1] * c[st][1] + 2.0 * c[st][1] * c[st][2] + (16.0 / 3.0) * c[st][2] * c[st][2];
+        double s2 = sig + 1e-14;
+        s2 = s2 * s2;
+        s2 = s2 * s2;
+        s2 = s2 * s2;   // (sigma + eps)^8
+        wt[st] = lam[st] / s2;
+        sum += wt[st];
+    }
+#pragma unroll
+    for (int qn = 0; qn < 3; qn++) {
+        const double x = T->xi3[qn];
+        double acc = 0.0;
+#pragma unroll
+        for (int st = 0; st < 3; st++) acc += (wt[st] / sum) * (c[st][0] + c[st][1] * x + c[st][2] * x * x);
+        out[qn] = acc;
+    }
+}
+
+// S2: dimension-by-dimension WENO3 reconstruction at every position -> nodal values at
+// the 3^d GL points of the subcell (x sweep on the averages, then y (then z) sweeps on
+// the nodal values of the previous sweep).
+template <int DIM, int N>
+__global__ void k_sub_recon(const Tables *__restrict__ T, Bufs B, int nch) {
+    constexpr int NV = DIM + 2, NS = 2 * N + 1, HN = NS + 6, HSZ = cpow(HN, DIM);
+    constexpr int NPOS = cpow(NS, DIM) + 2 * DIM * cpow(NS, DIM - 1), N3 = cpow(3, DIM);
+    constexpr int W5 = cpow(5, DIM);
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (int64_t)nch * NPOS) return;
+    const int ch = (int)(gid / NPOS), pos = (int)(gid % NPOS);
+    int L[3];
+    position_coords<DIM>(pos, NS, L);
+    const double *halo = B.halo + (int64_t)ch * NV * HSZ;
+    double *Y = B.Y + ((int64_t)ch * NPOS + pos) * NV * N3;
+    for (int v = 0; v < NV; v++) {
+        double w0[W5], w1[W5];
+        for (int e = 0; e < W5; e++) {
+            int mo[3] = {e % 5, (e / 5) % 5, e / 25};
+            int hidx = 0;
+            for (int j = DIM - 1; j >= 0; j--) hidx = hidx * HN + (L[j] + mo[j] - 2 + 3);
+            w0[e] = halo[v * HSZ + hidx];
+        }
+        double *src = w0, *dst = w1;
+        for (int k = 0; k < DIM; k++) {
+            int dimsb[3], dimsa[3], na = 1;
+            for (int j = 0; j < DIM; j++) {
+                dimsb[j] = j < k ? 3 : 5;
+                dimsa[j] = j <= k ? 3 : 5;
+                na *= dimsa[j];
+            }
+            for (int e = 0; e < na; e++) {
+                int ma[3] = {0, 0, 0}, r = e;
+                for (int j = 0; j < DIM; j++) {
+                    ma[j] = r % dimsa[j];
+                    r /= dimsa[j];
+                }
+                if (ma[k] != 0) continue;
+                double a5[5], o3[3];
+                for (int o = 0; o < 5; o++) {
+                    int mb[3] = {ma[0], ma[1], ma[2]};
+                    mb[k] = o;
+                    int ib = 0;
+                    for (int j = DIM - 1; j >= 0; j--) ib = ib * dimsb[j] + mb[j];
+                    a5[o] = src[ib];
+                }
+                weno3(T, a5, o3);
+                for (int qn = 0; qn < 3; qn++) {
+                    int mc[3] = {ma[0], ma[1], ma[2]};
+                    mc[k] = qn;
+                    int ic = 0;
+                    for (int j = DIM - 1; j >= 0; j--) ic = ic * dimsa[j] + mc[j];
+                    dst[ic] = o3[qn];
+                }
+            }
+            double *t = src;
+            src = dst;
+            dst = t;
+        }
+        for (int a = 0; a < N3; a++) Y[v * N3 + a] = src[a];
+    }
+}
+
+// S4: sub-face Rusanov fluxes, FV update, gather, pool store, boundary fluxes.
+template <int DIM, int N>
+__global__ __launch_bounds__(256) void k_sub_update(const Tables *__restrict__ T, Prob P, Bufs B, int cur, int first,
+                                                    int *nonphys) {
+    constexpr int n = N + 1, NV = DIM + 2, NN = cpow(n, DIM);
+    constexpr int NS = 2 * N + 1, NSUB = cpow(NS, DIM), NSF = cpow(NS, DIM - 1), HN = NS + 6, HSZ = cpow(HN, DIM);
+    constexpr int NPOS = NSUB + 2 * DIM * NSF, NF3 = cpow(3, DIM - 1);
+    constexpr int TRS = 2 * DIM * NV * NF3 * 3;   // trace size per position
+    constexpr int BIG = NSUB > NN ? NSUB : NN;
+    __shared__ double Fb[DIM * (NS + 1) * NSF * NV];
+    __shared__ double vn[NV * BIG];
+    __shared__ double tmp[NV * BIG];
+    __shared__ double ug[NV * BIG];
+    __shared__ int badc;
+    const int ch = blockIdx.x;
+    const int w = first + ch;
+    const int64_t c = B.tlist[w];
+    int ci[3];
+    coords_of(P, c, ci);
+    const double dt = B.scal[0], t0 = B.scal[1];
+    const double *tr = B.strace + (int64_t)ch * NPOS * TRS;
+    if (threadIdx.x == 0) badc = 0;
+    // neighbour existence per face of the cell
+    bool nbex[3][2];
+    for (int k = 0; k < DIM; k++)
+        for (int side = 0; side < 2; side++) {
+            const int nb = ci[k] + (side ? 1 : -1);
+            nbex[k][side] = P.periodic[k] || (nb >= 0 && nb < P.nc[k]);
+        }
+    const int nfaces = DIM * (NS + 1) * NSF;
+    for (int it = threadIdx.x; it < nfaces; it += 256) {
+        const int k = it / ((NS + 1) * NSF);
+        const int f = (it / NSF) % (NS + 1);
+        const int sp = it % NSF;
+        int mp[2] = {sp % NS, sp / NS};
+        // positions left (f-1) and right (f) of the sub-face
+        auto pos_of = [&](int Lk) -> int {
+            int Lv[3] = {0, 0, 0}, j2 = 0;
+            for (int j = 0; j < DIM; j++) {
+                if (j == k) Lv[j] = Lk;
+                else Lv[j] = mp[j2++];
+            }
+            if (Lk >= 0 && Lk < NS) {
+                int idx = 0;
+                for (int j = DIM - 1; j >= 0; j--) idx = idx * NS + Lv[j];
+                return idx;
+            }
+            return NSUB + (2 * k + (Lk >= NS ? 1 : 0)) * NSF + sp;
+        };
+        const int pL = pos_of(f - 1), pR = pos_of(f);
+        const int bside = (f == 0 && !nbex[k][0]) ? 0 : ((f == NS && !nbex[k][1]) ? 1 : -1);
+        // subcell averages of both sides (halo coordinates: local subcell + 3)
+        double avL[NV], avR[NV];
+        {
+            int hL = 0, hR = 0;
+            int j2 = 0;
+            int Lv[3] = {0, 0, 0}, Rv[3] = {0, 0, 0};
+            for (int j = 0; j < DIM; j++) {
+                if (j == k) { Lv[j] = f - 1; Rv[j] = f; }
+                else { Lv[j] = Rv[j] = mp[j2++]; }
+            }
+            for (int j = DIM - 1; j >= 0; j--) {
+                hL = hL * HN + (Lv[j] + 3);
+                hR = hR * HN + (Rv[j] + 3);
+            }
+            const double *hal = B.halo + (int64_t)ch * NV * HSZ;
+#pragma unroll
+            for (int v = 0; v < NV; v++) {
+                avL[v] = hal[v * HSZ + hL];
+                avR[v] = hal[v * HSZ + hR];
+            }
+        }
+        // Positivity safeguard: if any predictor trace on either side is not a physical
+        // state, the sub-face takes the first-order flux of the two subcell averages.
+        double Fbar[NV];
+        for (int pass = 0; pass < 2; pass++) {
+            bool ok = true;
+#pragma unroll
+            for (int v = 0; v < NV; v++) Fbar[v] = 0.0;
+            for (int s = 0; s < 3 && ok; s++)
+                for (int ap = 0; ap < NF3; ap++) {
+                    double qL[NV], qR[NV], G[NV];
+                    int ma[2] = {ap % 3, ap / 3};
+                    double wt = T->w3[s];
+                    double x[3] = {0, 0, 0};
+                    int j3 = 0;
+                    for (int j = 0; j < DIM; j++) {
+                        if (j == k) {
+                            x[j] = P.lo[j] + P.h[j] * (ci[j] + (double)f / NS);
+                        } else {
+                            wt *= T->w3[ma[j3]];
+                            x[j] = P.lo[j] + P.h[j] * (ci[j] + (mp[j3] + T->xi3[ma[j3]]) / NS);
+                            j3++;
+                        }
+                    }
+                    const double ts = t0 + T->xi3[s] * dt;
+                    const double *trL = tr + (int64_t)pL * TRS + (2 * k + 1) * NV * NF3 * 3;
+                    const double *trR = tr + (int64_t)pR * TRS + (2 * k + 0) * NV * NF3 * 3;
+#pragma unroll
+                    for (int v = 0; v < NV; v++) {
+                        qL[v] = pass ? avL[v] : trL[v * NF3 * 3 + ap + NF3 * s];
+                        qR[v] = pass ? avR[v] : trR[v * NF3 * 3 + ap + NF3 * s];
+                    }
+                    if (bside == 0) bc_ghost<DIM>(P, k, 0, qR, x, ts, qL);
+                    else if (bside == 1) bc_ghost<DIM>(P, k, 1, qL, x, ts, qR);
+                    if (!pass && !(physical<DIM>(qL, P.gamma) && physical<DIM>(qR, P.gamma))) {
+                        ok = false;
+                        break;
+                    }
+                    rusanov<DIM>(k, qL, qR, G, P.gamma);
+#pragma unroll
+                    for (int v = 0; v < NV; v++) Fbar[v] += wt * G[v];
+                }
+            if (ok) break;
+        }
+#pragma unroll
+        for (int v = 0; v < NV; v++) Fb[it * NV + v] = Fbar[v];
+    }
+    __syncthreads();
+    // FV update of the cell's own subcells
+    const double *halo = B.halo + (int64_t)ch * NV * HSZ;
+    const int slot = B.slot[1][c];
+    for (int sg = threadIdx.x; sg < NSUB; sg += 256) {
+        int ms[3] = {sg % NS, (sg / NS) % NS, sg / (NS * NS)};
+        int hidx = 0;
+        for (int j = DIM - 1; j >= 0; j--) hidx = hidx * HN + (ms[j] + 3);
+        double q[NV];
+#pragma unroll
+        for (int v = 0; v < NV; v++) q[v] = halo[v * HSZ + hidx];
+        for (int k = 0; k < DIM; k++) {
+            int sp = 0, mul = 1;
+            for (int j = 0; j < DIM; j++) {
+                if (j == k) continue;
+                sp += ms[j] * mul;
+                mul *= NS;
+            }
+            const double ck = dt * NS / P.h[k];
+#pragma unroll
+            for (int v = 0; v < NV; v++) {
+                const double Fp = Fb[((k * (NS + 1) + ms[k] + 1) * NSF + sp) * NV + v];
+                const double Fm = Fb[((k * (NS + 1) + ms[k]) * NSF + sp) * NV + v];
+                q[v] -= ck * (Fp - Fm);
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < NV; v++) {
+            vn[v * NSUB + sg] = q[v];
+            B.pool[1][((int64_t)slot * NV + v) * NSUB + sg] = q[v];
+        }
+        if (!(q[0] > 0.0) || !(pressure<DIM>(q, P.gamma) > 0.0)) badc = 1;
+    }
+    // boundary fluxes of the cell's faces for the flux correction
+    for (int it = threadIdx.x; it < 2 * DIM * NV * NSF; it += 256) {
+        const int face = it / (NV * NSF), v = (it / NSF) % NV, sp = it % NSF;
+        const int k = face >> 1, side = face & 1;
+        B.sflux[(int64_t)slot * 2 * DIM * NV * NSF + it] = Fb[((k * (NS + 1) + (side ? NS : 0)) * NSF + sp) * NV + v];
+    }
+    __syncthreads();
+    // gather: u = R v (eq. (subcell.r)), tensor application
+    tensor_apply<DIM>(&T->Rg[0][0], MAXNS, n, NS, NV, vn, ug, tmp, threadIdx.x, 256);
+    for (int it = threadIdx.x; it < NV * NN; it += 256) {
+        const int v = it / NN, a = it % NN;
+        B.u[cur ^ 1][((int64_t)v * P.ncell + c) * NN + a] = ug[it];
+    }
+    if (threadIdx.x == 0 && badc) atomicAdd(nonphys, 1);
+}
+
+// Flux correction of unlimited cells next to troubled cells (Sec. 4.4): the DG face
+// flux of each face shared with a troubled cell is replaced by the subcell fluxes of
+// that face, each integrated against the basis (P[sigma][a] / (Ns w_a) per tangential axis).
+template <int DIM, int N>
+__global__ __launch_bounds__(128) void k_fluxcorr(const Tables *__restrict__ T, Prob P, Bufs B, int cur) {
+    constexpr int n = N + 1, NV = DIM + 2, NN = cpow(n, DIM), NFN = cpow(n, DIM - 1);
+    constexpr int NS = 2 * N + 1, NSF = cpow(NS, DIM - 1);
+    const int64_t c = B.clist[blockIdx.x];
+    int ci[3];
+    coords_of(P, c, ci);
+    const double dt = B.scal[0];
+    int64_t nbc[3][2];
+    int nslot[3][2];
+    for (int k = 0; k < DIM; k++)
+        for (int side = 0; side < 2; side++) {
+            int nb[3] = {ci[0], ci[1], ci[2]};
+            nb[k] += side ? 1 : -1;
+            nbc[k][side] = -1;
+            nslot[k][side] = -1;
+            if (nb[k] < 0 || nb[k] >= P.nc[k]) {
+                if (!P.periodic[k]) continue;
+                nb[k] = (nb[k] + P.nc[k]) % P.nc[k];
+            }
+            const int64_t cn = cell_of(P, nb);
+            if (B.beta[1][cn] && B.slot[1][cn] >= 0) {
+                nbc[k][side] = cn;
+                nslot[k][side] = B.slot[1][cn];
+            }
+        }
+    for (int it = threadIdx.x; it < NV * NN; it += 128) {
+        const int v = it / NN, a = it % NN;
+        int m[3] = {a % n, (a / n) % n, a / (n * n)};
+        double val = B.u[cur ^ 1][((int64_t)v * P.ncell + c) * NN + a];
+        for (int k = 0; k < DIM; k++) {
+            int ap = 0, mul = 1;
+            for (int j = 0; j < DIM; j++) {
+                if (j == k) continue;
+                ap += m[j] * mul;
+                mul *= n;
+            }
+            const int ak = m[k];
+            const double ck = dt / P.h[k] / T->w[ak];
+            for (int side = 0; side < 2; side++) {
+                if (nbc[k][side] < 0) continue;
+                const int slot = nslot[k][side];
+                const double *fs = B.sflux + ((int64_t)slot * 2 * DIM + 2 * k + (1 - side)) * NV * NSF + v * NSF;
+                double Fsub = 0.0;
+                for (int sp = 0; sp < NSF; sp++) {
+                    int ms[2] = {sp % NS, sp / NS};
+                    double wgt = 1.0;
+                    int j2 = 0;
+                    for (int j = 0; j < DIM; j++) {
+                        if (j == k) continue;
+                        wgt *= T->Pt[ms[j2]][m[j]];
+                        j2++;
+                    }
+                    Fsub += wgt * fs[sp];
+                }
+                const double Gdg = B.gbar[((c * 2 * DIM + 2 * k + side) * NV + v) * NFN + ap];
+                val += side ? ck * T->R[ak] * (Gdg - Fsub) : ck * T->L[ak] * (Fsub - Gdg);
+            }
+        }
+        B.u[cur ^ 1][((int64_t)v * P.ncell + c) * NN + a] = val;
+    }
+}
+
+// ------------------------------------------------------------------ time step
+template <int DIM, int N>
+__global__ __launch_bounds__(256) void k_lambda(Prob P, const double *__restrict__ u, double *part) {
+    constexpr int n = N + 1, NV = DIM + 2, NN = cpow(n, DIM);
+    __shared__ double red[256];
+    double lam = 0.0;
+    const int64_t total = P.ncell * NN;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) {
+        double q[NV];
+#pragma unroll
+        for (int v = 0; v < NV; v++) q[v] = u[(int64_t)v * total + i];
+        const double cs = sqrt(P.gamma * pressure<DIM>(q, P.gamma) / q[0]);
+#pragma unroll
+        for (int k = 0; k < DIM; k++) lam = fmax(lam, fabs(q[1 + k] / q[0]) + cs);
+    }
+    red[threadIdx.x] = lam;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void k_dt_final(const double *part, int nparts, double *scal, double factor) {
+    __shared__ double red[256];
+    double lam = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += 256) lam = fmax(lam, part[i]);
+    red[threadIdx.x] = lam;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        scal[2] = red[0];
+        scal[0] = factor / red[0];
+    }
+}
+
+__global__ void k_set_scalar(double *scal, int idx, double val) { scal[idx] = val; }
+__global__ void k_advance_time(double *scal) { scal[1] += scal[0]; }
+
+// ------------------------------------------------------------------ launchers
+template <int DIM, int N>
+struct Launch {
+    static constexpr int n = N + 1, NV = DIM + 2, NN = cpow(n, DIM), NS = 2 * N + 1;
+    static constexpr int NPOS = cpow(NS, DIM) + 2 * DIM * cpow(NS, DIM - 1);
+
+    static void predictor(const StepCtx &C) {
+        using S = PredShape<DIM, N>;
+        PredArgs A;
+        A.in = C.B.u[C.cur];
+        A.in_cstride = NN;
+        A.in_vstride = (int64_t)C.P.ncell * NN;
+        A.trace = C.B.trace;
+        A.vol_out = C.B.u[C.cur ^ 1];
+        A.ncell = C.P.ncell;
+        A.cell0 = 0;
+        A.iters = C.picard_iters;
+        for (int k = 0; k < 3; k++) A.dth[k] = k < DIM ? 1.0 / C.P.h[k] : 0.0;
+        A.dt = C.B.scal;
+        A.D = &C.tab->D[0][0];
+        A.Kw = &C.tab->Kw[0][0];
+        A.Lb = C.tab->L;
+        A.Rb = C.tab->R;
+        A.w = C.tab->w;
+        A.Dvol = &C.tab->Dvol[0][0];
+        const int64_t grid = (C.P.ncell + S::CPB - 1) / S::CPB;
+        hipLaunchKernelGGL((k_predictor<DIM, N, true>), dim3((unsigned)grid), dim3(S::BS), 0, C.stream, C.tab, A,
+                           C.P.gamma);
+    }
+    static void faces(const StepCtx &C) {
+        constexpr int NFN = cpow(n, DIM - 1);
+        for (int k = 0; k < DIM; k++) {
+            int64_t nlines = 1;
+            for (int j = 0; j < DIM; j++)
+                if (j != k) nlines *= C.P.nc[j];
+            const int nfk = C.P.periodic[k] ? C.P.nc[k] : C.P.nc[k] + 1;
+            const int64_t total = nlines * nfk * NFN;
+            hipLaunchKernelGGL((k_face<DIM, N>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, C.stream, C.tab,
+                               C.P, C.B.trace, C.B.gbar, C.B.scal, k);
+        }
+    }
+    static void corrector_detect(const StepCtx &C) {
+        hipLaunchKernelGGL((k_corrector_detect<DIM, N>), dim3((unsigned)C.P.ncell), dim3(128), 0, C.stream, C.tab, C.P,
+                           C.B, C.cur, C.limiter);
+    }
+    static void bounds(const StepCtx &C) {
+        int64_t next = 1;
+        for (int j = 0; j < DIM; j++) next *= C.P.nc[j] + 2;
+        hipLaunchKernelGGL((k_cell_bounds<DIM, N>), dim3((unsigned)next), dim3(128), 0, C.stream, C.tab, C.P, C.B,
+                           C.cur);
+        hipLaunchKernelGGL((k_neigh_bounds<DIM>), dim3((unsigned)((C.P.ncell + 255) / 256)), dim3(256), 0, C.stream,
+                           C.P, C.B);
+    }
+    static void subcell_chunk(const StepCtx &C, int first, int count) {
+        hipLaunchKernelGGL((k_sub_halo<DIM, N>), dim3(count), dim3(256), 0, C.stream, C.tab, C.P, C.B, C.cur, first);
+        const int64_t npos = (int64_t)count * NPOS;
+        hipLaunchKernelGGL((k_sub_recon<DIM, N>), dim3((unsigned)((npos + 127) / 128)), dim3(128), 0, C.stream, C.tab,
+                           C.B, count);
+        using S = PredShape<DIM, 2>;
+        PredArgs A;
+        A.in = C.B.Y;
+        A.in_cstride = NV * cpow(3, DIM);
+        A.in_vstride = cpow(3, DIM);
+        A.trace = C.B.strace;
+        A.vol_out = nullptr;
+        A.ncell = npos;
+        A.cell0 = 0;
+        A.iters = 3;
+        for (int k = 0; k < 3; k++) A.dth[k] = k < DIM ? (double)NS / C.P.h[k] : 0.0;
+        A.dt = C.B.scal;
+        A.D = &C.tab->D3[0][0];
+        A.Kw = &C.tab->Kw3[0][0];
+        A.Lb = C.tab->L3;
+        A.Rb = C.tab->R3;
+        A.w = C.tab->w3;
+        A.Dvol = nullptr;
+        const int64_t grid = (npos + S::CPB - 1) / S::CPB;
+        hipLaunchKernelGGL((k_predictor<DIM, 2, false>), dim3((unsigned)grid), dim3(S::BS), 0, C.stream, C.tab, A,
+                           C.P.gamma);
+        hipLaunchKernelGGL((k_sub_update<DIM, N>), dim3(count), dim3(256), 0, C.stream, C.tab, C.P, C.B, C.cur, first,
+                           C.B.counts + 2);
+    }
+    static void fluxcorr(const StepCtx &C, int count) {
+        hipLaunchKernelGGL((k_fluxcorr<DIM, N>), dim3(count), dim3(128), 0, C.stream, C.tab, C.P, C.B, C.cur);
+    }
+    static void lambda(const StepCtx &C, const double *u, double factor) {
+        const int64_t total = C.P.ncell * NN;
+        int nb = (int)((total + 255) / 256);
+        if (nb > C.lam_blocks) nb = C.lam_blocks;
+        hipLaunchKernelGGL((k_lambda<DIM, N>), dim3(nb), dim3(256), 0, C.stream, C.P, u, C.B.lam_part);
+        hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(256), 0, C.stream, C.B.lam_part, nb, C.B.scal, factor);
+    }
+};
+
+struct Ops {
+    void (*predictor)(const StepCtx &);
+    void (*faces)(const StepCtx &);
+    void (*corrector_detect)(const StepCtx &);
+    void (*bounds)(const StepCtx &);
+    void (*subcell_chunk)(const StepCtx &, int, int);
+    void (*fluxcorr)(const StepCtx &, int);
+    void (*lambda)(const StepCtx &, const double *, double);
+    int npos;
+};
+
+template <int DIM, int N>
+static Ops make_ops() {
+    using L = Launch<DIM, N>;
+    return Ops{L::predictor, L::faces, L::corrector_detect, L::bounds, L::subcell_chunk, L::fluxcorr, L::lambda, L::NPOS};
+}
+
+static const Ops *ops_for(int dim, int N) {
+    static const Ops ops2[9] = {make_ops<2, 1>(), make_ops<2, 2>(), make_ops<2, 3>(), make_ops<2, 4>(), make_ops<2, 5>(),
+                                make_ops<2, 6>(), make_ops<2, 7>(), make_ops<2, 8>(), make_ops<2, 9>()};
+    static const Ops ops3[3] = {make_ops<3, 1>(), make_ops<3, 2>(), make_ops<3, 3>()};
+    if (dim == 2 && N >= 1 && N <= 9) return &ops2[N - 1];
+    if (dim == 3 && N >= 1 && N <= 3) return &ops3[N - 1];
+    return nullptr;
+}
+
+bool supported(int dim, int N) { return ops_for(dim, N) != nullptr; }
+int positions_per_cell(int dim, int N) { return ops_for(dim, N)->npos; }
+
+void launch_bounds(const StepCtx &C) { ops_for(C.P.dim, C.P.N)->bounds(C); }
+void launch_predictor(const StepCtx &C) { ops_for(C.P.dim, C.P.N)->predictor(C); }
+void launch_faces(const StepCtx &C) { ops_for(C.P.dim, C.P.N)->faces(C); }
+void launch_corrector_detect(const StepCtx &C) { ops_for(C.P.dim, C.P.N)->corrector_detect(C); }
+void launch_compact(const StepCtx &C) {
+    const int nblk = (int)((C.P.ncell + CBS - 1) / CBS);
+    hipLaunchKernelGGL(k_compact_count, dim3(nblk), dim3(CBS), 0, C.stream, C.P, C.B);
+    hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(1024), 0, C.stream, C.B, nblk, C.capacity);
+    hipLaunchKernelGGL(k_compact_scatter, dim3(nblk), dim3(CBS), 0, C.stream, C.P, C.B, C.capacity);
+}
+void launch_subcell_chunk(const StepCtx &C, int first, int count) {
+    ops_for(C.P.dim, C.P.N)->subcell_chunk(C, first, count);
+}
+void launch_fluxcorr(const StepCtx &C, int count) { ops_for(C.P.dim, C.P.N)->fluxcorr(C, count); }
+void launch_lambda(const StepCtx &C, const double *u, double factor) {
+    ops_for(C.P.dim, C.P.N)->lambda(C, u, factor);
+}
+void launch_set_scalar(const StepCtx &C, int idx, double val) {
+    hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(1), 0, C.stream, C.B.scal, idx, val);
+}
+void launch_advance_time(const StepCtx &C) {
+    hipLaunchKernelGGL(k_advance_time, dim3(1), dim3(1), 0, C.stream, C.B.scal);
+}
+
+}  // namespace adg

@@ -128,15 +128,21 @@ struct PredArgs {
 };
 
 // Contraction along axis k of every line held in LDS: line[i] <- c * sum_b M[i][b] line[b].
+// One work item handles the same line of LV variables (independent FMA chains; LV is
+// smaller for long lines to bound register use).
 template <int DIM, int N, int CPB, int VC, int BS>
 __device__ __forceinline__ void lds_lines(double *X, int k, int nlines_per_var, int lstride_s, const double (*M)[MAXN],
-                                          double c, int tid) {
+                                          double c, int tid, int nvalid) {
     constexpr int n = N + 1, NN = cpow(n, DIM), NST = NN * n;
+    constexpr int LV = (n >= 8) ? 1 : VC;
+    constexpr int NG = (VC + LV - 1) / LV;   // variable groups per line
     const int st = (k == 0) ? 1 : (k == 1 ? n : n * n);
-    const int nitems = CPB * VC * nlines_per_var;
+    const int nitems = CPB * NG * nlines_per_var;
     for (int it = tid; it < nitems; it += BS) {
-        const int lcl = it / (VC * nlines_per_var);
-        const int vv = (it / nlines_per_var) % VC;
+        // compiler barrier: keeps the operator rows from being hoisted into registers
+        __asm__ volatile("" ::: "memory");
+        const int lcl = it / (NG * nlines_per_var);
+        const int grp = (it / nlines_per_var) % NG;
         const int j = it % nlines_per_var;          // (a_perp, s) flattened, a_perp fastest
         const int s = j / (NN / n), ap = j % (NN / n);
         int base = 0, rem = ap, mul = 1;
@@ -147,37 +153,56 @@ __device__ __forceinline__ void lds_lines(double *X, int k, int nlines_per_var, 
             rem /= n;
             mul *= n;
         }
-        double *line = &X[(lcl * VC + vv) * NST + lstride_s * s + base];
-        double xb[n];
+        const int v0 = grp * LV;
+        double *line0 = &X[(lcl * VC + v0) * NST + lstride_s * s + base];
+        double xb[LV][n];
 #pragma unroll
-        for (int b = 0; b < n; b++) xb[b] = line[b * st];
+        for (int vv = 0; vv < LV; vv++)
+#pragma unroll
+            for (int b = 0; b < n; b++) xb[vv][b] = (v0 + vv < nvalid) ? line0[vv * NST + b * st] : 0.0;
 #pragma unroll
         for (int i = 0; i < n; i++) {
-            double acc = 0.0;
+            double acc[LV];
 #pragma unroll
-            for (int b = 0; b < n; b++) acc += M[i][b] * xb[b];
-            line[i * st] = c * acc;
+            for (int vv = 0; vv < LV; vv++) acc[vv] = 0.0;
+#pragma unroll
+            for (int b = 0; b < n; b++) {
+                const double m = M[i][b];
+#pragma unroll
+                for (int vv = 0; vv < LV; vv++) acc[vv] += m * xb[vv][b];
+            }
+#pragma unroll
+            for (int vv = 0; vv < LV; vv++)
+                if (v0 + vv < nvalid) line0[vv * NST + i * st] = c * acc[vv];
         }
     }
 }
 
 template <int DIM, int N, bool VOL>
-__global__ __launch_bounds__((PredShape<DIM, N>::BS)) void k_predictor(const Tables *__restrict__ T, PredArgs A,
+__global__ __launch_bounds__((PredShape<DIM, N>::BS), 2) void k_predictor(const Tables *__restrict__ T, PredArgs A,
                                                                       double gamma) {
     using S = PredShape<DIM, N>;
     constexpr int n = S::n, NV = S::NV, NN = S::NN, NST = S::NST, NFN = S::NFN, CPB = S::CPB, VC = S::VC;
     __shared__ double X[CPB * VC * NST];
+    // operators staged in LDS and read as wave-uniform broadcasts inside the loops (kept
+    // out of registers: the n x n matrices would otherwise be hoisted into VGPRs)
+    __shared__ double Ds[n][MAXN], Kws[n][MAXN], Dvs[n][MAXN];
 
     const int tid = threadIdx.x;
     const int lc = tid / NN, a = tid % NN;
     const int64_t c = (int64_t)blockIdx.x * CPB + lc;
     const bool owner = (tid < S::ACT) && (c < A.ncell);
     const double dt = *A.dt;
-
-    // operators on the hot path (wave-uniform loads)
-    const double(*D)[MAXN] = reinterpret_cast<const double(*)[MAXN]>(A.D);
-    const double(*Kw)[MAXN] = reinterpret_cast<const double(*)[MAXN]>(A.Kw);
-    const double(*Dvol)[MAXN] = reinterpret_cast<const double(*)[MAXN]>(A.Dvol);
+    for (int i = tid; i < n * n; i += S::BS) {
+        const int r = i / n, cc = i % n;
+        Ds[r][cc] = A.D[r * MAXN + cc];
+        Kws[r][cc] = A.Kw[r * MAXN + cc];
+        Dvs[r][cc] = VOL ? A.Dvol[r * MAXN + cc] : 0.0;
+    }
+    __syncthreads();
+    const double(*D)[MAXN] = Ds;
+    const double(*Kw)[MAXN] = Kws;
+    const double(*Dvol)[MAXN] = Dvs;
     (void)T;
 
     double u0[NV], q[NV][n], Sacc[NV][n];
@@ -200,6 +225,14 @@ __global__ __launch_bounds__((PredShape<DIM, N>::BS)) void k_predictor(const Tab
         for (int v = 0; v < NV; v++)
 #pragma unroll
             for (int s = 0; s < n; s++) Sacc[v][s] = 0.0;
+        // 1/rho of every node of the pencil, shared by the fluxes of all axes (for long
+        // pencils recomputed per axis instead, to stay within 256 registers)
+        constexpr bool CACHE_IRHO = n < 8;
+        double irho[CACHE_IRHO ? n : 1];
+        if constexpr (CACHE_IRHO) {
+#pragma unroll
+            for (int t = 0; t < n; t++) irho[t] = 1.0 / q[0][t];
+        }
 #pragma unroll
         for (int k = 0; k < DIM; k++) {
             const double ck = dt * A.dth[k];
@@ -208,17 +241,26 @@ __global__ __launch_bounds__((PredShape<DIM, N>::BS)) void k_predictor(const Tab
                 if (tid < S::ACT) {
 #pragma unroll
                     for (int t = 0; t < n; t++) {
-                        double qt[NV], F[NV];
+                        double ir;
+                        if constexpr (CACHE_IRHO) ir = irho[t];
+                        else ir = 1.0 / q[0][t];
+                        const double un = q[1 + k][t] * ir;
+                        double ke = 0.0;
 #pragma unroll
-                        for (int v = 0; v < NV; v++) qt[v] = q[v][t];
-                        euler_flux<DIM>(k, qt, F, gamma);
+                        for (int j = 0; j < DIM; j++) ke += q[1 + j][t] * q[1 + j][t];
+                        const double prt = (gamma - 1.0) * (q[NV - 1][t] - 0.5 * ke * ir);
+                        double F[NV];
+                        F[0] = q[1 + k][t];
+#pragma unroll
+                        for (int j = 0; j < DIM; j++) F[1 + j] = q[1 + j][t] * un + (j == k ? prt : 0.0);
+                        F[NV - 1] = un * (q[NV - 1][t] + prt);
 #pragma unroll
                         for (int vv = 0; vv < VC; vv++)
                             if (v0 + vv < NV) X[(lc * VC + vv) * NST + a + NN * t] = F[v0 + vv];
                     }
                 }
                 __syncthreads();
-                lds_lines<DIM, N, CPB, VC, S::BS>(X, k, NN, NN, D, ck, tid);
+                lds_lines<DIM, N, CPB, VC, S::BS>(X, k, NN, NN, D, ck, tid, NV - v0 < VC ? NV - v0 : VC);
                 __syncthreads();
                 if (tid < S::ACT) {
 #pragma unroll
@@ -230,16 +272,22 @@ __global__ __launch_bounds__((PredShape<DIM, N>::BS)) void k_predictor(const Tab
                 __syncthreads();
             }
         }
-        // time contraction in registers
+        // time contraction in registers (Kw row s broadcast from LDS, shared by the variables)
 #pragma unroll
-        for (int v = 0; v < NV; v++)
+        for (int s = 0; s < n; s++) {
+            __asm__ volatile("" ::: "memory");
+            double acc[NV];
 #pragma unroll
-            for (int s = 0; s < n; s++) {
-                double acc = 0.0;
+            for (int v = 0; v < NV; v++) acc[v] = 0.0;
 #pragma unroll
-                for (int t = 0; t < n; t++) acc += Kw[s][t] * Sacc[v][t];
-                q[v][s] = u0[v] - acc;
+            for (int t = 0; t < n; t++) {
+                const double kst = Kw[s][t];
+#pragma unroll
+                for (int v = 0; v < NV; v++) acc[v] += kst * Sacc[v][t];
             }
+#pragma unroll
+            for (int v = 0; v < NV; v++) q[v][s] = u0[v] - acc[v];
+        }
     }
 
     // ---- volume term of eq. (pde.nc.gw2), divided by the diagonal mass:
@@ -270,7 +318,7 @@ __global__ __launch_bounds__((PredShape<DIM, N>::BS)) void k_predictor(const Tab
                         if (v0 + vv < NV) X[(lc * VC + vv) * NST + a] = Fi[v0 + vv];
                 }
                 __syncthreads();
-                lds_lines<DIM, N, CPB, VC, S::BS>(X, k, NN / n, 0, Dvol, ck, tid);
+                lds_lines<DIM, N, CPB, VC, S::BS>(X, k, NN / n, 0, Dvol, ck, tid, NV - v0 < VC ? NV - v0 : VC);
                 __syncthreads();
                 if (tid < S::ACT) {
 #pragma unroll

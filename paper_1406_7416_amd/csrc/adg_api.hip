@@ -204,6 +204,7 @@ static StepCtx ctx(const adg_problem *pb) {
     C.picard_iters = pb->prm.picard_iters;
     C.capacity = pb->cap;
     C.lam_blocks = pb->lam_blocks;
+    C.precision = pb->prm.precision;
     return C;
 }
 
@@ -225,7 +226,7 @@ int adg_create(const adg_grid_desc *g, int N, double gamma, const adg_params *p,
     if (prm.picard_iters <= 0) prm.picard_iters = N + 1;
     if (prm.eps == 0) prm.eps = 1e-3;
     if (prm.delta0 == 0) prm.delta0 = 1e-4;
-    if (prm.precision != ADG_FP64) return fail(ADG_EINVAL, "precision mode not built");
+    if (prm.precision != ADG_FP64 && prm.precision != ADG_MIXED) return fail(ADG_EINVAL, "unknown precision mode");
     adg_problem *pb = new (std::nothrow) adg_problem();
     if (!pb) return fail(ADG_ENOMEM, "host allocation failed");
     Prob &P = pb->P;

@@ -24,6 +24,8 @@ struct Tables {
     double xi3[3], w3[3];
     double D3[MAXN][MAXN], L3[MAXN], R3[MAXN], Kw3[MAXN][MAXN];
     double weno[3][3][3];        // [stencil][monomial][cell]: averages -> coefficients
+    // FP32 copies for the mixed-precision predictor and face fluxes
+    float fD[MAXN][MAXN], fKw[MAXN][MAXN], fDvol[MAXN][MAXN], fL[MAXN], fR[MAXN], fw[MAXN];
 };
 
 struct BCDev {

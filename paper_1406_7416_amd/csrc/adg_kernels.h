@@ -14,6 +14,7 @@ struct StepCtx {
     int picard_iters;
     int64_t capacity;      // pool slots
     int lam_blocks;        // blocks of the lambda reduction
+    int precision;         // ADG_FP64 or ADG_MIXED
 };
 
 bool supported(int dim, int N);

@@ -9,6 +9,7 @@
 // Parallel mapping: every kernel is element-local or face-local and writes each output
 // from exactly one thread (no atomics on data), so results are bitwise reproducible.
 #include <cmath>
+#include <type_traits>
 #include "adg_internal.h"
 #include "adg_kernels.h"
 
@@ -20,37 +21,37 @@ template <int B> struct Pow<B, 0> { static constexpr int v = 1; };
 
 __host__ __device__ constexpr int cpow(int b, int e) { return e == 0 ? 1 : b * cpow(b, e - 1); }
 
-template <int DIM>
-__device__ __forceinline__ double pressure(const double *q, double g) {
-    double ke = 0.0;
+template <int DIM, typename R = double>
+__device__ __forceinline__ R pressure(const R *q, R g) {
+    R ke = 0;
 #pragma unroll
     for (int j = 0; j < DIM; j++) ke += q[1 + j] * q[1 + j];
-    return (g - 1.0) * (q[DIM + 1] - 0.5 * ke / q[0]);
+    return (g - R(1)) * (q[DIM + 1] - R(0.5) * ke / q[0]);
 }
 
 // Euler flux along axis k (Sec. 5).
-template <int DIM>
-__device__ __forceinline__ void euler_flux(int k, const double *q, double *F, double g) {
-    const double p = pressure<DIM>(q, g);
-    const double un = q[1 + k] / q[0];
+template <int DIM, typename R = double>
+__device__ __forceinline__ void euler_flux(int k, const R *q, R *F, R g) {
+    const R p = pressure<DIM, R>(q, g);
+    const R un = q[1 + k] / q[0];
     F[0] = q[1 + k];
 #pragma unroll
-    for (int j = 0; j < DIM; j++) F[1 + j] = q[1 + j] * un + (j == k ? p : 0.0);
+    for (int j = 0; j < DIM; j++) F[1 + j] = q[1 + j] * un + (j == k ? p : R(0));
     F[DIM + 1] = un * (q[DIM + 1] + p);
 }
 
 // Rusanov flux; wave speed per quadrature node: max over both sides of |u_n| + c.
-template <int DIM>
-__device__ __forceinline__ void rusanov(int k, const double *qL, const double *qR, double *G, double g) {
+template <int DIM, typename R = double>
+__device__ __forceinline__ void rusanov(int k, const R *qL, const R *qR, R *G, R g) {
     constexpr int NV = DIM + 2;
-    double FL[NV], FR[NV];
-    euler_flux<DIM>(k, qL, FL, g);
-    euler_flux<DIM>(k, qR, FR, g);
-    const double sL = fabs(qL[1 + k] / qL[0]) + sqrt(g * pressure<DIM>(qL, g) / qL[0]);
-    const double sR = fabs(qR[1 + k] / qR[0]) + sqrt(g * pressure<DIM>(qR, g) / qR[0]);
-    const double s = fmax(sL, sR);
+    R FL[NV], FR[NV];
+    euler_flux<DIM, R>(k, qL, FL, g);
+    euler_flux<DIM, R>(k, qR, FR, g);
+    const R sL = fabs(qL[1 + k] / qL[0]) + sqrt(g * pressure<DIM, R>(qL, g) / qL[0]);
+    const R sR = fabs(qR[1 + k] / qR[0]) + sqrt(g * pressure<DIM, R>(qR, g) / qR[0]);
+    const R s = fmax(sL, sR);
 #pragma unroll
-    for (int v = 0; v < NV; v++) G[v] = 0.5 * (FL[v] + FR[v]) - 0.5 * s * (qR[v] - qL[v]);
+    for (int v = 0; v < NV; v++) G[v] = R(0.5) * (FL[v] + FR[v]) - R(0.5) * s * (qR[v] - qL[v]);
 }
 
 template <int DIM>
@@ -98,7 +99,7 @@ __device__ __forceinline__ void coords_of(const Prob &P, int64_t c, int *ci) {
 // and stores them in LDS; "line owner" threads do the length-n spatial contractions
 // (n loads -> n outputs each, in place); the point owner accumulates S over the d axes
 // and applies the time contraction in registers: d + 1 contractions per sweep.
-template <int DIM, int N>
+template <int DIM, int N, typename R = double>
 struct PredShape {
     static constexpr int n = N + 1;
     static constexpr int NV = DIM + 2;
@@ -108,15 +109,16 @@ struct PredShape {
     static constexpr int CPB = NN <= 256 ? 256 / NN : 1;
     static constexpr int ACT = CPB * NN;                           // active point owners
     static constexpr int BS = ((ACT + 63) / 64) * 64;
-    static constexpr int VCMAX = 65536 / (CPB * NST * 8);
+    static constexpr int VCMAX = 65536 / (CPB * NST * (int)sizeof(R));
     static constexpr int VC = VCMAX < 1 ? 1 : (VCMAX > NV ? NV : VCMAX);  // vars per LDS chunk
 };
 
+template <typename R>
 struct PredArgs {
     const double *in;      // input nodal values
     int64_t in_cstride;    // stride between cells
     int64_t in_vstride;    // stride between variables
-    double *trace;         // [cell][2d][v][nfn*n]
+    R *trace;              // [cell][2d][v][nfn*n]
     double *vol_out;       // candidate with volume term [v][cell][node] (main scheme only)
     int64_t ncell;         // cells (or subcell positions) in this launch
     int64_t cell0;         // first cell index (for vol_out addressing)
@@ -124,15 +126,15 @@ struct PredArgs {
     double dth[3];         // dt/h_k multipliers (without dt)
     const double *dt;      // device scalar
     // operators of the n-node basis used by this launch (row stride MAXN)
-    const double *D, *Kw, *Lb, *Rb, *w, *Dvol;
+    const R *D, *Kw, *Lb, *Rb, *w, *Dvol;
 };
 
 // Contraction along axis k of every line held in LDS: line[i] <- c * sum_b M[i][b] line[b].
 // One work item handles the same line of LV variables (independent FMA chains; LV is
 // smaller for long lines to bound register use).
-template <int DIM, int N, int CPB, int VC, int BS>
-__device__ __forceinline__ void lds_lines(double *X, int k, int nlines_per_var, int lstride_s, const double (*M)[MAXN],
-                                          double c, int tid, int nvalid) {
+template <int DIM, int N, int CPB, int VC, int BS, typename R>
+__device__ __forceinline__ void lds_lines(R *X, int k, int nlines_per_var, int lstride_s, const R (*M)[MAXN], R c,
+                                          int tid, int nvalid) {
     constexpr int n = N + 1, NN = cpow(n, DIM), NST = NN * n;
     constexpr int LV = (n >= 8) ? 1 : VC;
     constexpr int NG = (VC + LV - 1) / LV;   // variable groups per line
@@ -154,20 +156,20 @@ __device__ __forceinline__ void lds_lines(double *X, int k, int nlines_per_var, 
             mul *= n;
         }
         const int v0 = grp * LV;
-        double *line0 = &X[(lcl * VC + v0) * NST + lstride_s * s + base];
-        double xb[LV][n];
+        R *line0 = &X[(lcl * VC + v0) * NST + lstride_s * s + base];
+        R xb[LV][n];
 #pragma unroll
         for (int vv = 0; vv < LV; vv++)
 #pragma unroll
-            for (int b = 0; b < n; b++) xb[vv][b] = (v0 + vv < nvalid) ? line0[vv * NST + b * st] : 0.0;
+            for (int b = 0; b < n; b++) xb[vv][b] = (v0 + vv < nvalid) ? line0[vv * NST + b * st] : R(0);
 #pragma unroll
         for (int i = 0; i < n; i++) {
-            double acc[LV];
+            R acc[LV];
 #pragma unroll
-            for (int vv = 0; vv < LV; vv++) acc[vv] = 0.0;
+            for (int vv = 0; vv < LV; vv++) acc[vv] = 0;
 #pragma unroll
             for (int b = 0; b < n; b++) {
-                const double m = M[i][b];
+                const R m = M[i][b];
 #pragma unroll
                 for (int vv = 0; vv < LV; vv++) acc[vv] += m * xb[vv][b];
             }
@@ -178,15 +180,16 @@ __device__ __forceinline__ void lds_lines(double *X, int k, int nlines_per_var, 
     }
 }
 
-template <int DIM, int N, bool VOL>
-__global__ __launch_bounds__((PredShape<DIM, N>::BS), 2) void k_predictor(const Tables *__restrict__ T, PredArgs A,
-                                                                      double gamma) {
-    using S = PredShape<DIM, N>;
+template <int DIM, int N, bool VOL, typename R>
+__global__ __launch_bounds__((PredShape<DIM, N, R>::BS), 2) void k_predictor(const Tables *__restrict__ T,
+                                                                         PredArgs<R> A, double gamma_d) {
+    using S = PredShape<DIM, N, R>;
+    const R gamma = (R)gamma_d;
     constexpr int n = S::n, NV = S::NV, NN = S::NN, NST = S::NST, NFN = S::NFN, CPB = S::CPB, VC = S::VC;
-    __shared__ double X[CPB * VC * NST];
+    __shared__ R X[CPB * VC * NST];
     // operators staged in LDS and read as wave-uniform broadcasts inside the loops (kept
     // out of registers: the n x n matrices would otherwise be hoisted into VGPRs)
-    __shared__ double Ds[n][MAXN], Kws[n][MAXN], Dvs[n][MAXN];
+    __shared__ R Ds[n][MAXN], Kws[n][MAXN], Dvs[n][MAXN];
 
     const int tid = threadIdx.x;
     const int lc = tid / NN, a = tid % NN;
@@ -197,24 +200,27 @@ __global__ __launch_bounds__((PredShape<DIM, N>::BS), 2) void k_predictor(const 
         const int r = i / n, cc = i % n;
         Ds[r][cc] = A.D[r * MAXN + cc];
         Kws[r][cc] = A.Kw[r * MAXN + cc];
-        Dvs[r][cc] = VOL ? A.Dvol[r * MAXN + cc] : 0.0;
+        Dvs[r][cc] = VOL ? A.Dvol[r * MAXN + cc] : R(0);
     }
     __syncthreads();
-    const double(*D)[MAXN] = Ds;
-    const double(*Kw)[MAXN] = Kws;
-    const double(*Dvol)[MAXN] = Dvs;
+    const R(*D)[MAXN] = Ds;
+    const R(*Kw)[MAXN] = Kws;
+    const R(*Dvol)[MAXN] = Dvs;
     (void)T;
 
-    double u0[NV], q[NV][n], Sacc[NV][n];
+    double u0d[NV];
+    R u0[NV], q[NV][n], Sacc[NV][n];
     if (owner) {
 #pragma unroll
-        for (int v = 0; v < NV; v++) u0[v] = A.in[c * A.in_cstride + v * A.in_vstride + a];
+        for (int v = 0; v < NV; v++) u0d[v] = A.in[c * A.in_cstride + v * A.in_vstride + a];
     } else {
         // idle lanes carry a valid constant state so that they never produce NaN
 #pragma unroll
-        for (int v = 0; v < NV; v++) u0[v] = (v == 0) ? 1.0 : 0.0;
-        u0[NV - 1] = 2.5;
+        for (int v = 0; v < NV; v++) u0d[v] = (v == 0) ? 1.0 : 0.0;
+        u0d[NV - 1] = 2.5;
     }
+#pragma unroll
+    for (int v = 0; v < NV; v++) u0[v] = (R)u0d[v];
 #pragma unroll
     for (int v = 0; v < NV; v++)
 #pragma unroll
@@ -224,35 +230,35 @@ __global__ __launch_bounds__((PredShape<DIM, N>::BS), 2) void k_predictor(const 
 #pragma unroll
         for (int v = 0; v < NV; v++)
 #pragma unroll
-            for (int s = 0; s < n; s++) Sacc[v][s] = 0.0;
+            for (int s = 0; s < n; s++) Sacc[v][s] = 0;
         // 1/rho of every node of the pencil, shared by the fluxes of all axes (for long
         // pencils recomputed per axis instead, to stay within 256 registers)
         constexpr bool CACHE_IRHO = n < 8;
-        double irho[CACHE_IRHO ? n : 1];
+        R irho[CACHE_IRHO ? n : 1];
         if constexpr (CACHE_IRHO) {
 #pragma unroll
-            for (int t = 0; t < n; t++) irho[t] = 1.0 / q[0][t];
+            for (int t = 0; t < n; t++) irho[t] = R(1) / q[0][t];
         }
 #pragma unroll
         for (int k = 0; k < DIM; k++) {
-            const double ck = dt * A.dth[k];
+            const R ck = (R)(dt * A.dth[k]);
             for (int v0 = 0; v0 < NV; v0 += VC) {
                 // point phase: fluxes of the time pencil straight into LDS
                 if (tid < S::ACT) {
 #pragma unroll
                     for (int t = 0; t < n; t++) {
-                        double ir;
+                        R ir;
                         if constexpr (CACHE_IRHO) ir = irho[t];
-                        else ir = 1.0 / q[0][t];
-                        const double un = q[1 + k][t] * ir;
-                        double ke = 0.0;
+                        else ir = R(1) / q[0][t];
+                        const R un = q[1 + k][t] * ir;
+                        R ke = 0;
 #pragma unroll
                         for (int j = 0; j < DIM; j++) ke += q[1 + j][t] * q[1 + j][t];
-                        const double prt = (gamma - 1.0) * (q[NV - 1][t] - 0.5 * ke * ir);
-                        double F[NV];
+                        const R prt = (gamma - R(1)) * (q[NV - 1][t] - R(0.5) * ke * ir);
+                        R F[NV];
                         F[0] = q[1 + k][t];
 #pragma unroll
-                        for (int j = 0; j < DIM; j++) F[1 + j] = q[1 + j][t] * un + (j == k ? prt : 0.0);
+                        for (int j = 0; j < DIM; j++) F[1 + j] = q[1 + j][t] * un + (j == k ? prt : R(0));
                         F[NV - 1] = un * (q[NV - 1][t] + prt);
 #pragma unroll
                         for (int vv = 0; vv < VC; vv++)
@@ -260,7 +266,7 @@ __global__ __launch_bounds__((PredShape<DIM, N>::BS), 2) void k_predictor(const 
                     }
                 }
                 __syncthreads();
-                lds_lines<DIM, N, CPB, VC, S::BS>(X, k, NN, NN, D, ck, tid, NV - v0 < VC ? NV - v0 : VC);
+                lds_lines<DIM, N, CPB, VC, S::BS, R>(X, k, NN, NN, D, ck, tid, NV - v0 < VC ? NV - v0 : VC);
                 __syncthreads();
                 if (tid < S::ACT) {
 #pragma unroll
@@ -276,12 +282,12 @@ __global__ __launch_bounds__((PredShape<DIM, N>::BS), 2) void k_predictor(const 
 #pragma unroll
         for (int s = 0; s < n; s++) {
             __asm__ volatile("" ::: "memory");
-            double acc[NV];
+            R acc[NV];
 #pragma unroll
-            for (int v = 0; v < NV; v++) acc[v] = 0.0;
+            for (int v = 0; v < NV; v++) acc[v] = 0;
 #pragma unroll
             for (int t = 0; t < n; t++) {
-                const double kst = Kw[s][t];
+                const R kst = Kw[s][t];
 #pragma unroll
                 for (int v = 0; v < NV; v++) acc[v] += kst * Sacc[v][t];
             }
@@ -293,21 +299,21 @@ __global__ __launch_bounds__((PredShape<DIM, N>::BS), 2) void k_predictor(const 
     // ---- volume term of eq. (pde.nc.gw2), divided by the diagonal mass:
     //   (dt/h_k) sum_b [w_b D[b][a_k] / w_{a_k}] sum_s w_s F_k(q(a|b, s))
     if constexpr (VOL) {
-        double vol[NV];
+        R vol[NV];
 #pragma unroll
-        for (int v = 0; v < NV; v++) vol[v] = 0.0;
+        for (int v = 0; v < NV; v++) vol[v] = 0;
 #pragma unroll
         for (int k = 0; k < DIM; k++) {
-            const double ck = dt * A.dth[k];
-            double Fi[NV];
+            const R ck = (R)(dt * A.dth[k]);
+            R Fi[NV];
 #pragma unroll
-            for (int v = 0; v < NV; v++) Fi[v] = 0.0;
+            for (int v = 0; v < NV; v++) Fi[v] = 0;
 #pragma unroll
             for (int t = 0; t < n; t++) {
-                double qt[NV], F[NV];
+                R qt[NV], F[NV];
 #pragma unroll
                 for (int v = 0; v < NV; v++) qt[v] = q[v][t];
-                euler_flux<DIM>(k, qt, F, gamma);
+                euler_flux<DIM, R>(k, qt, F, gamma);
 #pragma unroll
                 for (int v = 0; v < NV; v++) Fi[v] += A.w[t] * F[v];
             }
@@ -318,7 +324,7 @@ __global__ __launch_bounds__((PredShape<DIM, N>::BS), 2) void k_predictor(const 
                         if (v0 + vv < NV) X[(lc * VC + vv) * NST + a] = Fi[v0 + vv];
                 }
                 __syncthreads();
-                lds_lines<DIM, N, CPB, VC, S::BS>(X, k, NN / n, 0, Dvol, ck, tid, NV - v0 < VC ? NV - v0 : VC);
+                lds_lines<DIM, N, CPB, VC, S::BS, R>(X, k, NN / n, 0, Dvol, ck, tid, NV - v0 < VC ? NV - v0 : VC);
                 __syncthreads();
                 if (tid < S::ACT) {
 #pragma unroll
@@ -331,7 +337,7 @@ __global__ __launch_bounds__((PredShape<DIM, N>::BS), 2) void k_predictor(const 
         if (owner) {
 #pragma unroll
             for (int v = 0; v < NV; v++)
-                A.vol_out[(A.cell0 + c) * NN + (int64_t)v * A.in_vstride + a] = u0[v] + vol[v];
+                A.vol_out[(A.cell0 + c) * NN + (int64_t)v * A.in_vstride + a] = u0d[v] + (double)vol[v];
         }
     }
 
@@ -365,10 +371,10 @@ __global__ __launch_bounds__((PredShape<DIM, N>::BS), 2) void k_predictor(const 
                 rem /= n;
                 mul *= n;
             }
-            const double *line = &X[(lcl * VC + vv) * NST + NN * s + base];
+            const R *line = &X[(lcl * VC + vv) * NST + NN * s + base];
             const int st = (k == 0) ? 1 : (k == 1 ? n : n * n);
-            const double *Bv = side ? A.Rb : A.Lb;
-            double acc = 0.0;
+            const R *Bv = side ? A.Rb : A.Lb;
+            R acc = 0;
 #pragma unroll
             for (int b = 0; b < n; b++) acc += Bv[b] * line[b * st];
             A.trace[((cc * 2 * DIM + face) * NV + v0 + vv) * (NFN * n) + j] = acc;
@@ -380,9 +386,9 @@ __global__ __launch_bounds__((PredShape<DIM, N>::BS), 2) void k_predictor(const 
 // ------------------------------------------------------------------- face fluxes
 // One thread per (face, tangential node): time-integrated Rusanov flux, written into
 // the slot of both adjacent cells.
-template <int DIM, int N>
-__global__ void k_face(const Tables *__restrict__ T, Prob P, const double *__restrict__ trace,
-                       double *__restrict__ gbar, const double *__restrict__ scal, int k) {
+template <int DIM, int N, typename R>
+__global__ void k_face(const Tables *__restrict__ T, Prob P, const R *__restrict__ trace, R *__restrict__ gbar,
+                       const double *__restrict__ scal, int k) {
     constexpr int n = N + 1, NV = DIM + 2, NFN = cpow(n, DIM - 1);
     const int nk = P.nc[k];
     const int nfk = P.periodic[k] ? nk : nk + 1;           // faces along k per line
@@ -426,11 +432,11 @@ __global__ void k_face(const Tables *__restrict__ T, Prob P, const double *__res
             rem /= n;
         }
     }
-    double acc[NV];
+    R acc[NV];
 #pragma unroll
-    for (int v = 0; v < NV; v++) acc[v] = 0.0;
+    for (int v = 0; v < NV; v++) acc[v] = 0;
     for (int s = 0; s < n; s++) {
-        double qL[NV], qR[NV], G[NV];
+        R qL[NV], qR[NV], G[NV];
         if (hasL) {
 #pragma unroll
             for (int v = 0; v < NV; v++) qL[v] = trace[((cL * 2 * DIM + 2 * k + 1) * NV + v) * (NFN * n) + ap + NFN * s];
@@ -440,11 +446,21 @@ __global__ void k_face(const Tables *__restrict__ T, Prob P, const double *__res
             for (int v = 0; v < NV; v++) qR[v] = trace[((cR * 2 * DIM + 2 * k) * NV + v) * (NFN * n) + ap + NFN * s];
         }
         const double ts = t0 + T->xi[s] * dt;
-        if (!hasL) bc_ghost<DIM>(P, k, 0, qR, x, ts, qL);
-        if (!hasR) bc_ghost<DIM>(P, k, 1, qL, x, ts, qR);
-        rusanov<DIM>(k, qL, qR, G, P.gamma);
+        if (!hasL || !hasR) {
+            double qi[NV], qo[NV];
 #pragma unroll
-        for (int v = 0; v < NV; v++) acc[v] += T->w[s] * G[v];
+            for (int v = 0; v < NV; v++) qi[v] = hasL ? (double)qL[v] : (double)qR[v];
+            bc_ghost<DIM>(P, k, hasL ? 1 : 0, qi, x, ts, qo);
+#pragma unroll
+            for (int v = 0; v < NV; v++) {
+                if (hasL) qR[v] = (R)qo[v];
+                else qL[v] = (R)qo[v];
+            }
+        }
+        rusanov<DIM, R>(k, qL, qR, G, (R)P.gamma);
+        const R ws = std::is_same<R, double>::value ? (R)T->w[s] : (R)T->fw[s];
+#pragma unroll
+        for (int v = 0; v < NV; v++) acc[v] += ws * G[v];
     }
     if (hasL) {
 #pragma unroll
@@ -501,9 +517,10 @@ __device__ void tensor_apply(const double *Mbase, int mstride, int m, int n, int
 // ------------------------------------------- corrector + scatter + detection
 // Candidate of eq. (pde.nc.gw2) (face terms added to the volume-term candidate), then
 // v* = P(u*) (eq. (subcell.p)) and the PAD / relaxed-DMP tests of Sec. 4.3.
-template <int DIM, int N>
+template <int DIM, int N, typename R>
 __global__ __launch_bounds__(128) void k_corrector_detect(const Tables *__restrict__ T, Prob P, Bufs B, int cur,
                                                           int limiter) {
+    const R *gbar = reinterpret_cast<const R *>(B.gbar);
     constexpr int n = N + 1, NV = DIM + 2, NN = cpow(n, DIM), NFN = cpow(n, DIM - 1);
     constexpr int NS = 2 * N + 1, NSUB = cpow(NS, DIM);
     constexpr int BIG = cpow(NS, DIM) > cpow(n, DIM) ? cpow(NS, DIM) : cpow(n, DIM);
@@ -529,9 +546,11 @@ __global__ __launch_bounds__(128) void k_corrector_detect(const Tables *__restri
                 mul *= n;
             }
             const int ak = m[k];
-            const double Gm = B.gbar[((c * 2 * DIM + 2 * k) * NV + v) * NFN + ap];
-            const double Gp = B.gbar[((c * 2 * DIM + 2 * k + 1) * NV + v) * NFN + ap];
-            val += dt / P.h[k] / T->w[ak] * (T->L[ak] * Gm - T->R[ak] * Gp);
+            const R Gm = gbar[((c * 2 * DIM + 2 * k) * NV + v) * NFN + ap];
+            const R Gp = gbar[((c * 2 * DIM + 2 * k + 1) * NV + v) * NFN + ap];
+            // face increment in the working precision R, added to the FP64 candidate
+            const R coef = (R)(dt / P.h[k] / T->w[ak]);
+            val += (double)(coef * ((R)T->L[ak] * Gm - (R)T->R[ak] * Gp));
         }
         un[((int64_t)v * P.ncell + c) * NN + a] = val;
         us[it] = val;
@@ -1213,8 +1232,9 @@ __global__ __launch_bounds__(256) void k_sub_update(const Tables *__restrict__ T
 // Flux correction of unlimited cells next to troubled cells (Sec. 4.4): the DG face
 // flux of each face shared with a troubled cell is replaced by the subcell fluxes of
 // that face, each integrated against the basis (P[sigma][a] / (Ns w_a) per tangential axis).
-template <int DIM, int N>
+template <int DIM, int N, typename R>
 __global__ __launch_bounds__(128) void k_fluxcorr(const Tables *__restrict__ T, Prob P, Bufs B, int cur) {
+    const R *gbar = reinterpret_cast<const R *>(B.gbar);
     constexpr int n = N + 1, NV = DIM + 2, NN = cpow(n, DIM), NFN = cpow(n, DIM - 1);
     constexpr int NS = 2 * N + 1, NSF = cpow(NS, DIM - 1);
     const int64_t c = B.clist[blockIdx.x];
@@ -1268,7 +1288,7 @@ __global__ __launch_bounds__(128) void k_fluxcorr(const Tables *__restrict__ T, 
                     }
                     Fsub += wgt * fs[sp];
                 }
-                const double Gdg = B.gbar[((c * 2 * DIM + 2 * k + side) * NV + v) * NFN + ap];
+                const double Gdg = (double)gbar[((c * 2 * DIM + 2 * k + side) * NV + v) * NFN + ap];
                 val += side ? ck * T->R[ak] * (Gdg - Fsub) : ck * T->L[ak] * (Fsub - Gdg);
             }
         }
@@ -1325,30 +1345,45 @@ struct Launch {
     static constexpr int n = N + 1, NV = DIM + 2, NN = cpow(n, DIM), NS = 2 * N + 1;
     static constexpr int NPOS = cpow(NS, DIM) + 2 * DIM * cpow(NS, DIM - 1);
 
-    static void predictor(const StepCtx &C) {
-        using S = PredShape<DIM, N>;
-        PredArgs A;
+    template <typename R>
+    static void predictor_t(const StepCtx &C) {
+        using S = PredShape<DIM, N, R>;
+        PredArgs<R> A;
         A.in = C.B.u[C.cur];
         A.in_cstride = NN;
         A.in_vstride = (int64_t)C.P.ncell * NN;
-        A.trace = C.B.trace;
+        A.trace = reinterpret_cast<R *>(C.B.trace);
         A.vol_out = C.B.u[C.cur ^ 1];
         A.ncell = C.P.ncell;
         A.cell0 = 0;
         A.iters = C.picard_iters;
         for (int k = 0; k < 3; k++) A.dth[k] = k < DIM ? 1.0 / C.P.h[k] : 0.0;
         A.dt = C.B.scal;
-        A.D = &C.tab->D[0][0];
-        A.Kw = &C.tab->Kw[0][0];
-        A.Lb = C.tab->L;
-        A.Rb = C.tab->R;
-        A.w = C.tab->w;
-        A.Dvol = &C.tab->Dvol[0][0];
+        if constexpr (std::is_same<R, double>::value) {
+            A.D = &C.tab->D[0][0];
+            A.Kw = &C.tab->Kw[0][0];
+            A.Lb = C.tab->L;
+            A.Rb = C.tab->R;
+            A.w = C.tab->w;
+            A.Dvol = &C.tab->Dvol[0][0];
+        } else {
+            A.D = &C.tab->fD[0][0];
+            A.Kw = &C.tab->fKw[0][0];
+            A.Lb = C.tab->fL;
+            A.Rb = C.tab->fR;
+            A.w = C.tab->fw;
+            A.Dvol = &C.tab->fDvol[0][0];
+        }
         const int64_t grid = (C.P.ncell + S::CPB - 1) / S::CPB;
-        hipLaunchKernelGGL((k_predictor<DIM, N, true>), dim3((unsigned)grid), dim3(S::BS), 0, C.stream, C.tab, A,
+        hipLaunchKernelGGL((k_predictor<DIM, N, true, R>), dim3((unsigned)grid), dim3(S::BS), 0, C.stream, C.tab, A,
                            C.P.gamma);
     }
-    static void faces(const StepCtx &C) {
+    static void predictor(const StepCtx &C) {
+        if (C.precision == ADG_MIXED) predictor_t<float>(C);
+        else predictor_t<double>(C);
+    }
+    template <typename R>
+    static void faces_t(const StepCtx &C) {
         constexpr int NFN = cpow(n, DIM - 1);
         for (int k = 0; k < DIM; k++) {
             int64_t nlines = 1;
@@ -1356,13 +1391,22 @@ struct Launch {
                 if (j != k) nlines *= C.P.nc[j];
             const int nfk = C.P.periodic[k] ? C.P.nc[k] : C.P.nc[k] + 1;
             const int64_t total = nlines * nfk * NFN;
-            hipLaunchKernelGGL((k_face<DIM, N>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, C.stream, C.tab,
-                               C.P, C.B.trace, C.B.gbar, C.B.scal, k);
+            hipLaunchKernelGGL((k_face<DIM, N, R>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, C.stream,
+                               C.tab, C.P, reinterpret_cast<const R *>(C.B.trace), reinterpret_cast<R *>(C.B.gbar),
+                               C.B.scal, k);
         }
     }
+    static void faces(const StepCtx &C) {
+        if (C.precision == ADG_MIXED) faces_t<float>(C);
+        else faces_t<double>(C);
+    }
     static void corrector_detect(const StepCtx &C) {
-        hipLaunchKernelGGL((k_corrector_detect<DIM, N>), dim3((unsigned)C.P.ncell), dim3(128), 0, C.stream, C.tab, C.P,
-                           C.B, C.cur, C.limiter);
+        if (C.precision == ADG_MIXED)
+            hipLaunchKernelGGL((k_corrector_detect<DIM, N, float>), dim3((unsigned)C.P.ncell), dim3(128), 0, C.stream,
+                               C.tab, C.P, C.B, C.cur, C.limiter);
+        else
+            hipLaunchKernelGGL((k_corrector_detect<DIM, N, double>), dim3((unsigned)C.P.ncell), dim3(128), 0, C.stream,
+                               C.tab, C.P, C.B, C.cur, C.limiter);
     }
     static void bounds(const StepCtx &C) {
         int64_t next = 1;
@@ -1377,8 +1421,8 @@ struct Launch {
         const int64_t npos = (int64_t)count * NPOS;
         hipLaunchKernelGGL((k_sub_recon<DIM, N>), dim3((unsigned)((npos + 127) / 128)), dim3(128), 0, C.stream, C.tab,
                            C.B, count);
-        using S = PredShape<DIM, 2>;
-        PredArgs A;
+        using S = PredShape<DIM, 2, double>;
+        PredArgs<double> A;
         A.in = C.B.Y;
         A.in_cstride = NV * cpow(3, DIM);
         A.in_vstride = cpow(3, DIM);
@@ -1396,13 +1440,18 @@ struct Launch {
         A.w = C.tab->w3;
         A.Dvol = nullptr;
         const int64_t grid = (npos + S::CPB - 1) / S::CPB;
-        hipLaunchKernelGGL((k_predictor<DIM, 2, false>), dim3((unsigned)grid), dim3(S::BS), 0, C.stream, C.tab, A,
-                           C.P.gamma);
+        hipLaunchKernelGGL((k_predictor<DIM, 2, false, double>), dim3((unsigned)grid), dim3(S::BS), 0, C.stream,
+                           C.tab, A, C.P.gamma);
         hipLaunchKernelGGL((k_sub_update<DIM, N>), dim3(count), dim3(256), 0, C.stream, C.tab, C.P, C.B, C.cur, first,
                            C.B.counts + 2);
     }
     static void fluxcorr(const StepCtx &C, int count) {
-        hipLaunchKernelGGL((k_fluxcorr<DIM, N>), dim3(count), dim3(128), 0, C.stream, C.tab, C.P, C.B, C.cur);
+        if (C.precision == ADG_MIXED)
+            hipLaunchKernelGGL((k_fluxcorr<DIM, N, float>), dim3(count), dim3(128), 0, C.stream, C.tab, C.P, C.B,
+                               C.cur);
+        else
+            hipLaunchKernelGGL((k_fluxcorr<DIM, N, double>), dim3(count), dim3(128), 0, C.stream, C.tab, C.P, C.B,
+                               C.cur);
     }
     static void lambda(const StepCtx &C, const double *u, double factor) {
         const int64_t total = C.P.ncell * NN;

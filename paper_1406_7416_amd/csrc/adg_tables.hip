@@ -180,6 +180,16 @@ void build_tables(int N, int Ns, Tables *T) {
     B3.eval(0.0, T->L3);
     B3.eval(1.0, T->R3);
     time_operator(3, T->w3, T->D3, T->R3, T->Kw3);
+    for (int a = 0; a < MAXN; a++) {
+        T->fL[a] = (float)T->L[a];
+        T->fR[a] = (float)T->R[a];
+        T->fw[a] = (float)T->w[a];
+        for (int b = 0; b < MAXN; b++) {
+            T->fD[a][b] = (float)T->D[a][b];
+            T->fKw[a][b] = (float)T->Kw[a][b];
+            T->fDvol[a][b] = (float)T->Dvol[a][b];
+        }
+    }
     // WENO3 stencils {j-2..j}, {j-1..j+1}, {j..j+2}: the quadratic c0 + c1 x + c2 x^2 on
     // the central subcell (x in [0,1]) with the three given averages.
     for (int st = 0; st < 3; st++) {

@@ -1,0 +1,77 @@
+"""Mixed-precision form (FP32 predictor, face fluxes and increments; FP64 state,
+update addition, detection, projection/reconstruction, time step and subcell path)
+against the FP64 oracle.
+
+Tolerance: the FP32 part only enters through the increment du = u^{n+1} - u^n, whose
+relative rounding error is a small multiple of the FP32 unit round-off (2^-24 = 6e-8)
+times the contraction lengths; the state error per step is therefore bounded by
+about 1e-5 * max|du| and, for these workloads, far below 1e-6 of the state's scale.
+The bound used per step is 2e-6 relative to each variable's scale, and the troubled
+maps may differ only in cells whose oracle detection margin is below 1e-4."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1406_7416_amd import workloads as W
+from test_gpu_parity import rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def paired_mixed(wl, m=None, detect=True, mask=None):
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1406_7416_amd import adg
+    o = O.Oracle(wl)
+    u, v = o.project(wl.ic, wl.N + 1 if m is None else m)
+    o.set_state(u, v if detect else None)
+    g = adg.Problem(wl, precision=adg.ADG_MIXED)
+    g.set_state(u, v if detect else None)
+    if mask is not None:
+        o.force_troubled(mask)
+        g.force_troubled(mask)
+    return o, g
+
+
+def run_mixed(o, g, steps, tol=2e-6):
+    worst = 0.0
+    for s in range(steps):
+        u_before = o.state()
+        dt = o.cfl_dt()
+        o.step(dt)
+        g.step(dt)
+        uo, ug = o.state(), g.state()
+        e = rel_err(ug, uo)
+        du = np.abs(uo - u_before).max()
+        worst = max(worst, e)
+        bo, bg = o.troubled(), g.troubled()
+        diff = np.nonzero(bo != bg)[0]
+        if len(diff):
+            assert np.all(np.abs(o.margin()[diff]) < 1e-4), f"step {s}: flags differ away from the margin"
+            return worst, s
+        assert e < tol, f"step {s}: rel err {e} (max|du| {du})"
+    return worst, steps
+
+
+@pytest.mark.parametrize("N,n", [(9, 8), (5, 10), (3, 16)])
+def test_mixed_vortex(N, n):
+    o, g = paired_mixed(W.vortex(n, N), m=0)
+    worst, _ = run_mixed(o, g, 4)
+    assert worst > 0  # the mixed form really computes in reduced precision
+
+
+def test_mixed_explosion_with_limiter():
+    o, g = paired_mixed(W.explosion_2d(20, 3))
+    run_mixed(o, g, 5)
+    assert o.troubled().sum() > 0
+
+
+def test_mixed_forced_troubled_conservation():
+    wl = W.vortex(8, 3)
+    o, g = paired_mixed(wl, mask=W.random_mask(wl.num_cells, 0.3, seed=1))
+    run_mixed(o, g, 3)
+
+
+def test_mixed_3d_explosion():
+    o, g = paired_mixed(W.explosion_3d(6, 2))
+    run_mixed(o, g, 2)

@@ -41,8 +41,10 @@ struct adg_problem {
     // offsets into the workspace
     struct Off {
         size_t tab, u0, u1, emin, emax, bmin, bmax, trace, gbar, beta0, beta1, force, margin, tlist, clist, slot0,
-            slot1, pool0, pool1, sflux, blk, counts, scal, lampart, halo, Y, strace, end;
+            slot1, pool0, pool1, sflux, blk, counts, scal, lampart, ring, halo, Y, strace, end;
     } off;
+    int64_t nring = 0;       // ghost-ring cells of the extended grid
+    bool bounds_valid = false;  // interior old-time bounds were written by the previous step
     // bound state
     char *ws = nullptr;
     hipStream_t stream = nullptr;
@@ -51,6 +53,7 @@ struct adg_problem {
     int cur = 0;
     bool bound = false, has_state = false;
     int *pinned = nullptr;    // host-pinned copy of the counters
+    hipEvent_t counts_ready = nullptr;   // recorded after the asynchronous counter copy
     int64_t last_troubled = 0, last_corrected = 0, steps = 0;
     // kernel-group timing
     bool profiling = false;
@@ -116,7 +119,9 @@ static void plan(adg_problem *pb) {
     const int64_t nblk = (nc + 255) / 256;
     const int64_t hsz = ipow64(Ns + 6, d), n3 = ipow64(3, d), nf3 = ipow64(3, d - 1);
     const int64_t per_chunk_cell = (nv * hsz + pb->npos * nv * n3 + pb->npos * 2 * d * nv * nf3 * 3) * 8;
-    int64_t chunk = std::max<int64_t>(16, (int64_t)(512ll << 20) / per_chunk_cell);
+    // subcell scratch: up to 4 GB; when it covers the whole pool capacity the step runs
+    // without a host wait (the subcell kernels read the troubled count on the device)
+    int64_t chunk = std::max<int64_t>(16, (int64_t)(4096ll << 20) / per_chunk_cell);
     chunk = std::min<int64_t>(chunk, std::max<int64_t>(1, pb->cap));
     chunk = std::min<int64_t>(chunk, 65535);
     pb->chunk = (int)chunk;
@@ -152,6 +157,12 @@ static void plan(adg_problem *pb) {
     f.counts = take(4ull * 8);
     f.scal = take(8ull * 8);
     f.lampart = take(8ull * 1024);
+    {
+        int64_t inner = 1;
+        for (int j = 0; j < d; j++) inner *= P.nc[j];
+        pb->nring = next - inner;
+    }
+    f.ring = take(8ull * std::max<int64_t>(1, pb->nring));
     f.halo = take(8ull * chunk * nv * hsz);
     f.Y = take(8ull * chunk * pb->npos * nv * n3);
     f.strace = take(8ull * chunk * pb->npos * 2 * d * nv * nf3 * 3);
@@ -187,6 +198,7 @@ static void carve(adg_problem *pb) {
     B.counts = (int *)(w + f.counts);
     B.scal = (double *)(w + f.scal);
     B.lam_part = (double *)(w + f.lampart);
+    B.ring = (int64_t *)(w + f.ring);
     B.halo = (double *)(w + f.halo);
     B.Y = (double *)(w + f.Y);
     B.strace = (double *)(w + f.strace);
@@ -205,6 +217,8 @@ static StepCtx ctx(const adg_problem *pb) {
     C.capacity = pb->cap;
     C.lam_blocks = pb->lam_blocks;
     C.precision = pb->prm.precision;
+    C.ring_only = pb->bounds_valid ? 1 : 0;
+    C.nring = pb->nring;
     return C;
 }
 
@@ -304,6 +318,7 @@ int adg_destroy(adg_problem *pb) {
         (void)hipEventDestroy(m.b);
     }
     for (auto e : pb->spare) (void)hipEventDestroy(e);
+    if (pb->counts_ready) (void)hipEventDestroy(pb->counts_ready);
     if (pb->pinned) (void)hipHostFree(pb->pinned);
     delete pb;
     return ADG_OK;
@@ -320,6 +335,24 @@ int adg_bind(adg_problem *pb, void *dev_workspace, size_t bytes, void *hip_strea
     carve(pb);
     if (!pb->pinned) HIPCHK(hipHostMalloc((void **)&pb->pinned, 64, hipHostMallocDefault));
     HIPCHK(hipMemcpyAsync(pb->tab_dev, &pb->tab_host, sizeof(Tables), hipMemcpyHostToDevice, pb->stream));
+    {
+        // extended-grid indices of the one-cell ghost ring, x fastest
+        const Prob &P = pb->P;
+        std::vector<int64_t> ring;
+        ring.reserve(pb->nring);
+        const int64_t ne0 = P.nc[0] + 2, ne1 = P.dim > 1 ? P.nc[1] + 2 : 1, ne2 = P.dim > 2 ? P.nc[2] + 2 : 1;
+        for (int64_t k = 0; k < ne2; k++)
+            for (int64_t j = 0; j < ne1; j++)
+                for (int64_t i = 0; i < ne0; i++) {
+                    const bool ghost = i == 0 || i == ne0 - 1 || j == 0 || j == ne1 - 1 ||
+                                       (P.dim > 2 && (k == 0 || k == ne2 - 1));
+                    if (ghost) ring.push_back(i + ne0 * (j + ne1 * k));
+                }
+        if ((int64_t)ring.size() != pb->nring) return fail(ADG_EINVAL, "internal: ghost ring size");
+        if (pb->nring)
+            HIPCHK(hipMemcpyAsync(pb->B.ring, ring.data(), 8 * ring.size(), hipMemcpyHostToDevice, pb->stream));
+        HIPCHK(hipStreamSynchronize(pb->stream));
+    }
     HIPCHK(hipMemsetAsync(pb->B.counts, 0, 32, pb->stream));
     HIPCHK(hipMemsetAsync(pb->B.scal, 0, 64, pb->stream));
     HIPCHK(hipMemsetAsync(pb->B.force, 0, pb->P.ncell, pb->stream));
@@ -582,6 +615,7 @@ int adg_set_state(adg_problem *pb, const double *u, int on_device, const double 
     HIPCHK(hipMemsetAsync(pb->B.counts, 0, 32, pb->stream));
     HIPCHK(hipStreamSynchronize(pb->stream));
     pb->has_state = true;
+    pb->bounds_valid = false;
     pb->last_troubled = count;
     pb->last_corrected = 0;
     pb->steps = 0;
@@ -620,6 +654,9 @@ int adg_cfl_dt(adg_problem *pb, double cfl, double *dt_out) {
 static int do_step(adg_problem *pb) {
     StepCtx C = ctx(pb);
     Bufs &B = pb->B;
+    if (pb->counts_ready && hipEventQuery(pb->counts_ready) == hipSuccess && pb->pinned[3])
+        return fail(ADG_ECAPACITY, "troubled cells exceeded the pool capacity %lld in an earlier step",
+                    (long long)pb->cap);
     if (pb->prm.limiter) {
         GroupTimer g(pb, 0);
         launch_bounds(C);
@@ -645,32 +682,53 @@ static int do_step(adg_problem *pb) {
             launch_compact(C);
         }
         HIPCHK(hipGetLastError());
-        HIPCHK(hipMemcpyAsync(pb->pinned, B.counts, 16, hipMemcpyDeviceToHost, pb->stream));
-        HIPCHK(hipStreamSynchronize(pb->stream));
-        if (pb->profiling) harvest(pb);
-        troubled = pb->pinned[0];
-        corrected = pb->pinned[1];
-        if (troubled > pb->cap) rc = fail(ADG_ECAPACITY, "%lld troubled cells exceed pool capacity %lld",
-                                          (long long)troubled, (long long)pb->cap);
-        const int64_t todo = std::min<int64_t>(troubled, pb->cap);
-        if (todo > 0) {
-            GroupTimer g(pb, 5);
-            for (int64_t first = 0; first < todo; first += pb->chunk) {
-                const int cnt = (int)std::min<int64_t>(pb->chunk, todo - first);
-                launch_subcell_chunk(C, (int)first, cnt);
+        if (pb->chunk >= pb->cap) {
+            // device-driven: no host wait; the counts stay on the device
+            {
+                GroupTimer g(pb, 5);
+                launch_subcell_chunk(C, 0, -1);
             }
-        }
-        if (corrected > 0) {
-            GroupTimer g(pb, 6);
-            launch_fluxcorr(C, (int)corrected);
+            {
+                GroupTimer g(pb, 6);
+                launch_fluxcorr(C, -1);
+            }
+            troubled = corrected = -1;
+        } else {
+            HIPCHK(hipMemcpyAsync(pb->pinned, B.counts, 16, hipMemcpyDeviceToHost, pb->stream));
+            HIPCHK(hipStreamSynchronize(pb->stream));
+            if (pb->profiling) harvest(pb);
+            troubled = pb->pinned[0];
+            corrected = pb->pinned[1];
+            if (troubled > pb->cap) rc = fail(ADG_ECAPACITY, "%lld troubled cells exceed pool capacity %lld",
+                                              (long long)troubled, (long long)pb->cap);
+            const int64_t todo = std::min<int64_t>(troubled, pb->cap);
+            if (todo > 0) {
+                GroupTimer g(pb, 5);
+                for (int64_t first = 0; first < todo; first += pb->chunk) {
+                    const int cnt = (int)std::min<int64_t>(pb->chunk, todo - first);
+                    launch_subcell_chunk(C, (int)first, cnt);
+                }
+            }
+            if (corrected > 0) {
+                GroupTimer g(pb, 6);
+                launch_fluxcorr(C, (int)corrected);
+            }
         }
         HIPCHK(hipGetLastError());
         std::swap(B.beta[0], B.beta[1]);
         std::swap(B.slot[0], B.slot[1]);
         std::swap(B.pool[0], B.pool[1]);
+        // every interior cell's next old-time bounds were written by this step's kernels
+        pb->bounds_valid = true;
     }
     launch_advance_time(C);
     HIPCHK(hipGetLastError());
+    if (pb->prm.limiter && troubled < 0) {
+        // asynchronous copy of the counters (read by adg_get_stats and the next step)
+        HIPCHK(hipMemcpyAsync(pb->pinned, B.counts, 16, hipMemcpyDeviceToHost, pb->stream));
+        if (!pb->counts_ready) HIPCHK(hipEventCreateWithFlags(&pb->counts_ready, hipEventDisableTiming));
+        HIPCHK(hipEventRecord(pb->counts_ready, pb->stream));
+    }
     pb->cur ^= 1;
     pb->last_troubled = troubled;
     pb->last_corrected = corrected;
@@ -756,8 +814,8 @@ int adg_get_stats(const adg_problem *pb, int64_t *out4) {
     int cnt[4];
     HIPCHK(hipMemcpyAsync(cnt, pb->B.counts, sizeof cnt, hipMemcpyDeviceToHost, pb->stream));
     HIPCHK(hipStreamSynchronize(pb->stream));
-    out4[0] = pb->last_troubled;
-    out4[1] = pb->last_corrected;
+    out4[0] = pb->last_troubled >= 0 ? pb->last_troubled : cnt[0];
+    out4[1] = pb->last_corrected >= 0 ? pb->last_corrected : cnt[1];
     out4[2] = cnt[2];
     out4[3] = pb->steps;
     return ADG_OK;

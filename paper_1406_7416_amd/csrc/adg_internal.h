@@ -65,6 +65,7 @@ struct Bufs {
     int *counts;           // [0] troubled [1] corrected [2] nonphysical cumulative [3] capacity overflow
     double *scal;          // [0] dt [1] t [2] lambda_max ...
     double *lam_part;      // per-block lambda partials
+    int64_t *ring;         // extended-grid indices of the ghost ring
     // subcell chunk scratch
     double *halo;          // [chunk][v][(Ns+6)^d]
     double *Y;             // [chunk][pos][v][3^d]

@@ -15,6 +15,8 @@ struct StepCtx {
     int64_t capacity;      // pool slots
     int lam_blocks;        // blocks of the lambda reduction
     int precision;         // ADG_FP64 or ADG_MIXED
+    int ring_only;         // bounds pass over the ghost ring only
+    int64_t nring;         // ghost-ring cells
 };
 
 bool supported(int dim, int N);

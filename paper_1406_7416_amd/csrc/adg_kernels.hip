@@ -8,6 +8,7 @@
 //
 // Parallel mapping: every kernel is element-local or face-local and writes each output
 // from exactly one thread (no atomics on data), so results are bitwise reproducible.
+#include <algorithm>
 #include <cmath>
 #include <type_traits>
 #include "adg_internal.h"
@@ -127,6 +128,10 @@ struct PredArgs {
     const double *dt;      // device scalar
     // operators of the n-node basis used by this launch (row stride MAXN)
     const R *D, *Kw, *Lb, *Rb, *w, *Dvol;
+    // if set, the number of cells is min(*dcount, dcap) * dmult (read on the device)
+    const int *dcount;
+    int64_t dcap;
+    int dmult;
 };
 
 // Contraction along axis k of every line held in LDS: line[i] <- c * sum_b M[i][b] line[b].
@@ -193,9 +198,12 @@ __global__ __launch_bounds__((PredShape<DIM, N, R>::BS), 2) void k_predictor(con
 
     const int tid = threadIdx.x;
     const int lc = tid / NN, a = tid % NN;
-    const int64_t c = (int64_t)blockIdx.x * CPB + lc;
-    const bool owner = (tid < S::ACT) && (c < A.ncell);
     const double dt = *A.dt;
+    int64_t ncell = A.ncell;
+    if (A.dcount) {
+        const int64_t cnt = *A.dcount;
+        ncell = (cnt < A.dcap ? cnt : A.dcap) * A.dmult;
+    }
     for (int i = tid; i < n * n; i += S::BS) {
         const int r = i / n, cc = i % n;
         Ds[r][cc] = A.D[r * MAXN + cc];
@@ -207,6 +215,10 @@ __global__ __launch_bounds__((PredShape<DIM, N, R>::BS), 2) void k_predictor(con
     const R(*Kw)[MAXN] = Kws;
     const R(*Dvol)[MAXN] = Dvs;
     (void)T;
+    // persistent over blocks of CPB cells (uniform per block: barriers stay legal)
+    for (int64_t vb = blockIdx.x; vb * CPB < ncell; vb += gridDim.x) {
+    const int64_t c = vb * CPB + lc;
+    const bool owner = (tid < S::ACT) && (c < ncell);
 
     double u0d[NV];
     R u0[NV], q[NV][n], Sacc[NV][n];
@@ -361,8 +373,8 @@ __global__ __launch_bounds__((PredShape<DIM, N, R>::BS), 2) void k_predictor(con
             const int j = rem0 % (NFN * n);   // ap + NFN*s
             const int s = j / NFN, ap = j % NFN;
             const int k = face >> 1, side = face & 1;
-            const int64_t cc = (int64_t)blockIdx.x * CPB + lcl;
-            if (cc >= A.ncell || v0 + vv >= NV) continue;
+            const int64_t cc = vb * CPB + lcl;
+            if (cc >= ncell || v0 + vv >= NV) continue;
             int base = 0, rem = ap, mul = 1;
 #pragma unroll
             for (int jj = 0; jj < DIM; jj++) {
@@ -381,61 +393,72 @@ __global__ __launch_bounds__((PredShape<DIM, N, R>::BS), 2) void k_predictor(con
         }
         __syncthreads();
     }
+    }  // persistent loop
 }
 
 // ------------------------------------------------------------------- face fluxes
-// One thread per (face, tangential node): time-integrated Rusanov flux, written into
+// One thread per (face, tangential node, time node): Rusanov flux weighted by the time
+// quadrature weight; the time sum is then taken in LDS in fixed order and written into
 // the slot of both adjacent cells.
+template <int DIM, int N>
+struct FaceShape {
+    static constexpr int n = N + 1, NFN = cpow(n, DIM - 1), PER = NFN * n;
+    static constexpr int FPB = PER >= 256 ? 1 : 256 / PER;   // faces per block
+    static constexpr int BS = ((FPB * PER + 63) / 64) * 64;
+};
+
 template <int DIM, int N, typename R>
-__global__ void k_face(const Tables *__restrict__ T, Prob P, const R *__restrict__ trace, R *__restrict__ gbar,
-                       const double *__restrict__ scal, int k) {
-    constexpr int n = N + 1, NV = DIM + 2, NFN = cpow(n, DIM - 1);
+__global__ __launch_bounds__((FaceShape<DIM, N>::BS)) void k_face(const Tables *__restrict__ T, Prob P,
+                                                                 const R *__restrict__ trace, R *__restrict__ gbar,
+                                                                 const double *__restrict__ scal, int k) {
+    using FS = FaceShape<DIM, N>;
+    constexpr int n = N + 1, NV = DIM + 2, NFN = FS::NFN, PER = FS::PER, FPB = FS::FPB;
+    __shared__ R part[FPB * PER * NV];
     const int nk = P.nc[k];
     const int nfk = P.periodic[k] ? nk : nk + 1;           // faces along k per line
     int64_t nlines = 1;
     for (int j = 0; j < DIM; j++)
         if (j != k) nlines *= P.nc[j];
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t total = nlines * nfk * NFN;
-    if (gid >= total) return;
-    const int ap = (int)(gid % NFN);
-    const int64_t fidx = gid / NFN;
-    const int fk = (int)(fidx % nfk);
-    int64_t line = fidx / nfk;
-    int ci[3] = {0, 0, 0};
-    for (int j = 0; j < DIM; j++) {
-        if (j == k) continue;
-        ci[j] = (int)(line % P.nc[j]);
-        line /= P.nc[j];
-    }
-    // left cell index fk-1, right cell fk (wrapping when periodic)
-    int cl[3] = {ci[0], ci[1], ci[2]}, cr[3] = {ci[0], ci[1], ci[2]};
-    cl[k] = fk - 1;
-    cr[k] = fk;
-    bool hasL = true, hasR = true;
-    if (cl[k] < 0) {
-        if (P.periodic[k]) cl[k] += nk; else hasL = false;
-    }
-    if (cr[k] >= nk) hasR = false;
-    const int64_t cL = hasL ? cell_of(P, cl) : -1, cR = hasR ? cell_of(P, cr) : -1;
-    const double dt = scal[0], t0 = scal[1];
-    // node position on the face (for boundary states)
-    double x[3] = {0, 0, 0};
-    {
-        int rem = ap;
-        for (int j = 0; j < DIM; j++) {
-            if (j == k) {
-                x[j] = P.lo[j] + P.h[j] * fk;
-                continue;
-            }
-            x[j] = P.lo[j] + P.h[j] * (ci[j] + T->xi[rem % n]);
-            rem /= n;
+    const int64_t nfaces = nlines * nfk;
+    const int lf = threadIdx.x / PER, j = threadIdx.x % PER;
+    const int s = j / NFN, ap = j % NFN;
+    const int64_t fidx = (int64_t)blockIdx.x * FPB + lf;
+    const bool active = lf < FPB && fidx < nfaces;
+    int64_t cL = -1, cR = -1;
+    bool hasL = false, hasR = false;
+    if (active) {
+        const int fk = (int)(fidx % nfk);
+        int64_t line = fidx / nfk;
+        int ci[3] = {0, 0, 0};
+        for (int jj = 0; jj < DIM; jj++) {
+            if (jj == k) continue;
+            ci[jj] = (int)(line % P.nc[jj]);
+            line /= P.nc[jj];
         }
-    }
-    R acc[NV];
-#pragma unroll
-    for (int v = 0; v < NV; v++) acc[v] = 0;
-    for (int s = 0; s < n; s++) {
+        int cl[3] = {ci[0], ci[1], ci[2]}, cr[3] = {ci[0], ci[1], ci[2]};
+        cl[k] = fk - 1;
+        cr[k] = fk;
+        hasL = hasR = true;
+        if (cl[k] < 0) {
+            if (P.periodic[k]) cl[k] += nk; else hasL = false;
+        }
+        if (cr[k] >= nk) hasR = false;
+        cL = hasL ? cell_of(P, cl) : -1;
+        cR = hasR ? cell_of(P, cr) : -1;
+        const double dt = scal[0], t0 = scal[1];
+        // node position on the face (for boundary states)
+        double x[3] = {0, 0, 0};
+        {
+            int rem = ap;
+            for (int jj = 0; jj < DIM; jj++) {
+                if (jj == k) {
+                    x[jj] = P.lo[jj] + P.h[jj] * fk;
+                    continue;
+                }
+                x[jj] = P.lo[jj] + P.h[jj] * (ci[jj] + T->xi[rem % n]);
+                rem /= n;
+            }
+        }
         R qL[NV], qR[NV], G[NV];
         if (hasL) {
 #pragma unroll
@@ -445,8 +468,8 @@ __global__ void k_face(const Tables *__restrict__ T, Prob P, const R *__restrict
 #pragma unroll
             for (int v = 0; v < NV; v++) qR[v] = trace[((cR * 2 * DIM + 2 * k) * NV + v) * (NFN * n) + ap + NFN * s];
         }
-        const double ts = t0 + T->xi[s] * dt;
         if (!hasL || !hasR) {
+            const double ts = t0 + T->xi[s] * dt;
             double qi[NV], qo[NV];
 #pragma unroll
             for (int v = 0; v < NV; v++) qi[v] = hasL ? (double)qL[v] : (double)qR[v];
@@ -460,53 +483,137 @@ __global__ void k_face(const Tables *__restrict__ T, Prob P, const R *__restrict
         rusanov<DIM, R>(k, qL, qR, G, (R)P.gamma);
         const R ws = std::is_same<R, double>::value ? (R)T->w[s] : (R)T->fw[s];
 #pragma unroll
-        for (int v = 0; v < NV; v++) acc[v] += ws * G[v];
+        for (int v = 0; v < NV; v++) part[(lf * PER + j) * NV + v] = ws * G[v];
     }
-    if (hasL) {
+    __syncthreads();
+    if (active && s == 0) {
+        R acc[NV];
 #pragma unroll
-        for (int v = 0; v < NV; v++) gbar[((cL * 2 * DIM + 2 * k + 1) * NV + v) * NFN + ap] = acc[v];
+        for (int v = 0; v < NV; v++) acc[v] = 0;
+        for (int ss = 0; ss < n; ss++)
+#pragma unroll
+            for (int v = 0; v < NV; v++) acc[v] += part[(lf * PER + ap + NFN * ss) * NV + v];
+        if (hasL) {
+#pragma unroll
+            for (int v = 0; v < NV; v++) gbar[((cL * 2 * DIM + 2 * k + 1) * NV + v) * NFN + ap] = acc[v];
+        }
+        if (hasR) {
+#pragma unroll
+            for (int v = 0; v < NV; v++) gbar[((cR * 2 * DIM + 2 * k) * NV + v) * NFN + ap] = acc[v];
+        }
     }
-    if (hasR) {
+}
+
+// Block-wide reduction of per-thread (min, max) pairs of NV variables: wave shuffles,
+// then one LDS exchange between waves.  The result is valid in thread 0.
+template <int NV>
+__device__ __forceinline__ void block_minmax(double *lo, double *hi, int tid, int bs, double *scratch) {
 #pragma unroll
-        for (int v = 0; v < NV; v++) gbar[((cR * 2 * DIM + 2 * k) * NV + v) * NFN + ap] = acc[v];
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int v = 0; v < NV; v++) {
+            lo[v] = fmin(lo[v], __shfl_xor(lo[v], off));
+            hi[v] = fmax(hi[v], __shfl_xor(hi[v], off));
+        }
+    const int w = tid >> 6, lane = tid & 63, nw = bs >> 6;
+    if (lane == 0)
+#pragma unroll
+        for (int v = 0; v < NV; v++) {
+            scratch[(2 * w) * NV + v] = lo[v];
+            scratch[(2 * w + 1) * NV + v] = hi[v];
+        }
+    __syncthreads();
+    if (tid == 0)
+        for (int ww = 1; ww < nw; ww++)
+#pragma unroll
+            for (int v = 0; v < NV; v++) {
+                lo[v] = fmin(lo[v], scratch[(2 * ww) * NV + v]);
+                hi[v] = fmax(hi[v], scratch[(2 * ww + 1) * NV + v]);
+            }
+    __syncthreads();
+}
+
+// Extended-grid index (one ghost ring) of interior cell c.
+__device__ __forceinline__ int64_t ext_index(const Prob &P, int64_t c) {
+    int ci[3];
+    coords_of(P, c, ci);
+    int64_t e = 0;
+    for (int j = P.dim - 1; j >= 0; j--) e = e * (P.nc[j] + 2) + (ci[j] + 1);
+    return e;
+}
+
+__device__ __forceinline__ int64_t ext_count(const Prob &P) {
+    int64_t next = 1;
+    for (int j = 0; j < P.dim; j++) next *= P.nc[j] + 2;
+    return next;
+}
+
+// Per-variable min / max of one cell's subcell data held in LDS (v[var*nsub + s]),
+// stored as that cell's old-time bounds for the next step.
+template <int NV>
+__device__ __forceinline__ void store_cell_bounds(const Prob &P, const Bufs &B, int64_t c, const double *v, int nsub,
+                                                  int tid, int bs, double *scratch) {
+    double lo[NV], hi[NV];
+#pragma unroll
+    for (int k = 0; k < NV; k++) {
+        lo[k] = INFINITY;
+        hi[k] = -INFINITY;
+    }
+    for (int sg = tid; sg < nsub; sg += bs)
+#pragma unroll
+        for (int k = 0; k < NV; k++) {
+            lo[k] = fmin(lo[k], v[k * nsub + sg]);
+            hi[k] = fmax(hi[k], v[k * nsub + sg]);
+        }
+    block_minmax<NV>(lo, hi, tid, bs, scratch);
+    if (tid == 0) {
+        const int64_t e = ext_index(P, c), next = ext_count(P);
+        for (int k = 0; k < NV; k++) {
+            B.ext_min[(int64_t)k * next + e] = lo[k];
+            B.ext_max[(int64_t)k * next + e] = hi[k];
+        }
     }
 }
 
 // --------------------------------------------------- tensor application in LDS
-// out[v][...] = sum over axis k of M[i][b] in[...b...], applied axis by axis.  Shapes:
-// before stage k axes < k have size m (output), axes >= k have size n (input).
-template <int DIM>
-__device__ void tensor_apply(const double *Mbase, int mstride, int m, int n, int nvars, const double *in, double *out,
-                             double *tmp, int tid, int bs) {
-    // in: [v][n^DIM] ; out: [v][m^DIM] ; tmp: scratch of nvars*max(m,n)^DIM
+// out[v][...] = sum over axis k of M[i][b] in[...b...], applied axis by axis.  Before
+// stage k the axes < k have size M (output) and the axes >= k size NI (input).  Sizes
+// are compile-time so that the index arithmetic uses no integer division.
+template <int DIM, int M, int NI, int NVAR, int MSTRIDE>
+__device__ void tensor_apply(const double *Mbase, const double *in, double *out, double *tmp, int tid, int bs) {
     const double *src = in;
+#pragma unroll
     for (int k = 0; k < DIM; k++) {
         // alternate between the two buffers so that the last stage lands in `out`
         double *dst = ((DIM - 1 - k) % 2 == 0) ? out : tmp;
-        // sizes before: dims j<k: m, j>=k: n ; after: j<=k: m
-        int szb = 1, sza = 1;
-        for (int j = 0; j < DIM; j++) {
-            szb *= (j < k) ? m : n;
-            sza *= (j <= k) ? m : n;
-        }
-        const int total = nvars * sza;
+        const int d0b = (0 < k) ? M : NI, d1b = (1 < k) ? M : NI;          // sizes before the stage
+        const int d0a = (0 <= k) ? M : NI, d1a = (1 <= k) ? M : NI, d2a = (2 <= k) ? M : NI;  // after
+        const int szb = (DIM == 2) ? d0b * d1b : d0b * d1b * ((2 < k) ? M : NI);
+        const int sza = (DIM == 2) ? d0a * d1a : d0a * d1a * d2a;
+        const int total = NVAR * sza;
         for (int it = tid; it < total; it += bs) {
             const int v = it / sza;
-            int e = it % sza;
-            int idx[3] = {0, 0, 0};
-            for (int j = 0; j < DIM; j++) {
-                const int dj = (j <= k) ? m : n;
-                idx[j] = e % dj;
-                e /= dj;
-            }
+            int e = it - v * sza;
+            int idx[3];
+            idx[0] = e % d0a;
+            e /= d0a;
+            idx[1] = (DIM == 2) ? e : e % d1a;
+            idx[2] = (DIM == 2) ? 0 : e / d1a;
             const int i = idx[k];
-            double acc = 0.0;
-            for (int b = 0; b < n; b++) {
-                idx[k] = b;
-                int ib = 0;
-                for (int j = DIM - 1; j >= 0; j--) ib = ib * ((j < k) ? m : n) + idx[j];
-                acc += Mbase[i * mstride + b] * src[v * szb + ib];
+            int strideb = 1;
+            for (int j = 0; j < k; j++) strideb *= (j == 0 ? d0b : d1b);
+            int base = 0, mul = 1;
+#pragma unroll
+            for (int j = 0; j < DIM; j++) {
+                const int dj = (j == 0) ? d0b : ((j == 1) ? d1b : ((2 < k) ? M : NI));
+                if (j != k) base += idx[j] * mul;
+                mul *= dj;
             }
+            const double *row = Mbase + i * MSTRIDE;
+            const double *col = src + v * szb + base;
+            double acc = 0.0;
+#pragma unroll
+            for (int b = 0; b < NI; b++) acc += row[b] * col[b * strideb];
             dst[it] = acc;
         }
         __syncthreads();
@@ -523,16 +630,22 @@ __global__ __launch_bounds__(128) void k_corrector_detect(const Tables *__restri
     const R *gbar = reinterpret_cast<const R *>(B.gbar);
     constexpr int n = N + 1, NV = DIM + 2, NN = cpow(n, DIM), NFN = cpow(n, DIM - 1);
     constexpr int NS = 2 * N + 1, NSUB = cpow(NS, DIM);
-    constexpr int BIG = cpow(NS, DIM) > cpow(n, DIM) ? cpow(NS, DIM) : cpow(n, DIM);
+    // intermediate of the sum-factorised P: stage 0 (2D) or stage 1 (3D) output
+    constexpr int TMP = (DIM == 2) ? NS * n : NS * NS * n;
     __shared__ double us[NV * NN];
-    __shared__ double vs[NV * BIG];
-    __shared__ double tmp[NV * BIG];
-    __shared__ int bad_s[128];
-    __shared__ float mg_s[128];
+    __shared__ double vs[NV * NSUB];
+    __shared__ double tmp[NV * TMP];
+    __shared__ double red[2 * NV * 2];
+    __shared__ int bad_s[2];
+    __shared__ float mg_s[2];
     const int64_t c = blockIdx.x;
     const int tid = threadIdx.x;
     const double dt = B.scal[0];
     double *un = B.u[cur ^ 1];
+    // (dt/h_k)/w_a for every axis and node index: 2 divisions per entry, once per block
+    __shared__ double coef[3][n];
+    if (tid < DIM * n) coef[tid / n][tid % n] = dt / P.h[tid / n] / T->w[tid % n];
+    __syncthreads();
     for (int it = tid; it < NV * NN; it += 128) {
         const int v = it / NN, a = it % NN;
         int m[3] = {a % n, (a / n) % n, a / (n * n)};
@@ -549,15 +662,15 @@ __global__ __launch_bounds__(128) void k_corrector_detect(const Tables *__restri
             const R Gm = gbar[((c * 2 * DIM + 2 * k) * NV + v) * NFN + ap];
             const R Gp = gbar[((c * 2 * DIM + 2 * k + 1) * NV + v) * NFN + ap];
             // face increment in the working precision R, added to the FP64 candidate
-            const R coef = (R)(dt / P.h[k] / T->w[ak]);
-            val += (double)(coef * ((R)T->L[ak] * Gm - (R)T->R[ak] * Gp));
+            const R cf = (R)coef[k][ak];
+            val += (double)(cf * ((R)T->L[ak] * Gm - (R)T->R[ak] * Gp));
         }
         un[((int64_t)v * P.ncell + c) * NN + a] = val;
         us[it] = val;
     }
     if (!limiter) return;
     __syncthreads();
-    tensor_apply<DIM>(&T->P[0][0], MAXN, NS, n, NV, us, vs, tmp, tid, 128);
+    tensor_apply<DIM, NS, n, NV, MAXN>(&T->P[0][0], us, vs, tmp, tid, 128);
     // detection on the NSUB candidate subcell averages
     double m_[NV], M_[NV];
 #pragma unroll
@@ -571,6 +684,19 @@ __global__ __launch_bounds__(128) void k_corrector_detect(const Tables *__restri
     double se = fmax(fabs(M_[DIM + 1]), fabs(m_[DIM + 1]));
     if (!(sr > 0)) sr = 1.0;
     if (!(se > 0)) se = 1.0;
+    // per-variable bounds of eq. (dmp) relaxed by eq. (relax), hoisted out of the subcell loop;
+    // the margin (a diagnostic) is normalised with reciprocals
+    double lo_[NV], hi_[NV], isc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; v++) {
+        const double delta = fmax(P.delta0, P.eps * (M_[v] - m_[v]));
+        lo_[v] = m_[v] - delta;
+        hi_[v] = M_[v] + delta;
+        double sc = fmax(fabs(M_[v]), fabs(m_[v]));
+        if (!(sc > 0)) sc = 1.0;
+        isc[v] = 1.0 / sc;
+    }
+    const double isr = 1.0 / sr, ise = 1.0 / se;
     for (int sg = tid; sg < NSUB; sg += 128) {
         double q[NV];
         bool finite = true;
@@ -586,32 +712,33 @@ __global__ __launch_bounds__(128) void k_corrector_detect(const Tables *__restri
         }
         const double p = pressure<DIM>(q, P.gamma);
         if (!(q[0] > 0.0) || !(p > 0.0)) bad = 1;
-        double lmg = fmin(q[0] / sr, p / se);
+        double lmg = fmin(q[0] * isr, p * ise);
 #pragma unroll
         for (int v = 0; v < NV; v++) {
-            const double delta = fmax(P.delta0, P.eps * (M_[v] - m_[v]));
-            const double lo = m_[v] - delta, hi = M_[v] + delta;
-            if (q[v] < lo || q[v] > hi) bad = 1;
-            double sc = fmax(fabs(M_[v]), fabs(m_[v]));
-            if (!(sc > 0)) sc = 1.0;
-            lmg = fmin(lmg, fmin(q[v] - lo, hi - q[v]) / sc);
+            if (q[v] < lo_[v] || q[v] > hi_[v]) bad = 1;
+            lmg = fmin(lmg, fmin(q[v] - lo_[v], hi_[v] - q[v]) * isc[v]);
         }
         mg = fminf(mg, (float)lmg);
     }
-    bad_s[tid] = bad;
-    mg_s[tid] = mg;
-    __syncthreads();
-    for (int off = 64; off > 0; off >>= 1) {
-        if (tid < off) {
-            bad_s[tid] |= bad_s[tid + off];
-            mg_s[tid] = fminf(mg_s[tid], mg_s[tid + off]);
-        }
-        __syncthreads();
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        bad |= __shfl_xor(bad, off);
+        mg = fminf(mg, __shfl_xor(mg, off));
     }
+    if ((tid & 63) == 0) {
+        bad_s[tid >> 6] = bad;
+        mg_s[tid >> 6] = mg;
+    }
+    __syncthreads();
     if (tid == 0) {
+        bad_s[0] |= bad_s[1];
+        mg_s[0] = fminf(mg_s[0], mg_s[1]);
         B.beta[1][c] = (uint8_t)((bad_s[0] || B.force[c]) ? 1 : 0);
         B.margin[c] = mg_s[0];
     }
+    // the candidate's subcell min / max are the next step's old-time bounds of this cell
+    // (overwritten later in the step if the cell is recomputed or corrected)
+    store_cell_bounds<NV>(P, B, c, vs, NSUB, tid, 128, red);
 }
 
 // --------------------------------------------------------- old-time bounds
@@ -621,16 +748,19 @@ __global__ __launch_bounds__(128) void k_corrector_detect(const Tables *__restri
 // the boundary rule at the ghost subcell centre.  Output: per-variable min / max over
 // the cell's subcells, for the extended grid with a one-cell ghost ring.
 template <int DIM, int N>
-__global__ __launch_bounds__(128) void k_cell_bounds(const Tables *__restrict__ T, Prob P, Bufs B, int cur) {
+__global__ __launch_bounds__(128) void k_cell_bounds(const Tables *__restrict__ T, Prob P, Bufs B, int cur,
+                                                     const int64_t *__restrict__ ring) {
     constexpr int n = N + 1, NV = DIM + 2, NN = cpow(n, DIM);
     constexpr int NS = 2 * N + 1, NSUB = cpow(NS, DIM);
     constexpr int BIG = NSUB > NN ? NSUB : NN;
     __shared__ double us[NV * NN];
     __shared__ double vs[NV * BIG];
     __shared__ double tmp[NV * BIG];
-    __shared__ double red[2][NV][128];
+    __shared__ double red[2 * NV * 2];
     const int tid = threadIdx.x;
-    const int64_t e = blockIdx.x;
+    // all extended cells, or only the ghost ring (interior bounds then come from the
+    // kernels of the previous step that produced each cell's new subcell data)
+    const int64_t e = ring ? ring[blockIdx.x] : (int64_t)blockIdx.x;
     int ei[3] = {0, 0, 0}, ne[3] = {1, 1, 1};
     for (int j = 0; j < DIM; j++) ne[j] = P.nc[j] + 2;
     {
@@ -669,7 +799,7 @@ __global__ __launch_bounds__(128) void k_cell_bounds(const Tables *__restrict__ 
             us[it] = uo[((int64_t)v * P.ncell + cs) * NN + a];
         }
         __syncthreads();
-        tensor_apply<DIM>(&T->P[0][0], MAXN, NS, n, NV, us, vs, tmp, tid, 128);
+        tensor_apply<DIM, NS, n, NV, MAXN>(&T->P[0][0], us, vs, tmp, tid, 128);
     }
     const double t0 = B.scal[1];
     double lo[NV], hi[NV];
@@ -703,28 +833,13 @@ __global__ __launch_bounds__(128) void k_cell_bounds(const Tables *__restrict__ 
             hi[v] = fmax(hi[v], q[v]);
         }
     }
-#pragma unroll
-    for (int v = 0; v < NV; v++) {
-        red[0][v][tid] = lo[v];
-        red[1][v][tid] = hi[v];
-    }
-    __syncthreads();
-    for (int off = 64; off > 0; off >>= 1) {
-        if (tid < off) {
-#pragma unroll
-            for (int v = 0; v < NV; v++) {
-                red[0][v][tid] = fmin(red[0][v][tid], red[0][v][tid + off]);
-                red[1][v][tid] = fmax(red[1][v][tid], red[1][v][tid + off]);
-            }
-        }
-        __syncthreads();
-    }
+    block_minmax<NV>(lo, hi, tid, 128, red);
     if (tid == 0) {
         int64_t next = 1;
         for (int j = 0; j < DIM; j++) next *= ne[j];
         for (int v = 0; v < NV; v++) {
-            B.ext_min[(int64_t)v * next + e] = red[0][v][0];
-            B.ext_max[(int64_t)v * next + e] = red[1][v][0];
+            B.ext_min[(int64_t)v * next + e] = lo[v];
+            B.ext_max[(int64_t)v * next + e] = hi[v];
         }
     }
 }
@@ -903,15 +1018,18 @@ __device__ __forceinline__ void position_coords(int pos, int Ns, int *L) {
 
 // S1: halo of subcell data v^n (eq. (ader.icbc)) 3 subcells deep around the cell.
 template <int DIM, int N>
-__global__ __launch_bounds__(256) void k_sub_halo(const Tables *__restrict__ T, Prob P, Bufs B, int cur, int first) {
+__global__ __launch_bounds__(256) void k_sub_halo(const Tables *__restrict__ T, Prob P, Bufs B, int cur, int first,
+                                                  int count, int64_t cap) {
+    if (count < 0) count = (int)(B.counts[0] < cap ? B.counts[0] : cap);   // device-driven
+    for (int wb = blockIdx.x; wb < count; wb += gridDim.x) {
     constexpr int n = N + 1, NV = DIM + 2, NN = cpow(n, DIM);
     constexpr int NS = 2 * N + 1, NSUB = cpow(NS, DIM), HN = NS + 6, HSZ = cpow(HN, DIM);
-    const int w = first + blockIdx.x;
+    const int w = first + wb;
     const int64_t c = B.tlist[w];
     int ci[3];
     coords_of(P, c, ci);
     const double t0 = B.scal[1];
-    double *halo = B.halo + (int64_t)blockIdx.x * NV * HSZ;
+    double *halo = B.halo + (int64_t)wb * NV * HSZ;
     for (int hidx = threadIdx.x; hidx < HSZ; hidx += 256) {
         int hl[3] = {hidx % HN, (hidx / HN) % HN, hidx / (HN * HN)};
         int gci[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, src[3] = {0, 0, 0}, ss[3] = {0, 0, 0}, gside[3] = {-1, -1, -1};
@@ -965,6 +1083,7 @@ __global__ __launch_bounds__(256) void k_sub_halo(const Tables *__restrict__ T, 
 #pragma unroll
         for (int v = 0; v < NV; v++) halo[v * HSZ + hidx] = q[v];
     }
+    }  // persistent loop
 }
 
 // One-dimensional WENO3 (degree 2, three stencils, lambda = 1, 1e5, 1, eps 1e-14, r 8):
@@ -1003,12 +1122,13 @@ __device__ __forceinline__ void weno3(const Tables *__restrict__ T, const double
 // the 3^d GL points of the subcell (x sweep on the averages, then y (then z) sweeps on
 // the nodal values of the previous sweep).
 template <int DIM, int N>
-__global__ void k_sub_recon(const Tables *__restrict__ T, Bufs B, int nch) {
+__global__ void k_sub_recon(const Tables *__restrict__ T, Bufs B, int nch, int64_t cap) {
     constexpr int NV = DIM + 2, NS = 2 * N + 1, HN = NS + 6, HSZ = cpow(HN, DIM);
     constexpr int NPOS = cpow(NS, DIM) + 2 * DIM * cpow(NS, DIM - 1), N3 = cpow(3, DIM);
     constexpr int W5 = cpow(5, DIM);
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= (int64_t)nch * NPOS) return;
+    if (nch < 0) nch = (int)(B.counts[0] < cap ? B.counts[0] : cap);   // device-driven
+    for (int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gid < (int64_t)nch * NPOS;
+         gid += (int64_t)gridDim.x * blockDim.x) {
     const int ch = (int)(gid / NPOS), pos = (int)(gid % NPOS);
     int L[3];
     position_coords<DIM>(pos, NS, L);
@@ -1060,12 +1180,13 @@ __global__ void k_sub_recon(const Tables *__restrict__ T, Bufs B, int nch) {
         }
         for (int a = 0; a < N3; a++) Y[v * N3 + a] = src[a];
     }
+    }  // grid-stride loop
 }
 
 // S4: sub-face Rusanov fluxes, FV update, gather, pool store, boundary fluxes.
 template <int DIM, int N>
 __global__ __launch_bounds__(256) void k_sub_update(const Tables *__restrict__ T, Prob P, Bufs B, int cur, int first,
-                                                    int *nonphys) {
+                                                    int *nonphys, int count, int64_t cap) {
     constexpr int n = N + 1, NV = DIM + 2, NN = cpow(n, DIM);
     constexpr int NS = 2 * N + 1, NSUB = cpow(NS, DIM), NSF = cpow(NS, DIM - 1), HN = NS + 6, HSZ = cpow(HN, DIM);
     constexpr int NPOS = NSUB + 2 * DIM * NSF, NF3 = cpow(3, DIM - 1);
@@ -1075,8 +1196,10 @@ __global__ __launch_bounds__(256) void k_sub_update(const Tables *__restrict__ T
     __shared__ double vn[NV * BIG];
     __shared__ double tmp[NV * BIG];
     __shared__ double ug[NV * BIG];
+    __shared__ double red[2 * NV * 4];
     __shared__ int badc;
-    const int ch = blockIdx.x;
+    if (count < 0) count = (int)(B.counts[0] < cap ? B.counts[0] : cap);   // device-driven
+    for (int ch = blockIdx.x; ch < count; ch += gridDim.x) {
     const int w = first + ch;
     const int64_t c = B.tlist[w];
     int ci[3];
@@ -1220,24 +1343,35 @@ __global__ __launch_bounds__(256) void k_sub_update(const Tables *__restrict__ T
         B.sflux[(int64_t)slot * 2 * DIM * NV * NSF + it] = Fb[((k * (NS + 1) + (side ? NS : 0)) * NSF + sp) * NV + v];
     }
     __syncthreads();
+    store_cell_bounds<NV>(P, B, c, vn, NSUB, threadIdx.x, 256, red);
     // gather: u = R v (eq. (subcell.r)), tensor application
-    tensor_apply<DIM>(&T->Rg[0][0], MAXNS, n, NS, NV, vn, ug, tmp, threadIdx.x, 256);
+    tensor_apply<DIM, n, NS, NV, MAXNS>(&T->Rg[0][0], vn, ug, tmp, threadIdx.x, 256);
     for (int it = threadIdx.x; it < NV * NN; it += 256) {
         const int v = it / NN, a = it % NN;
         B.u[cur ^ 1][((int64_t)v * P.ncell + c) * NN + a] = ug[it];
     }
     if (threadIdx.x == 0 && badc) atomicAdd(nonphys, 1);
+    __syncthreads();   // LDS reused by the next troubled cell
+    }  // persistent loop
 }
 
 // Flux correction of unlimited cells next to troubled cells (Sec. 4.4): the DG face
 // flux of each face shared with a troubled cell is replaced by the subcell fluxes of
 // that face, each integrated against the basis (P[sigma][a] / (Ns w_a) per tangential axis).
 template <int DIM, int N, typename R>
-__global__ __launch_bounds__(128) void k_fluxcorr(const Tables *__restrict__ T, Prob P, Bufs B, int cur) {
+__global__ __launch_bounds__(128) void k_fluxcorr(const Tables *__restrict__ T, Prob P, Bufs B, int cur, int count) {
     const R *gbar = reinterpret_cast<const R *>(B.gbar);
+    constexpr int NS_ = 2 * N + 1, NSUB_ = cpow(NS_, DIM), NN_ = cpow(N + 1, DIM), NV_ = DIM + 2;
+    constexpr int TMP_ = (DIM == 2) ? NS_ * (N + 1) : NS_ * NS_ * (N + 1);
+    __shared__ double us[NV_ * NN_];
+    __shared__ double vs[NV_ * NSUB_];
+    __shared__ double tmp[NV_ * TMP_];
+    __shared__ double red[2 * NV_ * 2];
     constexpr int n = N + 1, NV = DIM + 2, NN = cpow(n, DIM), NFN = cpow(n, DIM - 1);
     constexpr int NS = 2 * N + 1, NSF = cpow(NS, DIM - 1);
-    const int64_t c = B.clist[blockIdx.x];
+    if (count < 0) count = B.counts[1];   // device-driven
+    for (int wb = blockIdx.x; wb < count; wb += gridDim.x) {
+    const int64_t c = B.clist[wb];
     int ci[3];
     coords_of(P, c, ci);
     const double dt = B.scal[0];
@@ -1293,7 +1427,14 @@ __global__ __launch_bounds__(128) void k_fluxcorr(const Tables *__restrict__ T, 
             }
         }
         B.u[cur ^ 1][((int64_t)v * P.ncell + c) * NN + a] = val;
+        us[it] = val;
     }
+    __syncthreads();
+    // the corrected state's subcell min / max are this cell's next old-time bounds
+    tensor_apply<DIM, NS, n, NV, MAXN>(&T->P[0][0], us, vs, tmp, threadIdx.x, 128);
+    store_cell_bounds<NV>(P, B, c, vs, NSUB_, threadIdx.x, 128, red);
+    __syncthreads();   // LDS reused by the next corrected cell
+    }  // persistent loop
 }
 
 // ------------------------------------------------------------------ time step
@@ -1374,6 +1515,9 @@ struct Launch {
             A.w = C.tab->fw;
             A.Dvol = &C.tab->fDvol[0][0];
         }
+        A.dcount = nullptr;
+        A.dcap = 0;
+        A.dmult = 1;
         const int64_t grid = (C.P.ncell + S::CPB - 1) / S::CPB;
         hipLaunchKernelGGL((k_predictor<DIM, N, true, R>), dim3((unsigned)grid), dim3(S::BS), 0, C.stream, C.tab, A,
                            C.P.gamma);
@@ -1384,16 +1528,16 @@ struct Launch {
     }
     template <typename R>
     static void faces_t(const StepCtx &C) {
-        constexpr int NFN = cpow(n, DIM - 1);
         for (int k = 0; k < DIM; k++) {
             int64_t nlines = 1;
             for (int j = 0; j < DIM; j++)
                 if (j != k) nlines *= C.P.nc[j];
             const int nfk = C.P.periodic[k] ? C.P.nc[k] : C.P.nc[k] + 1;
-            const int64_t total = nlines * nfk * NFN;
-            hipLaunchKernelGGL((k_face<DIM, N, R>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, C.stream,
-                               C.tab, C.P, reinterpret_cast<const R *>(C.B.trace), reinterpret_cast<R *>(C.B.gbar),
-                               C.B.scal, k);
+            const int64_t nfaces = nlines * nfk;
+            using FS = FaceShape<DIM, N>;
+            hipLaunchKernelGGL((k_face<DIM, N, R>), dim3((unsigned)((nfaces + FS::FPB - 1) / FS::FPB)), dim3(FS::BS), 0,
+                               C.stream, C.tab, C.P, reinterpret_cast<const R *>(C.B.trace),
+                               reinterpret_cast<R *>(C.B.gbar), C.B.scal, k);
         }
     }
     static void faces(const StepCtx &C) {
@@ -1411,16 +1555,23 @@ struct Launch {
     static void bounds(const StepCtx &C) {
         int64_t next = 1;
         for (int j = 0; j < DIM; j++) next *= C.P.nc[j] + 2;
-        hipLaunchKernelGGL((k_cell_bounds<DIM, N>), dim3((unsigned)next), dim3(128), 0, C.stream, C.tab, C.P, C.B,
-                           C.cur);
+        const int64_t nblk = C.ring_only ? C.nring : next;
+        if (nblk > 0)
+            hipLaunchKernelGGL((k_cell_bounds<DIM, N>), dim3((unsigned)nblk), dim3(128), 0, C.stream, C.tab, C.P, C.B,
+                               C.cur, C.ring_only ? C.B.ring : (const int64_t *)nullptr);
         hipLaunchKernelGGL((k_neigh_bounds<DIM>), dim3((unsigned)((C.P.ncell + 255) / 256)), dim3(256), 0, C.stream,
                            C.P, C.B);
     }
+    // count >= 0: a host-known chunk [first, first+count); count < 0: the whole troubled
+    // list, its length read on the device (first = 0, at most `capacity` cells).
     static void subcell_chunk(const StepCtx &C, int first, int count) {
-        hipLaunchKernelGGL((k_sub_halo<DIM, N>), dim3(count), dim3(256), 0, C.stream, C.tab, C.P, C.B, C.cur, first);
-        const int64_t npos = (int64_t)count * NPOS;
-        hipLaunchKernelGGL((k_sub_recon<DIM, N>), dim3((unsigned)((npos + 127) / 128)), dim3(128), 0, C.stream, C.tab,
-                           C.B, count);
+        const int64_t maxc = count >= 0 ? count : C.capacity;
+        const unsigned gcell = (unsigned)std::min<int64_t>(maxc, 512);
+        hipLaunchKernelGGL((k_sub_halo<DIM, N>), dim3(gcell), dim3(256), 0, C.stream, C.tab, C.P, C.B, C.cur, first,
+                           count, C.capacity);
+        const int64_t npos = maxc * NPOS;
+        hipLaunchKernelGGL((k_sub_recon<DIM, N>), dim3((unsigned)std::min<int64_t>((npos + 127) / 128, 1024)), dim3(128),
+                           0, C.stream, C.tab, C.B, count, C.capacity);
         using S = PredShape<DIM, 2, double>;
         PredArgs<double> A;
         A.in = C.B.Y;
@@ -1439,19 +1590,23 @@ struct Launch {
         A.Rb = C.tab->R3;
         A.w = C.tab->w3;
         A.Dvol = nullptr;
-        const int64_t grid = (npos + S::CPB - 1) / S::CPB;
+        A.dcount = count >= 0 ? nullptr : C.B.counts;
+        A.dcap = C.capacity;
+        A.dmult = NPOS;
+        const int64_t grid = std::min<int64_t>((npos + S::CPB - 1) / S::CPB, 1024);
         hipLaunchKernelGGL((k_predictor<DIM, 2, false, double>), dim3((unsigned)grid), dim3(S::BS), 0, C.stream,
                            C.tab, A, C.P.gamma);
-        hipLaunchKernelGGL((k_sub_update<DIM, N>), dim3(count), dim3(256), 0, C.stream, C.tab, C.P, C.B, C.cur, first,
-                           C.B.counts + 2);
+        hipLaunchKernelGGL((k_sub_update<DIM, N>), dim3(gcell), dim3(256), 0, C.stream, C.tab, C.P, C.B, C.cur, first,
+                           C.B.counts + 2, count, C.capacity);
     }
     static void fluxcorr(const StepCtx &C, int count) {
+        const unsigned g = (unsigned)std::min<int64_t>(count >= 0 ? count : C.P.ncell, 512);
         if (C.precision == ADG_MIXED)
-            hipLaunchKernelGGL((k_fluxcorr<DIM, N, float>), dim3(count), dim3(128), 0, C.stream, C.tab, C.P, C.B,
-                               C.cur);
+            hipLaunchKernelGGL((k_fluxcorr<DIM, N, float>), dim3(g), dim3(128), 0, C.stream, C.tab, C.P, C.B, C.cur,
+                               count);
         else
-            hipLaunchKernelGGL((k_fluxcorr<DIM, N, double>), dim3(count), dim3(128), 0, C.stream, C.tab, C.P, C.B,
-                               C.cur);
+            hipLaunchKernelGGL((k_fluxcorr<DIM, N, double>), dim3(g), dim3(128), 0, C.stream, C.tab, C.P, C.B, C.cur,
+                               count);
     }
     static void lambda(const StepCtx &C, const double *u, double factor) {
         const int64_t total = C.P.ncell * NN;

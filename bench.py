@@ -47,6 +47,9 @@ def main():
     ap.add_argument("--N", type=int, default=9)
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="bounded CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the four-quadrant batch measurement")
+    ap.add_argument("--batch-count", type=int, default=256)
+    ap.add_argument("--batch-steps", type=int, default=20)
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device-to-device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -164,10 +167,78 @@ def main():
         "rho_mixed_minus_fp64": {"max": float(drho.max()), "mean": float(drho.mean())},
     }
 
+    if not args.no_batch:
+        out["batch"] = batch_measurement(args.batch_count, args.batch_steps)
+
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, u0, args.cpu_seconds)
 
     print(json.dumps(out), flush=True)
+
+
+def batch_measurement(count, steps):
+    """Independent four-quadrant Riemann problems (random states, grids from
+    {32,64,128,256}^2, N from {3,4,5}): the mixed form advanced as one batch (one hipGraph
+    launch per batch step) against the plain FP64 form stepped problem by problem."""
+    import gc
+    import torch
+    from paper_1406_7416_amd import adg
+    from paper_1406_7416_amd import workloads as W
+    wls = W.quadrant_batch(count)
+    cfl = min(wl.cfl for wl in wls)
+    st_dof = sum(wl.st_dof_per_step() for wl in wls)
+    res = {"problems": count, "cells": sum(wl.num_cells for wl in wls), "st_dof_per_step": st_dof,
+           "steps": steps, "cfl": cfl}
+
+    def build(prec):
+        ps = []
+        for wl in wls:
+            cap = wl.num_cells if wl.num_cells <= 4096 else wl.num_cells // 3
+            p = adg.Problem(wl, precision=prec, pool_capacity=cap)
+            u, _ = p.project(wl.ic, 0)
+            p.set_state(u)
+            ps.append(p)
+        return ps
+
+    # mixed form, batched
+    ps = build(adg.ADG_MIXED)
+    b = adg.Batch(ps)
+    b.step_cfl(cfl, 3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step_cfl(cfl, steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    res["mixed_batched"] = {"value": st_dof * steps / el, "ms_per_batch_step": 1e3 * el / steps,
+                            "troubled_last_step": int(sum(int(p.troubled().sum()) for p in ps))}
+    b.close()
+    for p in ps:
+        p.close()
+    del ps, b
+    gc.collect()
+    torch.cuda.empty_cache()
+    # plain FP64 form, one problem after the other, per-problem launches
+    ps = build(adg.ADG_FP64)
+    for p in ps:
+        for _ in range(3):
+            p.step_cfl(cfl)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for p in ps:
+        for _ in range(steps):
+            p.step_cfl(cfl)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    res["fp64_per_problem"] = {"value": st_dof * steps / el, "ms_per_batch_step": 1e3 * el / steps}
+    res["speedup"] = res["mixed_batched"]["value"] / res["fp64_per_problem"]["value"]
+    for p in ps:
+        p.close()
+    del ps
+    gc.collect()
+    torch.cuda.empty_cache()
+    print(f"# batch: mixed batched {res['mixed_batched']['value']:.3e}, fp64 per problem "
+          f"{res['fp64_per_problem']['value']:.3e} st-dof/s", file=sys.stderr, flush=True)
+    return res
 
 
 def cpu_baseline(wl, u0, budget_s):

@@ -124,8 +124,11 @@ int adg_get_state(const adg_problem *pb, double *u, int to_device);
  * Synchronising. */
 int adg_cfl_dt(adg_problem *pb, double cfl, double *dt_out);
 
-/* One full step with the given dt.  Enqueued on the bound stream; one host wait for the
- * troubled-cell count is taken inside.  Errors: ADG_ESTATE, ADG_EDEVICE, ADG_ECAPACITY. */
+/* One full step with the given dt, enqueued on the bound stream without any host wait
+ * (the troubled-cell count stays on the device).  Errors: ADG_ESTATE, ADG_EDEVICE;
+ * ADG_ECAPACITY once an earlier step found more troubled cells than the pool holds
+ * (detected asynchronously; the state is then not advanced correctly; sticky until the
+ * next adg_set_state). */
 int adg_step(adg_problem *pb, double dt);
 
 /* As adg_step with dt from eq. (cfl) computed on the device from the current state. */
@@ -157,6 +160,22 @@ int adg_get_stats(const adg_problem *pb, int64_t *out4);
  * milliseconds) and launches[g] for g < ngroups (<= 8).  Synchronising. */
 int adg_profile(adg_problem *pb, int enable);
 int adg_profile_read(adg_problem *pb, double *ms, int64_t *launches, int ngroups);
+
+/* Batching of independent problems (not in the paper): the problems (each created and
+ * bound as above, with a state set, all on the current device) advance together.  The first call takes
+ * one ordinary step per problem, then captures one step of every problem -- each on its
+ * own stream branch of one fork/join capture, dt from eq. (cfl) per problem on the
+ * device -- into two hipGraphs (the two buffer parities) and from then on replays them:
+ * one hipGraphLaunch per batch step.  The problems' own streams are not used while the
+ * batch steps; the batch synchronises its streams before returning.  Problems must not
+ * be stepped outside the batch while it exists.  Errors: ADG_EINVAL, ADG_ESTATE,
+ * ADG_EDEVICE. */
+typedef struct adg_batch adg_batch;
+int adg_batch_create(adg_problem *const *ps, int count, adg_batch **out);
+int adg_batch_step_cfl(adg_batch *b, double cfl, int nsteps);
+/* Per-problem dt of the last batch step (host memory, count doubles).  Synchronising. */
+int adg_batch_dt(adg_batch *b, double *dts);
+int adg_batch_destroy(adg_batch *b);
 
 /* Debug hook: cells with mask[c] != 0 are flagged troubled at every following detection
  * (NULL clears).  Host memory, one byte per cell. */

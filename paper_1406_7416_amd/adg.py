@@ -22,7 +22,8 @@ EXPORTS = [
     "adg_last_error", "adg_create", "adg_destroy", "adg_workspace_bytes", "adg_bind", "adg_axis_points",
     "adg_project_samples", "adg_set_state", "adg_get_state", "adg_cfl_dt", "adg_step", "adg_step_cfl",
     "adg_time", "adg_get_troubled", "adg_get_margin", "adg_get_subcells", "adg_get_stats",
-    "adg_profile", "adg_profile_read", "adg_debug_force_troubled",
+    "adg_profile", "adg_profile_read", "adg_batch_create", "adg_batch_step_cfl", "adg_batch_dt",
+    "adg_batch_destroy", "adg_debug_force_troubled",
 ]
 
 KERNEL_GROUPS = ["bounds", "predictor", "faces", "corrector_detect", "compact", "subcell", "fluxcorr", "dt"]
@@ -80,6 +81,10 @@ def load():
     L.adg_debug_force_troubled.argtypes = [vp, C.POINTER(C.c_uint8)]
     L.adg_profile.argtypes = [vp, C.c_int]
     L.adg_profile_read.argtypes = [vp, dp, C.POINTER(i64), C.c_int]
+    L.adg_batch_create.argtypes = [C.POINTER(vp), C.c_int, C.POINTER(vp)]
+    L.adg_batch_step_cfl.argtypes = [vp, C.c_double, C.c_int]
+    L.adg_batch_dt.argtypes = [vp, dp]
+    L.adg_batch_destroy.argtypes = [vp]
     for name in EXPORTS[1:]:
         if name != "adg_workspace_bytes":
             getattr(L, name).restype = C.c_int
@@ -258,3 +263,34 @@ class Problem:
         out = (C.c_int64 * 4)()
         _check(load().adg_get_stats(self.h, out))
         return {"troubled": out[0], "corrected": out[1], "nonphysical": out[2], "steps": out[3]}
+
+
+class Batch:
+    """Independent problems advanced together: one hipGraph launch per batch step."""
+
+    def __init__(self, problems):
+        L = load()
+        self.problems = list(problems)
+        arr = (C.c_void_p * len(self.problems))(*[p.h.value for p in self.problems])
+        h = C.c_void_p()
+        _check(L.adg_batch_create(arr, len(self.problems), C.byref(h)))
+        self.h = h
+
+    def step_cfl(self, cfl: float, nsteps: int = 1):
+        _check(load().adg_batch_step_cfl(self.h, cfl, nsteps))
+
+    def dts(self) -> np.ndarray:
+        out = np.zeros(len(self.problems))
+        _check(load().adg_batch_dt(self.h, _dp(out)))
+        return out
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().adg_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -34,7 +34,7 @@ struct adg_problem {
     adg_params prm;
     Tables tab_host;
     int64_t cap;            // pool slots
-    int chunk;              // troubled cells per subcell chunk
+    int chunk;              // workgroups (scratch slots) of the persistent subcell kernel
     int npos;               // subcell positions per troubled cell
     int lam_blocks;
     size_t ws_bytes;
@@ -54,6 +54,7 @@ struct adg_problem {
     bool bound = false, has_state = false;
     int *pinned = nullptr;    // host-pinned copy of the counters
     hipEvent_t counts_ready = nullptr;   // recorded after the asynchronous counter copy
+    bool capturing = false;              // inside a batch graph capture
     int64_t last_troubled = 0, last_corrected = 0, steps = 0;
     // kernel-group timing
     bool profiling = false;
@@ -119,11 +120,10 @@ static void plan(adg_problem *pb) {
     const int64_t nblk = (nc + 255) / 256;
     const int64_t hsz = ipow64(Ns + 6, d), n3 = ipow64(3, d), nf3 = ipow64(3, d - 1);
     const int64_t per_chunk_cell = (nv * hsz + pb->npos * nv * n3 + pb->npos * 2 * d * nv * nf3 * 3) * 8;
-    // subcell scratch: up to 4 GB; when it covers the whole pool capacity the step runs
-    // without a host wait (the subcell kernels read the troubled count on the device)
-    int64_t chunk = std::max<int64_t>(16, (int64_t)(4096ll << 20) / per_chunk_cell);
-    chunk = std::min<int64_t>(chunk, std::max<int64_t>(1, pb->cap));
-    chunk = std::min<int64_t>(chunk, 65535);
+    // subcell scratch: one slot per workgroup of the persistent subcell kernel (two per CU
+    // of MI355X, fewer if the pool holds fewer cells)
+    const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(512, pb->cap));
+    (void)per_chunk_cell;
     pb->chunk = (int)chunk;
     pb->lam_blocks = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (nc * nn + 255) / 256));
     size_t o = 0;
@@ -218,6 +218,7 @@ static StepCtx ctx(const adg_problem *pb) {
     C.lam_blocks = pb->lam_blocks;
     C.precision = pb->prm.precision;
     C.ring_only = pb->bounds_valid ? 1 : 0;
+    C.subcell_grid = pb->chunk;
     C.nring = pb->nring;
     return C;
 }
@@ -654,7 +655,7 @@ int adg_cfl_dt(adg_problem *pb, double cfl, double *dt_out) {
 static int do_step(adg_problem *pb) {
     StepCtx C = ctx(pb);
     Bufs &B = pb->B;
-    if (pb->counts_ready && hipEventQuery(pb->counts_ready) == hipSuccess && pb->pinned[3])
+    if (!pb->capturing && pb->counts_ready && hipEventQuery(pb->counts_ready) == hipSuccess && pb->pinned[3])
         return fail(ADG_ECAPACITY, "troubled cells exceeded the pool capacity %lld in an earlier step",
                     (long long)pb->cap);
     if (pb->prm.limiter) {
@@ -682,38 +683,17 @@ static int do_step(adg_problem *pb) {
             launch_compact(C);
         }
         HIPCHK(hipGetLastError());
-        if (pb->chunk >= pb->cap) {
-            // device-driven: no host wait; the counts stay on the device
-            {
-                GroupTimer g(pb, 5);
-                launch_subcell_chunk(C, 0, -1);
-            }
-            {
-                GroupTimer g(pb, 6);
-                launch_fluxcorr(C, -1);
-            }
-            troubled = corrected = -1;
-        } else {
-            HIPCHK(hipMemcpyAsync(pb->pinned, B.counts, 16, hipMemcpyDeviceToHost, pb->stream));
-            HIPCHK(hipStreamSynchronize(pb->stream));
-            if (pb->profiling) harvest(pb);
-            troubled = pb->pinned[0];
-            corrected = pb->pinned[1];
-            if (troubled > pb->cap) rc = fail(ADG_ECAPACITY, "%lld troubled cells exceed pool capacity %lld",
-                                              (long long)troubled, (long long)pb->cap);
-            const int64_t todo = std::min<int64_t>(troubled, pb->cap);
-            if (todo > 0) {
-                GroupTimer g(pb, 5);
-                for (int64_t first = 0; first < todo; first += pb->chunk) {
-                    const int cnt = (int)std::min<int64_t>(pb->chunk, todo - first);
-                    launch_subcell_chunk(C, (int)first, cnt);
-                }
-            }
-            if (corrected > 0) {
-                GroupTimer g(pb, 6);
-                launch_fluxcorr(C, (int)corrected);
-            }
+        // no host wait: the subcell recompute and the flux correction read the counts on
+        // the device
+        {
+            GroupTimer g(pb, 5);
+            launch_subcell(C);
         }
+        {
+            GroupTimer g(pb, 6);
+            launch_fluxcorr(C, -1);
+        }
+        troubled = corrected = -1;
         HIPCHK(hipGetLastError());
         std::swap(B.beta[0], B.beta[1]);
         std::swap(B.slot[0], B.slot[1]);
@@ -723,7 +703,7 @@ static int do_step(adg_problem *pb) {
     }
     launch_advance_time(C);
     HIPCHK(hipGetLastError());
-    if (pb->prm.limiter && troubled < 0) {
+    if (pb->prm.limiter && troubled < 0 && !pb->capturing) {
         // asynchronous copy of the counters (read by adg_get_stats and the next step)
         HIPCHK(hipMemcpyAsync(pb->pinned, B.counts, 16, hipMemcpyDeviceToHost, pb->stream));
         if (!pb->counts_ready) HIPCHK(hipEventCreateWithFlags(&pb->counts_ready, hipEventDisableTiming));
@@ -845,6 +825,174 @@ int adg_profile_read(adg_problem *pb, double *ms, int64_t *launches, int ngroups
         if (ms) ms[g] = pb->prof_ms[g];
         if (launches) launches[g] = pb->prof_n[g];
     }
+    return ADG_OK;
+}
+
+}  // extern "C"
+
+struct adg_batch {
+    std::vector<adg_problem *> ps;
+    std::vector<hipStream_t> streams;     // one branch per problem
+    std::vector<hipStream_t> saved;       // the problems' own streams
+    std::vector<hipEvent_t> evs;          // fork / join events
+    hipStream_t origin = nullptr;
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    int parity = 0;                       // which graph advances the current state
+    bool captured = false;
+    double cfl = 0;
+};
+
+// Host-side bookkeeping of one step (what do_step does after its launches), for replays.
+static void host_advance(adg_problem *pb) {
+    Bufs &B = pb->B;
+    if (pb->prm.limiter) {
+        std::swap(B.beta[0], B.beta[1]);
+        std::swap(B.slot[0], B.slot[1]);
+        std::swap(B.pool[0], B.pool[1]);
+        pb->bounds_valid = true;
+    }
+    pb->cur ^= 1;
+    pb->last_troubled = pb->last_corrected = -1;
+    pb->steps++;
+}
+
+static int batch_capture(adg_batch *b) {
+    for (int g = 0; g < 2; g++) {
+        HIPCHK(hipStreamBeginCapture(b->origin, hipStreamCaptureModeThreadLocal));
+        HIPCHK(hipEventRecord(b->evs[0], b->origin));
+        int rc = ADG_OK;
+        for (size_t i = 0; i < b->ps.size() && rc == ADG_OK; i++) {
+            adg_problem *pb = b->ps[i];
+            hipStream_t st = b->streams[i];
+            if (hipStreamWaitEvent(st, b->evs[0], 0) != hipSuccess) { rc = fail(ADG_EDEVICE, "fork"); break; }
+            pb->stream = st;
+            pb->capturing = true;
+            StepCtx C = ctx(pb);
+            launch_lambda(C, pb->B.u[pb->cur], dt_factor(pb, b->cfl));
+            rc = do_step(pb);
+            pb->capturing = false;
+            if (rc == ADG_OK && hipEventRecord(b->evs[1 + i], st) != hipSuccess) rc = fail(ADG_EDEVICE, "join record");
+            if (rc == ADG_OK && hipStreamWaitEvent(b->origin, b->evs[1 + i], 0) != hipSuccess)
+                rc = fail(ADG_EDEVICE, "join wait");
+        }
+        hipGraph_t gr = nullptr;
+        hipError_t e = hipStreamEndCapture(b->origin, &gr);
+        if (rc != ADG_OK) return rc;
+        if (e != hipSuccess) return fail(ADG_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+        b->graph[g] = gr;
+        HIPCHK(hipGraphInstantiate(&b->exec[g], gr, nullptr, nullptr, 0));
+    }
+    // capturing advanced the host bookkeeping twice (one step per graph): back to start
+    for (auto *pb : b->ps) {
+        pb->steps -= 2;
+    }
+    b->parity = 0;
+    b->captured = true;
+    return ADG_OK;
+}
+
+extern "C" {
+
+int adg_batch_create(adg_problem *const *ps, int count, adg_batch **out) {
+    if (!ps || count <= 0 || !out) return fail(ADG_EINVAL, "bad argument");
+    *out = nullptr;
+    for (int i = 0; i < count; i++) {
+        adg_problem *pb = ps[i];
+        if (!pb || !pb->has_state) return fail(ADG_ESTATE, "problem %d has no state", i);
+        for (int j = 0; j < i; j++)
+            if (ps[j] == pb) return fail(ADG_EINVAL, "problem listed twice");
+    }
+    adg_batch *b = new (std::nothrow) adg_batch();
+    if (!b) return fail(ADG_ENOMEM, "host allocation failed");
+    b->ps.assign(ps, ps + count);
+    b->streams.resize(count, nullptr);
+    b->evs.resize(count + 1, nullptr);
+    for (int i = 0; i < count; i++) {
+        b->saved.push_back(ps[i]->stream);
+        if (hipStreamCreateWithFlags(&b->streams[i], hipStreamNonBlocking) != hipSuccess) {
+            adg_batch_destroy(b);
+            return fail(ADG_EDEVICE, "hipStreamCreate failed");
+        }
+    }
+    for (int i = 0; i <= count; i++)
+        if (hipEventCreateWithFlags(&b->evs[i], hipEventDisableTiming) != hipSuccess) {
+            adg_batch_destroy(b);
+            return fail(ADG_EDEVICE, "hipEventCreate failed");
+        }
+    if (hipStreamCreateWithFlags(&b->origin, hipStreamNonBlocking) != hipSuccess) {
+        adg_batch_destroy(b);
+        return fail(ADG_EDEVICE, "hipStreamCreate failed");
+    }
+    *out = b;
+    return ADG_OK;
+}
+
+int adg_batch_step_cfl(adg_batch *b, double cfl, int nsteps) {
+    if (!b || !(cfl > 0) || nsteps < 0) return fail(ADG_EINVAL, "bad argument");
+    // make the problems' pending work visible to the batch streams
+    for (size_t i = 0; i < b->ps.size(); i++) HIPCHK(hipStreamSynchronize(b->saved[i]));
+    int done = 0;
+    if (!b->captured || b->cfl != cfl) {
+        if (b->captured) {
+            for (int g = 0; g < 2; g++) {
+                if (b->exec[g]) (void)hipGraphExecDestroy(b->exec[g]);
+                if (b->graph[g]) (void)hipGraphDestroy(b->graph[g]);
+                b->exec[g] = nullptr;
+                b->graph[g] = nullptr;
+            }
+            b->captured = false;
+        }
+        b->cfl = cfl;
+        // one ordinary step per problem (initialises the old-time bounds), then capture
+        if (nsteps > 0) {
+            for (size_t i = 0; i < b->ps.size(); i++) {
+                adg_problem *pb = b->ps[i];
+                pb->stream = b->streams[i];
+                int rc = adg_step_cfl(pb, cfl);
+                pb->stream = b->saved[i];
+                if (rc != ADG_OK) return rc;
+            }
+            done = 1;
+        }
+        for (size_t i = 0; i < b->ps.size(); i++) HIPCHK(hipStreamSynchronize(b->streams[i]));
+        int rc = batch_capture(b);
+        for (size_t i = 0; i < b->ps.size(); i++) b->ps[i]->stream = b->saved[i];
+        if (rc != ADG_OK) return rc;
+    }
+    for (int s = done; s < nsteps; s++) {
+        HIPCHK(hipGraphLaunch(b->exec[b->parity], b->origin));
+        for (auto *pb : b->ps) host_advance(pb);
+        b->parity ^= 1;
+    }
+    HIPCHK(hipStreamSynchronize(b->origin));
+    return ADG_OK;
+}
+
+int adg_batch_dt(adg_batch *b, double *dts) {
+    if (!b || !dts) return fail(ADG_EINVAL, "bad argument");
+    for (size_t i = 0; i < b->ps.size(); i++) {
+        double s[1];
+        HIPCHK(hipMemcpy(s, b->ps[i]->B.scal, sizeof s, hipMemcpyDeviceToHost));
+        dts[i] = s[0];
+    }
+    return ADG_OK;
+}
+
+int adg_batch_destroy(adg_batch *b) {
+    if (!b) return ADG_OK;
+    if (b->origin) (void)hipStreamSynchronize(b->origin);
+    for (int g = 0; g < 2; g++) {
+        if (b->exec[g]) (void)hipGraphExecDestroy(b->exec[g]);
+        if (b->graph[g]) (void)hipGraphDestroy(b->graph[g]);
+    }
+    for (size_t i = 0; i < b->streams.size(); i++)
+        if (b->streams[i]) (void)hipStreamDestroy(b->streams[i]);
+    for (auto e : b->evs)
+        if (e) (void)hipEventDestroy(e);
+    if (b->origin) (void)hipStreamDestroy(b->origin);
+    for (size_t i = 0; i < b->ps.size(); i++) b->ps[i]->stream = b->saved[i];
+    delete b;
     return ADG_OK;
 }
 

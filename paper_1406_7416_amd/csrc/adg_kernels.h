@@ -17,6 +17,7 @@ struct StepCtx {
     int precision;         // ADG_FP64 or ADG_MIXED
     int ring_only;         // bounds pass over the ghost ring only
     int64_t nring;         // ghost-ring cells
+    int subcell_grid;      // workgroups (= scratch slots) of the subcell recompute
 };
 
 bool supported(int dim, int N);
@@ -30,7 +31,7 @@ void launch_predictor(const StepCtx &C);
 void launch_faces(const StepCtx &C);
 void launch_corrector_detect(const StepCtx &C);
 void launch_compact(const StepCtx &C);
-void launch_subcell_chunk(const StepCtx &C, int first, int count);
+void launch_subcell(const StepCtx &C);
 void launch_fluxcorr(const StepCtx &C, int count);
 void launch_lambda(const StepCtx &C, const double *u, double factor);
 void launch_set_scalar(const StepCtx &C, int idx, double val);

@@ -185,9 +185,9 @@ __device__ __forceinline__ void lds_lines(R *X, int k, int nlines_per_var, int l
     }
 }
 
+// Blocks vb = vb0, vb0 + vbs, ... of CPB cells each, out of ncell cells.
 template <int DIM, int N, bool VOL, typename R>
-__global__ __launch_bounds__((PredShape<DIM, N, R>::BS), 2) void k_predictor(const Tables *__restrict__ T,
-                                                                         PredArgs<R> A, double gamma_d) {
+__device__ void pred_cells(const PredArgs<R> &A, double gamma_d, int64_t ncell, int64_t vb0, int64_t vbs) {
     using S = PredShape<DIM, N, R>;
     const R gamma = (R)gamma_d;
     constexpr int n = S::n, NV = S::NV, NN = S::NN, NST = S::NST, NFN = S::NFN, CPB = S::CPB, VC = S::VC;
@@ -199,11 +199,6 @@ __global__ __launch_bounds__((PredShape<DIM, N, R>::BS), 2) void k_predictor(con
     const int tid = threadIdx.x;
     const int lc = tid / NN, a = tid % NN;
     const double dt = *A.dt;
-    int64_t ncell = A.ncell;
-    if (A.dcount) {
-        const int64_t cnt = *A.dcount;
-        ncell = (cnt < A.dcap ? cnt : A.dcap) * A.dmult;
-    }
     for (int i = tid; i < n * n; i += S::BS) {
         const int r = i / n, cc = i % n;
         Ds[r][cc] = A.D[r * MAXN + cc];
@@ -214,9 +209,8 @@ __global__ __launch_bounds__((PredShape<DIM, N, R>::BS), 2) void k_predictor(con
     const R(*D)[MAXN] = Ds;
     const R(*Kw)[MAXN] = Kws;
     const R(*Dvol)[MAXN] = Dvs;
-    (void)T;
     // persistent over blocks of CPB cells (uniform per block: barriers stay legal)
-    for (int64_t vb = blockIdx.x; vb * CPB < ncell; vb += gridDim.x) {
+    for (int64_t vb = vb0; vb * CPB < ncell; vb += vbs) {
     const int64_t c = vb * CPB + lc;
     const bool owner = (tid < S::ACT) && (c < ncell);
 
@@ -394,6 +388,11 @@ __global__ __launch_bounds__((PredShape<DIM, N, R>::BS), 2) void k_predictor(con
         __syncthreads();
     }
     }  // persistent loop
+}
+
+template <int DIM, int N, bool VOL, typename R>
+__global__ __launch_bounds__((PredShape<DIM, N, R>::BS), 2) void k_predictor(PredArgs<R> A, double gamma_d) {
+    pred_cells<DIM, N, VOL, R>(A, gamma_d, A.ncell, blockIdx.x, gridDim.x);
 }
 
 // ------------------------------------------------------------------- face fluxes
@@ -1017,20 +1016,17 @@ __device__ __forceinline__ void position_coords(int pos, int Ns, int *L) {
 }
 
 // S1: halo of subcell data v^n (eq. (ader.icbc)) 3 subcells deep around the cell.
+// Troubled cell number w of the worklist; scratch slot sidx.
 template <int DIM, int N>
-__global__ __launch_bounds__(256) void k_sub_halo(const Tables *__restrict__ T, Prob P, Bufs B, int cur, int first,
-                                                  int count, int64_t cap) {
-    if (count < 0) count = (int)(B.counts[0] < cap ? B.counts[0] : cap);   // device-driven
-    for (int wb = blockIdx.x; wb < count; wb += gridDim.x) {
+__device__ void sub_halo_cell(const Tables *__restrict__ T, const Prob &P, const Bufs &B, int cur, int w, int sidx) {
     constexpr int n = N + 1, NV = DIM + 2, NN = cpow(n, DIM);
     constexpr int NS = 2 * N + 1, NSUB = cpow(NS, DIM), HN = NS + 6, HSZ = cpow(HN, DIM);
-    const int w = first + wb;
     const int64_t c = B.tlist[w];
     int ci[3];
     coords_of(P, c, ci);
     const double t0 = B.scal[1];
-    double *halo = B.halo + (int64_t)wb * NV * HSZ;
-    for (int hidx = threadIdx.x; hidx < HSZ; hidx += 256) {
+    double *halo = B.halo + (int64_t)sidx * NV * HSZ;
+    for (int hidx = threadIdx.x; hidx < HSZ; hidx += blockDim.x) {
         int hl[3] = {hidx % HN, (hidx / HN) % HN, hidx / (HN * HN)};
         int gci[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, src[3] = {0, 0, 0}, ss[3] = {0, 0, 0}, gside[3] = {-1, -1, -1};
         for (int j = 0; j < DIM; j++) {
@@ -1083,7 +1079,6 @@ __global__ __launch_bounds__(256) void k_sub_halo(const Tables *__restrict__ T, 
 #pragma unroll
         for (int v = 0; v < NV; v++) halo[v * HSZ + hidx] = q[v];
     }
-    }  // persistent loop
 }
 
 // One-dimensional WENO3 (degree 2, three stencils, lambda = 1, 1e5, 1, eps 1e-14, r 8):
@@ -1122,14 +1117,12 @@ __device__ __forceinline__ void weno3(const Tables *__restrict__ T, const double
 // the 3^d GL points of the subcell (x sweep on the averages, then y (then z) sweeps on
 // the nodal values of the previous sweep).
 template <int DIM, int N>
-__global__ void k_sub_recon(const Tables *__restrict__ T, Bufs B, int nch, int64_t cap) {
+__device__ void sub_recon_cell(const Tables *__restrict__ T, const Bufs &B, int sidx) {
     constexpr int NV = DIM + 2, NS = 2 * N + 1, HN = NS + 6, HSZ = cpow(HN, DIM);
     constexpr int NPOS = cpow(NS, DIM) + 2 * DIM * cpow(NS, DIM - 1), N3 = cpow(3, DIM);
     constexpr int W5 = cpow(5, DIM);
-    if (nch < 0) nch = (int)(B.counts[0] < cap ? B.counts[0] : cap);   // device-driven
-    for (int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gid < (int64_t)nch * NPOS;
-         gid += (int64_t)gridDim.x * blockDim.x) {
-    const int ch = (int)(gid / NPOS), pos = (int)(gid % NPOS);
+    const int ch = sidx;
+    for (int pos = threadIdx.x; pos < NPOS; pos += blockDim.x) {
     int L[3];
     position_coords<DIM>(pos, NS, L);
     const double *halo = B.halo + (int64_t)ch * NV * HSZ;
@@ -1180,13 +1173,13 @@ __global__ void k_sub_recon(const Tables *__restrict__ T, Bufs B, int nch, int64
         }
         for (int a = 0; a < N3; a++) Y[v * N3 + a] = src[a];
     }
-    }  // grid-stride loop
+    }
 }
 
 // S4: sub-face Rusanov fluxes, FV update, gather, pool store, boundary fluxes.
 template <int DIM, int N>
-__global__ __launch_bounds__(256) void k_sub_update(const Tables *__restrict__ T, Prob P, Bufs B, int cur, int first,
-                                                    int *nonphys, int count, int64_t cap) {
+__device__ void sub_update_cell(const Tables *__restrict__ T, const Prob &P, const Bufs &B, int cur, int w, int sidx,
+                                int *nonphys) {
     constexpr int n = N + 1, NV = DIM + 2, NN = cpow(n, DIM);
     constexpr int NS = 2 * N + 1, NSUB = cpow(NS, DIM), NSF = cpow(NS, DIM - 1), HN = NS + 6, HSZ = cpow(HN, DIM);
     constexpr int NPOS = NSUB + 2 * DIM * NSF, NF3 = cpow(3, DIM - 1);
@@ -1198,9 +1191,7 @@ __global__ __launch_bounds__(256) void k_sub_update(const Tables *__restrict__ T
     __shared__ double ug[NV * BIG];
     __shared__ double red[2 * NV * 4];
     __shared__ int badc;
-    if (count < 0) count = (int)(B.counts[0] < cap ? B.counts[0] : cap);   // device-driven
-    for (int ch = blockIdx.x; ch < count; ch += gridDim.x) {
-    const int w = first + ch;
+    const int ch = sidx;
     const int64_t c = B.tlist[w];
     int ci[3];
     coords_of(P, c, ci);
@@ -1352,7 +1343,49 @@ __global__ __launch_bounds__(256) void k_sub_update(const Tables *__restrict__ T
     }
     if (threadIdx.x == 0 && badc) atomicAdd(nonphys, 1);
     __syncthreads();   // LDS reused by the next troubled cell
-    }  // persistent loop
+}
+
+// Subcell ADER-WENO3 recompute (operator A of eq. (aderweno)) of every troubled cell:
+// one persistent launch over the global troubled worklist.  A workgroup takes a
+// troubled cell and runs its halo (eq. (ader.icbc)), WENO3 reconstruction, degree-2
+// space-time predictor, sub-face fluxes, FV update and gather, using its own scratch
+// slot (blockIdx.x), so the scratch scales with the grid, not with the worklist.
+template <int DIM, int N>
+__global__ __launch_bounds__(256) void k_subcell(const Tables *__restrict__ T, Prob P, Bufs B, int cur, int64_t cap,
+                                                 int *nonphys) {
+    constexpr int NV = DIM + 2, NS = 2 * N + 1;
+    constexpr int NPOS = cpow(NS, DIM) + 2 * DIM * cpow(NS, DIM - 1), N3 = cpow(3, DIM);
+    static_assert(PredShape<DIM, 2, double>::BS == 256, "subcell predictor block shape");
+    const int count = (int)(B.counts[0] < cap ? B.counts[0] : cap);
+    const int sidx = blockIdx.x;
+    PredArgs<double> A;
+    A.in = B.Y + (int64_t)sidx * NPOS * NV * N3;
+    A.in_cstride = NV * N3;
+    A.in_vstride = N3;
+    A.trace = B.strace + (int64_t)sidx * NPOS * (2 * DIM * NV * cpow(3, DIM - 1) * 3);
+    A.vol_out = nullptr;
+    A.ncell = NPOS;
+    A.cell0 = 0;
+    A.iters = 3;
+    for (int k = 0; k < 3; k++) A.dth[k] = k < DIM ? (double)NS / P.h[k] : 0.0;
+    A.dt = B.scal;
+    A.D = &T->D3[0][0];
+    A.Kw = &T->Kw3[0][0];
+    A.Lb = T->L3;
+    A.Rb = T->R3;
+    A.w = T->w3;
+    A.Dvol = nullptr;
+    A.dcount = nullptr;
+    A.dcap = 0;
+    A.dmult = 1;
+    for (int w = blockIdx.x; w < count; w += gridDim.x) {
+        sub_halo_cell<DIM, N>(T, P, B, cur, w, sidx);
+        __syncthreads();
+        sub_recon_cell<DIM, N>(T, B, sidx);
+        __syncthreads();
+        pred_cells<DIM, 2, false, double>(A, P.gamma, NPOS, 0, 1);
+        sub_update_cell<DIM, N>(T, P, B, cur, w, sidx, nonphys);
+    }
 }
 
 // Flux correction of unlimited cells next to troubled cells (Sec. 4.4): the DG face
@@ -1519,7 +1552,7 @@ struct Launch {
         A.dcap = 0;
         A.dmult = 1;
         const int64_t grid = (C.P.ncell + S::CPB - 1) / S::CPB;
-        hipLaunchKernelGGL((k_predictor<DIM, N, true, R>), dim3((unsigned)grid), dim3(S::BS), 0, C.stream, C.tab, A,
+        hipLaunchKernelGGL((k_predictor<DIM, N, true, R>), dim3((unsigned)grid), dim3(S::BS), 0, C.stream, A,
                            C.P.gamma);
     }
     static void predictor(const StepCtx &C) {
@@ -1562,42 +1595,9 @@ struct Launch {
         hipLaunchKernelGGL((k_neigh_bounds<DIM>), dim3((unsigned)((C.P.ncell + 255) / 256)), dim3(256), 0, C.stream,
                            C.P, C.B);
     }
-    // count >= 0: a host-known chunk [first, first+count); count < 0: the whole troubled
-    // list, its length read on the device (first = 0, at most `capacity` cells).
-    static void subcell_chunk(const StepCtx &C, int first, int count) {
-        const int64_t maxc = count >= 0 ? count : C.capacity;
-        const unsigned gcell = (unsigned)std::min<int64_t>(maxc, 512);
-        hipLaunchKernelGGL((k_sub_halo<DIM, N>), dim3(gcell), dim3(256), 0, C.stream, C.tab, C.P, C.B, C.cur, first,
-                           count, C.capacity);
-        const int64_t npos = maxc * NPOS;
-        hipLaunchKernelGGL((k_sub_recon<DIM, N>), dim3((unsigned)std::min<int64_t>((npos + 127) / 128, 1024)), dim3(128),
-                           0, C.stream, C.tab, C.B, count, C.capacity);
-        using S = PredShape<DIM, 2, double>;
-        PredArgs<double> A;
-        A.in = C.B.Y;
-        A.in_cstride = NV * cpow(3, DIM);
-        A.in_vstride = cpow(3, DIM);
-        A.trace = C.B.strace;
-        A.vol_out = nullptr;
-        A.ncell = npos;
-        A.cell0 = 0;
-        A.iters = 3;
-        for (int k = 0; k < 3; k++) A.dth[k] = k < DIM ? (double)NS / C.P.h[k] : 0.0;
-        A.dt = C.B.scal;
-        A.D = &C.tab->D3[0][0];
-        A.Kw = &C.tab->Kw3[0][0];
-        A.Lb = C.tab->L3;
-        A.Rb = C.tab->R3;
-        A.w = C.tab->w3;
-        A.Dvol = nullptr;
-        A.dcount = count >= 0 ? nullptr : C.B.counts;
-        A.dcap = C.capacity;
-        A.dmult = NPOS;
-        const int64_t grid = std::min<int64_t>((npos + S::CPB - 1) / S::CPB, 1024);
-        hipLaunchKernelGGL((k_predictor<DIM, 2, false, double>), dim3((unsigned)grid), dim3(S::BS), 0, C.stream,
-                           C.tab, A, C.P.gamma);
-        hipLaunchKernelGGL((k_sub_update<DIM, N>), dim3(gcell), dim3(256), 0, C.stream, C.tab, C.P, C.B, C.cur, first,
-                           C.B.counts + 2, count, C.capacity);
+    static void subcell(const StepCtx &C) {
+        hipLaunchKernelGGL((k_subcell<DIM, N>), dim3((unsigned)C.subcell_grid), dim3(256), 0, C.stream, C.tab, C.P,
+                           C.B, C.cur, C.capacity, C.B.counts + 2);
     }
     static void fluxcorr(const StepCtx &C, int count) {
         const unsigned g = (unsigned)std::min<int64_t>(count >= 0 ? count : C.P.ncell, 512);
@@ -1622,7 +1622,7 @@ struct Ops {
     void (*faces)(const StepCtx &);
     void (*corrector_detect)(const StepCtx &);
     void (*bounds)(const StepCtx &);
-    void (*subcell_chunk)(const StepCtx &, int, int);
+    void (*subcell)(const StepCtx &);
     void (*fluxcorr)(const StepCtx &, int);
     void (*lambda)(const StepCtx &, const double *, double);
     int npos;
@@ -1631,7 +1631,7 @@ struct Ops {
 template <int DIM, int N>
 static Ops make_ops() {
     using L = Launch<DIM, N>;
-    return Ops{L::predictor, L::faces, L::corrector_detect, L::bounds, L::subcell_chunk, L::fluxcorr, L::lambda, L::NPOS};
+    return Ops{L::predictor, L::faces, L::corrector_detect, L::bounds, L::subcell, L::fluxcorr, L::lambda, L::NPOS};
 }
 
 static const Ops *ops_for(int dim, int N) {
@@ -1656,9 +1656,7 @@ void launch_compact(const StepCtx &C) {
     hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(1024), 0, C.stream, C.B, nblk, C.capacity);
     hipLaunchKernelGGL(k_compact_scatter, dim3(nblk), dim3(CBS), 0, C.stream, C.P, C.B, C.capacity);
 }
-void launch_subcell_chunk(const StepCtx &C, int first, int count) {
-    ops_for(C.P.dim, C.P.N)->subcell_chunk(C, first, count);
-}
+void launch_subcell(const StepCtx &C) { ops_for(C.P.dim, C.P.N)->subcell(C); }
 void launch_fluxcorr(const StepCtx &C, int count) { ops_for(C.P.dim, C.P.N)->fluxcorr(C, count); }
 void launch_lambda(const StepCtx &C, const double *u, double factor) {
     ops_for(C.P.dim, C.P.N)->lambda(C, u, factor);

@@ -40,7 +40,7 @@ struct adg_problem {
     size_t ws_bytes;
     // offsets into the workspace
     struct Off {
-        size_t tab, u0, u1, emin, emax, bmin, bmax, trace, gbar, beta0, beta1, force, margin, tlist, clist, slot0,
+        size_t tab, u0, u1, emin0, emax0, emin1, emax1, trace, gbar, beta0, beta1, force, margin, tlist, clist, slot0,
             slot1, pool0, pool1, sflux, blk, counts, scal, lampart, ring, halo, Y, strace, end;
     } off;
     int64_t nring = 0;       // ghost-ring cells of the extended grid
@@ -136,10 +136,10 @@ static void plan(adg_problem *pb) {
     f.tab = take(sizeof(Tables));
     f.u0 = take(8ull * nv * nc * nn);
     f.u1 = take(8ull * nv * nc * nn);
-    f.emin = take(8ull * nv * next);
-    f.emax = take(8ull * nv * next);
-    f.bmin = take(8ull * nv * nc);
-    f.bmax = take(8ull * nv * nc);
+    f.emin0 = take(8ull * nv * next);
+    f.emax0 = take(8ull * nv * next);
+    f.emin1 = take(8ull * nv * next);
+    f.emax1 = take(8ull * nv * next);
     f.trace = take(8ull * nc * 2 * d * nv * nfn * n);
     f.gbar = take(8ull * nc * 2 * d * nv * nfn);
     f.beta0 = take(nc);
@@ -177,10 +177,10 @@ static void carve(adg_problem *pb) {
     B.tab = (Tables *)(w + f.tab);
     B.u[0] = (double *)(w + f.u0);
     B.u[1] = (double *)(w + f.u1);
-    B.ext_min = (double *)(w + f.emin);
-    B.ext_max = (double *)(w + f.emax);
-    B.bmin = (double *)(w + f.bmin);
-    B.bmax = (double *)(w + f.bmax);
+    B.ext_min[0] = (double *)(w + f.emin0);
+    B.ext_max[0] = (double *)(w + f.emax0);
+    B.ext_min[1] = (double *)(w + f.emin1);
+    B.ext_max[1] = (double *)(w + f.emax1);
     B.trace = (double *)(w + f.trace);
     B.gbar = (double *)(w + f.gbar);
     B.beta[0] = (uint8_t *)(w + f.beta0);
@@ -698,6 +698,8 @@ static int do_step(adg_problem *pb) {
         std::swap(B.beta[0], B.beta[1]);
         std::swap(B.slot[0], B.slot[1]);
         std::swap(B.pool[0], B.pool[1]);
+        std::swap(B.ext_min[0], B.ext_min[1]);
+        std::swap(B.ext_max[0], B.ext_max[1]);
         // every interior cell's next old-time bounds were written by this step's kernels
         pb->bounds_valid = true;
     }
@@ -850,6 +852,8 @@ static void host_advance(adg_problem *pb) {
         std::swap(B.beta[0], B.beta[1]);
         std::swap(B.slot[0], B.slot[1]);
         std::swap(B.pool[0], B.pool[1]);
+        std::swap(B.ext_min[0], B.ext_min[1]);
+        std::swap(B.ext_max[0], B.ext_max[1]);
         pb->bounds_valid = true;
     }
     pb->cur ^= 1;

@@ -50,8 +50,8 @@ struct Prob {
 struct Bufs {
     Tables *tab;
     double *u[2];          // [v][cell][node] current / next
-    double *ext_min, *ext_max;   // [v][ext cell] per-cell subcell min/max incl. ghost ring
-    double *bmin, *bmax;   // [v][cell] neighbourhood bounds
+    double *ext_min[2], *ext_max[2];   // [v][ext cell] per-cell subcell min/max incl. ghost ring:
+                                       // [0] this step's old-time data, [1] the next step's
     double *trace;         // [cell][2d][v][nfn*n]
     double *gbar;          // [cell][2d][v][nfn]
     uint8_t *beta[2];      // [cell] old / new
@@ -63,6 +63,7 @@ struct Bufs {
     double *sflux;         // [slot][2d][v][subf]
     int *blk;              // block partial counts for compaction [2][nblk]
     int *counts;           // [0] troubled [1] corrected [2] nonphysical cumulative [3] capacity overflow
+                           // [4] block ticket of the compaction
     double *scal;          // [0] dt [1] t [2] lambda_max ...
     double *lam_part;      // per-block lambda partials
     int64_t *ring;         // extended-grid indices of the ghost ring

@@ -548,7 +548,8 @@ __device__ __forceinline__ int64_t ext_count(const Prob &P) {
 }
 
 // Per-variable min / max of one cell's subcell data held in LDS (v[var*nsub + s]),
-// stored as that cell's old-time bounds for the next step.
+// stored as that cell's old-time bounds for the next step (the second bounds buffer:
+// the first still holds this step's, read by the detection of other cells).
 template <int NV>
 __device__ __forceinline__ void store_cell_bounds(const Prob &P, const Bufs &B, int64_t c, const double *v, int nsub,
                                                   int tid, int bs, double *scratch) {
@@ -568,8 +569,8 @@ __device__ __forceinline__ void store_cell_bounds(const Prob &P, const Bufs &B, 
     if (tid == 0) {
         const int64_t e = ext_index(P, c), next = ext_count(P);
         for (int k = 0; k < NV; k++) {
-            B.ext_min[(int64_t)k * next + e] = lo[k];
-            B.ext_max[(int64_t)k * next + e] = hi[k];
+            B.ext_min[1][(int64_t)k * next + e] = lo[k];
+            B.ext_max[1][(int64_t)k * next + e] = hi[k];
         }
     }
 }
@@ -637,6 +638,8 @@ __global__ __launch_bounds__(128) void k_corrector_detect(const Tables *__restri
     __shared__ double red[2 * NV * 2];
     __shared__ int bad_s[2];
     __shared__ float mg_s[2];
+    __shared__ double Ps[NS * MAXN];      // projection operator of eq. (subcell.p)
+    __shared__ double bnd[2][NV];         // m_i, M_i of eq. (dmp) for this cell
     const int64_t c = blockIdx.x;
     const int tid = threadIdx.x;
     const double dt = B.scal[0];
@@ -644,6 +647,30 @@ __global__ __launch_bounds__(128) void k_corrector_detect(const Tables *__restri
     // (dt/h_k)/w_a for every axis and node index: 2 divisions per entry, once per block
     __shared__ double coef[3][n];
     if (tid < DIM * n) coef[tid / n][tid % n] = dt / P.h[tid / n] / T->w[tid % n];
+    if (limiter) {
+        for (int i = tid; i < NS * MAXN; i += 128) Ps[i] = (&T->P[0][0])[i];
+        // min (mm = 0) / max (mm = 1) of variable v over the 3^d block V_i of the
+        // per-cell old-time bounds, held on the extended grid (cell c sits at ci + 1)
+        const int mm = tid / NV, v = tid % NV;
+        if (tid < 2 * NV) {
+            int ci[3];
+            coords_of(P, c, ci);
+            int ne[3] = {1, 1, 1};
+            for (int j = 0; j < DIM; j++) ne[j] = P.nc[j] + 2;
+            const int64_t next = ext_count(P);
+            const double *src = (mm ? B.ext_max[0] : B.ext_min[0]) + (int64_t)v * next;
+            double acc = mm ? -INFINITY : INFINITY;
+            constexpr int NB = cpow(3, DIM);
+#pragma unroll
+            for (int o = 0; o < NB; o++) {
+                const int off[3] = {o % 3, (o / 3) % 3, o / 9};
+                int64_t e = 0;
+                for (int j = DIM - 1; j >= 0; j--) e = e * ne[j] + (ci[j] + off[j]);
+                acc = mm ? fmax(acc, src[e]) : fmin(acc, src[e]);
+            }
+            bnd[mm][v] = acc;
+        }
+    }
     __syncthreads();
     for (int it = tid; it < NV * NN; it += 128) {
         const int v = it / NN, a = it % NN;
@@ -669,13 +696,13 @@ __global__ __launch_bounds__(128) void k_corrector_detect(const Tables *__restri
     }
     if (!limiter) return;
     __syncthreads();
-    tensor_apply<DIM, NS, n, NV, MAXN>(&T->P[0][0], us, vs, tmp, tid, 128);
+    tensor_apply<DIM, NS, n, NV, MAXN>(Ps, us, vs, tmp, tid, 128);
     // detection on the NSUB candidate subcell averages
     double m_[NV], M_[NV];
 #pragma unroll
     for (int v = 0; v < NV; v++) {
-        m_[v] = B.bmin[(int64_t)v * P.ncell + c];
-        M_[v] = B.bmax[(int64_t)v * P.ncell + c];
+        m_[v] = bnd[0][v];
+        M_[v] = bnd[1][v];
     }
     int bad = 0;
     float mg = INFINITY;
@@ -756,7 +783,9 @@ __global__ __launch_bounds__(128) void k_cell_bounds(const Tables *__restrict__ 
     __shared__ double vs[NV * BIG];
     __shared__ double tmp[NV * BIG];
     __shared__ double red[2 * NV * 2];
+    __shared__ double Ps[NS * MAXN];
     const int tid = threadIdx.x;
+    for (int i = tid; i < NS * MAXN; i += 128) Ps[i] = (&T->P[0][0])[i];
     // all extended cells, or only the ghost ring (interior bounds then come from the
     // kernels of the previous step that produced each cell's new subcell data)
     const int64_t e = ring ? ring[blockIdx.x] : (int64_t)blockIdx.x;
@@ -798,7 +827,7 @@ __global__ __launch_bounds__(128) void k_cell_bounds(const Tables *__restrict__ 
             us[it] = uo[((int64_t)v * P.ncell + cs) * NN + a];
         }
         __syncthreads();
-        tensor_apply<DIM, NS, n, NV, MAXN>(&T->P[0][0], us, vs, tmp, tid, 128);
+        tensor_apply<DIM, NS, n, NV, MAXN>(Ps, us, vs, tmp, tid, 128);
     }
     const double t0 = B.scal[1];
     double lo[NV], hi[NV];
@@ -837,53 +866,16 @@ __global__ __launch_bounds__(128) void k_cell_bounds(const Tables *__restrict__ 
         int64_t next = 1;
         for (int j = 0; j < DIM; j++) next *= ne[j];
         for (int v = 0; v < NV; v++) {
-            B.ext_min[(int64_t)v * next + e] = lo[v];
-            B.ext_max[(int64_t)v * next + e] = hi[v];
+            B.ext_min[0][(int64_t)v * next + e] = lo[v];
+            B.ext_max[0][(int64_t)v * next + e] = hi[v];
         }
-    }
-}
-
-// min / max over the 3^d block V_i of the extended per-cell bounds (eq. (dmp)).
-template <int DIM>
-__global__ void k_neigh_bounds(Prob P, Bufs B) {
-    constexpr int NV = DIM + 2;
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= P.ncell) return;
-    int ci[3];
-    coords_of(P, c, ci);
-    int ne[3] = {1, 1, 1};
-    int64_t next = 1;
-    for (int j = 0; j < DIM; j++) {
-        ne[j] = P.nc[j] + 2;
-        next *= ne[j];
-    }
-    double lo[NV], hi[NV];
-#pragma unroll
-    for (int v = 0; v < NV; v++) {
-        lo[v] = INFINITY;
-        hi[v] = -INFINITY;
-    }
-    constexpr int NB = cpow(3, DIM);
-    for (int o = 0; o < NB; o++) {
-        int off[3] = {o % 3, (o / 3) % 3, o / 9};
-        int64_t e = 0;
-        for (int j = DIM - 1; j >= 0; j--) e = e * ne[j] + (ci[j] + off[j]);  // ext index = ci + 1 + (off - 1)
-#pragma unroll
-        for (int v = 0; v < NV; v++) {
-            lo[v] = fmin(lo[v], B.ext_min[(int64_t)v * next + e]);
-            hi[v] = fmax(hi[v], B.ext_max[(int64_t)v * next + e]);
-        }
-    }
-#pragma unroll
-    for (int v = 0; v < NV; v++) {
-        B.bmin[(int64_t)v * P.ncell + c] = lo[v];
-        B.bmax[(int64_t)v * P.ncell + c] = hi[v];
     }
 }
 
 // ------------------------------------------------------------------ compaction
 // Troubled cells and unlimited neighbours of troubled cells, compacted in cell order
-// with wavefront ballots and a block prefix; three passes (count, scan, scatter).
+// with wavefront ballots and a block prefix; two passes (count, with the scan of the
+// block counts done by the last block to finish, then scatter).
 __device__ __forceinline__ bool corr_flag(const Prob &P, const uint8_t *beta, int64_t c) {
     if (beta[c]) return false;
     int ci[3];
@@ -903,8 +895,10 @@ __device__ __forceinline__ bool corr_flag(const Prob &P, const uint8_t *beta, in
 
 constexpr int CBS = 256;   // compaction block size
 
-__global__ __launch_bounds__(CBS) void k_compact_count(Prob P, Bufs B) {
+__global__ __launch_bounds__(CBS) void k_compact_count(Prob P, Bufs B, int64_t cap) {
     __shared__ int cnt[2][CBS / 64];
+    __shared__ int last;
+    __shared__ int carry[2];
     const int64_t c = (int64_t)blockIdx.x * CBS + threadIdx.x;
     const bool t = c < P.ncell && B.beta[1][c];
     const bool f = c < P.ncell && corr_flag(P, B.beta[1], c);
@@ -915,46 +909,53 @@ __global__ __launch_bounds__(CBS) void k_compact_count(Prob P, Bufs B) {
         cnt[1][wv] = __popcll(bf);
     }
     __syncthreads();
+    const int nblk = gridDim.x;
     if (threadIdx.x == 0) {
         int s0 = 0, s1 = 0;
         for (int w = 0; w < CBS / 64; w++) { s0 += cnt[0][w]; s1 += cnt[1][w]; }
         B.blk[blockIdx.x] = s0;
-        B.blk[gridDim.x + blockIdx.x] = s1;
+        B.blk[nblk + blockIdx.x] = s1;
+        __threadfence();
+        // the block that arrives last (no block waits for another) turns the block
+        // counts into exclusive offsets
+        last = (atomicAdd(&B.counts[4], 1) == nblk - 1);
     }
-}
-
-__global__ __launch_bounds__(1024) void k_compact_scan(Bufs B, int nblk, int64_t cap) {
-    // exclusive scan of both block-count arrays, single block, sequential chunks
-    __shared__ int part[2][1024];
-    __shared__ int carry[2];
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
     if (threadIdx.x == 0) { carry[0] = 0; carry[1] = 0; }
     __syncthreads();
-    for (int base = 0; base < nblk; base += 1024) {
+    for (int base = 0; base < nblk; base += CBS) {
         const int i = base + threadIdx.x;
-        for (int a = 0; a < 2; a++) part[a][threadIdx.x] = (i < nblk) ? B.blk[a * nblk + i] : 0;
-        __syncthreads();
-        // Hillis-Steele inclusive scan
-        for (int off = 1; off < 1024; off <<= 1) {
-            int v0 = 0, v1 = 0;
-            if (threadIdx.x >= off) { v0 = part[0][threadIdx.x - off]; v1 = part[1][threadIdx.x - off]; }
-            __syncthreads();
-            part[0][threadIdx.x] += v0;
-            part[1][threadIdx.x] += v1;
-            __syncthreads();
-        }
+        int v0 = 0, v1 = 0;
         if (i < nblk) {
-            const int in0 = B.blk[i], in1 = B.blk[nblk + i];
-            B.blk[i] = carry[0] + part[0][threadIdx.x] - in0;
-            B.blk[nblk + i] = carry[1] + part[1][threadIdx.x] - in1;
+            v0 = __atomic_load_n(&B.blk[i], __ATOMIC_RELAXED);
+            v1 = __atomic_load_n(&B.blk[nblk + i], __ATOMIC_RELAXED);
+        }
+        // inclusive scan: within each wave by shuffles, then across the waves' totals
+        int x0 = v0, x1 = v1;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int y0 = __shfl_up(x0, off), y1 = __shfl_up(x1, off);
+            if (lane >= off) { x0 += y0; x1 += y1; }
+        }
+        if (lane == 63) { cnt[0][wv] = x0; cnt[1][wv] = x1; }
+        __syncthreads();
+        int p0 = carry[0], p1 = carry[1];
+        for (int w = 0; w < wv; w++) { p0 += cnt[0][w]; p1 += cnt[1][w]; }
+        if (i < nblk) {
+            B.blk[i] = p0 + x0 - v0;
+            B.blk[nblk + i] = p1 + x1 - v1;
         }
         __syncthreads();
-        if (threadIdx.x == 0) { carry[0] += part[0][1023]; carry[1] += part[1][1023]; }
+        if (threadIdx.x == CBS - 1) { carry[0] = p0 + x0; carry[1] = p1 + x1; }
         __syncthreads();
     }
     if (threadIdx.x == 0) {
         B.counts[0] = carry[0];
         B.counts[1] = carry[1];
         if (carry[0] > cap) B.counts[3] = 1;
+        B.counts[4] = 0;   // ticket for the next step
     }
 }
 
@@ -1400,9 +1401,11 @@ __global__ __launch_bounds__(128) void k_fluxcorr(const Tables *__restrict__ T, 
     __shared__ double vs[NV_ * NSUB_];
     __shared__ double tmp[NV_ * TMP_];
     __shared__ double red[2 * NV_ * 2];
+    __shared__ double Ps[NS_ * MAXN];
     constexpr int n = N + 1, NV = DIM + 2, NN = cpow(n, DIM), NFN = cpow(n, DIM - 1);
     constexpr int NS = 2 * N + 1, NSF = cpow(NS, DIM - 1);
     if (count < 0) count = B.counts[1];   // device-driven
+    for (int i = threadIdx.x; i < NS * MAXN; i += 128) Ps[i] = (&T->P[0][0])[i];
     for (int wb = blockIdx.x; wb < count; wb += gridDim.x) {
     const int64_t c = B.clist[wb];
     int ci[3];
@@ -1464,7 +1467,7 @@ __global__ __launch_bounds__(128) void k_fluxcorr(const Tables *__restrict__ T, 
     }
     __syncthreads();
     // the corrected state's subcell min / max are this cell's next old-time bounds
-    tensor_apply<DIM, NS, n, NV, MAXN>(&T->P[0][0], us, vs, tmp, threadIdx.x, 128);
+    tensor_apply<DIM, NS, n, NV, MAXN>(Ps, us, vs, tmp, threadIdx.x, 128);
     store_cell_bounds<NV>(P, B, c, vs, NSUB_, threadIdx.x, 128, red);
     __syncthreads();   // LDS reused by the next corrected cell
     }  // persistent loop
@@ -1592,8 +1595,6 @@ struct Launch {
         if (nblk > 0)
             hipLaunchKernelGGL((k_cell_bounds<DIM, N>), dim3((unsigned)nblk), dim3(128), 0, C.stream, C.tab, C.P, C.B,
                                C.cur, C.ring_only ? C.B.ring : (const int64_t *)nullptr);
-        hipLaunchKernelGGL((k_neigh_bounds<DIM>), dim3((unsigned)((C.P.ncell + 255) / 256)), dim3(256), 0, C.stream,
-                           C.P, C.B);
     }
     static void subcell(const StepCtx &C) {
         hipLaunchKernelGGL((k_subcell<DIM, N>), dim3((unsigned)C.subcell_grid), dim3(256), 0, C.stream, C.tab, C.P,
@@ -1652,8 +1653,7 @@ void launch_faces(const StepCtx &C) { ops_for(C.P.dim, C.P.N)->faces(C); }
 void launch_corrector_detect(const StepCtx &C) { ops_for(C.P.dim, C.P.N)->corrector_detect(C); }
 void launch_compact(const StepCtx &C) {
     const int nblk = (int)((C.P.ncell + CBS - 1) / CBS);
-    hipLaunchKernelGGL(k_compact_count, dim3(nblk), dim3(CBS), 0, C.stream, C.P, C.B);
-    hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(1024), 0, C.stream, C.B, nblk, C.capacity);
+    hipLaunchKernelGGL(k_compact_count, dim3(nblk), dim3(CBS), 0, C.stream, C.P, C.B, C.capacity);
     hipLaunchKernelGGL(k_compact_scatter, dim3(nblk), dim3(CBS), 0, C.stream, C.P, C.B, C.capacity);
 }
 void launch_subcell(const StepCtx &C) { ops_for(C.P.dim, C.P.N)->subcell(C); }

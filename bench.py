@@ -45,6 +45,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--grid", type=int, default=64)
     ap.add_argument("--N", type=int, default=9)
+    ap.add_argument("--breakdown-steps", type=int, default=10,
+                    help="untimed steps with events around every kernel group (per-kernel breakdown)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="bounded CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the four-quadrant batch measurement")
@@ -95,20 +97,28 @@ def main():
         for _ in range(args.warmup):
             prob.step_cfl()
         torch.cuda.synchronize()
-        prob.profile(True)
+        # timed region: HIP events around the dominant kernel only (two event records per
+        # step on the problem's stream)
+        prob.profile(True, groups=["predictor"])
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
             prob.step_cfl()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        prof = prob.profile_read()
+        pred_ms, pred_n = prob.profile_read()["predictor"]
         prob.profile(False)
         elapsed = t1 - t0
+        # per-kernel-group breakdown from a separate, untimed pass with events around
+        # every group
+        prob.profile(True)
+        for _ in range(args.breakdown_steps):
+            prob.step_cfl()
+        prof = prob.profile_read()
+        prob.profile(False)
         t_sim = prob.time
         u = prob.state()
         ue, _ = prob.project(lambda x, t: wl.ic(x, t_sim), 0)
-        pred_ms, pred_n = prof["predictor"]
         forms[form] = {
             "value": st_dof_step * args.steps / elapsed,
             "ms_per_step": 1e3 * elapsed / args.steps,

@@ -156,8 +156,10 @@ int adg_get_stats(const adg_problem *pb, int64_t *out4);
 /* Per-kernel timing with hipEvents recorded on the bound stream around each kernel
  * group.  Groups: 0 old-time bounds, 1 predictor, 2 face fluxes, 3 corrector + detection,
  * 4 compaction, 5 subcell ADER-WENO3, 6 flux correction, 7 time-step reduction.
- * adg_profile(pb, 1) starts (and clears), 0 stops.  adg_profile_read fills ms[g] (total
- * milliseconds) and launches[g] for g < ngroups (<= 8).  Synchronising. */
+ * adg_profile(pb, mask) clears the totals and times the groups whose bit is set in mask
+ * (bit g: group g; 0xFF: all; each timed group adds two event records per step);
+ * adg_profile(pb, 0) stops.  adg_profile_read fills ms[g] (total milliseconds) and
+ * launches[g] for g < ngroups (<= 8).  Synchronising. */
 int adg_profile(adg_problem *pb, int enable);
 int adg_profile_read(adg_problem *pb, double *ms, int64_t *launches, int ngroups);
 

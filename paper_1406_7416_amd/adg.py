@@ -250,8 +250,15 @@ class Problem:
         _check(load().adg_get_subcells(self.h, _dp(v)))
         return v
 
-    def profile(self, enable: bool):
-        _check(load().adg_profile(self.h, 1 if enable else 0))
+    def profile(self, enable, groups=None):
+        """Starts (clears) or stops per-kernel-group timing; `groups` names the groups
+        to time (default: all of KERNEL_GROUPS)."""
+        mask = 0
+        if enable:
+            names = KERNEL_GROUPS if groups is None else groups
+            for g in names:
+                mask |= 1 << KERNEL_GROUPS.index(g)
+        _check(load().adg_profile(self.h, mask))
 
     def profile_read(self) -> dict:
         ms = np.zeros(8)

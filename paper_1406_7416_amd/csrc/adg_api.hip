@@ -57,7 +57,7 @@ struct adg_problem {
     bool capturing = false;              // inside a batch graph capture
     int64_t last_troubled = 0, last_corrected = 0, steps = 0;
     // kernel-group timing
-    bool profiling = false;
+    unsigned prof_mask = 0;   // kernel groups timed (bit g: group g)
     struct Mark { int group; hipEvent_t a, b; };
     std::vector<Mark> pending;
     std::vector<hipEvent_t> spare;
@@ -76,19 +76,19 @@ static hipEvent_t take_event(adg_problem *pb) {
     return e;
 }
 
-// Records events around one kernel group when profiling is on.
+// Records events around one kernel group when that group is timed.
 struct GroupTimer {
     adg_problem *pb;
     int group;
     hipEvent_t a = nullptr, b = nullptr;
     GroupTimer(adg_problem *p, int g) : pb(p), group(g) {
-        if (!pb->profiling) return;
+        if (!((pb->prof_mask >> g) & 1u)) return;
         a = take_event(pb);
         b = take_event(pb);
         if (a) (void)hipEventRecord(a, pb->stream);
     }
     ~GroupTimer() {
-        if (!pb->profiling || !a || !b) return;
+        if (!a || !b) return;
         (void)hipEventRecord(b, pb->stream);
         pb->pending.push_back({group, a, b});
     }
@@ -814,7 +814,7 @@ int adg_profile(adg_problem *pb, int enable) {
             pb->prof_n[g] = 0;
         }
     }
-    pb->profiling = enable != 0;
+    pb->prof_mask = (unsigned)enable & 0xFFu;
     return ADG_OK;
 }
 

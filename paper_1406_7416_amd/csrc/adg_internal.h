@@ -24,8 +24,13 @@ struct Tables {
     double xi3[3], w3[3];
     double D3[MAXN][MAXN], L3[MAXN], R3[MAXN], Kw3[MAXN][MAXN];
     double weno[3][3][3];        // [stencil][monomial][cell]: averages -> coefficients
+    // Even / odd parts of D on the symmetric nodes, where D[n-1-a][n-1-b] = -D[a][b]:
+    //   DE[a][b] = (D[a][b] + D[a][n-1-b]) / 2,  DO[a][b] = (D[a][b] - D[a][n-1-b]) / 2
+    // for a, b < n/2; odd n adds DE[a][n/2] = D[a][n/2] and the middle row DO[n/2][b] = D[n/2][b].
+    double DE[MAXN / 2][MAXN / 2 + 1], DO[MAXN / 2 + 1][MAXN / 2];
     // FP32 copies for the mixed-precision predictor and face fluxes
     float fD[MAXN][MAXN], fKw[MAXN][MAXN], fDvol[MAXN][MAXN], fL[MAXN], fR[MAXN], fw[MAXN];
+    float fDE[MAXN / 2][MAXN / 2 + 1], fDO[MAXN / 2 + 1][MAXN / 2];
 };
 
 struct BCDev {

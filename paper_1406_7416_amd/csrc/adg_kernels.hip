@@ -101,6 +101,14 @@ __device__ __forceinline__ void coords_of(const Prob &P, int64_t c, int *ci) {
 // (n loads -> n outputs each, in place); the point owner accumulates S over the d axes
 // and applies the time contraction in registers: d + 1 contractions per sweep.
 template <int DIM, int N, typename R = double>
+struct PredShape;
+
+// 1/x: correctly rounded division in FP64; the hardware reciprocal (within 1 ulp) in
+// the FP32 working precision of the mixed form.
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+
+template <int DIM, int N, typename R>
 struct PredShape {
     static constexpr int n = N + 1;
     static constexpr int NV = DIM + 2;
@@ -128,20 +136,24 @@ struct PredArgs {
     const double *dt;      // device scalar
     // operators of the n-node basis used by this launch (row stride MAXN)
     const R *D, *Kw, *Lb, *Rb, *w, *Dvol;
+    const R *DE, *DO;      // even / odd parts of D (row strides MAXN/2 + 1 and MAXN/2)
     // if set, the number of cells is min(*dcount, dcap) * dmult (read on the device)
     const int *dcount;
     int64_t dcap;
     int dmult;
 };
 
-// Contraction along axis k of every line held in LDS: line[i] <- c * sum_b M[i][b] line[b].
-// One work item handles the same line of LV variables (independent FMA chains; LV is
-// smaller for long lines to bound register use).
-template <int DIM, int N, int CPB, int VC, int BS, typename R>
+// Contraction along axis k of every line held in LDS: line[i] <- c * sum_b M[i][b] line[b]
+// (c only if SCALE).  One work item handles the same line of LV variables (independent FMA
+// chains sharing each operator entry; LV is 1 for long FP64 lines to bound register use).
+// EO: M is the derivative matrix on symmetric nodes, applied through its even / odd parts
+// E, O (half-size products on x_b +- x_{n-1-b}: n^2/2 + 2n operations instead of n^2).
+template <int DIM, int N, int CPB, int VC, int BS, typename R, bool EO = false, bool SCALE = true>
 __device__ __forceinline__ void lds_lines(R *X, int k, int nlines_per_var, int lstride_s, const R (*M)[MAXN], R c,
-                                          int tid, int nvalid) {
+                                          int tid, int nvalid, const R (*E)[MAXN / 2 + 1] = nullptr,
+                                          const R (*O)[MAXN / 2] = nullptr) {
     constexpr int n = N + 1, NN = cpow(n, DIM), NST = NN * n;
-    constexpr int LV = (n >= 8) ? 1 : VC;
+    constexpr int LV = (n >= 8 && sizeof(R) == 8) ? 1 : VC;
     constexpr int NG = (VC + LV - 1) / LV;   // variable groups per line
     const int st = (k == 0) ? 1 : (k == 1 ? n : n * n);
     const int nitems = CPB * NG * nlines_per_var;
@@ -167,20 +179,73 @@ __device__ __forceinline__ void lds_lines(R *X, int k, int nlines_per_var, int l
         for (int vv = 0; vv < LV; vv++)
 #pragma unroll
             for (int b = 0; b < n; b++) xb[vv][b] = (v0 + vv < nvalid) ? line0[vv * NST + b * st] : R(0);
-#pragma unroll
-        for (int i = 0; i < n; i++) {
-            R acc[LV];
-#pragma unroll
-            for (int vv = 0; vv < LV; vv++) acc[vv] = 0;
-#pragma unroll
-            for (int b = 0; b < n; b++) {
-                const R m = M[i][b];
-#pragma unroll
-                for (int vv = 0; vv < LV; vv++) acc[vv] += m * xb[vv][b];
-            }
+        if constexpr (EO) {
+            constexpr int h = n / 2;
+            R e[LV][h], o[LV][h];
 #pragma unroll
             for (int vv = 0; vv < LV; vv++)
-                if (v0 + vv < nvalid) line0[vv * NST + i * st] = c * acc[vv];
+#pragma unroll
+                for (int b = 0; b < h; b++) {
+                    e[vv][b] = xb[vv][b] + xb[vv][n - 1 - b];
+                    o[vv][b] = xb[vv][b] - xb[vv][n - 1 - b];
+                }
+#pragma unroll
+            for (int i = 0; i < h; i++) {
+                R pe[LV], po[LV];
+#pragma unroll
+                for (int vv = 0; vv < LV; vv++) pe[vv] = po[vv] = 0;
+#pragma unroll
+                for (int b = 0; b < h; b++) {
+                    const R me = E[i][b], mo = O[i][b];
+#pragma unroll
+                    for (int vv = 0; vv < LV; vv++) {
+                        pe[vv] += me * e[vv][b];
+                        po[vv] += mo * o[vv][b];
+                    }
+                }
+                if constexpr (n % 2) {
+                    const R mm = E[i][h];
+#pragma unroll
+                    for (int vv = 0; vv < LV; vv++) pe[vv] += mm * xb[vv][h];
+                }
+#pragma unroll
+                for (int vv = 0; vv < LV; vv++)
+                    if (v0 + vv < nvalid) {
+                        const R yi = po[vv] + pe[vv], yr = po[vv] - pe[vv];
+                        line0[vv * NST + i * st] = SCALE ? c * yi : yi;
+                        line0[vv * NST + (n - 1 - i) * st] = SCALE ? c * yr : yr;
+                    }
+            }
+            if constexpr (n % 2) {
+                R acc[LV];
+#pragma unroll
+                for (int vv = 0; vv < LV; vv++) acc[vv] = 0;
+#pragma unroll
+                for (int b = 0; b < h; b++) {
+                    const R mo = O[h][b];
+#pragma unroll
+                    for (int vv = 0; vv < LV; vv++) acc[vv] += mo * o[vv][b];
+                }
+#pragma unroll
+                for (int vv = 0; vv < LV; vv++)
+                    if (v0 + vv < nvalid) line0[vv * NST + h * st] = SCALE ? c * acc[vv] : acc[vv];
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < n; i++) {
+                R acc[LV];
+#pragma unroll
+                for (int vv = 0; vv < LV; vv++) acc[vv] = 0;
+#pragma unroll
+                for (int b = 0; b < n; b++) {
+                    const R m = M[i][b];
+#pragma unroll
+                    for (int vv = 0; vv < LV; vv++) acc[vv] += m * xb[vv][b];
+                }
+#pragma unroll
+                for (int vv = 0; vv < LV; vv++)
+                    if (v0 + vv < nvalid) line0[vv * NST + i * st] = SCALE ? c * acc[vv] : acc[vv];
+            }
         }
     }
 }
@@ -195,6 +260,9 @@ __device__ void pred_cells(const PredArgs<R> &A, double gamma_d, int64_t ncell, 
     // operators staged in LDS and read as wave-uniform broadcasts inside the loops (kept
     // out of registers: the n x n matrices would otherwise be hoisted into VGPRs)
     __shared__ R Ds[n][MAXN], Kws[n][MAXN], Dvs[n][MAXN];
+    // the spatial contractions use the even / odd form where it saves work (n >= 6)
+    constexpr bool EO = n >= 6;
+    __shared__ R Es[EO ? MAXN / 2 : 1][MAXN / 2 + 1], Os[EO ? MAXN / 2 + 1 : 1][MAXN / 2];
 
     const int tid = threadIdx.x;
     const int lc = tid / NN, a = tid % NN;
@@ -204,6 +272,12 @@ __device__ void pred_cells(const PredArgs<R> &A, double gamma_d, int64_t ncell, 
         Ds[r][cc] = A.D[r * MAXN + cc];
         Kws[r][cc] = A.Kw[r * MAXN + cc];
         Dvs[r][cc] = VOL ? A.Dvol[r * MAXN + cc] : R(0);
+    }
+    if constexpr (EO) {
+        for (int i = tid; i < (MAXN / 2) * (MAXN / 2 + 1); i += S::BS) {
+            Es[i / (MAXN / 2 + 1)][i % (MAXN / 2 + 1)] = A.DE[i];
+            Os[i / (MAXN / 2)][i % (MAXN / 2)] = A.DO[i];
+        }
     }
     __syncthreads();
     const R(*D)[MAXN] = Ds;
@@ -233,17 +307,13 @@ __device__ void pred_cells(const PredArgs<R> &A, double gamma_d, int64_t ncell, 
         for (int s = 0; s < n; s++) q[v][s] = u0[v];
 
     for (int r = 0; r < A.iters; r++) {
-#pragma unroll
-        for (int v = 0; v < NV; v++)
-#pragma unroll
-            for (int s = 0; s < n; s++) Sacc[v][s] = 0;
         // 1/rho of every node of the pencil, shared by the fluxes of all axes (for long
-        // pencils recomputed per axis instead, to stay within 256 registers)
-        constexpr bool CACHE_IRHO = n < 8;
+        // FP64 pencils recomputed per axis instead, to stay within 256 registers)
+        constexpr bool CACHE_IRHO = n < 8 || sizeof(R) == 4;
         R irho[CACHE_IRHO ? n : 1];
         if constexpr (CACHE_IRHO) {
 #pragma unroll
-            for (int t = 0; t < n; t++) irho[t] = R(1) / q[0][t];
+            for (int t = 0; t < n; t++) irho[t] = recip(q[0][t]);
         }
 #pragma unroll
         for (int k = 0; k < DIM; k++) {
@@ -255,7 +325,7 @@ __device__ void pred_cells(const PredArgs<R> &A, double gamma_d, int64_t ncell, 
                     for (int t = 0; t < n; t++) {
                         R ir;
                         if constexpr (CACHE_IRHO) ir = irho[t];
-                        else ir = R(1) / q[0][t];
+                        else ir = recip(q[0][t]);
                         const R un = q[1 + k][t] * ir;
                         R ke = 0;
 #pragma unroll
@@ -272,14 +342,25 @@ __device__ void pred_cells(const PredArgs<R> &A, double gamma_d, int64_t ncell, 
                     }
                 }
                 __syncthreads();
-                lds_lines<DIM, N, CPB, VC, S::BS, R>(X, k, NN, NN, D, ck, tid, NV - v0 < VC ? NV - v0 : VC);
+                lds_lines<DIM, N, CPB, VC, S::BS, R, EO, false>(X, k, NN, NN, D, R(1), tid,
+                                                                NV - v0 < VC ? NV - v0 : VC, Es, Os);
                 __syncthreads();
+                // S = sum_k (dt/h_k) D_k F_k, the factor applied while accumulating
                 if (tid < S::ACT) {
 #pragma unroll
                     for (int vv = 0; vv < VC; vv++)
                         if (v0 + vv < NV)
 #pragma unroll
-                            for (int t = 0; t < n; t++) Sacc[v0 + vv][t] += X[(lc * VC + vv) * NST + a + NN * t];
+                            for (int t = 0; t < n; t++) {
+                                const R xk = X[(lc * VC + vv) * NST + a + NN * t];
+                                Sacc[v0 + vv][t] = (k == 0) ? ck * xk : Sacc[v0 + vv][t] + ck * xk;
+                            }
+                } else if (k == 0) {
+#pragma unroll
+                    for (int vv = 0; vv < VC; vv++)
+                        if (v0 + vv < NV)
+#pragma unroll
+                            for (int t = 0; t < n; t++) Sacc[v0 + vv][t] = 0;
                 }
                 __syncthreads();
             }
@@ -576,48 +657,56 @@ __device__ __forceinline__ void store_cell_bounds(const Prob &P, const Bufs &B, 
 }
 
 // --------------------------------------------------- tensor application in LDS
-// out[v][...] = sum over axis k of M[i][b] in[...b...], applied axis by axis.  Before
-// stage k the axes < k have size M (output) and the axes >= k size NI (input).  Sizes
-// are compile-time so that the index arithmetic uses no integer division.
-template <int DIM, int M, int NI, int NVAR, int MSTRIDE>
-__device__ void tensor_apply(const double *Mbase, const double *in, double *out, double *tmp, int tid, int bs) {
-    const double *src = in;
+// out[v][...] = sum over axis k of M[i][b] in[...b...], applied axis by axis (sum
+// factorisation).  Before stage k the axes < k have size M (output) and the axes >= k size
+// NI (input).  One thread owns one line along axis k: it loads the NI inputs of its line
+// once and produces the M outputs.  The operator entries are the same for every lane, so
+// they are read from the table in global memory through scalar loads, not from LDS.
+template <int DIM, int K, int M, int NI, int NVAR, int MSTRIDE>
+__device__ __forceinline__ void tensor_stage(const double *__restrict__ Mat, const double *src, double *dst, int tid,
+                                             int bs) {
+    constexpr int S0 = (0 < K) ? M : NI, S1 = (1 < K) ? M : NI, S2 = (DIM == 3) ? ((2 < K) ? M : NI) : 1;
+    constexpr int IS[3] = {1, S0, S0 * S1};                               // input strides
+    constexpr int O0 = (0 <= K) ? M : NI, O1 = (1 <= K) ? M : NI;
+    constexpr int OS[3] = {1, O0, O0 * O1};                               // output strides
+    constexpr int SZB = S0 * S1 * S2;
+    constexpr int SZA = SZB / NI * M;
+    // the one or two axes other than K, with their (common) sizes
+    constexpr int A1 = (K == 0) ? 1 : 0, A2 = (K == 2) ? 1 : 2;
+    constexpr int SZ[3] = {S0, S1, S2};
+    constexpr int N1 = SZ[A1], N2 = (DIM == 3) ? SZ[A2] : 1;
+    constexpr int LINES = NVAR * N1 * N2;
+    for (int l = tid; l < LINES; l += bs) {
+        const int v = l / (N1 * N2);
+        const int r = l - v * (N1 * N2);
+        const int j1 = r % N1, j2 = r / N1;
+        const double *x = src + v * SZB + j1 * IS[A1] + ((DIM == 3) ? j2 * IS[A2] : 0);
+        double *y = dst + v * SZA + j1 * OS[A1] + ((DIM == 3) ? j2 * OS[A2] : 0);
+        double xin[NI];
 #pragma unroll
-    for (int k = 0; k < DIM; k++) {
-        // alternate between the two buffers so that the last stage lands in `out`
-        double *dst = ((DIM - 1 - k) % 2 == 0) ? out : tmp;
-        const int d0b = (0 < k) ? M : NI, d1b = (1 < k) ? M : NI;          // sizes before the stage
-        const int d0a = (0 <= k) ? M : NI, d1a = (1 <= k) ? M : NI, d2a = (2 <= k) ? M : NI;  // after
-        const int szb = (DIM == 2) ? d0b * d1b : d0b * d1b * ((2 < k) ? M : NI);
-        const int sza = (DIM == 2) ? d0a * d1a : d0a * d1a * d2a;
-        const int total = NVAR * sza;
-        for (int it = tid; it < total; it += bs) {
-            const int v = it / sza;
-            int e = it - v * sza;
-            int idx[3];
-            idx[0] = e % d0a;
-            e /= d0a;
-            idx[1] = (DIM == 2) ? e : e % d1a;
-            idx[2] = (DIM == 2) ? 0 : e / d1a;
-            const int i = idx[k];
-            int strideb = 1;
-            for (int j = 0; j < k; j++) strideb *= (j == 0 ? d0b : d1b);
-            int base = 0, mul = 1;
+        for (int b = 0; b < NI; b++) xin[b] = x[b * IS[K]];
 #pragma unroll
-            for (int j = 0; j < DIM; j++) {
-                const int dj = (j == 0) ? d0b : ((j == 1) ? d1b : ((2 < k) ? M : NI));
-                if (j != k) base += idx[j] * mul;
-                mul *= dj;
-            }
-            const double *row = Mbase + i * MSTRIDE;
-            const double *col = src + v * szb + base;
+        for (int i = 0; i < M; i++) {
             double acc = 0.0;
 #pragma unroll
-            for (int b = 0; b < NI; b++) acc += row[b] * col[b * strideb];
-            dst[it] = acc;
+            for (int b = 0; b < NI; b++) acc += Mat[i * MSTRIDE + b] * xin[b];
+            y[i * OS[K]] = acc;
         }
-        __syncthreads();
-        src = dst;
+    }
+    __syncthreads();
+}
+
+template <int DIM, int M, int NI, int NVAR, int MSTRIDE>
+__device__ __forceinline__ void tensor_apply(const double *__restrict__ Mbase, const double *in, double *out, double *tmp, int tid,
+                             int bs) {
+    // the buffers alternate so that the last stage lands in `out`
+    if constexpr (DIM == 2) {
+        tensor_stage<2, 0, M, NI, NVAR, MSTRIDE>(Mbase, in, tmp, tid, bs);
+        tensor_stage<2, 1, M, NI, NVAR, MSTRIDE>(Mbase, tmp, out, tid, bs);
+    } else {
+        tensor_stage<3, 0, M, NI, NVAR, MSTRIDE>(Mbase, in, out, tid, bs);
+        tensor_stage<3, 1, M, NI, NVAR, MSTRIDE>(Mbase, out, tmp, tid, bs);
+        tensor_stage<3, 2, M, NI, NVAR, MSTRIDE>(Mbase, tmp, out, tid, bs);
     }
 }
 
@@ -638,7 +727,6 @@ __global__ __launch_bounds__(128) void k_corrector_detect(const Tables *__restri
     __shared__ double red[2 * NV * 2];
     __shared__ int bad_s[2];
     __shared__ float mg_s[2];
-    __shared__ double Ps[NS * MAXN];      // projection operator of eq. (subcell.p)
     __shared__ double bnd[2][NV];         // m_i, M_i of eq. (dmp) for this cell
     const int64_t c = blockIdx.x;
     const int tid = threadIdx.x;
@@ -648,7 +736,6 @@ __global__ __launch_bounds__(128) void k_corrector_detect(const Tables *__restri
     __shared__ double coef[3][n];
     if (tid < DIM * n) coef[tid / n][tid % n] = dt / P.h[tid / n] / T->w[tid % n];
     if (limiter) {
-        for (int i = tid; i < NS * MAXN; i += 128) Ps[i] = (&T->P[0][0])[i];
         // min (mm = 0) / max (mm = 1) of variable v over the 3^d block V_i of the
         // per-cell old-time bounds, held on the extended grid (cell c sits at ci + 1)
         const int mm = tid / NV, v = tid % NV;
@@ -696,7 +783,7 @@ __global__ __launch_bounds__(128) void k_corrector_detect(const Tables *__restri
     }
     if (!limiter) return;
     __syncthreads();
-    tensor_apply<DIM, NS, n, NV, MAXN>(Ps, us, vs, tmp, tid, 128);
+    tensor_apply<DIM, NS, n, NV, MAXN>(&T->P[0][0], us, vs, tmp, tid, 128);
     // detection on the NSUB candidate subcell averages
     double m_[NV], M_[NV];
 #pragma unroll
@@ -723,12 +810,23 @@ __global__ __launch_bounds__(128) void k_corrector_detect(const Tables *__restri
         isc[v] = 1.0 / sc;
     }
     const double isr = 1.0 / sr, ise = 1.0 / se;
+    // the same pass takes the candidate's subcell min / max: the next step's old-time
+    // bounds of this cell (overwritten later in the step if the cell is recomputed or
+    // corrected)
+    double lo[NV], hi[NV];
+#pragma unroll
+    for (int v = 0; v < NV; v++) {
+        lo[v] = INFINITY;
+        hi[v] = -INFINITY;
+    }
     for (int sg = tid; sg < NSUB; sg += 128) {
         double q[NV];
         bool finite = true;
 #pragma unroll
         for (int v = 0; v < NV; v++) {
             q[v] = vs[v * NSUB + sg];
+            lo[v] = fmin(lo[v], q[v]);
+            hi[v] = fmax(hi[v], q[v]);
             if (!isfinite(q[v])) finite = false;
         }
         if (!finite) {
@@ -750,21 +848,33 @@ __global__ __launch_bounds__(128) void k_corrector_detect(const Tables *__restri
     for (int off = 32; off > 0; off >>= 1) {
         bad |= __shfl_xor(bad, off);
         mg = fminf(mg, __shfl_xor(mg, off));
+#pragma unroll
+        for (int v = 0; v < NV; v++) {
+            lo[v] = fmin(lo[v], __shfl_xor(lo[v], off));
+            hi[v] = fmax(hi[v], __shfl_xor(hi[v], off));
+        }
     }
     if ((tid & 63) == 0) {
         bad_s[tid >> 6] = bad;
         mg_s[tid >> 6] = mg;
+#pragma unroll
+        for (int v = 0; v < NV; v++) {
+            red[(tid >> 6) * 2 * NV + v] = lo[v];
+            red[(tid >> 6) * 2 * NV + NV + v] = hi[v];
+        }
     }
     __syncthreads();
     if (tid == 0) {
-        bad_s[0] |= bad_s[1];
-        mg_s[0] = fminf(mg_s[0], mg_s[1]);
-        B.beta[1][c] = (uint8_t)((bad_s[0] || B.force[c]) ? 1 : 0);
-        B.margin[c] = mg_s[0];
+        B.beta[1][c] = (uint8_t)(((bad_s[0] | bad_s[1]) || B.force[c]) ? 1 : 0);
+        B.margin[c] = fminf(mg_s[0], mg_s[1]);
     }
-    // the candidate's subcell min / max are the next step's old-time bounds of this cell
-    // (overwritten later in the step if the cell is recomputed or corrected)
-    store_cell_bounds<NV>(P, B, c, vs, NSUB, tid, 128, red);
+    if (tid < 2 * NV) {
+        // thread v: min of variable v; thread NV + v: max of variable v
+        const int v = tid % NV;
+        const double r = (tid < NV) ? fmin(red[v], red[2 * NV + v]) : fmax(red[NV + v], red[3 * NV + v]);
+        const int64_t e = ext_index(P, c), next = ext_count(P);
+        ((tid < NV) ? B.ext_min[1] : B.ext_max[1])[(int64_t)v * next + e] = r;
+    }
 }
 
 // --------------------------------------------------------- old-time bounds
@@ -783,9 +893,7 @@ __global__ __launch_bounds__(128) void k_cell_bounds(const Tables *__restrict__ 
     __shared__ double vs[NV * BIG];
     __shared__ double tmp[NV * BIG];
     __shared__ double red[2 * NV * 2];
-    __shared__ double Ps[NS * MAXN];
     const int tid = threadIdx.x;
-    for (int i = tid; i < NS * MAXN; i += 128) Ps[i] = (&T->P[0][0])[i];
     // all extended cells, or only the ghost ring (interior bounds then come from the
     // kernels of the previous step that produced each cell's new subcell data)
     const int64_t e = ring ? ring[blockIdx.x] : (int64_t)blockIdx.x;
@@ -827,7 +935,7 @@ __global__ __launch_bounds__(128) void k_cell_bounds(const Tables *__restrict__ 
             us[it] = uo[((int64_t)v * P.ncell + cs) * NN + a];
         }
         __syncthreads();
-        tensor_apply<DIM, NS, n, NV, MAXN>(Ps, us, vs, tmp, tid, 128);
+        tensor_apply<DIM, NS, n, NV, MAXN>(&T->P[0][0], us, vs, tmp, tid, 128);
     }
     const double t0 = B.scal[1];
     double lo[NV], hi[NV];
@@ -1376,6 +1484,8 @@ __global__ __launch_bounds__(256) void k_subcell(const Tables *__restrict__ T, P
     A.Rb = T->R3;
     A.w = T->w3;
     A.Dvol = nullptr;
+    A.DE = nullptr;
+    A.DO = nullptr;
     A.dcount = nullptr;
     A.dcap = 0;
     A.dmult = 1;
@@ -1401,11 +1511,9 @@ __global__ __launch_bounds__(128) void k_fluxcorr(const Tables *__restrict__ T, 
     __shared__ double vs[NV_ * NSUB_];
     __shared__ double tmp[NV_ * TMP_];
     __shared__ double red[2 * NV_ * 2];
-    __shared__ double Ps[NS_ * MAXN];
     constexpr int n = N + 1, NV = DIM + 2, NN = cpow(n, DIM), NFN = cpow(n, DIM - 1);
     constexpr int NS = 2 * N + 1, NSF = cpow(NS, DIM - 1);
     if (count < 0) count = B.counts[1];   // device-driven
-    for (int i = threadIdx.x; i < NS * MAXN; i += 128) Ps[i] = (&T->P[0][0])[i];
     for (int wb = blockIdx.x; wb < count; wb += gridDim.x) {
     const int64_t c = B.clist[wb];
     int ci[3];
@@ -1467,7 +1575,7 @@ __global__ __launch_bounds__(128) void k_fluxcorr(const Tables *__restrict__ T, 
     }
     __syncthreads();
     // the corrected state's subcell min / max are this cell's next old-time bounds
-    tensor_apply<DIM, NS, n, NV, MAXN>(Ps, us, vs, tmp, threadIdx.x, 128);
+    tensor_apply<DIM, NS, n, NV, MAXN>(&T->P[0][0], us, vs, tmp, threadIdx.x, 128);
     store_cell_bounds<NV>(P, B, c, vs, NSUB_, threadIdx.x, 128, red);
     __syncthreads();   // LDS reused by the next corrected cell
     }  // persistent loop
@@ -1543,6 +1651,8 @@ struct Launch {
             A.Rb = C.tab->R;
             A.w = C.tab->w;
             A.Dvol = &C.tab->Dvol[0][0];
+            A.DE = &C.tab->DE[0][0];
+            A.DO = &C.tab->DO[0][0];
         } else {
             A.D = &C.tab->fD[0][0];
             A.Kw = &C.tab->fKw[0][0];
@@ -1550,6 +1660,8 @@ struct Launch {
             A.Rb = C.tab->fR;
             A.w = C.tab->fw;
             A.Dvol = &C.tab->fDvol[0][0];
+            A.DE = &C.tab->fDE[0][0];
+            A.DO = &C.tab->fDO[0][0];
         }
         A.dcount = nullptr;
         A.dcap = 0;

@@ -180,6 +180,23 @@ void build_tables(int N, int Ns, Tables *T) {
     B3.eval(0.0, T->L3);
     B3.eval(1.0, T->R3);
     time_operator(3, T->w3, T->D3, T->R3, T->Kw3);
+    {
+        const int h = n / 2;
+        for (int a = 0; a < h; a++)
+            for (int b = 0; b < h; b++) {
+                T->DE[a][b] = 0.5 * (T->D[a][b] + T->D[a][n - 1 - b]);
+                T->DO[a][b] = 0.5 * (T->D[a][b] - T->D[a][n - 1 - b]);
+            }
+        if (n % 2) {
+            for (int a = 0; a < h; a++) T->DE[a][h] = T->D[a][h];
+            for (int b = 0; b < h; b++) T->DO[h][b] = T->D[h][b];
+        }
+        for (int a = 0; a <= MAXN / 2; a++)
+            for (int b = 0; b <= MAXN / 2; b++) {
+                if (a < MAXN / 2) T->fDE[a][b] = (float)T->DE[a][b];
+                if (b < MAXN / 2) T->fDO[a][b] = (float)T->DO[a][b];
+            }
+    }
     for (int a = 0; a < MAXN; a++) {
         T->fL[a] = (float)T->L[a];
         T->fR[a] = (float)T->R[a];

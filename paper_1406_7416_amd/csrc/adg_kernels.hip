@@ -145,7 +145,8 @@ struct PredArgs {
 
 // Contraction along axis k of every line held in LDS: line[i] <- c * sum_b M[i][b] line[b]
 // (c only if SCALE).  One work item handles the same line of LV variables (independent FMA
-// chains sharing each operator entry; LV is 1 for long FP64 lines to bound register use).
+// chains sharing each operator entry; for long lines LV is 2 (FP32) or 1 (FP64) to bound
+// register use).
 // EO: M is the derivative matrix on symmetric nodes, applied through its even / odd parts
 // E, O (half-size products on x_b +- x_{n-1-b}: n^2/2 + 2n operations instead of n^2).
 template <int DIM, int N, int CPB, int VC, int BS, typename R, bool EO = false, bool SCALE = true>
@@ -153,7 +154,7 @@ __device__ __forceinline__ void lds_lines(R *X, int k, int nlines_per_var, int l
                                           int tid, int nvalid, const R (*E)[MAXN / 2 + 1] = nullptr,
                                           const R (*O)[MAXN / 2] = nullptr) {
     constexpr int n = N + 1, NN = cpow(n, DIM), NST = NN * n;
-    constexpr int LV = (n >= 8 && sizeof(R) == 8) ? 1 : VC;
+    constexpr int LV = (n >= 8) ? (sizeof(R) == 8 ? 1 : 2) : VC;
     constexpr int NG = (VC + LV - 1) / LV;   // variable groups per line
     const int st = (k == 0) ? 1 : (k == 1 ? n : n * n);
     const int nitems = CPB * NG * nlines_per_var;
@@ -472,7 +473,9 @@ __device__ void pred_cells(const PredArgs<R> &A, double gamma_d, int64_t ncell, 
 }
 
 template <int DIM, int N, bool VOL, typename R>
-__global__ __launch_bounds__((PredShape<DIM, N, R>::BS), 2) void k_predictor(PredArgs<R> A, double gamma_d) {
+// FP32: at most 128 registers, four waves per SIMD; FP64: two waves per SIMD
+__global__ __launch_bounds__((PredShape<DIM, N, R>::BS), (sizeof(R) == 4 ? 4 : 2)) void k_predictor(PredArgs<R> A,
+                                                                                                   double gamma_d) {
     pred_cells<DIM, N, VOL, R>(A, gamma_d, A.ncell, blockIdx.x, gridDim.x);
 }
 

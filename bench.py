@@ -28,6 +28,13 @@ PEAK_FP64_VALU_TFLOPS = 78.6
 PEAK_FP32_VALU_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 
+# HBM bytes per launch of k_predictor<2, 9, true, float> on the N=9, 64x64 vortex: rocprofv3
+# FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (the factors that make a plain 256 MiB copy read its
+# own size), taken on the kernel source whose SHA-256 starts with the prefix below; reported
+# as null once that source has changed.
+PREDICTOR_TRAFFIC_BYTES = 85152397
+PREDICTOR_TRAFFIC_SOURCE = "faed6031eb0eef70"
+
 
 def predictor_flops_per_cell(d: int, N: int) -> float:
     """Algorithmic flops of the local space-time predictor per cell: n Picard sweeps,
@@ -36,6 +43,18 @@ def predictor_flops_per_cell(d: int, N: int) -> float:
     node for the d fluxes)."""
     n, nv = N + 1, d + 2
     return n * (2.0 * (d + 1) * nv * n ** (d + 2) + (10 + 8 * d) * n ** (d + 1))
+
+
+def traffic_bytes(N, grid):
+    """Measured HBM traffic of the dominant kernel, if it was measured on this workload and
+    on the kernel source as it stands."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_1406_7416_amd", "csrc", "adg_kernels.hip")
+    with open(src, "rb") as f:
+        h = hashlib.sha256(f.read()).hexdigest()
+    if N != 9 or grid != 64 or not h.startswith(PREDICTOR_TRAFFIC_SOURCE):
+        return None
+    return PREDICTOR_TRAFFIC_BYTES
 
 
 def main():
@@ -168,7 +187,8 @@ def main():
             "peak": PEAK_FP32_VALU_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved_tflops / PEAK_FP32_VALU_TFLOPS,
-            "traffic": None,
+            "traffic": traffic_bytes(args.N, args.grid),
+            "traffic_unit": "bytes per launch (HBM, calibrated rocprofv3 counters)",
             "flops_per_launch": flops_launch,
             "avg_launch_us": h["predictor_avg_us"],
         },

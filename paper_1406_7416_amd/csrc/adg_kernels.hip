@@ -100,7 +100,7 @@ __device__ __forceinline__ void coords_of(const Prob &P, int64_t c, int *ci) {
 // and stores them in LDS; "line owner" threads do the length-n spatial contractions
 // (n loads -> n outputs each, in place); the point owner accumulates S over the d axes
 // and applies the time contraction in registers: d + 1 contractions per sweep.
-template <int DIM, int N, typename R = double>
+template <int DIM, int N, typename R = double, int TB = 256>
 struct PredShape;
 
 // 1/x: correctly rounded division in FP64; the hardware reciprocal (within 1 ulp) in
@@ -108,14 +108,15 @@ struct PredShape;
 __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 
-template <int DIM, int N, typename R>
+// TB: thread budget of a workgroup (cells per block = TB / n^d)
+template <int DIM, int N, typename R, int TB>
 struct PredShape {
     static constexpr int n = N + 1;
     static constexpr int NV = DIM + 2;
     static constexpr int NN = cpow(n, DIM);
     static constexpr int NST = NN * n;
     static constexpr int NFN = cpow(n, DIM - 1);
-    static constexpr int CPB = NN <= 256 ? 256 / NN : 1;
+    static constexpr int CPB = NN <= TB ? TB / NN : 1;
     static constexpr int ACT = CPB * NN;                           // active point owners
     static constexpr int BS = ((ACT + 63) / 64) * 64;
     static constexpr int VCMAX = 65536 / (CPB * NST * (int)sizeof(R));
@@ -252,9 +253,9 @@ __device__ __forceinline__ void lds_lines(R *X, int k, int nlines_per_var, int l
 }
 
 // Blocks vb = vb0, vb0 + vbs, ... of CPB cells each, out of ncell cells.
-template <int DIM, int N, bool VOL, typename R>
+template <int DIM, int N, bool VOL, typename R, int TB = 256>
 __device__ void pred_cells(const PredArgs<R> &A, double gamma_d, int64_t ncell, int64_t vb0, int64_t vbs) {
-    using S = PredShape<DIM, N, R>;
+    using S = PredShape<DIM, N, R, TB>;
     const R gamma = (R)gamma_d;
     constexpr int n = S::n, NV = S::NV, NN = S::NN, NST = S::NST, NFN = S::NFN, CPB = S::CPB, VC = S::VC;
     __shared__ R X[CPB * VC * NST];
@@ -1100,6 +1101,8 @@ __global__ __launch_bounds__(CBS) void k_compact_scatter(Prob P, Bufs B, int64_t
 }
 
 // ------------------------------------------------------ subcell ADER-WENO3
+constexpr int SUB_BS = 256;   // threads per workgroup of the subcell recompute
+
 // Positions of one troubled cell's subcell scheme: the Ns^d own subcells first, then
 // for each axis k and side the Ns^(d-1) face-adjacent subcells of the neighbour.
 template <int DIM>
@@ -1215,76 +1218,97 @@ __device__ __forceinline__ void weno3(const Tables *__restrict__ T, const double
         wt[st] = lam[st] / s2;
         sum += wt[st];
     }
+    const double isum = 1.0 / sum;
 #pragma unroll
     for (int qn = 0; qn < 3; qn++) {
         const double x = T->xi3[qn];
         double acc = 0.0;
 #pragma unroll
-        for (int st = 0; st < 3; st++) acc += (wt[st] / sum) * (c[st][0] + c[st][1] * x + c[st][2] * x * x);
+        for (int st = 0; st < 3; st++) acc += (wt[st] * isum) * (c[st][0] + c[st][1] * x + c[st][2] * x * x);
         out[qn] = acc;
     }
 }
 
 // S2: dimension-by-dimension WENO3 reconstruction at every position -> nodal values at
 // the 3^d GL points of the subcell (x sweep on the averages, then y (then z) sweeps on
-// the nodal values of the previous sweep).
+// the nodal values of the previous sweep).  One work item per (position, variable).
 template <int DIM, int N>
 __device__ void sub_recon_cell(const Tables *__restrict__ T, const Bufs &B, int sidx) {
     constexpr int NV = DIM + 2, NS = 2 * N + 1, HN = NS + 6, HSZ = cpow(HN, DIM);
     constexpr int NPOS = cpow(NS, DIM) + 2 * DIM * cpow(NS, DIM - 1), N3 = cpow(3, DIM);
     constexpr int W5 = cpow(5, DIM);
-    const int ch = sidx;
-    for (int pos = threadIdx.x; pos < NPOS; pos += blockDim.x) {
-    int L[3];
-    position_coords<DIM>(pos, NS, L);
-    const double *halo = B.halo + (int64_t)ch * NV * HSZ;
-    double *Y = B.Y + ((int64_t)ch * NPOS + pos) * NV * N3;
-    for (int v = 0; v < NV; v++) {
-        double w0[W5], w1[W5];
-        for (int e = 0; e < W5; e++) {
-            int mo[3] = {e % 5, (e / 5) % 5, e / 25};
-            int hidx = 0;
-            for (int j = DIM - 1; j >= 0; j--) hidx = hidx * HN + (L[j] + mo[j] - 2 + 3);
-            w0[e] = halo[v * HSZ + hidx];
-        }
-        double *src = w0, *dst = w1;
-        for (int k = 0; k < DIM; k++) {
-            int dimsb[3], dimsa[3], na = 1;
-            for (int j = 0; j < DIM; j++) {
-                dimsb[j] = j < k ? 3 : 5;
-                dimsa[j] = j <= k ? 3 : 5;
-                na *= dimsa[j];
+    const double *halo = B.halo + (int64_t)sidx * NV * HSZ;
+    for (int item = threadIdx.x; item < NPOS * NV; item += blockDim.x) {
+        const int v = item / NPOS, pos = item % NPOS;
+        int L[3];
+        position_coords<DIM>(pos, NS, L);
+        const double *h = halo + v * HSZ;
+        double *Y = B.Y + ((int64_t)sidx * NPOS + pos) * NV * N3 + v * N3;
+        if constexpr (DIM == 2) {
+            // x sweep on the five rows of the 5 x 5 stencil, then y sweep per x node
+            double w1[5][3];
+#pragma unroll
+            for (int r = 0; r < 5; r++) {
+                double a5[5];
+#pragma unroll
+                for (int o = 0; o < 5; o++) a5[o] = h[(L[1] + r + 1) * HN + (L[0] + o + 1)];
+                weno3(T, a5, w1[r]);
             }
-            for (int e = 0; e < na; e++) {
-                int ma[3] = {0, 0, 0}, r = e;
-                for (int j = 0; j < DIM; j++) {
-                    ma[j] = r % dimsa[j];
-                    r /= dimsa[j];
-                }
-                if (ma[k] != 0) continue;
+#pragma unroll
+            for (int qx = 0; qx < 3; qx++) {
                 double a5[5], o3[3];
-                for (int o = 0; o < 5; o++) {
-                    int mb[3] = {ma[0], ma[1], ma[2]};
-                    mb[k] = o;
-                    int ib = 0;
-                    for (int j = DIM - 1; j >= 0; j--) ib = ib * dimsb[j] + mb[j];
-                    a5[o] = src[ib];
-                }
+#pragma unroll
+                for (int r = 0; r < 5; r++) a5[r] = w1[r][qx];
                 weno3(T, a5, o3);
-                for (int qn = 0; qn < 3; qn++) {
-                    int mc[3] = {ma[0], ma[1], ma[2]};
-                    mc[k] = qn;
-                    int ic = 0;
-                    for (int j = DIM - 1; j >= 0; j--) ic = ic * dimsa[j] + mc[j];
-                    dst[ic] = o3[qn];
-                }
+#pragma unroll
+                for (int qy = 0; qy < 3; qy++) Y[qy * 3 + qx] = o3[qy];
             }
-            double *t = src;
-            src = dst;
-            dst = t;
+        } else {
+            double w0[W5], w1[W5];
+            for (int e = 0; e < W5; e++) {
+                int mo[3] = {e % 5, (e / 5) % 5, e / 25};
+                int hidx = 0;
+                for (int j = DIM - 1; j >= 0; j--) hidx = hidx * HN + (L[j] + mo[j] - 2 + 3);
+                w0[e] = h[hidx];
+            }
+            double *src = w0, *dst = w1;
+            for (int k = 0; k < DIM; k++) {
+                int dimsb[3], dimsa[3], na = 1;
+                for (int j = 0; j < DIM; j++) {
+                    dimsb[j] = j < k ? 3 : 5;
+                    dimsa[j] = j <= k ? 3 : 5;
+                    na *= dimsa[j];
+                }
+                for (int e = 0; e < na; e++) {
+                    int ma[3] = {0, 0, 0}, r = e;
+                    for (int j = 0; j < DIM; j++) {
+                        ma[j] = r % dimsa[j];
+                        r /= dimsa[j];
+                    }
+                    if (ma[k] != 0) continue;
+                    double a5[5], o3[3];
+                    for (int o = 0; o < 5; o++) {
+                        int mb[3] = {ma[0], ma[1], ma[2]};
+                        mb[k] = o;
+                        int ib = 0;
+                        for (int j = DIM - 1; j >= 0; j--) ib = ib * dimsb[j] + mb[j];
+                        a5[o] = src[ib];
+                    }
+                    weno3(T, a5, o3);
+                    for (int qn = 0; qn < 3; qn++) {
+                        int mc[3] = {ma[0], ma[1], ma[2]};
+                        mc[k] = qn;
+                        int ic = 0;
+                        for (int j = DIM - 1; j >= 0; j--) ic = ic * dimsa[j] + mc[j];
+                        dst[ic] = o3[qn];
+                    }
+                }
+                double *t = src;
+                src = dst;
+                dst = t;
+            }
+            for (int a = 0; a < N3; a++) Y[a] = src[a];
         }
-        for (int a = 0; a < N3; a++) Y[v * N3 + a] = src[a];
-    }
     }
 }
 
@@ -1301,7 +1325,7 @@ __device__ void sub_update_cell(const Tables *__restrict__ T, const Prob &P, con
     __shared__ double vn[NV * BIG];
     __shared__ double tmp[NV * BIG];
     __shared__ double ug[NV * BIG];
-    __shared__ double red[2 * NV * 4];
+    __shared__ double red[2 * NV * (SUB_BS / 64)];
     __shared__ int badc;
     const int ch = sidx;
     const int64_t c = B.tlist[w];
@@ -1318,7 +1342,7 @@ __device__ void sub_update_cell(const Tables *__restrict__ T, const Prob &P, con
             nbex[k][side] = P.periodic[k] || (nb >= 0 && nb < P.nc[k]);
         }
     const int nfaces = DIM * (NS + 1) * NSF;
-    for (int it = threadIdx.x; it < nfaces; it += 256) {
+    for (int it = threadIdx.x; it < nfaces; it += SUB_BS) {
         const int k = it / ((NS + 1) * NSF);
         const int f = (it / NSF) % (NS + 1);
         const int sp = it % NSF;
@@ -1410,7 +1434,7 @@ __device__ void sub_update_cell(const Tables *__restrict__ T, const Prob &P, con
     // FV update of the cell's own subcells
     const double *halo = B.halo + (int64_t)ch * NV * HSZ;
     const int slot = B.slot[1][c];
-    for (int sg = threadIdx.x; sg < NSUB; sg += 256) {
+    for (int sg = threadIdx.x; sg < NSUB; sg += SUB_BS) {
         int ms[3] = {sg % NS, (sg / NS) % NS, sg / (NS * NS)};
         int hidx = 0;
         for (int j = DIM - 1; j >= 0; j--) hidx = hidx * HN + (ms[j] + 3);
@@ -1440,21 +1464,152 @@ __device__ void sub_update_cell(const Tables *__restrict__ T, const Prob &P, con
         if (!(q[0] > 0.0) || !(pressure<DIM>(q, P.gamma) > 0.0)) badc = 1;
     }
     // boundary fluxes of the cell's faces for the flux correction
-    for (int it = threadIdx.x; it < 2 * DIM * NV * NSF; it += 256) {
+    for (int it = threadIdx.x; it < 2 * DIM * NV * NSF; it += SUB_BS) {
         const int face = it / (NV * NSF), v = (it / NSF) % NV, sp = it % NSF;
         const int k = face >> 1, side = face & 1;
         B.sflux[(int64_t)slot * 2 * DIM * NV * NSF + it] = Fb[((k * (NS + 1) + (side ? NS : 0)) * NSF + sp) * NV + v];
     }
     __syncthreads();
-    store_cell_bounds<NV>(P, B, c, vn, NSUB, threadIdx.x, 256, red);
+    store_cell_bounds<NV>(P, B, c, vn, NSUB, threadIdx.x, SUB_BS, red);
     // gather: u = R v (eq. (subcell.r)), tensor application
-    tensor_apply<DIM, n, NS, NV, MAXNS>(&T->Rg[0][0], vn, ug, tmp, threadIdx.x, 256);
-    for (int it = threadIdx.x; it < NV * NN; it += 256) {
+    tensor_apply<DIM, n, NS, NV, MAXNS>(&T->Rg[0][0], vn, ug, tmp, threadIdx.x, SUB_BS);
+    for (int it = threadIdx.x; it < NV * NN; it += SUB_BS) {
         const int v = it / NN, a = it % NN;
         B.u[cur ^ 1][((int64_t)v * P.ncell + c) * NN + a] = ug[it];
     }
     if (threadIdx.x == 0 && badc) atomicAdd(nonphys, 1);
     __syncthreads();   // LDS reused by the next troubled cell
+}
+
+// S3: degree-2 local space-time predictor (eq. (pde.nc.dg2) on the subgrid, mesh size
+// h/Ns, three sweeps) of every position of one troubled cell.  The 3^d spatial nodes of a
+// position sit on consecutive lanes of one wave (64 / 3^d positions per wave), each lane
+// holding its node's time pencil; a contraction along an axis gathers the three nodes of
+// the line by lane permutation, so the waves work without LDS or workgroup barriers.
+// Output: the face traces of every position, [pos][2d][v][3^(d-1) tangential x 3 time].
+template <int DIM>
+__device__ void sub_predictor(const Tables *__restrict__ T, const double *__restrict__ Y, double *__restrict__ tr,
+                              int npos, double dt, const double *dth, double gamma) {
+    constexpr int NV = DIM + 2, NN = cpow(3, DIM), NF = cpow(3, DIM - 1), PPW = 64 / NN;
+    constexpr int TRS = 2 * DIM * NV * NF * 3;
+    constexpr int ST[3] = {1, 3, 9};
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int slot = lane / NN, a = lane % NN;
+    const int ia[3] = {a % 3, (a / 3) % 3, a / 9};
+    // this lane's rows of the derivative matrix, per axis, and dt/h_k
+    double Dk[DIM][3], ck[DIM];
+#pragma unroll
+    for (int k = 0; k < DIM; k++) {
+        ck[k] = dt * dth[k];
+#pragma unroll
+        for (int b = 0; b < 3; b++) Dk[k][b] = T->D3[ia[k]][b];
+    }
+    for (int base = wv * PPW; base < npos; base += nw * PPW) {
+        const int pos = base + slot;
+        const bool valid = slot < PPW && pos < npos;
+        double u0[NV], q[NV][3];
+        if (valid) {
+#pragma unroll
+            for (int v = 0; v < NV; v++) u0[v] = Y[((int64_t)pos * NV + v) * NN + a];
+        } else {
+            // idle lanes carry a valid constant state
+#pragma unroll
+            for (int v = 0; v < NV; v++) u0[v] = (v == 0) ? 1.0 : 0.0;
+            u0[NV - 1] = 2.5;
+        }
+#pragma unroll
+        for (int v = 0; v < NV; v++)
+#pragma unroll
+            for (int s = 0; s < 3; s++) q[v][s] = u0[v];
+        for (int r = 0; r < 3; r++) {
+            double S[NV][3];
+#pragma unroll
+            for (int k = 0; k < DIM; k++) {
+                double F[NV][3];
+#pragma unroll
+                for (int t = 0; t < 3; t++) {
+                    const double ir = 1.0 / q[0][t];
+                    const double un = q[1 + k][t] * ir;
+                    double ke = 0.0;
+#pragma unroll
+                    for (int j = 0; j < DIM; j++) ke += q[1 + j][t] * q[1 + j][t];
+                    const double prt = (gamma - 1.0) * (q[NV - 1][t] - 0.5 * ke * ir);
+                    F[0][t] = q[1 + k][t];
+#pragma unroll
+                    for (int j = 0; j < DIM; j++) F[1 + j][t] = q[1 + j][t] * un + (j == k ? prt : 0.0);
+                    F[NV - 1][t] = un * (q[NV - 1][t] + prt);
+                }
+                // sum_b D[a_k][b] F(node b of the line), b ascending
+                double x[NV][3];
+#pragma unroll
+                for (int v = 0; v < NV; v++)
+#pragma unroll
+                    for (int t = 0; t < 3; t++) x[v][t] = 0.0;
+#pragma unroll
+                for (int b = 0; b < 3; b++) {
+                    const int src = lane + (b - ia[k]) * ST[k];
+#pragma unroll
+                    for (int v = 0; v < NV; v++)
+#pragma unroll
+                        for (int t = 0; t < 3; t++) x[v][t] += Dk[k][b] * __shfl(F[v][t], src);
+                }
+#pragma unroll
+                for (int v = 0; v < NV; v++)
+#pragma unroll
+                    for (int t = 0; t < 3; t++) S[v][t] = (k == 0) ? ck[k] * x[v][t] : S[v][t] + ck[k] * x[v][t];
+            }
+            // time contraction K1^{-1} diag(w)
+#pragma unroll
+            for (int s = 0; s < 3; s++) {
+                double acc[NV];
+#pragma unroll
+                for (int v = 0; v < NV; v++) acc[v] = 0.0;
+#pragma unroll
+                for (int t = 0; t < 3; t++) {
+                    const double kst = T->Kw3[s][t];
+#pragma unroll
+                    for (int v = 0; v < NV; v++) acc[v] += kst * S[v][t];
+                }
+#pragma unroll
+                for (int v = 0; v < NV; v++) q[v][s] = u0[v] - acc[v];
+            }
+        }
+        // face traces: the lane at the low end of a line writes the xi_k = 0 trace, the lane
+        // at the high end the xi_k = 1 trace
+#pragma unroll
+        for (int k = 0; k < DIM; k++) {
+            double qb[3][NV][3];
+#pragma unroll
+            for (int b = 0; b < 3; b++) {
+                const int src = lane + (b - ia[k]) * ST[k];
+#pragma unroll
+                for (int v = 0; v < NV; v++)
+#pragma unroll
+                    for (int s = 0; s < 3; s++) qb[b][v][s] = __shfl(q[v][s], src);
+            }
+            if (valid && ia[k] != 1) {
+                const int side = ia[k] == 2;
+                const double *Bv = side ? T->R3 : T->L3;
+                int ap = 0, mul = 1;
+#pragma unroll
+                for (int j = 0; j < DIM; j++) {
+                    if (j == k) continue;
+                    ap += ia[j] * mul;
+                    mul *= 3;
+                }
+                double *o = tr + (int64_t)pos * TRS + (2 * k + side) * NV * NF * 3;
+#pragma unroll
+                for (int v = 0; v < NV; v++)
+#pragma unroll
+                    for (int s = 0; s < 3; s++) {
+                        double acc = 0.0;
+#pragma unroll
+                        for (int b = 0; b < 3; b++) acc += Bv[b] * qb[b][v][s];
+                        o[v * NF * 3 + ap + NF * s] = acc;
+                    }
+            }
+        }
+    }
 }
 
 // Subcell ADER-WENO3 recompute (operator A of eq. (aderweno)) of every troubled cell:
@@ -1463,41 +1618,25 @@ __device__ void sub_update_cell(const Tables *__restrict__ T, const Prob &P, con
 // space-time predictor, sub-face fluxes, FV update and gather, using its own scratch
 // slot (blockIdx.x), so the scratch scales with the grid, not with the worklist.
 template <int DIM, int N>
-__global__ __launch_bounds__(256) void k_subcell(const Tables *__restrict__ T, Prob P, Bufs B, int cur, int64_t cap,
+__global__ __launch_bounds__(SUB_BS, 2) void k_subcell(const Tables *__restrict__ T, Prob P, Bufs B, int cur, int64_t cap,
                                                  int *nonphys) {
     constexpr int NV = DIM + 2, NS = 2 * N + 1;
     constexpr int NPOS = cpow(NS, DIM) + 2 * DIM * cpow(NS, DIM - 1), N3 = cpow(3, DIM);
-    static_assert(PredShape<DIM, 2, double>::BS == 256, "subcell predictor block shape");
+    constexpr int TRS = 2 * DIM * NV * cpow(3, DIM - 1) * 3;
     const int count = (int)(B.counts[0] < cap ? B.counts[0] : cap);
     const int sidx = blockIdx.x;
-    PredArgs<double> A;
-    A.in = B.Y + (int64_t)sidx * NPOS * NV * N3;
-    A.in_cstride = NV * N3;
-    A.in_vstride = N3;
-    A.trace = B.strace + (int64_t)sidx * NPOS * (2 * DIM * NV * cpow(3, DIM - 1) * 3);
-    A.vol_out = nullptr;
-    A.ncell = NPOS;
-    A.cell0 = 0;
-    A.iters = 3;
-    for (int k = 0; k < 3; k++) A.dth[k] = k < DIM ? (double)NS / P.h[k] : 0.0;
-    A.dt = B.scal;
-    A.D = &T->D3[0][0];
-    A.Kw = &T->Kw3[0][0];
-    A.Lb = T->L3;
-    A.Rb = T->R3;
-    A.w = T->w3;
-    A.Dvol = nullptr;
-    A.DE = nullptr;
-    A.DO = nullptr;
-    A.dcount = nullptr;
-    A.dcap = 0;
-    A.dmult = 1;
+    const double dt = B.scal[0];
+    double dth[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < DIM; k++) dth[k] = (double)NS / P.h[k];
+    const double *Ys = B.Y + (int64_t)sidx * NPOS * NV * N3;
+    double *trs = B.strace + (int64_t)sidx * NPOS * TRS;
     for (int w = blockIdx.x; w < count; w += gridDim.x) {
         sub_halo_cell<DIM, N>(T, P, B, cur, w, sidx);
         __syncthreads();
         sub_recon_cell<DIM, N>(T, B, sidx);
         __syncthreads();
-        pred_cells<DIM, 2, false, double>(A, P.gamma, NPOS, 0, 1);
+        sub_predictor<DIM>(T, Ys, trs, NPOS, dt, dth, P.gamma);
+        __syncthreads();
         sub_update_cell<DIM, N>(T, P, B, cur, w, sidx, nonphys);
     }
 }
@@ -1712,7 +1851,7 @@ struct Launch {
                                C.cur, C.ring_only ? C.B.ring : (const int64_t *)nullptr);
     }
     static void subcell(const StepCtx &C) {
-        hipLaunchKernelGGL((k_subcell<DIM, N>), dim3((unsigned)C.subcell_grid), dim3(256), 0, C.stream, C.tab, C.P,
+        hipLaunchKernelGGL((k_subcell<DIM, N>), dim3((unsigned)C.subcell_grid), dim3(SUB_BS), 0, C.stream, C.tab, C.P,
                            C.B, C.cur, C.capacity, C.B.counts + 2);
     }
     static void fluxcorr(const StepCtx &C, int count) {

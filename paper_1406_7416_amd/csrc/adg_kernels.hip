@@ -715,85 +715,101 @@ __device__ __forceinline__ void tensor_apply(const double *__restrict__ Mbase, c
 }
 
 // ------------------------------------------- corrector + scatter + detection
+// Threads per cell (one wave while the cell has at most 128 subcells, else two) and cells
+// per workgroup.
+template <int DIM, int N>
+struct CorrShape {
+    static constexpr int NSUB = cpow(2 * N + 1, DIM);
+    static constexpr int CW = NSUB <= 128 ? 64 : 128;
+    static constexpr int CPB = (CW == 64) ? 4 : 1;
+    static constexpr int BS = CW * CPB;
+    static constexpr int NW = CW / 64;   // waves per cell
+};
+
 // Candidate of eq. (pde.nc.gw2) (face terms added to the volume-term candidate), then
 // v* = P(u*) (eq. (subcell.p)) and the PAD / relaxed-DMP tests of Sec. 4.3.
 template <int DIM, int N, typename R>
-__global__ __launch_bounds__(128) void k_corrector_detect(const Tables *__restrict__ T, Prob P, Bufs B, int cur,
-                                                          int limiter) {
+__global__ __launch_bounds__((CorrShape<DIM, N>::BS)) void k_corrector_detect(const Tables *__restrict__ T, Prob P,
+                                                                         Bufs B, int cur, int limiter) {
+    using CS = CorrShape<DIM, N>;
+    constexpr int CW = CS::CW, CPB = CS::CPB, NW = CS::NW;
     const R *gbar = reinterpret_cast<const R *>(B.gbar);
     constexpr int n = N + 1, NV = DIM + 2, NN = cpow(n, DIM), NFN = cpow(n, DIM - 1);
     constexpr int NS = 2 * N + 1, NSUB = cpow(NS, DIM);
     // intermediate of the sum-factorised P: stage 0 (2D) or stage 1 (3D) output
     constexpr int TMP = (DIM == 2) ? NS * n : NS * NS * n;
-    __shared__ double us[NV * NN];
-    __shared__ double vs[NV * NSUB];
-    __shared__ double tmp[NV * TMP];
-    __shared__ double red[2 * NV * 2];
-    __shared__ int bad_s[2];
-    __shared__ float mg_s[2];
-    __shared__ double bnd[2][NV];         // m_i, M_i of eq. (dmp) for this cell
-    const int64_t c = blockIdx.x;
-    const int tid = threadIdx.x;
+    __shared__ double us_[CPB][NV * NN];
+    __shared__ double vs_[CPB][NV * NSUB];
+    __shared__ double tmp_[CPB][NV * TMP];
+    __shared__ double red_[CPB][NW * 2 * NV];
+    __shared__ int bad_s[CPB][NW];
+    __shared__ float mg_s[CPB][NW];
+    __shared__ double bnd[CPB][2][NV];    // m_i, M_i of eq. (dmp) per cell
+    const int lc = threadIdx.x / CW, tid = threadIdx.x % CW;
+    const int64_t c = (int64_t)blockIdx.x * CPB + lc;
+    const bool live = c < P.ncell;         // every thread stays for the barriers
+    double *us = us_[lc], *vs = vs_[lc], *tmp = tmp_[lc], *red = red_[lc];
     const double dt = B.scal[0];
     double *un = B.u[cur ^ 1];
     // (dt/h_k)/w_a for every axis and node index: 2 divisions per entry, once per block
     __shared__ double coef[3][n];
-    if (tid < DIM * n) coef[tid / n][tid % n] = dt / P.h[tid / n] / T->w[tid % n];
-    if (limiter) {
+    if (threadIdx.x < DIM * n) coef[threadIdx.x / n][threadIdx.x % n] = dt / P.h[threadIdx.x / n] / T->w[threadIdx.x % n];
+    if (limiter && live && tid < 2 * NV) {
         // min (mm = 0) / max (mm = 1) of variable v over the 3^d block V_i of the
         // per-cell old-time bounds, held on the extended grid (cell c sits at ci + 1)
         const int mm = tid / NV, v = tid % NV;
-        if (tid < 2 * NV) {
-            int ci[3];
-            coords_of(P, c, ci);
-            int ne[3] = {1, 1, 1};
-            for (int j = 0; j < DIM; j++) ne[j] = P.nc[j] + 2;
-            const int64_t next = ext_count(P);
-            const double *src = (mm ? B.ext_max[0] : B.ext_min[0]) + (int64_t)v * next;
-            double acc = mm ? -INFINITY : INFINITY;
-            constexpr int NB = cpow(3, DIM);
+        int ci[3];
+        coords_of(P, c, ci);
+        int ne[3] = {1, 1, 1};
+        for (int j = 0; j < DIM; j++) ne[j] = P.nc[j] + 2;
+        const int64_t next = ext_count(P);
+        const double *src = (mm ? B.ext_max[0] : B.ext_min[0]) + (int64_t)v * next;
+        double acc = mm ? -INFINITY : INFINITY;
+        constexpr int NB = cpow(3, DIM);
 #pragma unroll
-            for (int o = 0; o < NB; o++) {
-                const int off[3] = {o % 3, (o / 3) % 3, o / 9};
-                int64_t e = 0;
-                for (int j = DIM - 1; j >= 0; j--) e = e * ne[j] + (ci[j] + off[j]);
-                acc = mm ? fmax(acc, src[e]) : fmin(acc, src[e]);
-            }
-            bnd[mm][v] = acc;
+        for (int o = 0; o < NB; o++) {
+            const int off[3] = {o % 3, (o / 3) % 3, o / 9};
+            int64_t e = 0;
+            for (int j = DIM - 1; j >= 0; j--) e = e * ne[j] + (ci[j] + off[j]);
+            acc = mm ? fmax(acc, src[e]) : fmin(acc, src[e]);
         }
+        bnd[lc][mm][v] = acc;
     }
     __syncthreads();
-    for (int it = tid; it < NV * NN; it += 128) {
+    for (int it = tid; it < NV * NN; it += CW) {
         const int v = it / NN, a = it % NN;
         int m[3] = {a % n, (a / n) % n, a / (n * n)};
-        double val = un[((int64_t)v * P.ncell + c) * NN + a];
+        double val = 0.0;
+        if (live) {
+            val = un[((int64_t)v * P.ncell + c) * NN + a];
 #pragma unroll
-        for (int k = 0; k < DIM; k++) {
-            int ap = 0, mul = 1;
-            for (int j = 0; j < DIM; j++) {
-                if (j == k) continue;
-                ap += m[j] * mul;
-                mul *= n;
+            for (int k = 0; k < DIM; k++) {
+                int ap = 0, mul = 1;
+                for (int j = 0; j < DIM; j++) {
+                    if (j == k) continue;
+                    ap += m[j] * mul;
+                    mul *= n;
+                }
+                const int ak = m[k];
+                const R Gm = gbar[((c * 2 * DIM + 2 * k) * NV + v) * NFN + ap];
+                const R Gp = gbar[((c * 2 * DIM + 2 * k + 1) * NV + v) * NFN + ap];
+                // face increment in the working precision R, added to the FP64 candidate
+                const R cf = (R)coef[k][ak];
+                val += (double)(cf * ((R)T->L[ak] * Gm - (R)T->R[ak] * Gp));
             }
-            const int ak = m[k];
-            const R Gm = gbar[((c * 2 * DIM + 2 * k) * NV + v) * NFN + ap];
-            const R Gp = gbar[((c * 2 * DIM + 2 * k + 1) * NV + v) * NFN + ap];
-            // face increment in the working precision R, added to the FP64 candidate
-            const R cf = (R)coef[k][ak];
-            val += (double)(cf * ((R)T->L[ak] * Gm - (R)T->R[ak] * Gp));
+            un[((int64_t)v * P.ncell + c) * NN + a] = val;
         }
-        un[((int64_t)v * P.ncell + c) * NN + a] = val;
         us[it] = val;
     }
     if (!limiter) return;
     __syncthreads();
-    tensor_apply<DIM, NS, n, NV, MAXN>(&T->P[0][0], us, vs, tmp, tid, 128);
+    tensor_apply<DIM, NS, n, NV, MAXN>(&T->P[0][0], us, vs, tmp, tid, CW);
     // detection on the NSUB candidate subcell averages
     double m_[NV], M_[NV];
 #pragma unroll
     for (int v = 0; v < NV; v++) {
-        m_[v] = bnd[0][v];
-        M_[v] = bnd[1][v];
+        m_[v] = live ? bnd[lc][0][v] : 0.0;
+        M_[v] = live ? bnd[lc][1][v] : 0.0;
     }
     int bad = 0;
     float mg = INFINITY;
@@ -823,7 +839,7 @@ __global__ __launch_bounds__(128) void k_corrector_detect(const Tables *__restri
         lo[v] = INFINITY;
         hi[v] = -INFINITY;
     }
-    for (int sg = tid; sg < NSUB; sg += 128) {
+    for (int sg = tid; sg < NSUB; sg += CW) {
         double q[NV];
         bool finite = true;
 #pragma unroll
@@ -858,26 +874,38 @@ __global__ __launch_bounds__(128) void k_corrector_detect(const Tables *__restri
             hi[v] = fmax(hi[v], __shfl_xor(hi[v], off));
         }
     }
+    const int w = tid >> 6;
     if ((tid & 63) == 0) {
-        bad_s[tid >> 6] = bad;
-        mg_s[tid >> 6] = mg;
+        bad_s[lc][w] = bad;
+        mg_s[lc][w] = mg;
 #pragma unroll
         for (int v = 0; v < NV; v++) {
-            red[(tid >> 6) * 2 * NV + v] = lo[v];
-            red[(tid >> 6) * 2 * NV + NV + v] = hi[v];
+            red[w * 2 * NV + v] = lo[v];
+            red[w * 2 * NV + NV + v] = hi[v];
         }
     }
     __syncthreads();
+    if (!live) return;
     if (tid == 0) {
-        B.beta[1][c] = (uint8_t)(((bad_s[0] | bad_s[1]) || B.force[c]) ? 1 : 0);
-        B.margin[c] = fminf(mg_s[0], mg_s[1]);
+        int bd = 0;
+        float m = INFINITY;
+#pragma unroll
+        for (int ww = 0; ww < NW; ww++) {
+            bd |= bad_s[lc][ww];
+            m = fminf(m, mg_s[lc][ww]);
+        }
+        B.beta[1][c] = (uint8_t)((bd || B.force[c]) ? 1 : 0);
+        B.margin[c] = m;
     }
     if (tid < 2 * NV) {
         // thread v: min of variable v; thread NV + v: max of variable v
-        const int v = tid % NV;
-        const double r = (tid < NV) ? fmin(red[v], red[2 * NV + v]) : fmax(red[NV + v], red[3 * NV + v]);
+        const int v = tid % NV, mx = tid >= NV;
+        double r = red[mx * NV + v];
+#pragma unroll
+        for (int ww = 1; ww < NW; ww++)
+            r = mx ? fmax(r, red[ww * 2 * NV + NV + v]) : fmin(r, red[ww * 2 * NV + v]);
         const int64_t e = ext_index(P, c), next = ext_count(P);
-        ((tid < NV) ? B.ext_min[1] : B.ext_max[1])[(int64_t)v * next + e] = r;
+        (mx ? B.ext_max[1] : B.ext_min[1])[(int64_t)v * next + e] = r;
     }
 }
 
@@ -1835,12 +1863,14 @@ struct Launch {
         else faces_t<double>(C);
     }
     static void corrector_detect(const StepCtx &C) {
+        using CS = CorrShape<DIM, N>;
+        const unsigned grid = (unsigned)((C.P.ncell + CS::CPB - 1) / CS::CPB);
         if (C.precision == ADG_MIXED)
-            hipLaunchKernelGGL((k_corrector_detect<DIM, N, float>), dim3((unsigned)C.P.ncell), dim3(128), 0, C.stream,
-                               C.tab, C.P, C.B, C.cur, C.limiter);
+            hipLaunchKernelGGL((k_corrector_detect<DIM, N, float>), dim3(grid), dim3(CS::BS), 0, C.stream, C.tab, C.P,
+                               C.B, C.cur, C.limiter);
         else
-            hipLaunchKernelGGL((k_corrector_detect<DIM, N, double>), dim3((unsigned)C.P.ncell), dim3(128), 0, C.stream,
-                               C.tab, C.P, C.B, C.cur, C.limiter);
+            hipLaunchKernelGGL((k_corrector_detect<DIM, N, double>), dim3(grid), dim3(CS::BS), 0, C.stream, C.tab, C.P,
+                               C.B, C.cur, C.limiter);
     }
     static void bounds(const StepCtx &C) {
         int64_t next = 1;

@@ -45,6 +45,21 @@ def predictor_flops_per_cell(d: int, N: int) -> float:
     return n * (2.0 * (d + 1) * nv * n ** (d + 2) + (10 + 8 * d) * n ** (d + 1))
 
 
+def l1_norm(f, wl):
+    """L1 norm over the domain of a nodal field f[cell][node] (tensor Gauss-Legendre
+    quadrature of the cells' nodes)."""
+    import numpy as np
+    n = wl.N + 1
+    w1 = np.polynomial.legendre.leggauss(n)[1] / 2.0
+    w = w1
+    for _ in range(wl.dim - 1):
+        w = np.multiply.outer(w1, w).reshape(-1)
+    vol = 1.0
+    for k in range(wl.dim):
+        vol *= (wl.hi[k] - wl.lo[k]) / wl.ncell[k]
+    return float((np.abs(f) * w[None, :]).sum() * vol)
+
+
 def traffic_bytes(N, grid):
     """Measured HBM traffic of the dominant kernel, if it was measured on this workload and
     on the kernel source as it stands."""
@@ -147,6 +162,7 @@ def main():
             "troubled_last_step": prob.stats()["troubled"],
             "t_simulated": t_sim,
             "linf_rho_vs_exact": float(np.abs(u[0] - ue[0]).max()),
+            "l1_rho_vs_exact": l1_norm(u[0] - ue[0], wl),
         }
         finals[form] = u
         prob.close()
@@ -195,6 +211,9 @@ def main():
         "forms": forms,
         "speedup_mixed_vs_fp64": forms["mixed"]["value"] / forms["fp64"]["value"],
         "rho_mixed_minus_fp64": {"max": float(drho.max()), "mean": float(drho.mean())},
+        # both forms after the same steps, against the exact (advected) vortex
+        "matched_l1_rho": {"fp64": forms["fp64"]["l1_rho_vs_exact"], "mixed": forms["mixed"]["l1_rho_vs_exact"],
+                           "mixed_over_fp64": forms["mixed"]["l1_rho_vs_exact"] / forms["fp64"]["l1_rho_vs_exact"]},
     }
 
     if not args.no_batch:

@@ -183,6 +183,12 @@ int adg_batch_destroy(adg_batch *b);
  * (NULL clears).  Host memory, one byte per cell. */
 int adg_debug_force_troubled(adg_problem *pb, const uint8_t *mask);
 
+/* Debug hook for the a-posteriori detection (Sec. 4.3, 4.4): at the next step only, every
+ * node of variable var (0..dim+1) of cell's unlimited candidate is set to value (NaN, a
+ * negative density, ...) before the detection tests it.  Errors: ADG_EINVAL (cell or var
+ * out of range), ADG_ESTATE.  Synchronising. */
+int adg_debug_poison(adg_problem *pb, int64_t cell, int var, double value);
+
 #ifdef __cplusplus
 }
 #endif

@@ -50,6 +50,9 @@ struct or_solver {
     uint8_t *beta, *force;
     double t;
     long nonphys;
+    long poison_cell;          /* test hook: cell whose next candidate is overwritten (-1: none) */
+    int poison_var;
+    double poison_value;
 };
 
 /* ------------------------------------------------------------------ helpers */
@@ -412,6 +415,7 @@ or_solver *or_create(const or_config *c) {
         return NULL;
     or_solver *S = calloc(1, sizeof *S);
     S->c = *c;
+    S->poison_cell = -1;
     S->d = c->dim; S->nv = c->dim + 2; S->n = c->N + 1; S->Ns = c->Ns;
     S->nn = ipow(S->n, S->d); S->nst = S->nn * S->n; S->nfn = ipow(S->n, S->d - 1);
     S->nsub = ipow(S->Ns, S->d); S->nsubf = ipow(S->Ns, S->d - 1);
@@ -753,6 +757,16 @@ void or_get_bounds(const or_solver *S, double *bmin, double *bmax) {
     memcpy(bmin, S->bmin, sizeof(double) * S->nv * S->ncell);
     memcpy(bmax, S->bmax, sizeof(double) * S->nv * S->ncell);
 }
+/* Test hook: at the next step, every node of variable `var` of cell `cell`'s candidate is
+ * set to `value` before the detection of Sec. 4.3 sees it (one step only). */
+int or_poison(or_solver *S, long cell, int var, double value) {
+    if (cell < 0 || cell >= S->ncell || var < 0 || var >= S->nv) return -1;
+    S->poison_cell = cell;
+    S->poison_var = var;
+    S->poison_value = value;
+    return 0;
+}
+
 void or_force_troubled(or_solver *S, const uint8_t *mask) {
     if (mask) memcpy(S->force, mask, S->ncell); else memset(S->force, 0, S->ncell);
 }
@@ -1141,6 +1155,11 @@ int or_step(or_solver *S, double dt) {
                 }
             }
         }
+
+    if (S->poison_cell >= 0) {
+        for (int a = 0; a < nn; a++) ustar[((long)S->poison_var * ncell + S->poison_cell) * nn + a] = S->poison_value;
+        S->poison_cell = -1;
+    }
 
     if (!S->c.limiter) {
         memcpy(S->u, ustar, sizeof(double) * nv * ncell * nn);

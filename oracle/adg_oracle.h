@@ -65,6 +65,7 @@ void or_get_margin(const or_solver *s, double *margin);
 void or_get_subcells(const or_solver *s, double *v);
 void or_get_bounds(const or_solver *s, double *bmin, double *bmax);
 void or_force_troubled(or_solver *s, const uint8_t *mask);
+int or_poison(or_solver *s, long cell, int var, double value);
 double or_time(const or_solver *s);
 void or_set_time(or_solver *s, double t);
 double or_cfl_dt(const or_solver *s, double cfl);

@@ -52,6 +52,7 @@ def lib():
         L.or_get_subcells.argtypes = [C.c_void_p, dp]
         L.or_get_bounds.argtypes = [C.c_void_p, dp, dp]
         L.or_force_troubled.argtypes = [C.c_void_p, C.POINTER(C.c_uint8)]
+        L.or_poison.argtypes = [C.c_void_p, C.c_long, C.c_int, C.c_double]
         L.or_time.restype = C.c_double
         L.or_time.argtypes = [C.c_void_p]
         L.or_set_time.argtypes = [C.c_void_p, C.c_double]
@@ -198,6 +199,11 @@ class Oracle:
 
     def step(self, dt: float) -> int:
         return lib().or_step(self.h, dt)
+
+    def poison(self, cell: int, var: int, value: float):
+        """Overwrites variable `var` of cell `cell`'s next candidate with `value` (one step)."""
+        if lib().or_poison(self.h, cell, var, value) != 0:
+            raise ValueError("poison: cell or variable out of range")
 
     def force_troubled(self, mask: Optional[np.ndarray]):
         if mask is None:

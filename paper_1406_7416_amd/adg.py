@@ -23,7 +23,7 @@ EXPORTS = [
     "adg_project_samples", "adg_set_state", "adg_get_state", "adg_cfl_dt", "adg_step", "adg_step_cfl",
     "adg_time", "adg_get_troubled", "adg_get_margin", "adg_get_subcells", "adg_get_stats",
     "adg_profile", "adg_profile_read", "adg_batch_create", "adg_batch_step_cfl", "adg_batch_dt",
-    "adg_batch_destroy", "adg_debug_force_troubled",
+    "adg_batch_destroy", "adg_debug_force_troubled", "adg_debug_poison",
 ]
 
 KERNEL_GROUPS = ["bounds", "predictor", "faces", "corrector_detect", "compact", "subcell", "fluxcorr", "dt"]
@@ -79,6 +79,7 @@ def load():
     L.adg_get_subcells.argtypes = [vp, dp]
     L.adg_get_stats.argtypes = [vp, C.POINTER(i64)]
     L.adg_debug_force_troubled.argtypes = [vp, C.POINTER(C.c_uint8)]
+    L.adg_debug_poison.argtypes = [vp, C.c_int64, C.c_int, C.c_double]
     L.adg_profile.argtypes = [vp, C.c_int]
     L.adg_profile_read.argtypes = [vp, dp, C.POINTER(i64), C.c_int]
     L.adg_batch_create.argtypes = [C.POINTER(vp), C.c_int, C.POINTER(vp)]
@@ -265,6 +266,10 @@ class Problem:
         n = (C.c_int64 * 8)()
         _check(load().adg_profile_read(self.h, _dp(ms), n, 8))
         return {g: (float(ms[i]), int(n[i])) for i, g in enumerate(KERNEL_GROUPS)}
+
+    def poison(self, cell: int, var: int, value: float):
+        """Debug hook: variable `var` of cell `cell`'s next candidate is set to `value`."""
+        _check(load().adg_debug_poison(self.h, int(cell), int(var), float(value)))
 
     def stats(self) -> dict:
         out = (C.c_int64 * 4)()

@@ -1000,6 +1000,18 @@ int adg_batch_destroy(adg_batch *b) {
     return ADG_OK;
 }
 
+int adg_debug_poison(adg_problem *pb, int64_t cell, int var, double value) {
+    if (!pb) return fail(ADG_EINVAL, "null argument");
+    if (!pb->bound) return fail(ADG_ESTATE, "not bound");
+    if (cell < 0 || cell >= pb->P.ncell || var < 0 || var >= pb->P.nv)
+        return fail(ADG_EINVAL, "poison: cell %lld or variable %d out of range", (long long)cell, var);
+    // armed flag, cell, variable, value: read by the next corrector, cleared at the end of that step
+    const double rec[4] = {1.0, (double)cell, (double)var, value};
+    HIPCHK(hipMemcpyAsync(pb->B.scal + 4, rec, sizeof rec, hipMemcpyHostToDevice, pb->stream));
+    HIPCHK(hipStreamSynchronize(pb->stream));
+    return ADG_OK;
+}
+
 int adg_debug_force_troubled(adg_problem *pb, const uint8_t *mask) {
     if (!pb) return fail(ADG_EINVAL, "null argument");
     if (!pb->bound) return fail(ADG_ESTATE, "not bound");

@@ -69,7 +69,7 @@ struct Bufs {
     int *blk;              // block partial counts for compaction [2][nblk]
     int *counts;           // [0] troubled [1] corrected [2] nonphysical cumulative [3] capacity overflow
                            // [4] block ticket of the compaction
-    double *scal;          // [0] dt [1] t [2] lambda_max ...
+    double *scal;          // [0] dt [1] t [2] lambda_max [4] poison armed [5] cell [6] var [7] value
     double *lam_part;      // per-block lambda partials
     int64_t *ring;         // extended-grid indices of the ghost ring
     // subcell chunk scratch

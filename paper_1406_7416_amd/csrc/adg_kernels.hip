@@ -751,6 +751,10 @@ __global__ __launch_bounds__((CorrShape<DIM, N>::BS)) void k_corrector_detect(co
     double *us = us_[lc], *vs = vs_[lc], *tmp = tmp_[lc], *red = red_[lc];
     const double dt = B.scal[0];
     double *un = B.u[cur ^ 1];
+    // debug poison of one variable of one cell's candidate (armed by the host for one step)
+    const bool poisoned = live && B.scal[4] != 0.0 && (int64_t)B.scal[5] == c;
+    const int pvar = poisoned ? (int)B.scal[6] : -1;
+    const double pval = B.scal[7];
     // (dt/h_k)/w_a for every axis and node index: 2 divisions per entry, once per block
     __shared__ double coef[3][n];
     if (threadIdx.x < DIM * n) coef[threadIdx.x / n][threadIdx.x % n] = dt / P.h[threadIdx.x / n] / T->w[threadIdx.x % n];
@@ -797,6 +801,7 @@ __global__ __launch_bounds__((CorrShape<DIM, N>::BS)) void k_corrector_detect(co
                 const R cf = (R)coef[k][ak];
                 val += (double)(cf * ((R)T->L[ak] * Gm - (R)T->R[ak] * Gp));
             }
+            if (v == pvar) val = pval;
             un[((int64_t)v * P.ncell + c) * NN + a] = val;
         }
         us[it] = val;
@@ -1792,7 +1797,11 @@ __global__ void k_dt_final(const double *part, int nparts, double *scal, double 
 }
 
 __global__ void k_set_scalar(double *scal, int idx, double val) { scal[idx] = val; }
-__global__ void k_advance_time(double *scal) { scal[1] += scal[0]; }
+// t += dt; a debug poison of the candidate lasts one step
+__global__ void k_advance_time(double *scal) {
+    scal[1] += scal[0];
+    scal[4] = 0.0;
+}
 
 // ------------------------------------------------------------------ launchers
 template <int DIM, int N>

@@ -46,6 +46,7 @@ def test_create_and_plan_without_gpu():
     assert L.adg_create(ctypes.byref(g), 12, 1.4, ctypes.byref(prm), ctypes.byref(h2)) == -1
     assert b"not built" in L.adg_last_error()
     assert L.adg_step(h, 1e-3) == -6   # no state bound yet
+    assert L.adg_debug_poison(h, 0, 0, 1.0) == -6
     L.adg_destroy(h)
 
 

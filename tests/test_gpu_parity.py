@@ -184,3 +184,60 @@ def test_vortex_full_size_one_step():
     o, g = paired(wl, m=0)
     run_parity(o, g, 1)
     assert o.troubled().sum() == 0 and g.troubled().sum() == 0
+
+
+@pytest.mark.parametrize("var,value", [(0, float("nan")), (0, -0.5), (3, 50.0)])
+def test_poisoned_candidate(var, value):
+    """adg_debug_poison: a corrupted candidate is caught by the a-posteriori detection and
+    recomputed by the subcell scheme, as in the oracle; on the GPU the step equals, bit for
+    bit, the step with that cell forced troubled, and the poison lasts one step."""
+    wl = W.vortex(8, 9)
+    cell = 27
+    o, g = paired(wl, m=0)
+    dt = o.cfl_dt()
+    o.poison(cell, var, value)
+    g.poison(cell, var, value)
+    o.step(dt)
+    g.step(dt)
+    bo, bg = o.troubled(), g.troubled()
+    assert bg[cell] == 1 and bg.sum() == 1 and np.array_equal(bo, bg)
+    assert rel_err(g.state(), o.state()) < 1e-12
+    _, gf = paired(wl, m=0)
+    mask = np.zeros(wl.num_cells, dtype=np.uint8)
+    mask[cell] = 1
+    gf.force_troubled(mask)
+    gf.step(dt)
+    assert np.array_equal(g.state(), gf.state())
+    g.step(dt)
+    assert g.troubled()[cell] == 0
+    # the mixed form catches it the same way
+    from paper_1406_7416_amd import adg
+    gm = gpu_problem(wl, precision=adg.ADG_MIXED)
+    gm.set_state(o.project(wl.ic, 0)[0])
+    gm.poison(cell, var, value)
+    gm.step(dt)
+    assert gm.troubled()[cell] == 1 and np.isfinite(gm.state()).all()
+
+
+def test_config_explosion_2d_full_size():
+    """The 2D explosion at its full size (40 x 40, N = 3), initial detection, 5 steps."""
+    o, g = paired(W.explosion_2d(40, 3))
+    run_parity(o, g, 5)
+    assert o.troubled().sum() > 0
+
+
+def test_config_double_mach_full_size_one_step():
+    """The double Mach reflection at its full size (400 x 100 cells on [0,4] x [0,1], N = 5),
+    initial detection against one-point subcell averages (exact for its piecewise-constant
+    state away from the shock line), one step."""
+    o, g = paired(W.double_mach(400, 100, 5), m=1)
+    run_parity(o, g, 1)
+    assert o.troubled().sum() > 0
+
+
+def test_config_explosion_3d_16cubed():
+    """3D explosion, 16^3 cells, N = 3 (the 3D workload's degree), initial detection against
+    one-point subcell averages."""
+    o, g = paired(W.explosion_3d(16, 3), m=1)
+    run_parity(o, g, 2)
+    assert o.troubled().sum() > 0

@@ -311,3 +311,36 @@ def test_double_mach_post_shock_state_is_rankine_hugoniot():
     u2 = M * c1 * (1 - rho1 / rho2)
     assert abs(post[0] - rho2) < 1e-12 and abs(post[3] - p2) < 1e-12
     assert abs(math.hypot(post[1], post[2]) - u2) < 1e-12
+
+
+@pytest.mark.parametrize("var,value", [(0, float("nan")), (0, -0.5), (3, 50.0)])
+def test_poisoned_candidate_equals_forced_troubled_cell(var, value):
+    """Sec. 4.3-4.4: the detection acts on the unlimited candidate only.  A candidate made
+    non-finite, non-positive or far outside the relaxed DMP bounds flags its cell, and the
+    step then equals, bit for bit, the step with that cell forced troubled: the troubled
+    cell's candidate is discarded, and no other cell's candidate or bounds depend on it."""
+    wl = W.vortex(8, 9)          # resolved: the limiter stays idle without the poison
+    cell = 27
+    u0, _ = O.Oracle(wl).project(wl.ic, 0)
+    runs = {}
+    for mode in ("plain", "poison", "force"):
+        o = O.Oracle(wl)
+        o.set_state(u0)
+        dt = o.cfl_dt()
+        if mode == "poison":
+            o.poison(cell, var, value)
+        if mode == "force":
+            m = np.zeros(wl.num_cells, dtype=np.uint8)
+            m[cell] = 1
+            o.force_troubled(m)
+        o.step(dt)
+        runs[mode] = (o.state(), o.troubled())
+        if mode == "poison":
+            # one step only: the next step is unpoisoned and the cell goes back to DG
+            o.step(dt)
+            assert o.troubled()[cell] == 0
+    assert runs["plain"][1].sum() == 0
+    assert runs["poison"][1][cell] == 1 and runs["poison"][1].sum() == 1
+    assert np.array_equal(runs["poison"][1], runs["force"][1])
+    assert np.array_equal(runs["poison"][0], runs["force"][0])
+    assert np.isfinite(runs["poison"][0]).all()

@@ -43,7 +43,8 @@ struct adg_problem {
         size_t tab, u0, u1, emin0, emax0, emin1, emax1, trace, gbar, beta0, beta1, force, margin, tlist, clist, slot0,
             slot1, pool0, pool1, sflux, blk, counts, scal, lampart, ring, halo, Y, strace, end;
     } off;
-    int64_t nring = 0;       // ghost-ring cells of the extended grid
+    int64_t ring_cap = 0;    // ghost-ring cells of the extended grid
+    int64_t nring = 0;       // of which the detection reads (non-periodic sides)
     bool bounds_valid = false;  // interior old-time bounds were written by the previous step
     // bound state
     char *ws = nullptr;
@@ -160,9 +161,9 @@ static void plan(adg_problem *pb) {
     {
         int64_t inner = 1;
         for (int j = 0; j < d; j++) inner *= P.nc[j];
-        pb->nring = next - inner;
+        pb->ring_cap = next - inner;
     }
-    f.ring = take(8ull * std::max<int64_t>(1, pb->nring));
+    f.ring = take(8ull * std::max<int64_t>(1, pb->ring_cap));
     f.halo = take(8ull * chunk * nv * hsz);
     f.Y = take(8ull * chunk * pb->npos * nv * n3);
     f.strace = take(8ull * chunk * pb->npos * 2 * d * nv * nf3 * 3);
@@ -337,19 +338,27 @@ int adg_bind(adg_problem *pb, void *dev_workspace, size_t bytes, void *hip_strea
     if (!pb->pinned) HIPCHK(hipHostMalloc((void **)&pb->pinned, 64, hipHostMallocDefault));
     HIPCHK(hipMemcpyAsync(pb->tab_dev, &pb->tab_host, sizeof(Tables), hipMemcpyHostToDevice, pb->stream));
     {
-        // extended-grid indices of the one-cell ghost ring, x fastest
+        // extended-grid indices of the ghost-ring cells the detection reads, x fastest: a
+        // ring cell whose out-of-range coordinates all lie on non-periodic axes (along a
+        // periodic axis the detection wraps to the interior cell instead)
         const Prob &P = pb->P;
         std::vector<int64_t> ring;
-        ring.reserve(pb->nring);
+        ring.reserve(pb->ring_cap);
         const int64_t ne0 = P.nc[0] + 2, ne1 = P.dim > 1 ? P.nc[1] + 2 : 1, ne2 = P.dim > 2 ? P.nc[2] + 2 : 1;
         for (int64_t k = 0; k < ne2; k++)
             for (int64_t j = 0; j < ne1; j++)
                 for (int64_t i = 0; i < ne0; i++) {
-                    const bool ghost = i == 0 || i == ne0 - 1 || j == 0 || j == ne1 - 1 ||
-                                       (P.dim > 2 && (k == 0 || k == ne2 - 1));
-                    if (ghost) ring.push_back(i + ne0 * (j + ne1 * k));
+                    const int64_t e[3] = {i, j, k}, ne[3] = {ne0, ne1, ne2};
+                    bool ghost = false, periodic_image = false;
+                    for (int a = 0; a < P.dim; a++)
+                        if (e[a] == 0 || e[a] == ne[a] - 1) {
+                            ghost = true;
+                            if (P.periodic[a]) periodic_image = true;
+                        }
+                    if (ghost && !periodic_image) ring.push_back(i + ne0 * (j + ne1 * k));
                 }
-        if ((int64_t)ring.size() != pb->nring) return fail(ADG_EINVAL, "internal: ghost ring size");
+        if ((int64_t)ring.size() > pb->ring_cap) return fail(ADG_EINVAL, "internal: ghost ring size");
+        pb->nring = (int64_t)ring.size();
         if (pb->nring)
             HIPCHK(hipMemcpyAsync(pb->B.ring, ring.data(), 8 * ring.size(), hipMemcpyHostToDevice, pb->stream));
         HIPCHK(hipStreamSynchronize(pb->stream));

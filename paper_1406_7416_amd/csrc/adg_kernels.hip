@@ -494,7 +494,11 @@ struct FaceShape {
 template <int DIM, int N, typename R>
 __global__ __launch_bounds__((FaceShape<DIM, N>::BS)) void k_face(const Tables *__restrict__ T, Prob P,
                                                                  const R *__restrict__ trace, R *__restrict__ gbar,
-                                                                 const double *__restrict__ scal, int k) {
+                                                                 const double *__restrict__ scal, int64_t kb1,
+                                                                 int64_t kb2) {
+    // one launch for the faces of every axis: blocks [0, kb1) axis 0, [kb1, kb2) axis 1, then axis 2
+    const int k = (blockIdx.x < kb1) ? 0 : ((blockIdx.x < kb2) ? 1 : 2);
+    const int64_t blk = (int64_t)blockIdx.x - (k == 0 ? 0 : (k == 1 ? kb1 : kb2));
     using FS = FaceShape<DIM, N>;
     constexpr int n = N + 1, NV = DIM + 2, NFN = FS::NFN, PER = FS::PER, FPB = FS::FPB;
     __shared__ R part[FPB * PER * NV];
@@ -506,7 +510,7 @@ __global__ __launch_bounds__((FaceShape<DIM, N>::BS)) void k_face(const Tables *
     const int64_t nfaces = nlines * nfk;
     const int lf = threadIdx.x / PER, j = threadIdx.x % PER;
     const int s = j / NFN, ap = j % NFN;
-    const int64_t fidx = (int64_t)blockIdx.x * FPB + lf;
+    const int64_t fidx = blk * FPB + lf;
     const bool active = lf < FPB && fidx < nfaces;
     int64_t cL = -1, cR = -1;
     bool hasL = false, hasR = false;
@@ -760,7 +764,8 @@ __global__ __launch_bounds__((CorrShape<DIM, N>::BS)) void k_corrector_detect(co
     if (threadIdx.x < DIM * n) coef[threadIdx.x / n][threadIdx.x % n] = dt / P.h[threadIdx.x / n] / T->w[threadIdx.x % n];
     if (limiter && live && tid < 2 * NV) {
         // min (mm = 0) / max (mm = 1) of variable v over the 3^d block V_i of the
-        // per-cell old-time bounds, held on the extended grid (cell c sits at ci + 1)
+        // per-cell old-time bounds, held on the extended grid (cell c sits at ci + 1; along a
+        // periodic axis a neighbour beyond the edge is the wrapped interior cell)
         const int mm = tid / NV, v = tid % NV;
         int ci[3];
         coords_of(P, c, ci);
@@ -774,7 +779,11 @@ __global__ __launch_bounds__((CorrShape<DIM, N>::BS)) void k_corrector_detect(co
         for (int o = 0; o < NB; o++) {
             const int off[3] = {o % 3, (o / 3) % 3, o / 9};
             int64_t e = 0;
-            for (int j = DIM - 1; j >= 0; j--) e = e * ne[j] + (ci[j] + off[j]);
+            for (int j = DIM - 1; j >= 0; j--) {
+                int x = ci[j] + off[j];   // extended coordinate
+                if (P.periodic[j]) x += (x == 0) ? P.nc[j] : ((x == P.nc[j] + 1) ? -P.nc[j] : 0);
+                e = e * ne[j] + x;
+            }
             acc = mm ? fmax(acc, src[e]) : fmin(acc, src[e]);
         }
         bnd[lc][mm][v] = acc;
@@ -1855,17 +1864,20 @@ struct Launch {
     }
     template <typename R>
     static void faces_t(const StepCtx &C) {
+        using FS = FaceShape<DIM, N>;
+        int64_t start[4] = {0, 0, 0, 0};   // first block of each axis
         for (int k = 0; k < DIM; k++) {
             int64_t nlines = 1;
             for (int j = 0; j < DIM; j++)
                 if (j != k) nlines *= C.P.nc[j];
             const int nfk = C.P.periodic[k] ? C.P.nc[k] : C.P.nc[k] + 1;
             const int64_t nfaces = nlines * nfk;
-            using FS = FaceShape<DIM, N>;
-            hipLaunchKernelGGL((k_face<DIM, N, R>), dim3((unsigned)((nfaces + FS::FPB - 1) / FS::FPB)), dim3(FS::BS), 0,
-                               C.stream, C.tab, C.P, reinterpret_cast<const R *>(C.B.trace),
-                               reinterpret_cast<R *>(C.B.gbar), C.B.scal, k);
+            start[k + 1] = start[k] + (nfaces + FS::FPB - 1) / FS::FPB;
         }
+        const int64_t kb2 = DIM == 3 ? start[2] : start[DIM];
+        hipLaunchKernelGGL((k_face<DIM, N, R>), dim3((unsigned)start[DIM]), dim3(FS::BS), 0, C.stream, C.tab, C.P,
+                           reinterpret_cast<const R *>(C.B.trace), reinterpret_cast<R *>(C.B.gbar), C.B.scal,
+                           start[1], kb2);
     }
     static void faces(const StepCtx &C) {
         if (C.precision == ADG_MIXED) faces_t<float>(C);

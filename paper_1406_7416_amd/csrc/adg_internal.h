@@ -31,6 +31,8 @@ struct Tables {
     // FP32 copies for the mixed-precision predictor and face fluxes
     float fD[MAXN][MAXN], fKw[MAXN][MAXN], fDvol[MAXN][MAXN], fL[MAXN], fR[MAXN], fw[MAXN];
     float fDE[MAXN / 2][MAXN / 2 + 1], fDO[MAXN / 2 + 1][MAXN / 2];
+    // FP32 copies of the degree-2 subcell operators (mixed form)
+    float fD3[3][3], fKw3[3][3], fL3[3], fR3[3], fw3[3];
 };
 
 struct BCDev {

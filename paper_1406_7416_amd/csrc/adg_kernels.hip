@@ -55,12 +55,12 @@ __device__ __forceinline__ void rusanov(int k, const R *qL, const R *qR, R *G, R
     for (int v = 0; v < NV; v++) G[v] = R(0.5) * (FL[v] + FR[v]) - R(0.5) * s * (qR[v] - qL[v]);
 }
 
-template <int DIM>
-__device__ __forceinline__ bool physical(const double *q, double g) {
+template <int DIM, typename R = double>
+__device__ __forceinline__ bool physical(const R *q, R g) {
 #pragma unroll
     for (int v = 0; v < DIM + 2; v++)
         if (!isfinite(q[v])) return false;
-    return q[0] > 0.0 && pressure<DIM>(q, g) > 0.0;
+    return q[0] > R(0) && pressure<DIM, R>(q, g) > R(0);
 }
 
 // Ghost state of one boundary side (transmissive / reflective / Dirichlet with split).
@@ -788,31 +788,43 @@ __global__ __launch_bounds__((CorrShape<DIM, N>::BS)) void k_corrector_detect(co
         }
         bnd[lc][mm][v] = acc;
     }
+    // every global load of the update issued before any store: the cell's face fluxes
+    // into LDS, its volume-term candidate into registers
+    constexpr int GSZ = 2 * DIM * NV * NFN, EPT = (NV * NN + CW - 1) / CW;
+    __shared__ R gs_[CPB][GSZ];
+    R *gs = gs_[lc];
+    for (int i = tid; i < GSZ; i += CW) gs[i] = live ? gbar[c * GSZ + i] : R(0);
+    double uv[EPT];
+#pragma unroll
+    for (int e = 0; e < EPT; e++) {
+        const int it = tid + e * CW;
+        uv[e] = (live && it < NV * NN) ? un[((int64_t)(it / NN) * P.ncell + c) * NN + it % NN] : 0.0;
+    }
     __syncthreads();
-    for (int it = tid; it < NV * NN; it += CW) {
+#pragma unroll
+    for (int e = 0; e < EPT; e++) {
+        const int it = tid + e * CW;
+        if (it >= NV * NN) break;
         const int v = it / NN, a = it % NN;
         int m[3] = {a % n, (a / n) % n, a / (n * n)};
-        double val = 0.0;
-        if (live) {
-            val = un[((int64_t)v * P.ncell + c) * NN + a];
+        double val = uv[e];
 #pragma unroll
-            for (int k = 0; k < DIM; k++) {
-                int ap = 0, mul = 1;
-                for (int j = 0; j < DIM; j++) {
-                    if (j == k) continue;
-                    ap += m[j] * mul;
-                    mul *= n;
-                }
-                const int ak = m[k];
-                const R Gm = gbar[((c * 2 * DIM + 2 * k) * NV + v) * NFN + ap];
-                const R Gp = gbar[((c * 2 * DIM + 2 * k + 1) * NV + v) * NFN + ap];
-                // face increment in the working precision R, added to the FP64 candidate
-                const R cf = (R)coef[k][ak];
-                val += (double)(cf * ((R)T->L[ak] * Gm - (R)T->R[ak] * Gp));
+        for (int k = 0; k < DIM; k++) {
+            int ap = 0, mul = 1;
+            for (int j = 0; j < DIM; j++) {
+                if (j == k) continue;
+                ap += m[j] * mul;
+                mul *= n;
             }
-            if (v == pvar) val = pval;
-            un[((int64_t)v * P.ncell + c) * NN + a] = val;
+            const int ak = m[k];
+            const R Gm = gs[((2 * k) * NV + v) * NFN + ap];
+            const R Gp = gs[((2 * k + 1) * NV + v) * NFN + ap];
+            // face increment in the working precision R, added to the FP64 candidate
+            const R cf = (R)coef[k][ak];
+            val += (double)(cf * ((R)T->L[ak] * Gm - (R)T->R[ak] * Gp));
         }
+        if (v == pvar) val = pval;
+        if (live) un[((int64_t)v * P.ncell + c) * NN + a] = val;
         us[it] = val;
     }
     if (!limiter) return;
@@ -1355,7 +1367,7 @@ __device__ void sub_recon_cell(const Tables *__restrict__ T, const Bufs &B, int 
 }
 
 // S4: sub-face Rusanov fluxes, FV update, gather, pool store, boundary fluxes.
-template <int DIM, int N>
+template <int DIM, int N, typename R>
 __device__ void sub_update_cell(const Tables *__restrict__ T, const Prob &P, const Bufs &B, int cur, int w, int sidx,
                                 int *nonphys) {
     constexpr int n = N + 1, NV = DIM + 2, NN = cpow(n, DIM);
@@ -1374,7 +1386,8 @@ __device__ void sub_update_cell(const Tables *__restrict__ T, const Prob &P, con
     int ci[3];
     coords_of(P, c, ci);
     const double dt = B.scal[0], t0 = B.scal[1];
-    const double *tr = B.strace + (int64_t)ch * NPOS * TRS;
+    const R *tr = reinterpret_cast<const R *>(B.strace) + (int64_t)ch * NPOS * TRS;
+    const R gam = (R)P.gamma;
     if (threadIdx.x == 0) badc = 0;
     // neighbour existence per face of the cell
     bool nbex[3][2];
@@ -1428,14 +1441,14 @@ __device__ void sub_update_cell(const Tables *__restrict__ T, const Prob &P, con
         }
         // Positivity safeguard: if any predictor trace on either side is not a physical
         // state, the sub-face takes the first-order flux of the two subcell averages.
-        double Fbar[NV];
+        R Fbar[NV];
         for (int pass = 0; pass < 2; pass++) {
             bool ok = true;
 #pragma unroll
-            for (int v = 0; v < NV; v++) Fbar[v] = 0.0;
+            for (int v = 0; v < NV; v++) Fbar[v] = 0;
             for (int s = 0; s < 3 && ok; s++)
                 for (int ap = 0; ap < NF3; ap++) {
-                    double qL[NV], qR[NV], G[NV];
+                    R qL[NV], qR[NV], G[NV];
                     int ma[2] = {ap % 3, ap / 3};
                     double wt = T->w3[s];
                     double x[3] = {0, 0, 0};
@@ -1450,27 +1463,37 @@ __device__ void sub_update_cell(const Tables *__restrict__ T, const Prob &P, con
                         }
                     }
                     const double ts = t0 + T->xi3[s] * dt;
-                    const double *trL = tr + (int64_t)pL * TRS + (2 * k + 1) * NV * NF3 * 3;
-                    const double *trR = tr + (int64_t)pR * TRS + (2 * k + 0) * NV * NF3 * 3;
+                    const R *trL = tr + (int64_t)pL * TRS + (2 * k + 1) * NV * NF3 * 3;
+                    const R *trR = tr + (int64_t)pR * TRS + (2 * k + 0) * NV * NF3 * 3;
 #pragma unroll
                     for (int v = 0; v < NV; v++) {
-                        qL[v] = pass ? avL[v] : trL[v * NF3 * 3 + ap + NF3 * s];
-                        qR[v] = pass ? avR[v] : trR[v * NF3 * 3 + ap + NF3 * s];
+                        qL[v] = pass ? (R)avL[v] : trL[v * NF3 * 3 + ap + NF3 * s];
+                        qR[v] = pass ? (R)avR[v] : trR[v * NF3 * 3 + ap + NF3 * s];
                     }
-                    if (bside == 0) bc_ghost<DIM>(P, k, 0, qR, x, ts, qL);
-                    else if (bside == 1) bc_ghost<DIM>(P, k, 1, qL, x, ts, qR);
-                    if (!pass && !(physical<DIM>(qL, P.gamma) && physical<DIM>(qR, P.gamma))) {
+                    if (bside >= 0) {
+                        // ghost state of the boundary rule, evaluated in FP64
+                        double qi[NV], qo[NV];
+#pragma unroll
+                        for (int v = 0; v < NV; v++) qi[v] = (double)(bside == 0 ? qR[v] : qL[v]);
+                        bc_ghost<DIM>(P, k, bside, qi, x, ts, qo);
+#pragma unroll
+                        for (int v = 0; v < NV; v++) {
+                            if (bside == 0) qL[v] = (R)qo[v];
+                            else qR[v] = (R)qo[v];
+                        }
+                    }
+                    if (!pass && !(physical<DIM, R>(qL, gam) && physical<DIM, R>(qR, gam))) {
                         ok = false;
                         break;
                     }
-                    rusanov<DIM>(k, qL, qR, G, P.gamma);
+                    rusanov<DIM, R>(k, qL, qR, G, gam);
 #pragma unroll
-                    for (int v = 0; v < NV; v++) Fbar[v] += wt * G[v];
+                    for (int v = 0; v < NV; v++) Fbar[v] += (R)wt * G[v];
                 }
             if (ok) break;
         }
 #pragma unroll
-        for (int v = 0; v < NV; v++) Fb[it * NV + v] = Fbar[v];
+        for (int v = 0; v < NV; v++) Fb[it * NV + v] = (double)Fbar[v];
     }
     __syncthreads();
     // FV update of the cell's own subcells
@@ -1528,65 +1551,68 @@ __device__ void sub_update_cell(const Tables *__restrict__ T, const Prob &P, con
 // position sit on consecutive lanes of one wave (64 / 3^d positions per wave), each lane
 // holding its node's time pencil; a contraction along an axis gathers the three nodes of
 // the line by lane permutation, so the waves work without LDS or workgroup barriers.
-// Output: the face traces of every position, [pos][2d][v][3^(d-1) tangential x 3 time].
-template <int DIM>
-__device__ void sub_predictor(const Tables *__restrict__ T, const double *__restrict__ Y, double *__restrict__ tr,
-                              int npos, double dt, const double *dth, double gamma) {
+// Output: the face traces of every position, [pos][2d][v][3^(d-1) tangential x 3 time],
+// in the working precision R (FP32 in the mixed form).
+template <int DIM, typename R>
+__device__ void sub_predictor(const Tables *__restrict__ T, const double *__restrict__ Y, R *__restrict__ tr,
+                              int npos, double dt, const double *dth, double gamma_d) {
     constexpr int NV = DIM + 2, NN = cpow(3, DIM), NF = cpow(3, DIM - 1), PPW = 64 / NN;
     constexpr int TRS = 2 * DIM * NV * NF * 3;
     constexpr int ST[3] = {1, 3, 9};
+    constexpr bool F32 = sizeof(R) == 4;
+    const R gamma = (R)gamma_d;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const int slot = lane / NN, a = lane % NN;
     const int ia[3] = {a % 3, (a / 3) % 3, a / 9};
     // this lane's rows of the derivative matrix, per axis, and dt/h_k
-    double Dk[DIM][3], ck[DIM];
+    R Dk[DIM][3], ck[DIM];
 #pragma unroll
     for (int k = 0; k < DIM; k++) {
-        ck[k] = dt * dth[k];
+        ck[k] = (R)(dt * dth[k]);
 #pragma unroll
-        for (int b = 0; b < 3; b++) Dk[k][b] = T->D3[ia[k]][b];
+        for (int b = 0; b < 3; b++) Dk[k][b] = F32 ? (R)T->fD3[ia[k]][b] : (R)T->D3[ia[k]][b];
     }
     for (int base = wv * PPW; base < npos; base += nw * PPW) {
         const int pos = base + slot;
         const bool valid = slot < PPW && pos < npos;
-        double u0[NV], q[NV][3];
+        R u0[NV], q[NV][3];
         if (valid) {
 #pragma unroll
-            for (int v = 0; v < NV; v++) u0[v] = Y[((int64_t)pos * NV + v) * NN + a];
+            for (int v = 0; v < NV; v++) u0[v] = (R)Y[((int64_t)pos * NV + v) * NN + a];
         } else {
             // idle lanes carry a valid constant state
 #pragma unroll
-            for (int v = 0; v < NV; v++) u0[v] = (v == 0) ? 1.0 : 0.0;
-            u0[NV - 1] = 2.5;
+            for (int v = 0; v < NV; v++) u0[v] = (v == 0) ? R(1) : R(0);
+            u0[NV - 1] = R(2.5);
         }
 #pragma unroll
         for (int v = 0; v < NV; v++)
 #pragma unroll
             for (int s = 0; s < 3; s++) q[v][s] = u0[v];
         for (int r = 0; r < 3; r++) {
-            double S[NV][3];
+            R S[NV][3];
 #pragma unroll
             for (int k = 0; k < DIM; k++) {
-                double F[NV][3];
+                R F[NV][3];
 #pragma unroll
                 for (int t = 0; t < 3; t++) {
-                    const double ir = 1.0 / q[0][t];
-                    const double un = q[1 + k][t] * ir;
-                    double ke = 0.0;
+                    const R ir = recip(q[0][t]);
+                    const R un = q[1 + k][t] * ir;
+                    R ke = 0;
 #pragma unroll
                     for (int j = 0; j < DIM; j++) ke += q[1 + j][t] * q[1 + j][t];
-                    const double prt = (gamma - 1.0) * (q[NV - 1][t] - 0.5 * ke * ir);
+                    const R prt = (gamma - R(1)) * (q[NV - 1][t] - R(0.5) * ke * ir);
                     F[0][t] = q[1 + k][t];
 #pragma unroll
-                    for (int j = 0; j < DIM; j++) F[1 + j][t] = q[1 + j][t] * un + (j == k ? prt : 0.0);
+                    for (int j = 0; j < DIM; j++) F[1 + j][t] = q[1 + j][t] * un + (j == k ? prt : R(0));
                     F[NV - 1][t] = un * (q[NV - 1][t] + prt);
                 }
                 // sum_b D[a_k][b] F(node b of the line), b ascending
-                double x[NV][3];
+                R x[NV][3];
 #pragma unroll
                 for (int v = 0; v < NV; v++)
 #pragma unroll
-                    for (int t = 0; t < 3; t++) x[v][t] = 0.0;
+                    for (int t = 0; t < 3; t++) x[v][t] = 0;
 #pragma unroll
                 for (int b = 0; b < 3; b++) {
                     const int src = lane + (b - ia[k]) * ST[k];
@@ -1603,12 +1629,12 @@ __device__ void sub_predictor(const Tables *__restrict__ T, const double *__rest
             // time contraction K1^{-1} diag(w)
 #pragma unroll
             for (int s = 0; s < 3; s++) {
-                double acc[NV];
+                R acc[NV];
 #pragma unroll
-                for (int v = 0; v < NV; v++) acc[v] = 0.0;
+                for (int v = 0; v < NV; v++) acc[v] = 0;
 #pragma unroll
                 for (int t = 0; t < 3; t++) {
-                    const double kst = T->Kw3[s][t];
+                    const R kst = F32 ? (R)T->fKw3[s][t] : (R)T->Kw3[s][t];
 #pragma unroll
                     for (int v = 0; v < NV; v++) acc[v] += kst * S[v][t];
                 }
@@ -1620,7 +1646,7 @@ __device__ void sub_predictor(const Tables *__restrict__ T, const double *__rest
         // at the high end the xi_k = 1 trace
 #pragma unroll
         for (int k = 0; k < DIM; k++) {
-            double qb[3][NV][3];
+            R qb[3][NV][3];
 #pragma unroll
             for (int b = 0; b < 3; b++) {
                 const int src = lane + (b - ia[k]) * ST[k];
@@ -1631,7 +1657,10 @@ __device__ void sub_predictor(const Tables *__restrict__ T, const double *__rest
             }
             if (valid && ia[k] != 1) {
                 const int side = ia[k] == 2;
-                const double *Bv = side ? T->R3 : T->L3;
+                R Bv[3];
+#pragma unroll
+                for (int b = 0; b < 3; b++)
+                    Bv[b] = F32 ? (R)(side ? T->fR3[b] : T->fL3[b]) : (R)(side ? T->R3[b] : T->L3[b]);
                 int ap = 0, mul = 1;
 #pragma unroll
                 for (int j = 0; j < DIM; j++) {
@@ -1639,12 +1668,12 @@ __device__ void sub_predictor(const Tables *__restrict__ T, const double *__rest
                     ap += ia[j] * mul;
                     mul *= 3;
                 }
-                double *o = tr + (int64_t)pos * TRS + (2 * k + side) * NV * NF * 3;
+                R *o = tr + (int64_t)pos * TRS + (2 * k + side) * NV * NF * 3;
 #pragma unroll
                 for (int v = 0; v < NV; v++)
 #pragma unroll
                     for (int s = 0; s < 3; s++) {
-                        double acc = 0.0;
+                        R acc = 0;
 #pragma unroll
                         for (int b = 0; b < 3; b++) acc += Bv[b] * qb[b][v][s];
                         o[v * NF * 3 + ap + NF * s] = acc;
@@ -1659,7 +1688,9 @@ __device__ void sub_predictor(const Tables *__restrict__ T, const double *__rest
 // troubled cell and runs its halo (eq. (ader.icbc)), WENO3 reconstruction, degree-2
 // space-time predictor, sub-face fluxes, FV update and gather, using its own scratch
 // slot (blockIdx.x), so the scratch scales with the grid, not with the worklist.
-template <int DIM, int N>
+// R: working precision of the degree-2 predictor and the sub-face fluxes (FP32 in the mixed
+// form); halo, WENO3, FV update, gather and pool stay FP64.
+template <int DIM, int N, typename R>
 __global__ __launch_bounds__(SUB_BS, 2) void k_subcell(const Tables *__restrict__ T, Prob P, Bufs B, int cur, int64_t cap,
                                                  int *nonphys) {
     constexpr int NV = DIM + 2, NS = 2 * N + 1;
@@ -1671,15 +1702,15 @@ __global__ __launch_bounds__(SUB_BS, 2) void k_subcell(const Tables *__restrict_
     double dth[3] = {0.0, 0.0, 0.0};
     for (int k = 0; k < DIM; k++) dth[k] = (double)NS / P.h[k];
     const double *Ys = B.Y + (int64_t)sidx * NPOS * NV * N3;
-    double *trs = B.strace + (int64_t)sidx * NPOS * TRS;
+    R *trs = reinterpret_cast<R *>(B.strace) + (int64_t)sidx * NPOS * TRS;
     for (int w = blockIdx.x; w < count; w += gridDim.x) {
         sub_halo_cell<DIM, N>(T, P, B, cur, w, sidx);
         __syncthreads();
         sub_recon_cell<DIM, N>(T, B, sidx);
         __syncthreads();
-        sub_predictor<DIM>(T, Ys, trs, NPOS, dt, dth, P.gamma);
+        sub_predictor<DIM, R>(T, Ys, trs, NPOS, dt, dth, P.gamma);
         __syncthreads();
-        sub_update_cell<DIM, N>(T, P, B, cur, w, sidx, nonphys);
+        sub_update_cell<DIM, N, R>(T, P, B, cur, w, sidx, nonphys);
     }
 }
 
@@ -1902,8 +1933,12 @@ struct Launch {
                                C.cur, C.ring_only ? C.B.ring : (const int64_t *)nullptr);
     }
     static void subcell(const StepCtx &C) {
-        hipLaunchKernelGGL((k_subcell<DIM, N>), dim3((unsigned)C.subcell_grid), dim3(SUB_BS), 0, C.stream, C.tab, C.P,
-                           C.B, C.cur, C.capacity, C.B.counts + 2);
+        if (C.precision == ADG_MIXED)
+            hipLaunchKernelGGL((k_subcell<DIM, N, float>), dim3((unsigned)C.subcell_grid), dim3(SUB_BS), 0, C.stream,
+                               C.tab, C.P, C.B, C.cur, C.capacity, C.B.counts + 2);
+        else
+            hipLaunchKernelGGL((k_subcell<DIM, N, double>), dim3((unsigned)C.subcell_grid), dim3(SUB_BS), 0, C.stream,
+                               C.tab, C.P, C.B, C.cur, C.capacity, C.B.counts + 2);
     }
     static void fluxcorr(const StepCtx &C, int count) {
         const unsigned g = (unsigned)std::min<int64_t>(count >= 0 ? count : C.P.ncell, 512);

@@ -197,6 +197,15 @@ void build_tables(int N, int Ns, Tables *T) {
                 if (b < MAXN / 2) T->fDO[a][b] = (float)T->DO[a][b];
             }
     }
+    for (int a = 0; a < 3; a++) {
+        T->fL3[a] = (float)T->L3[a];
+        T->fR3[a] = (float)T->R3[a];
+        T->fw3[a] = (float)T->w3[a];
+        for (int b = 0; b < 3; b++) {
+            T->fD3[a][b] = (float)T->D3[a][b];
+            T->fKw3[a][b] = (float)T->Kw3[a][b];
+        }
+    }
     for (int a = 0; a < MAXN; a++) {
         T->fL[a] = (float)T->L[a];
         T->fR[a] = (float)T->R[a];

@@ -1184,38 +1184,62 @@ __device__ __forceinline__ void position_coords(int pos, int Ns, int *L) {
     if (DIM == 2) L[2] = 0;
 }
 
-// S1: halo of subcell data v^n (eq. (ader.icbc)) 3 subcells deep around the cell.
-// Troubled cell number w of the worklist; scratch slot sidx.
+// S1: halo of subcell data v^n (eq. (ader.icbc)) 3 subcells deep around the cell, into
+// halo[v][HN^d].  Troubled cell number w of the worklist.  The 3^d source cells of the halo
+// (the cell, its neighbours, or the interior cells a non-periodic ghost mirrors) have their
+// DG coefficients staged in LDS first (nbu, 3^d x NV x n^d values; null: read from HBM).
 template <int DIM, int N>
-__device__ void sub_halo_cell(const Tables *__restrict__ T, const Prob &P, const Bufs &B, int cur, int w, int sidx) {
+__device__ __forceinline__ void sub_halo_cell(const Tables *__restrict__ T, const Prob &P, const Bufs &B, int cur, int w,
+                              double *halo, double *nbu) {
     constexpr int n = N + 1, NV = DIM + 2, NN = cpow(n, DIM);
-    constexpr int NS = 2 * N + 1, NSUB = cpow(NS, DIM), HN = NS + 6, HSZ = cpow(HN, DIM);
+    constexpr int NS = 2 * N + 1, NSUB = cpow(NS, DIM), HN = NS + 6, HSZ = cpow(HN, DIM), NB = cpow(3, DIM);
     const int64_t c = B.tlist[w];
     int ci[3];
     coords_of(P, c, ci);
     const double t0 = B.scal[1];
-    double *halo = B.halo + (int64_t)sidx * NV * HSZ;
-    for (int hidx = threadIdx.x; hidx < HSZ; hidx += blockDim.x) {
-        int hl[3] = {hidx % HN, (hidx / HN) % HN, hidx / (HN * HN)};
-        int gci[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, src[3] = {0, 0, 0}, ss[3] = {0, 0, 0}, gside[3] = {-1, -1, -1};
+    // source cell of the halo block at offset (o_j - 1) along every axis
+    auto source = [&](const int *off, int *src, int *mir, int *gside, int *gci) {
+        for (int j = 0; j < 3; j++) {
+            src[j] = j < DIM ? ci[j] + off[j] : 0;
+            gci[j] = src[j];
+            mir[j] = 0;
+            gside[j] = -1;
+        }
         for (int j = 0; j < DIM; j++) {
-            const int Lj = hl[j] - 3;
-            const int off = Lj < 0 ? -1 : (Lj >= NS ? 1 : 0);
-            gci[j] = ci[j] + off;
-            gs[j] = Lj - off * NS;
-            src[j] = gci[j];
-            ss[j] = gs[j];
             if (gci[j] < 0 || gci[j] >= P.nc[j]) {
                 const int side = gci[j] >= P.nc[j];
                 if (P.periodic[j]) {
                     src[j] = (gci[j] + P.nc[j]) % P.nc[j];
                 } else {
                     src[j] = side ? 2 * P.nc[j] - 1 - gci[j] : -1 - gci[j];
-                    ss[j] = NS - 1 - gs[j];
+                    mir[j] = 1;
                     gside[j] = side;
                 }
             }
         }
+    };
+    if (nbu) {
+        for (int i = threadIdx.x; i < NB * NV * NN; i += blockDim.x) {
+            const int o = i / (NV * NN), v = (i / NN) % NV, a = i % NN;
+            int off[3] = {0, 0, 0};
+            for (int j = 0, r = o; j < DIM; j++, r /= 3) off[j] = r % 3 - 1;
+            int src[3], mir[3], gside[3], gci[3];
+            source(off, src, mir, gside, gci);
+            nbu[i] = B.u[cur][((int64_t)v * P.ncell + cell_of(P, src)) * NN + a];
+        }
+        __syncthreads();
+    }
+    for (int hidx = threadIdx.x; hidx < HSZ; hidx += blockDim.x) {
+        int hl[3] = {hidx % HN, (hidx / HN) % HN, hidx / (HN * HN)};
+        int off[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, ss[3] = {0, 0, 0};
+        for (int j = 0; j < DIM; j++) {
+            const int Lj = hl[j] - 3;
+            off[j] = Lj < 0 ? -1 : (Lj >= NS ? 1 : 0);
+            gs[j] = Lj - off[j] * NS;
+        }
+        int src[3], mir[3], gside[3], gci[3];
+        source(off, src, mir, gside, gci);
+        for (int j = 0; j < DIM; j++) ss[j] = mir[j] ? NS - 1 - gs[j] : gs[j];
         const int64_t cs = cell_of(P, src);
         int sidx = 0;
         for (int j = DIM - 1; j >= 0; j--) sidx = sidx * NS + ss[j];
@@ -1226,6 +1250,8 @@ __device__ void sub_halo_cell(const Tables *__restrict__ T, const Prob &P, const
             for (int v = 0; v < NV; v++) q[v] = B.pool[0][((int64_t)slot * NV + v) * NSUB + sidx];
         } else {
             // P(u^n) at one subcell: plain tensor sum over the nodes
+            int o = 0;
+            for (int j = DIM - 1; j >= 0; j--) o = o * 3 + (off[j] + 1);
 #pragma unroll
             for (int v = 0; v < NV; v++) q[v] = 0.0;
             for (int a = 0; a < NN; a++) {
@@ -1233,7 +1259,8 @@ __device__ void sub_halo_cell(const Tables *__restrict__ T, const Prob &P, const
                 double wgt = 1.0;
                 for (int j = 0; j < DIM; j++) wgt *= T->P[ss[j]][m[j]];
 #pragma unroll
-                for (int v = 0; v < NV; v++) q[v] += wgt * B.u[cur][((int64_t)v * P.ncell + cs) * NN + a];
+                for (int v = 0; v < NV; v++)
+                    q[v] += wgt * (nbu ? nbu[(o * NV + v) * NN + a] : B.u[cur][((int64_t)v * P.ncell + cs) * NN + a]);
             }
         }
         double x[3] = {0, 0, 0};
@@ -1287,11 +1314,10 @@ __device__ __forceinline__ void weno3(const Tables *__restrict__ T, const double
 // the 3^d GL points of the subcell (x sweep on the averages, then y (then z) sweeps on
 // the nodal values of the previous sweep).  One work item per (position, variable).
 template <int DIM, int N>
-__device__ void sub_recon_cell(const Tables *__restrict__ T, const Bufs &B, int sidx) {
+__device__ __forceinline__ void sub_recon_cell(const Tables *__restrict__ T, const Bufs &B, int sidx, const double *halo) {
     constexpr int NV = DIM + 2, NS = 2 * N + 1, HN = NS + 6, HSZ = cpow(HN, DIM);
     constexpr int NPOS = cpow(NS, DIM) + 2 * DIM * cpow(NS, DIM - 1), N3 = cpow(3, DIM);
     constexpr int W5 = cpow(5, DIM);
-    const double *halo = B.halo + (int64_t)sidx * NV * HSZ;
     for (int item = threadIdx.x; item < NPOS * NV; item += blockDim.x) {
         const int v = item / NPOS, pos = item % NPOS;
         int L[3];
@@ -1368,8 +1394,8 @@ __device__ void sub_recon_cell(const Tables *__restrict__ T, const Bufs &B, int 
 
 // S4: sub-face Rusanov fluxes, FV update, gather, pool store, boundary fluxes.
 template <int DIM, int N, typename R>
-__device__ void sub_update_cell(const Tables *__restrict__ T, const Prob &P, const Bufs &B, int cur, int w, int sidx,
-                                int *nonphys) {
+__device__ __forceinline__ void sub_update_cell(const Tables *__restrict__ T, const Prob &P, const Bufs &B, int cur, int w, int sidx,
+                                int *nonphys, const double *halo) {
     constexpr int n = N + 1, NV = DIM + 2, NN = cpow(n, DIM);
     constexpr int NS = 2 * N + 1, NSUB = cpow(NS, DIM), NSF = cpow(NS, DIM - 1), HN = NS + 6, HSZ = cpow(HN, DIM);
     constexpr int NPOS = NSUB + 2 * DIM * NSF, NF3 = cpow(3, DIM - 1);
@@ -1432,11 +1458,10 @@ __device__ void sub_update_cell(const Tables *__restrict__ T, const Prob &P, con
                 hL = hL * HN + (Lv[j] + 3);
                 hR = hR * HN + (Rv[j] + 3);
             }
-            const double *hal = B.halo + (int64_t)ch * NV * HSZ;
 #pragma unroll
             for (int v = 0; v < NV; v++) {
-                avL[v] = hal[v * HSZ + hL];
-                avR[v] = hal[v * HSZ + hR];
+                avL[v] = halo[v * HSZ + hL];
+                avR[v] = halo[v * HSZ + hR];
             }
         }
         // Positivity safeguard: if any predictor trace on either side is not a physical
@@ -1497,7 +1522,6 @@ __device__ void sub_update_cell(const Tables *__restrict__ T, const Prob &P, con
     }
     __syncthreads();
     // FV update of the cell's own subcells
-    const double *halo = B.halo + (int64_t)ch * NV * HSZ;
     const int slot = B.slot[1][c];
     for (int sg = threadIdx.x; sg < NSUB; sg += SUB_BS) {
         int ms[3] = {sg % NS, (sg / NS) % NS, sg / (NS * NS)};
@@ -1703,14 +1727,20 @@ __global__ __launch_bounds__(SUB_BS, 2) void k_subcell(const Tables *__restrict_
     for (int k = 0; k < DIM; k++) dth[k] = (double)NS / P.h[k];
     const double *Ys = B.Y + (int64_t)sidx * NPOS * NV * N3;
     R *trs = reinterpret_cast<R *>(B.strace) + (int64_t)sidx * NPOS * TRS;
+    // 2D: the halo and the source cells' coefficients live in LDS; 3D: halo in HBM scratch
+    constexpr int HSZ = cpow(NS + 6, DIM), NNS = cpow(N + 1, DIM);
+    __shared__ double halo_s[DIM == 2 ? NV * HSZ : 1];
+    __shared__ double nbu_s[DIM == 2 ? 9 * NV * NNS : 1];
+    double *halo = (DIM == 2) ? halo_s : B.halo + (int64_t)sidx * NV * HSZ;
+    double *nbu = (DIM == 2) ? nbu_s : nullptr;
     for (int w = blockIdx.x; w < count; w += gridDim.x) {
-        sub_halo_cell<DIM, N>(T, P, B, cur, w, sidx);
+        sub_halo_cell<DIM, N>(T, P, B, cur, w, halo, nbu);
         __syncthreads();
-        sub_recon_cell<DIM, N>(T, B, sidx);
+        sub_recon_cell<DIM, N>(T, B, sidx, halo);
         __syncthreads();
         sub_predictor<DIM, R>(T, Ys, trs, NPOS, dt, dth, P.gamma);
         __syncthreads();
-        sub_update_cell<DIM, N, R>(T, P, B, cur, w, sidx, nonphys);
+        sub_update_cell<DIM, N, R>(T, P, B, cur, w, sidx, nonphys, halo);
     }
 }
 

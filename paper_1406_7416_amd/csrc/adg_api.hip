@@ -624,6 +624,8 @@ int adg_set_state(adg_problem *pb, const double *u, int on_device, const double 
     HIPCHK(hipMemsetAsync(pb->B.scal, 0, 64, pb->stream));
     HIPCHK(hipMemsetAsync(pb->B.counts, 0, 32, pb->stream));
     HIPCHK(hipStreamSynchronize(pb->stream));
+    // the host copy of the counters starts over too (a pool overflow is reported until here)
+    std::memset(pb->pinned, 0, 16);
     pb->has_state = true;
     pb->bounds_valid = false;
     pb->last_troubled = count;

@@ -241,3 +241,30 @@ def test_config_explosion_3d_16cubed():
     o, g = paired(W.explosion_3d(16, 3), m=1)
     run_parity(o, g, 2)
     assert o.troubled().sum() > 0
+
+
+def test_pool_overflow_is_reported_and_cleared():
+    """More troubled cells than the subcell pool holds: the initial detection refuses at
+    once; a step that overflows is reported by the following call (the counts stay on the
+    device), and a new state clears the error."""
+    from paper_1406_7416_amd import adg
+    wl = W.explosion_2d(20, 3)
+    o = O.Oracle(wl)
+    u, v = o.project(wl.ic, wl.N + 1)
+    g = gpu_problem(wl, pool_capacity=2)
+    with pytest.raises(adg.AdgError, match="-4"):
+        g.set_state(u, v)
+    g.set_state(u)                  # no initial detection: the first step flags the ring
+    o.set_state(u)
+    dt = o.cfl_dt()
+    g.step(dt)
+    assert g.stats()["troubled"] > 2
+    with pytest.raises(adg.AdgError, match="-4"):
+        g.step(dt)
+    with pytest.raises(adg.AdgError, match="-4"):
+        g.step(dt)                  # sticky
+    # a constant state flags nothing: the error is gone after the new state
+    g.set_state(np.ones_like(u) * np.array([1.0, 0.0, 0.0, 2.5])[:, None, None])
+    g.step(dt)
+    g.step(dt)
+    assert g.stats()["troubled"] == 0

@@ -702,7 +702,7 @@ static int do_step(adg_problem *pb) {
         }
         {
             GroupTimer g(pb, 6);
-            launch_fluxcorr(C, -1);
+            launch_fluxcorr(C, -1, 1);
         }
         troubled = corrected = -1;
         HIPCHK(hipGetLastError());
@@ -714,7 +714,7 @@ static int do_step(adg_problem *pb) {
         // every interior cell's next old-time bounds were written by this step's kernels
         pb->bounds_valid = true;
     }
-    launch_advance_time(C);
+    if (!pb->prm.limiter) launch_advance_time(C);   // else done by the flux correction
     HIPCHK(hipGetLastError());
     if (pb->prm.limiter && troubled < 0 && !pb->capturing) {
         // asynchronous copy of the counters (read by adg_get_stats and the next step)

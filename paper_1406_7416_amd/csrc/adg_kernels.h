@@ -32,7 +32,8 @@ void launch_faces(const StepCtx &C);
 void launch_corrector_detect(const StepCtx &C);
 void launch_compact(const StepCtx &C);
 void launch_subcell(const StepCtx &C);
-void launch_fluxcorr(const StepCtx &C, int count);
+// advance != 0: the launch also advances t by dt (the step's last kernel)
+void launch_fluxcorr(const StepCtx &C, int count, int advance);
 void launch_lambda(const StepCtx &C, const double *u, double factor);
 void launch_set_scalar(const StepCtx &C, int idx, double val);
 void launch_advance_time(const StepCtx &C);

@@ -1748,7 +1748,8 @@ __global__ __launch_bounds__(SUB_BS, 2) void k_subcell(const Tables *__restrict_
 // flux of each face shared with a troubled cell is replaced by the subcell fluxes of
 // that face, each integrated against the basis (P[sigma][a] / (Ns w_a) per tangential axis).
 template <int DIM, int N, typename R>
-__global__ __launch_bounds__(128) void k_fluxcorr(const Tables *__restrict__ T, Prob P, Bufs B, int cur, int count) {
+__global__ __launch_bounds__(128) void k_fluxcorr(const Tables *__restrict__ T, Prob P, Bufs B, int cur, int count,
+                                                  int advance) {
     const R *gbar = reinterpret_cast<const R *>(B.gbar);
     constexpr int NS_ = 2 * N + 1, NSUB_ = cpow(NS_, DIM), NN_ = cpow(N + 1, DIM), NV_ = DIM + 2;
     constexpr int TMP_ = (DIM == 2) ? NS_ * (N + 1) : NS_ * NS_ * (N + 1);
@@ -1758,6 +1759,12 @@ __global__ __launch_bounds__(128) void k_fluxcorr(const Tables *__restrict__ T, 
     __shared__ double red[2 * NV_ * 2];
     constexpr int n = N + 1, NV = DIM + 2, NN = cpow(n, DIM), NFN = cpow(n, DIM - 1);
     constexpr int NS = 2 * N + 1, NSF = cpow(NS, DIM - 1);
+    // the step's last kernel also advances t (no other workgroup reads t here) and ends a
+    // one-step debug poison of the candidate
+    if (advance && blockIdx.x == 0 && threadIdx.x == 0) {
+        B.scal[1] += B.scal[0];
+        B.scal[4] = 0.0;
+    }
     if (count < 0) count = B.counts[1];   // device-driven
     for (int wb = blockIdx.x; wb < count; wb += gridDim.x) {
     const int64_t c = B.clist[wb];
@@ -1970,14 +1977,14 @@ struct Launch {
             hipLaunchKernelGGL((k_subcell<DIM, N, double>), dim3((unsigned)C.subcell_grid), dim3(SUB_BS), 0, C.stream,
                                C.tab, C.P, C.B, C.cur, C.capacity, C.B.counts + 2);
     }
-    static void fluxcorr(const StepCtx &C, int count) {
-        const unsigned g = (unsigned)std::min<int64_t>(count >= 0 ? count : C.P.ncell, 512);
+    static void fluxcorr(const StepCtx &C, int count, int advance) {
+        const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(count >= 0 ? count : C.P.ncell, 512));
         if (C.precision == ADG_MIXED)
             hipLaunchKernelGGL((k_fluxcorr<DIM, N, float>), dim3(g), dim3(128), 0, C.stream, C.tab, C.P, C.B, C.cur,
-                               count);
+                               count, advance);
         else
             hipLaunchKernelGGL((k_fluxcorr<DIM, N, double>), dim3(g), dim3(128), 0, C.stream, C.tab, C.P, C.B, C.cur,
-                               count);
+                               count, advance);
     }
     static void lambda(const StepCtx &C, const double *u, double factor) {
         const int64_t total = C.P.ncell * NN;
@@ -1994,7 +2001,7 @@ struct Ops {
     void (*corrector_detect)(const StepCtx &);
     void (*bounds)(const StepCtx &);
     void (*subcell)(const StepCtx &);
-    void (*fluxcorr)(const StepCtx &, int);
+    void (*fluxcorr)(const StepCtx &, int, int);
     void (*lambda)(const StepCtx &, const double *, double);
     int npos;
 };
@@ -2027,7 +2034,9 @@ void launch_compact(const StepCtx &C) {
     hipLaunchKernelGGL(k_compact_scatter, dim3(nblk), dim3(CBS), 0, C.stream, C.P, C.B, C.capacity);
 }
 void launch_subcell(const StepCtx &C) { ops_for(C.P.dim, C.P.N)->subcell(C); }
-void launch_fluxcorr(const StepCtx &C, int count) { ops_for(C.P.dim, C.P.N)->fluxcorr(C, count); }
+void launch_fluxcorr(const StepCtx &C, int count, int advance) {
+    ops_for(C.P.dim, C.P.N)->fluxcorr(C, count, advance);
+}
 void launch_lambda(const StepCtx &C, const double *u, double factor) {
     ops_for(C.P.dim, C.P.N)->lambda(C, u, factor);
 }

@@ -30,12 +30,24 @@ __device__ __forceinline__ R pressure(const R *q, R g) {
     return (g - R(1)) * (q[DIM + 1] - R(0.5) * ke / q[0]);
 }
 
+// a[1 + k] for a runtime axis k, by selection: a dynamic index would place the
+// register array in scratch memory
+template <int DIM, typename R>
+__device__ __forceinline__ R along(const R *a, int k) {
+    R r = a[1];
+#pragma unroll
+    for (int j = 1; j < DIM; j++)
+        if (k == j) r = a[1 + j];
+    return r;
+}
+
 // Euler flux along axis k (Sec. 5).
 template <int DIM, typename R = double>
 __device__ __forceinline__ void euler_flux(int k, const R *q, R *F, R g) {
     const R p = pressure<DIM, R>(q, g);
-    const R un = q[1 + k] / q[0];
-    F[0] = q[1 + k];
+    const R qk = along<DIM, R>(q, k);
+    const R un = qk / q[0];
+    F[0] = qk;
 #pragma unroll
     for (int j = 0; j < DIM; j++) F[1 + j] = q[1 + j] * un + (j == k ? p : R(0));
     F[DIM + 1] = un * (q[DIM + 1] + p);
@@ -48,8 +60,8 @@ __device__ __forceinline__ void rusanov(int k, const R *qL, const R *qR, R *G, R
     R FL[NV], FR[NV];
     euler_flux<DIM, R>(k, qL, FL, g);
     euler_flux<DIM, R>(k, qR, FR, g);
-    const R sL = fabs(qL[1 + k] / qL[0]) + sqrt(g * pressure<DIM, R>(qL, g) / qL[0]);
-    const R sR = fabs(qR[1 + k] / qR[0]) + sqrt(g * pressure<DIM, R>(qR, g) / qR[0]);
+    const R sL = fabs(along<DIM, R>(qL, k) / qL[0]) + sqrt(g * pressure<DIM, R>(qL, g) / qL[0]);
+    const R sR = fabs(along<DIM, R>(qR, k) / qR[0]) + sqrt(g * pressure<DIM, R>(qR, g) / qR[0]);
     const R s = fmax(sL, sR);
 #pragma unroll
     for (int v = 0; v < NV; v++) G[v] = R(0.5) * (FL[v] + FR[v]) - R(0.5) * s * (qR[v] - qL[v]);
@@ -70,16 +82,22 @@ __device__ __forceinline__ void bc_ghost(const Prob &P, int k, int side, const d
     constexpr int NV = DIM + 2;
     const BCDev &b = P.bc[k][side];
     int which = 0;
-    if (b.split_axis >= 0) which = (x[b.split_axis] < b.split0 + b.split_speed * t) ? 0 : 1;
+    if (b.split_axis >= 0) {
+        double xs = x[0];
+#pragma unroll
+        for (int j = 1; j < DIM; j++)
+            if (b.split_axis == j) xs = x[j];
+        which = (xs < b.split0 + b.split_speed * t) ? 0 : 1;
+    }
     const int kind = b.kind[which];
     if (kind == ADG_DIRICHLET) {
 #pragma unroll
         for (int v = 0; v < NV; v++) qout[v] = b.state[which][v];
         return;
     }
+    const bool refl = kind == ADG_REFLECTIVE;
 #pragma unroll
-    for (int v = 0; v < NV; v++) qout[v] = qin[v];
-    if (kind == ADG_REFLECTIVE) qout[1 + k] = -qout[1 + k];
+    for (int v = 0; v < NV; v++) qout[v] = (refl && v == 1 + k) ? -qin[v] : qin[v];
 }
 
 __device__ __forceinline__ int64_t cell_of(const Prob &P, const int *ci) {
@@ -517,20 +535,23 @@ __global__ __launch_bounds__((FaceShape<DIM, N>::BS)) void k_face(const Tables *
     if (active) {
         const int fk = (int)(fidx % nfk);
         int64_t line = fidx / nfk;
-        int ci[3] = {0, 0, 0};
+        // cell coordinates, selected per axis with compile-time indices (a runtime index
+        // would move the arrays to scratch memory)
+        hasL = fk > 0 || P.periodic[k];
+        hasR = fk < nk;
+        const int fl = fk > 0 ? fk - 1 : fk - 1 + nk;
+        int cl[3] = {0, 0, 0}, cr[3] = {0, 0, 0}, ci[3] = {0, 0, 0};
+#pragma unroll
         for (int jj = 0; jj < DIM; jj++) {
-            if (jj == k) continue;
-            ci[jj] = (int)(line % P.nc[jj]);
-            line /= P.nc[jj];
+            if (jj == k) {
+                cl[jj] = fl;
+                cr[jj] = fk;
+            } else {
+                ci[jj] = (int)(line % P.nc[jj]);
+                line /= P.nc[jj];
+                cl[jj] = cr[jj] = ci[jj];
+            }
         }
-        int cl[3] = {ci[0], ci[1], ci[2]}, cr[3] = {ci[0], ci[1], ci[2]};
-        cl[k] = fk - 1;
-        cr[k] = fk;
-        hasL = hasR = true;
-        if (cl[k] < 0) {
-            if (P.periodic[k]) cl[k] += nk; else hasL = false;
-        }
-        if (cr[k] >= nk) hasR = false;
         cL = hasL ? cell_of(P, cl) : -1;
         cR = hasR ? cell_of(P, cr) : -1;
         const double dt = scal[0], t0 = scal[1];
@@ -538,13 +559,14 @@ __global__ __launch_bounds__((FaceShape<DIM, N>::BS)) void k_face(const Tables *
         double x[3] = {0, 0, 0};
         {
             int rem = ap;
+#pragma unroll
             for (int jj = 0; jj < DIM; jj++) {
                 if (jj == k) {
                     x[jj] = P.lo[jj] + P.h[jj] * fk;
-                    continue;
+                } else {
+                    x[jj] = P.lo[jj] + P.h[jj] * (ci[jj] + T->xi[rem % n]);
+                    rem /= n;
                 }
-                x[jj] = P.lo[jj] + P.h[jj] * (ci[jj] + T->xi[rem % n]);
-                rem /= n;
             }
         }
         R qL[NV], qR[NV], G[NV];

@@ -51,6 +51,7 @@ struct or_solver {
     double t;
     long nonphys;
     long poison_cell;          /* test hook: cell whose next candidate is overwritten (-1: none) */
+    long mood_flagged, mood_redone;   /* MOOD layer of the last step: flagged subcells, recomputed cells */
     int poison_var;
     double poison_value;
 };
@@ -759,6 +760,11 @@ void or_get_bounds(const or_solver *S, double *bmin, double *bmax) {
 }
 /* Test hook: at the next step, every node of variable `var` of cell `cell`'s candidate is
  * set to `value` before the detection of Sec. 4.3 sees it (one step only). */
+void or_mood_stats(const or_solver *S, long *flagged, long *redone) {
+    *flagged = S->mood_flagged;
+    *redone = S->mood_redone;
+}
+
 int or_poison(or_solver *S, long cell, int var, double value) {
     if (cell < 0 || cell >= S->ncell || var < 0 || var >= S->nv) return -1;
     S->poison_cell = cell;
@@ -835,8 +841,23 @@ static int floordiv(int a, int b) { return (a >= 0) ? a / b : -((-a + b - 1) / b
  * steps 2-4 as stated; sub-faces on the domain boundary take the boundary ghost state of
  * the DG scheme.  Outputs vnew [v][nsub] and the averaged fluxes on the cell's own faces
  * sf[(2k+side)][v][nsubf]. */
+/* 1 if subcell (global cell gci, local subcell ms) carries a MOOD flag; cells outside a
+ * non-periodic boundary and untroubled cells carry none. */
+static int mood_flag(const or_solver *S, const uint8_t *flag, const uint8_t *troubled, const int *gci, const int *ms) {
+    int ci[3] = {gci[0], gci[1], gci[2]};
+    for (int k = 0; k < S->d; k++) {
+        if (ci[k] < 0 || ci[k] >= S->nc[k]) {
+            if (S->c.bc[k][0].kind[0] != OR_PERIODIC) return 0;
+            ci[k] = (ci[k] + S->nc[k]) % S->nc[k];
+        }
+    }
+    long cn = cell_index(S, ci);
+    if (!troubled[cn]) return 0;
+    return flag[cn * S->nsub + flat(ms, S->Ns, S->d)];
+}
+
 static void subcell_update(const or_solver *S, const double *vn, long c, double dt, sc_work *W, double *vnew,
-                           double *sf) {
+                           double *sf, const uint8_t *flag, const uint8_t *troubled) {
     int d = S->d, Ns = S->Ns, nv = S->nv;
     double g = S->c.gamma, t = S->t;
     int ci[3];
@@ -955,9 +976,20 @@ static void subcell_update(const or_solver *S, const double *vn, long c, double 
                 /* reading (positivity safeguard; the paper leaves the subcell scheme to its
                  * references and notes that WENO3 may fail positivity): if any predictor
                  * trace on either side of the sub-face is not a physical state, the
-                 * sub-face takes the first-order flux of the two subcell averages. */
+                 * sub-face takes the first-order flux of the two subcell averages.
+                 * MOOD layer (Sec. 6, Fig. algo2): a sub-face next to a subcell whose WENO3
+                 * candidate failed the detection takes that first-order flux too. */
+                int low = 0;
+                if (flag) {
+                    int gL[3] = {ci[0], ci[1], ci[2]}, gR[3] = {ci[0], ci[1], ci[2]};
+                    int mL[3] = {0, 0, 0}, mR[3] = {0, 0, 0};
+                    for (int j = 0; j < d; j++) { mL[j] = pL[j] - 1; mR[j] = pR[j] - 1; }
+                    if (mL[k] < 0) { gL[k] -= 1; mL[k] += Ns; }
+                    if (mR[k] >= Ns) { gR[k] += 1; mR[k] -= Ns; }
+                    low = mood_flag(S, flag, troubled, gL, mL) || mood_flag(S, flag, troubled, gR, mR);
+                }
                 double Fbar[5] = {0, 0, 0, 0, 0};
-                for (int pass = 0; pass < 2; pass++) {
+                for (int pass = low; pass < 2; pass++) {
                     int ok = 1;
                     for (int v = 0; v < nv; v++) Fbar[v] = 0.0;
                     for (int s = 0; s < 3 && ok; s++)
@@ -1196,20 +1228,98 @@ int or_step(or_solver *S, double dt) {
         sc_work W;
         sc_alloc(S, &W);
         double *vc = malloc(sizeof(double) * nv * S->nsub);
-#pragma omp for schedule(dynamic, 1) reduction(+ : nonphys)
+#pragma omp for schedule(dynamic, 1)
         for (long c = 0; c < ncell; c++) {
             if (!bnew[c]) continue;
-            subcell_update(S, vn, c, dt, &W, vc, sf + c * 2 * d * nv * nsf);
+            subcell_update(S, vn, c, dt, &W, vc, sf + c * 2 * d * nv * nsf, NULL, NULL);
             for (int v = 0; v < nv; v++)
                 memcpy(vnew + ((long)v * ncell + c) * S->nsub, vc + v * S->nsub, sizeof(double) * S->nsub);
-            for (int sg = 0; sg < S->nsub; sg++) {
-                double q[5];
-                for (int v = 0; v < nv; v++) q[v] = vc[v * S->nsub + sg];
-                if (!(q[0] > 0) || !(pressure(d, g, q) > 0)) { nonphys++; break; }
-            }
         }
         free(vc);
         sc_free(&W);
+    }
+
+    /* MOOD layer after the subcell scheme (Sec. 6, Fig. algo2).  reading: the WENO3
+     * candidate of a troubled cell is tested subcell by subcell with the criteria of Sec.
+     * 4.3 (PAD, and the relaxed DMP against that cell's bounds of eq. (dmp)); every
+     * troubled cell with a flagged subcell on or next to its sub-faces is recomputed with
+     * the first-order flux of the subcell averages on each sub-face adjacent to a flagged
+     * subcell (adjacent troubled cells then agree on their shared sub-faces: conservative). */
+    if (S->c.mood) {
+        const int nsub = S->nsub;
+        uint8_t *flag = calloc((size_t)ncell * nsub, 1);
+        uint8_t *redo = calloc((size_t)ncell, 1);
+#pragma omp parallel for schedule(static)
+        for (long c = 0; c < ncell; c++) {
+            if (!bnew[c]) continue;
+            for (int sg = 0; sg < nsub; sg++) {
+                double q[5];
+                int bad = 0;
+                for (int v = 0; v < nv; v++) {
+                    q[v] = vnew[((long)v * ncell + c) * nsub + sg];
+                    if (!isfinite(q[v])) bad = 1;
+                }
+                if (!bad && (!(q[0] > 0) || !(pressure(d, g, q) > 0))) bad = 1;
+                for (int v = 0; v < nv && !bad; v++) {
+                    double m = S->bmin[v * ncell + c], M = S->bmax[v * ncell + c];
+                    double delta = fmax(S->c.delta0, S->c.eps * (M - m));
+                    if (q[v] < m - delta || q[v] > M + delta) bad = 1;
+                }
+                flag[c * nsub + sg] = (uint8_t)bad;
+            }
+        }
+        /* cells to recompute: a flagged subcell of their own or on a neighbour's face layer */
+#pragma omp parallel for schedule(static)
+        for (long c = 0; c < ncell; c++) {
+            if (!bnew[c]) continue;
+            int any = 0;
+            for (int sg = 0; sg < nsub && !any; sg++) any = flag[c * nsub + sg];
+            int ci[3];
+            cell_coords(S, c, ci);
+            for (int k = 0; k < d && !any; k++)
+                for (int side = 0; side < 2 && !any; side++) {
+                    int gci[3] = {ci[0], ci[1], ci[2]};
+                    gci[k] += side ? 1 : -1;
+                    for (int sp = 0; sp < S->nsubf && !any; sp++) {
+                        int mp[3] = {0, 0, 0}, ms[3] = {0, 0, 0}, j2 = 0;
+                        unflat(sp, Ns, d - 1, mp);
+                        for (int j = 0; j < d; j++) ms[j] = (j == k) ? (side ? 0 : Ns - 1) : mp[j2++];
+                        any = mood_flag(S, flag, bnew, gci, ms);
+                    }
+                }
+            redo[c] = (uint8_t)any;
+        }
+#pragma omp parallel
+        {
+            sc_work W;
+            sc_alloc(S, &W);
+            double *vc = malloc(sizeof(double) * nv * nsub);
+#pragma omp for schedule(dynamic, 1)
+            for (long c = 0; c < ncell; c++) {
+                if (!redo[c]) continue;
+                subcell_update(S, vn, c, dt, &W, vc, sf + c * 2 * d * nv * nsf, flag, bnew);
+                for (int v = 0; v < nv; v++)
+                    memcpy(vnew + ((long)v * ncell + c) * nsub, vc + v * nsub, sizeof(double) * nsub);
+            }
+            free(vc);
+            sc_free(&W);
+        }
+        long nf = 0, nr = 0;
+        for (long i = 0; i < ncell * (long)nsub; i++) nf += flag[i];
+        for (long c = 0; c < ncell; c++) nr += redo[c];
+        S->mood_flagged = nf;
+        S->mood_redone = nr;
+        free(flag);
+        free(redo);
+    }
+    /* subcell results that fail PAD (counted, not corrected) */
+    for (long c = 0; c < ncell; c++) {
+        if (!bnew[c]) continue;
+        for (int sg = 0; sg < S->nsub; sg++) {
+            double q[5];
+            for (int v = 0; v < nv; v++) q[v] = vnew[((long)v * ncell + c) * S->nsub + sg];
+            if (!(q[0] > 0) || !(pressure(d, g, q) > 0)) { nonphys++; break; }
+        }
     }
     S->nonphys += nonphys;
 

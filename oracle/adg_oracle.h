@@ -43,6 +43,7 @@ typedef struct {
     double lo[3], hi[3];
     double gamma, eps, delta0;
     or_bc bc[3][2];
+    int mood;             /* 1: one more MOOD layer after the subcell WENO3 scheme (first order) */
 } or_config;
 
 typedef struct or_solver or_solver;
@@ -66,6 +67,8 @@ void or_get_subcells(const or_solver *s, double *v);
 void or_get_bounds(const or_solver *s, double *bmin, double *bmax);
 void or_force_troubled(or_solver *s, const uint8_t *mask);
 int or_poison(or_solver *s, long cell, int var, double value);
+/* MOOD layer of the last step: subcells whose WENO3 candidate failed, cells recomputed. */
+void or_mood_stats(const or_solver *s, long *flagged, long *redone);
 double or_time(const or_solver *s);
 void or_set_time(or_solver *s, double t);
 double or_cfl_dt(const or_solver *s, double cfl);

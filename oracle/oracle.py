@@ -24,7 +24,7 @@ class _Config(C.Structure):
     _fields_ = [("dim", C.c_int), ("N", C.c_int), ("Ns", C.c_int), ("picard_iters", C.c_int),
                 ("limiter", C.c_int), ("ncell", C.c_int * 3), ("lo", C.c_double * 3),
                 ("hi", C.c_double * 3), ("gamma", C.c_double), ("eps", C.c_double),
-                ("delta0", C.c_double), ("bc", (_BC * 2) * 3)]
+                ("delta0", C.c_double), ("bc", (_BC * 2) * 3), ("mood", C.c_int)]
 
 
 _lib = None
@@ -53,6 +53,7 @@ def lib():
         L.or_get_bounds.argtypes = [C.c_void_p, dp, dp]
         L.or_force_troubled.argtypes = [C.c_void_p, C.POINTER(C.c_uint8)]
         L.or_poison.argtypes = [C.c_void_p, C.c_long, C.c_int, C.c_double]
+        L.or_mood_stats.argtypes = [C.c_void_p, C.POINTER(C.c_long), C.POINTER(C.c_long)]
         L.or_time.restype = C.c_double
         L.or_time.argtypes = [C.c_void_p]
         L.or_set_time.argtypes = [C.c_void_p, C.c_double]
@@ -122,8 +123,9 @@ def get_threads() -> int:
     return lib().or_get_threads()
 
 
-def make_config(wl, limiter: bool = True, picard_iters: int = 0) -> _Config:
+def make_config(wl, limiter: bool = True, picard_iters: int = 0, mood: bool = False) -> _Config:
     c = _Config()
+    c.mood = 1 if mood else 0
     c.dim, c.N = wl.dim, wl.N
     c.Ns = wl.Ns if wl.Ns else 2 * wl.N + 1
     c.picard_iters = picard_iters if picard_iters else wl.N + 1
@@ -148,9 +150,9 @@ def make_config(wl, limiter: bool = True, picard_iters: int = 0) -> _Config:
 class Oracle:
     """One problem advanced by the CPU oracle."""
 
-    def __init__(self, wl, limiter: bool = True, picard_iters: int = 0):
+    def __init__(self, wl, limiter: bool = True, picard_iters: int = 0, mood: bool = False):
         self.wl = wl
-        self.cfg = make_config(wl, limiter, picard_iters)
+        self.cfg = make_config(wl, limiter, picard_iters, mood)
         self.h = lib().or_create(C.byref(self.cfg))
         if not self.h:
             raise ValueError("oracle rejected the configuration")
@@ -204,6 +206,12 @@ class Oracle:
         """Overwrites variable `var` of cell `cell`'s next candidate with `value` (one step)."""
         if lib().or_poison(self.h, cell, var, value) != 0:
             raise ValueError("poison: cell or variable out of range")
+
+    def mood_stats(self):
+        """(flagged subcells, recomputed cells) of the last step's MOOD layer."""
+        f, r = C.c_long(), C.c_long()
+        lib().or_mood_stats(self.h, C.byref(f), C.byref(r))
+        return f.value, r.value
 
     def force_troubled(self, mask: Optional[np.ndarray]):
         if mask is None:

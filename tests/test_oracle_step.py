@@ -344,3 +344,71 @@ def test_poisoned_candidate_equals_forced_troubled_cell(var, value):
     assert np.array_equal(runs["poison"][1], runs["force"][1])
     assert np.array_equal(runs["poison"][0], runs["force"][0])
     assert np.isfinite(runs["poison"][0]).all()
+
+
+def _periodic_quadrant(n=24, N=3):
+    """A four-quadrant Riemann problem made periodic (discontinuities on a periodic domain:
+    mass, momentum and energy are conserved exactly by the scheme)."""
+    wl = W.quadrant_batch(8)[0]
+    wl.ncell = (n, n)
+    wl.N = N
+    wl.bcs = [(W.BC.simple(W.PERIODIC), W.BC.simple(W.PERIODIC))] * 2
+    return wl
+
+
+def test_mood_layer_conserves_and_is_active():
+    """MOOD layer after the subcell WENO3 scheme (Sec. 6, Fig. algo2): with first-order
+    fluxes on the sub-faces next to flagged subcells, adjacent troubled cells still agree
+    on every shared sub-face, so the step stays conservative to round-off; the layer acts
+    (flags, recomputed cells) and every result stays physical."""
+    wl = _periodic_quadrant()
+    o = O.Oracle(wl, mood=True)
+    o.init()
+    m0 = totals(o)
+    flagged = 0
+    for i in range(4):
+        o.step(o.cfl_dt())
+        f, r = o.mood_stats()
+        flagged += f
+        assert r <= o.troubled().sum()
+        assert np.abs(totals(o) - m0).max() < 1e-13 * np.abs(m0).max()
+    assert flagged > 0 and o.nonphysical() == 0
+    u = o.state()
+    assert np.isfinite(u).all()
+
+
+def test_mood_layer_changes_nothing_without_flags():
+    """On data whose WENO3 candidates pass the detection the layer flags nothing and the
+    step is bit for bit the one without it."""
+    wl = W.vortex(8, 9)
+    mask = W.random_mask(wl.num_cells, 0.3, seed=5)
+    out = []
+    for mood in (False, True):
+        o = O.Oracle(wl, mood=mood)
+        o.init(m=0, detect=False)
+        o.force_troubled(mask)
+        o.step(o.cfl_dt())
+        out.append(o.state())
+        if mood:
+            assert o.mood_stats() == (0, 0)
+    assert np.array_equal(out[0], out[1])
+
+
+def test_mood_first_order_fluxes_where_flagged():
+    """Where the layer acts the result differs from the plain subcell scheme and only in
+    troubled cells and their face neighbours (the flux correction)."""
+    wl = _periodic_quadrant()
+    states = []
+    for mood in (False, True):
+        o = O.Oracle(wl, mood=mood)
+        o.init()
+        o.step(o.cfl_dt())
+        states.append((o.state(), o.troubled()))
+    (ua, ba), (ub, bb) = states
+    assert np.array_equal(ba, bb)
+    diff = np.abs(ua - ub).max(axis=(0, 2)) > 0
+    assert diff.any()
+    nx, ny = wl.ncell
+    t = ba.reshape(ny, nx).astype(bool)
+    near = t | np.roll(t, 1, 0) | np.roll(t, -1, 0) | np.roll(t, 1, 1) | np.roll(t, -1, 1)
+    assert not (diff.reshape(ny, nx) & ~near).any()

@@ -80,6 +80,10 @@ typedef struct {
     double eps;           /* eq. (relax) epsilon; 0 -> 1e-3 */
     double delta0;        /* absolute floor of delta; 0 -> 1e-4 (reading: not in the paper) */
     int64_t pool_capacity;/* troubled cells the subcell pool holds; 0 -> all cells */
+    int mood;             /* 1: one more MOOD layer after the subcell WENO3 scheme (Sec. 6, Fig.
+                             algo2): subcells whose WENO3 result fails PAD or the relaxed DMP
+                             against their cell's bounds get the first-order flux of the subcell
+                             averages on all their sub-faces (reading); 0: off (default) */
 } adg_params;
 
 typedef struct adg_problem adg_problem;
@@ -152,6 +156,10 @@ int adg_get_subcells(const adg_problem *pb, double *v);
 /* Statistics of the last step: out[0] troubled cells, out[1] corrected neighbours,
  * out[2] cumulative subcell results failing PAD, out[3] steps taken.  Synchronising. */
 int adg_get_stats(const adg_problem *pb, int64_t *out4);
+
+/* MOOD layer of the last step (adg_params.mood): subcells whose WENO3 result failed the
+ * detection, and troubled cells recomputed.  Synchronising. */
+int adg_get_mood_stats(const adg_problem *pb, int64_t *flagged, int64_t *redone);
 
 /* Per-kernel timing with hipEvents recorded on the bound stream around each kernel
  * group.  Groups: 0 old-time bounds, 1 predictor, 2 face fluxes, 3 corrector + detection,

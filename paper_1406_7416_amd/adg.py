@@ -23,7 +23,7 @@ EXPORTS = [
     "adg_project_samples", "adg_set_state", "adg_get_state", "adg_cfl_dt", "adg_step", "adg_step_cfl",
     "adg_time", "adg_get_troubled", "adg_get_margin", "adg_get_subcells", "adg_get_stats",
     "adg_profile", "adg_profile_read", "adg_batch_create", "adg_batch_step_cfl", "adg_batch_dt",
-    "adg_batch_destroy", "adg_debug_force_troubled", "adg_debug_poison",
+    "adg_batch_destroy", "adg_debug_force_troubled", "adg_debug_poison", "adg_get_mood_stats",
 ]
 
 KERNEL_GROUPS = ["bounds", "predictor", "faces", "corrector_detect", "compact", "subcell", "fluxcorr", "dt"]
@@ -45,7 +45,7 @@ class _Grid(C.Structure):
 
 class _Params(C.Structure):
     _fields_ = [("Ns", C.c_int), ("picard_iters", C.c_int), ("precision", C.c_int), ("limiter", C.c_int),
-                ("eps", C.c_double), ("delta0", C.c_double), ("pool_capacity", C.c_int64)]
+                ("eps", C.c_double), ("delta0", C.c_double), ("pool_capacity", C.c_int64), ("mood", C.c_int)]
 
 
 _lib = None
@@ -80,6 +80,7 @@ def load():
     L.adg_get_stats.argtypes = [vp, C.POINTER(i64)]
     L.adg_debug_force_troubled.argtypes = [vp, C.POINTER(C.c_uint8)]
     L.adg_debug_poison.argtypes = [vp, C.c_int64, C.c_int, C.c_double]
+    L.adg_get_mood_stats.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     L.adg_profile.argtypes = [vp, C.c_int]
     L.adg_profile_read.argtypes = [vp, dp, C.POINTER(i64), C.c_int]
     L.adg_batch_create.argtypes = [C.POINTER(vp), C.c_int, C.POINTER(vp)]
@@ -126,7 +127,7 @@ class Problem:
     """One problem on one GPU: owns a torch workspace, drives the C ABI."""
 
     def __init__(self, wl, precision: int = ADG_FP64, limiter: bool = True, pool_capacity: int = 0,
-                 picard_iters: int = 0, device: str = "cuda:0", stream=None):
+                 picard_iters: int = 0, device: str = "cuda:0", stream=None, mood: bool = False):
         import torch
         L = load()
         self.wl = wl
@@ -142,6 +143,7 @@ class Problem:
         prm.limiter = 1 if limiter else 0
         prm.eps, prm.delta0 = wl.eps, wl.delta0
         prm.pool_capacity = pool_capacity
+        prm.mood = 1 if mood else 0
         self._grid = _grid(wl)
         h = C.c_void_p()
         _check(L.adg_create(C.byref(self._grid), wl.N, wl.gamma, C.byref(prm), C.byref(h)))
@@ -270,6 +272,12 @@ class Problem:
     def poison(self, cell: int, var: int, value: float):
         """Debug hook: variable `var` of cell `cell`'s next candidate is set to `value`."""
         _check(load().adg_debug_poison(self.h, int(cell), int(var), float(value)))
+
+    def mood_stats(self):
+        """(flagged subcells, recomputed cells) of the last step's MOOD layer."""
+        f, r = C.c_int64(), C.c_int64()
+        _check(load().adg_get_mood_stats(self.h, C.byref(f), C.byref(r)))
+        return f.value, r.value
 
     def stats(self) -> dict:
         out = (C.c_int64 * 4)()

@@ -40,7 +40,8 @@ struct adg_problem {
     size_t ws_bytes;
     // offsets into the workspace
     struct Off {
-        size_t tab, u0, u1, emin0, emax0, emin1, emax1, trace, gbar, beta0, beta1, force, margin, tlist, clist, slot0,
+        size_t tab, u0, u1, emin0, emax0, emin1, emax1, trace, gbar, beta0, beta1, force, mflag, margin, tlist, clist,
+            slot0,
             slot1, pool0, pool1, sflux, blk, counts, scal, lampart, ring, halo, Y, strace, end;
     } off;
     int64_t ring_cap = 0;    // ghost-ring cells of the extended grid
@@ -146,6 +147,7 @@ static void plan(adg_problem *pb) {
     f.beta0 = take(nc);
     f.beta1 = take(nc);
     f.force = take(nc);
+    f.mflag = take(pb->prm.mood ? pb->cap * nsub : 1);
     f.margin = take(4ull * nc);
     f.tlist = take(4ull * nc);
     f.clist = take(4ull * nc);
@@ -187,6 +189,7 @@ static void carve(adg_problem *pb) {
     B.beta[0] = (uint8_t *)(w + f.beta0);
     B.beta[1] = (uint8_t *)(w + f.beta1);
     B.force = (uint8_t *)(w + f.force);
+    B.mflag = (uint8_t *)(w + f.mflag);
     B.margin = (float *)(w + f.margin);
     B.tlist = (int *)(w + f.tlist);
     B.clist = (int *)(w + f.clist);
@@ -218,6 +221,7 @@ static StepCtx ctx(const adg_problem *pb) {
     C.capacity = pb->cap;
     C.lam_blocks = pb->lam_blocks;
     C.precision = pb->prm.precision;
+    C.mood = pb->prm.mood;
     C.ring_only = pb->bounds_valid ? 1 : 0;
     C.subcell_grid = pb->chunk;
     C.nring = pb->nring;
@@ -243,6 +247,7 @@ int adg_create(const adg_grid_desc *g, int N, double gamma, const adg_params *p,
     if (prm.eps == 0) prm.eps = 1e-3;
     if (prm.delta0 == 0) prm.delta0 = 1e-4;
     if (prm.precision != ADG_FP64 && prm.precision != ADG_MIXED) return fail(ADG_EINVAL, "unknown precision mode");
+    if (prm.mood != 0 && prm.mood != 1) return fail(ADG_EINVAL, "mood must be 0 or 1");
     adg_problem *pb = new (std::nothrow) adg_problem();
     if (!pb) return fail(ADG_ENOMEM, "host allocation failed");
     Prob &P = pb->P;
@@ -698,7 +703,8 @@ static int do_step(adg_problem *pb) {
         // the device
         {
             GroupTimer g(pb, 5);
-            launch_subcell(C);
+            launch_subcell(C, 0);
+            if (pb->prm.mood) launch_subcell(C, 1);   // the MOOD layer's recompute
         }
         {
             GroupTimer g(pb, 6);
@@ -811,6 +817,17 @@ int adg_get_stats(const adg_problem *pb, int64_t *out4) {
     out4[1] = pb->last_corrected >= 0 ? pb->last_corrected : cnt[1];
     out4[2] = cnt[2];
     out4[3] = pb->steps;
+    return ADG_OK;
+}
+
+int adg_get_mood_stats(const adg_problem *pb, int64_t *flagged, int64_t *redone) {
+    if (!pb || !flagged || !redone) return fail(ADG_EINVAL, "null argument");
+    if (!pb->bound) return fail(ADG_ESTATE, "not bound");
+    int c[8];
+    HIPCHK(hipMemcpyAsync(c, pb->B.counts, sizeof c, hipMemcpyDeviceToHost, pb->stream));
+    HIPCHK(hipStreamSynchronize(pb->stream));
+    *flagged = c[5];
+    *redone = c[6];
     return ADG_OK;
 }
 

@@ -63,6 +63,7 @@ struct Bufs {
     double *gbar;          // [cell][2d][v][nfn]
     uint8_t *beta[2];      // [cell] old / new
     uint8_t *force;        // [cell] forced troubled mask
+    uint8_t *mflag;        // [slot][subcell] MOOD flags of the troubled cells' WENO3 results
     float *margin;         // [cell]
     int *tlist, *clist;    // troubled cells, corrected cells
     int *slot[2];          // cell -> pool slot (old / new), -1 if none
@@ -70,7 +71,8 @@ struct Bufs {
     double *sflux;         // [slot][2d][v][subf]
     int *blk;              // block partial counts for compaction [2][nblk]
     int *counts;           // [0] troubled [1] corrected [2] nonphysical cumulative [3] capacity overflow
-                           // [4] block ticket of the compaction
+                           // [4] block ticket of the compaction [5] MOOD-flagged subcells
+                           // [6] cells recomputed by the MOOD layer
     double *scal;          // [0] dt [1] t [2] lambda_max [4] poison armed [5] cell [6] var [7] value
     double *lam_part;      // per-block lambda partials
     int64_t *ring;         // extended-grid indices of the ghost ring

@@ -18,6 +18,7 @@ struct StepCtx {
     int ring_only;         // bounds pass over the ghost ring only
     int64_t nring;         // ghost-ring cells
     int subcell_grid;      // workgroups (= scratch slots) of the subcell recompute
+    int mood;              // MOOD layer after the subcell scheme
 };
 
 bool supported(int dim, int N);
@@ -31,7 +32,8 @@ void launch_predictor(const StepCtx &C);
 void launch_faces(const StepCtx &C);
 void launch_corrector_detect(const StepCtx &C);
 void launch_compact(const StepCtx &C);
-void launch_subcell(const StepCtx &C);
+// redo = 0: the subcell scheme; 1: the MOOD layer's recompute
+void launch_subcell(const StepCtx &C, int redo);
 // advance != 0: the launch also advances t by dt (the step's last kernel)
 void launch_fluxcorr(const StepCtx &C, int count, int advance);
 void launch_lambda(const StepCtx &C, const double *u, double factor);

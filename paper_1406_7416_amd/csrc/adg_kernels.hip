@@ -1144,6 +1144,8 @@ __global__ __launch_bounds__(CBS) void k_compact_count(Prob P, Bufs B, int64_t c
         B.counts[1] = carry[1];
         if (carry[0] > cap) B.counts[3] = 1;
         B.counts[4] = 0;   // ticket for the next step
+        B.counts[5] = 0;   // MOOD layer: flagged subcells, recomputed cells of this step
+        B.counts[6] = 0;
     }
 }
 
@@ -1415,9 +1417,14 @@ __device__ __forceinline__ void sub_recon_cell(const Tables *__restrict__ T, con
 }
 
 // S4: sub-face Rusanov fluxes, FV update, gather, pool store, boundary fluxes.
-template <int DIM, int N, typename R>
-__device__ __forceinline__ void sub_update_cell(const Tables *__restrict__ T, const Prob &P, const Bufs &B, int cur, int w, int sidx,
-                                int *nonphys, const double *halo) {
+// MOOD layer (Sec. 6, Fig. algo2): with flagging set, every subcell of the WENO3 result
+// that fails PAD or the relaxed DMP against this cell's bounds (mb) is flagged; REDO
+// recomputes with the first-order flux on every sub-face next to a flagged subcell (own
+// flags, or the face neighbour's, whose pool slot is in nslot).
+template <int DIM, int N, typename R, bool REDO>
+__device__ __forceinline__ void sub_update_cell(const Tables *__restrict__ T, const Prob &P, const Bufs &B, int cur,
+                                                int w, int sidx, int *nonphys, const double *halo, int flagging,
+                                                const double (*mb)[DIM + 2], const int (*nslot)[2]) {
     constexpr int n = N + 1, NV = DIM + 2, NN = cpow(n, DIM);
     constexpr int NS = 2 * N + 1, NSUB = cpow(NS, DIM), NSF = cpow(NS, DIM - 1), HN = NS + 6, HSZ = cpow(HN, DIM);
     constexpr int NPOS = NSUB + 2 * DIM * NSF, NF3 = cpow(3, DIM - 1);
@@ -1465,6 +1472,28 @@ __device__ __forceinline__ void sub_update_cell(const Tables *__restrict__ T, co
             return NSUB + (2 * k + (Lk >= NS ? 1 : 0)) * NSF + sp;
         };
         const int pL = pos_of(f - 1), pR = pos_of(f);
+        int low = 0;
+        if constexpr (REDO) {
+            // flags of the subcells on both sides: own subcells, or the neighbour's layer
+            const int own = B.slot[1][B.tlist[w]];
+            auto flag_at = [&](int Lk) -> int {
+                int Lv[3] = {0, 0, 0}, j2 = 0, sl = own, side = -1;
+#pragma unroll
+                for (int j = 0; j < DIM; j++) {
+                    if (j == k) Lv[j] = Lk;
+                    else Lv[j] = mp[j2++];
+                }
+                if (Lk < 0) { side = 0; Lk += NS; }
+                if (Lk >= NS) { side = 1; Lk -= NS; }
+                if (side >= 0) sl = nslot[k][side];
+                if (sl < 0) return 0;
+                int idx = 0;
+#pragma unroll
+                for (int j = DIM - 1; j >= 0; j--) idx = idx * NS + (j == k ? Lk : Lv[j]);
+                return B.mflag[(int64_t)sl * NSUB + idx];
+            };
+            low = flag_at(f - 1) | flag_at(f);
+        }
         const int bside = (f == 0 && !nbex[k][0]) ? 0 : ((f == NS && !nbex[k][1]) ? 1 : -1);
         // subcell averages of both sides (halo coordinates: local subcell + 3)
         double avL[NV], avR[NV];
@@ -1489,7 +1518,7 @@ __device__ __forceinline__ void sub_update_cell(const Tables *__restrict__ T, co
         // Positivity safeguard: if any predictor trace on either side is not a physical
         // state, the sub-face takes the first-order flux of the two subcell averages.
         R Fbar[NV];
-        for (int pass = 0; pass < 2; pass++) {
+        for (int pass = low; pass < 2; pass++) {
             bool ok = true;
 #pragma unroll
             for (int v = 0; v < NV; v++) Fbar[v] = 0;
@@ -1572,7 +1601,20 @@ __device__ __forceinline__ void sub_update_cell(const Tables *__restrict__ T, co
             vn[v * NSUB + sg] = q[v];
             B.pool[1][((int64_t)slot * NV + v) * NSUB + sg] = q[v];
         }
-        if (!(q[0] > 0.0) || !(pressure<DIM>(q, P.gamma) > 0.0)) badc = 1;
+        const bool pad = isfinite(q[0]) && isfinite(q[NV - 1]) && q[0] > 0.0 && pressure<DIM>(q, P.gamma) > 0.0;
+        if (!pad) badc = 1;
+        if (flagging) {
+            // the criteria of Sec. 4.3 on the WENO3 result: PAD and the relaxed DMP
+            bool bad = !pad;
+#pragma unroll
+            for (int v = 0; v < NV; v++) {
+                if (!isfinite(q[v])) bad = true;
+                const double delta = fmax(P.delta0, P.eps * (mb[1][v] - mb[0][v]));
+                if (q[v] < mb[0][v] - delta || q[v] > mb[1][v] + delta) bad = true;
+            }
+            B.mflag[(int64_t)slot * NSUB + sg] = (uint8_t)bad;
+            if (bad) atomicAdd(&B.counts[5], 1);
+        }
     }
     // boundary fluxes of the cell's faces for the flux correction
     for (int it = threadIdx.x; it < 2 * DIM * NV * NSF; it += SUB_BS) {
@@ -1735,12 +1777,14 @@ __device__ void sub_predictor(const Tables *__restrict__ T, const double *__rest
 // space-time predictor, sub-face fluxes, FV update and gather, using its own scratch
 // slot (blockIdx.x), so the scratch scales with the grid, not with the worklist.
 // R: working precision of the degree-2 predictor and the sub-face fluxes (FP32 in the mixed
-// form); halo, WENO3, FV update, gather and pool stay FP64.
-template <int DIM, int N, typename R>
+// form); halo, WENO3, FV update, gather and pool stay FP64.  flagging: also flag the WENO3
+// result for the MOOD layer; REDO: the MOOD layer's recompute (only cells with a flag on or
+// next to their sub-faces).
+template <int DIM, int N, typename R, bool REDO>
 __global__ __launch_bounds__(SUB_BS, 2) void k_subcell(const Tables *__restrict__ T, Prob P, Bufs B, int cur, int64_t cap,
-                                                 int *nonphys) {
-    constexpr int NV = DIM + 2, NS = 2 * N + 1;
-    constexpr int NPOS = cpow(NS, DIM) + 2 * DIM * cpow(NS, DIM - 1), N3 = cpow(3, DIM);
+                                                 int *nonphys, int flagging) {
+    constexpr int NV = DIM + 2, NS = 2 * N + 1, NSUB = cpow(NS, DIM), NSF = cpow(NS, DIM - 1);
+    constexpr int NPOS = NSUB + 2 * DIM * NSF, N3 = cpow(3, DIM);
     constexpr int TRS = 2 * DIM * NV * cpow(3, DIM - 1) * 3;
     const int count = (int)(B.counts[0] < cap ? B.counts[0] : cap);
     const int sidx = blockIdx.x;
@@ -1753,16 +1797,83 @@ __global__ __launch_bounds__(SUB_BS, 2) void k_subcell(const Tables *__restrict_
     constexpr int HSZ = cpow(NS + 6, DIM), NNS = cpow(N + 1, DIM);
     __shared__ double halo_s[DIM == 2 ? NV * HSZ : 1];
     __shared__ double nbu_s[DIM == 2 ? 9 * NV * NNS : 1];
+    __shared__ double mb[2][NV];      // m_i, M_i of eq. (dmp) (MOOD flags)
+    __shared__ int nslot[3][2];       // pool slots of troubled face neighbours (MOOD recompute)
     double *halo = (DIM == 2) ? halo_s : B.halo + (int64_t)sidx * NV * HSZ;
     double *nbu = (DIM == 2) ? nbu_s : nullptr;
     for (int w = blockIdx.x; w < count; w += gridDim.x) {
+        const int64_t c = B.tlist[w];
+        if (!REDO && flagging) {
+            // neighbourhood bounds of the cell, as in the detection
+            if (threadIdx.x < 2 * NV) {
+                const int mm = threadIdx.x / NV, v = threadIdx.x % NV;
+                int ci[3];
+                coords_of(P, c, ci);
+                int ne[3] = {1, 1, 1};
+                for (int j = 0; j < DIM; j++) ne[j] = P.nc[j] + 2;
+                const int64_t next = ext_count(P);
+                const double *src = (mm ? B.ext_max[0] : B.ext_min[0]) + (int64_t)v * next;
+                double acc = mm ? -INFINITY : INFINITY;
+                constexpr int NB = cpow(3, DIM);
+                for (int o = 0; o < NB; o++) {
+                    const int off[3] = {o % 3, (o / 3) % 3, o / 9};
+                    int64_t e = 0;
+                    for (int j = DIM - 1; j >= 0; j--) {
+                        int x = ci[j] + off[j];
+                        if (P.periodic[j]) x += (x == 0) ? P.nc[j] : ((x == P.nc[j] + 1) ? -P.nc[j] : 0);
+                        e = e * ne[j] + x;
+                    }
+                    acc = mm ? fmax(acc, src[e]) : fmin(acc, src[e]);
+                }
+                mb[mm][v] = acc;
+            }
+        }
+        if constexpr (REDO) {
+            // neighbour slots, then: does a flagged subcell touch one of this cell's sub-faces?
+            if (threadIdx.x < 2 * DIM) {
+                const int k = threadIdx.x >> 1, side = threadIdx.x & 1;
+                int ci[3];
+                coords_of(P, c, ci);
+                int nb[3] = {ci[0], ci[1], ci[2]};
+                nb[k] += side ? 1 : -1;
+                int sl = -1;
+                if (nb[k] >= 0 && nb[k] < P.nc[k]) sl = 0;
+                else if (P.periodic[k]) { nb[k] = (nb[k] + P.nc[k]) % P.nc[k]; sl = 0; }
+                if (sl == 0) {
+                    const int64_t cn = cell_of(P, nb);
+                    sl = B.beta[1][cn] ? B.slot[1][cn] : -1;
+                }
+                nslot[k][side] = sl;
+            }
+            __syncthreads();
+            const int own = B.slot[1][c];
+            int any = 0;
+            for (int i = threadIdx.x; i < NSUB + 2 * DIM * NSF; i += SUB_BS) {
+                if (i < NSUB) {
+                    any |= B.mflag[(int64_t)own * NSUB + i];
+                } else {
+                    const int r = i - NSUB, face = r / NSF, sp = r % NSF;
+                    const int k = face >> 1, side = face & 1;
+                    const int sl = nslot[k][side];
+                    if (sl >= 0) {
+                        // the neighbour's subcell layer facing this cell
+                        int mp[2] = {sp % NS, sp / NS}, idx = 0, j2 = 0, L[3];
+                        for (int j = 0; j < DIM; j++) L[j] = (j == k) ? (side ? 0 : NS - 1) : mp[j2++];
+                        for (int j = DIM - 1; j >= 0; j--) idx = idx * NS + L[j];
+                        any |= B.mflag[(int64_t)sl * NSUB + idx];
+                    }
+                }
+            }
+            if (!__syncthreads_or(any)) continue;
+            if (threadIdx.x == 0) atomicAdd(&B.counts[6], 1);
+        }
         sub_halo_cell<DIM, N>(T, P, B, cur, w, halo, nbu);
         __syncthreads();
         sub_recon_cell<DIM, N>(T, B, sidx, halo);
         __syncthreads();
         sub_predictor<DIM, R>(T, Ys, trs, NPOS, dt, dth, P.gamma);
         __syncthreads();
-        sub_update_cell<DIM, N, R>(T, P, B, cur, w, sidx, nonphys, halo);
+        sub_update_cell<DIM, N, R, REDO>(T, P, B, cur, w, sidx, nonphys, halo, REDO ? 0 : flagging, mb, nslot);
     }
 }
 
@@ -1991,13 +2102,21 @@ struct Launch {
             hipLaunchKernelGGL((k_cell_bounds<DIM, N>), dim3((unsigned)nblk), dim3(128), 0, C.stream, C.tab, C.P, C.B,
                                C.cur, C.ring_only ? C.B.ring : (const int64_t *)nullptr);
     }
-    static void subcell(const StepCtx &C) {
-        if (C.precision == ADG_MIXED)
-            hipLaunchKernelGGL((k_subcell<DIM, N, float>), dim3((unsigned)C.subcell_grid), dim3(SUB_BS), 0, C.stream,
-                               C.tab, C.P, C.B, C.cur, C.capacity, C.B.counts + 2);
+    template <typename R>
+    static void subcell_t(const StepCtx &C, int redo) {
+        const dim3 g((unsigned)C.subcell_grid), b(SUB_BS);
+        if (redo)
+            hipLaunchKernelGGL((k_subcell<DIM, N, R, true>), g, b, 0, C.stream, C.tab, C.P, C.B, C.cur, C.capacity,
+                               C.B.counts + 2, 0);
         else
-            hipLaunchKernelGGL((k_subcell<DIM, N, double>), dim3((unsigned)C.subcell_grid), dim3(SUB_BS), 0, C.stream,
-                               C.tab, C.P, C.B, C.cur, C.capacity, C.B.counts + 2);
+            hipLaunchKernelGGL((k_subcell<DIM, N, R, false>), g, b, 0, C.stream, C.tab, C.P, C.B, C.cur, C.capacity,
+                               C.B.counts + 2, C.mood);
+    }
+    // redo = 0: the subcell scheme (flagging its result when the MOOD layer is on); 1: the
+    // MOOD layer's recompute
+    static void subcell(const StepCtx &C, int redo) {
+        if (C.precision == ADG_MIXED) subcell_t<float>(C, redo);
+        else subcell_t<double>(C, redo);
     }
     static void fluxcorr(const StepCtx &C, int count, int advance) {
         const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(count >= 0 ? count : C.P.ncell, 512));
@@ -2022,7 +2141,7 @@ struct Ops {
     void (*faces)(const StepCtx &);
     void (*corrector_detect)(const StepCtx &);
     void (*bounds)(const StepCtx &);
-    void (*subcell)(const StepCtx &);
+    void (*subcell)(const StepCtx &, int);
     void (*fluxcorr)(const StepCtx &, int, int);
     void (*lambda)(const StepCtx &, const double *, double);
     int npos;
@@ -2055,7 +2174,7 @@ void launch_compact(const StepCtx &C) {
     hipLaunchKernelGGL(k_compact_count, dim3(nblk), dim3(CBS), 0, C.stream, C.P, C.B, C.capacity);
     hipLaunchKernelGGL(k_compact_scatter, dim3(nblk), dim3(CBS), 0, C.stream, C.P, C.B, C.capacity);
 }
-void launch_subcell(const StepCtx &C) { ops_for(C.P.dim, C.P.N)->subcell(C); }
+void launch_subcell(const StepCtx &C, int redo) { ops_for(C.P.dim, C.P.N)->subcell(C, redo); }
 void launch_fluxcorr(const StepCtx &C, int count, int advance) {
     ops_for(C.P.dim, C.P.N)->fluxcorr(C, count, advance);
 }

@@ -268,6 +268,18 @@ SHOCK_TUBES = {  # Table 1: left (rho, u, p), right (rho, u, p), t_final
 }
 
 
+
+def periodic_quadrant(n: int = 24, N: int = 3, index: int = 0) -> Workload:
+    """A four-quadrant Riemann problem of quadrant_batch on an n x n periodic grid:
+    discontinuities on a periodic domain, where mass, momentum and energy are conserved
+    exactly by the scheme."""
+    wl = quadrant_batch(max(8, index + 1))[index]
+    wl.ncell = (n, n)
+    wl.N = N
+    wl.cfl = STABLE_CFL[N - 1]
+    wl.bcs = [(BC.simple(PERIODIC), BC.simple(PERIODIC))] * 2
+    return wl
+
 def shock_tube(name: str = "sod", nx: int = 20, ny: int = 5, N: int = 9, gamma: float = 1.4) -> Workload:
     """Sec. 5 shock tubes on [0,1]x[-0.5,0.5], discontinuity at x = 0.5, Dirichlet in x
     (the constant left/right states), periodic in y."""

@@ -346,22 +346,12 @@ def test_poisoned_candidate_equals_forced_troubled_cell(var, value):
     assert np.isfinite(runs["poison"][0]).all()
 
 
-def _periodic_quadrant(n=24, N=3):
-    """A four-quadrant Riemann problem made periodic (discontinuities on a periodic domain:
-    mass, momentum and energy are conserved exactly by the scheme)."""
-    wl = W.quadrant_batch(8)[0]
-    wl.ncell = (n, n)
-    wl.N = N
-    wl.bcs = [(W.BC.simple(W.PERIODIC), W.BC.simple(W.PERIODIC))] * 2
-    return wl
-
-
 def test_mood_layer_conserves_and_is_active():
     """MOOD layer after the subcell WENO3 scheme (Sec. 6, Fig. algo2): with first-order
     fluxes on the sub-faces next to flagged subcells, adjacent troubled cells still agree
     on every shared sub-face, so the step stays conservative to round-off; the layer acts
     (flags, recomputed cells) and every result stays physical."""
-    wl = _periodic_quadrant()
+    wl = W.periodic_quadrant()
     o = O.Oracle(wl, mood=True)
     o.init()
     m0 = totals(o)
@@ -397,7 +387,7 @@ def test_mood_layer_changes_nothing_without_flags():
 def test_mood_first_order_fluxes_where_flagged():
     """Where the layer acts the result differs from the plain subcell scheme and only in
     troubled cells and their face neighbours (the flux correction)."""
-    wl = _periodic_quadrant()
+    wl = W.periodic_quadrant()
     states = []
     for mood in (False, True):
         o = O.Oracle(wl, mood=mood)

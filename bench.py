@@ -239,11 +239,11 @@ def batch_measurement(count, steps):
     res = {"problems": count, "cells": sum(wl.num_cells for wl in wls), "st_dof_per_step": st_dof,
            "steps": steps, "cfl": cfl}
 
-    def build(prec):
+    def build(prec, mood=False):
         ps = []
         for wl in wls:
             cap = wl.num_cells if wl.num_cells <= 4096 else wl.num_cells // 3
-            p = adg.Problem(wl, precision=prec, pool_capacity=cap)
+            p = adg.Problem(wl, precision=prec, pool_capacity=cap, mood=mood)
             u, _ = p.project(wl.ic, 0)
             p.set_state(u)
             ps.append(p)
@@ -283,6 +283,26 @@ def batch_measurement(count, steps):
     for p in ps:
         p.close()
     del ps
+    gc.collect()
+    torch.cuda.empty_cache()
+    # the same batch with the MOOD layer after the subcell scheme (Sec. 6, Fig. algo2)
+    ps = build(adg.ADG_MIXED, mood=True)
+    b = adg.Batch(ps)
+    b.step_cfl(cfl, 3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step_cfl(cfl, steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    fl = [p.mood_stats() for p in ps]
+    res["mixed_batched_mood"] = {"value": st_dof * steps / el, "ms_per_batch_step": 1e3 * el / steps,
+                                 "flagged_subcells_last_step": int(sum(f for f, _ in fl)),
+                                 "recomputed_cells_last_step": int(sum(r for _, r in fl)),
+                                 "troubled_last_step": int(sum(int(p.troubled().sum()) for p in ps))}
+    b.close()
+    for p in ps:
+        p.close()
+    del ps, b
     gc.collect()
     torch.cuda.empty_cache()
     print(f"# batch: mixed batched {res['mixed_batched']['value']:.3e}, fp64 per problem "

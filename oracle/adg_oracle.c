@@ -262,6 +262,75 @@ static void rusanov(int d, int k, double g, const double *qL, const double *qR, 
     for (int v = 0; v < d + 2; v++) G[v] = 0.5 * (FL[v] + FR[v]) - 0.5 * s * (qR[v] - qL[v]);
 }
 
+/* |A(Q)| dQ for the Euler flux Jacobian A along axis k: dQ is split into the waves of A at
+ * Q (acoustic, entropy, shear) and each part scaled by the modulus of its eigenvalue
+ * (u_k - c, u_k, u_k + c). */
+void or_abs_jacobian(int d, int k, double g, const double *Q, const double *dQ, double *out) {
+    int nv = d + 2;
+    double rho = Q[0], u[3] = {0, 0, 0}, q2 = 0;
+    for (int j = 0; j < d; j++) { u[j] = Q[1 + j] / rho; q2 += u[j] * u[j]; }
+    double p = pressure(d, g, Q), c2 = g * p / rho, c = sqrt(c2), H = (Q[d + 1] + p) / rho, un = u[k];
+    /* primitive increments of dQ at Q */
+    double drho = dQ[0], du[3] = {0, 0, 0}, mdq = 0;
+    for (int j = 0; j < d; j++) { du[j] = (dQ[1 + j] - u[j] * drho) / rho; mdq += u[j] * dQ[1 + j]; }
+    double dp = (g - 1.0) * (dQ[d + 1] - mdq + 0.5 * q2 * drho);
+    double a1 = (dp - rho * c * du[k]) / (2.0 * c2), a5 = (dp + rho * c * du[k]) / (2.0 * c2);
+    double a2 = drho - dp / c2;
+    double l1 = fabs(un - c), l2 = fabs(un), l5 = fabs(un + c);
+    for (int v = 0; v < nv; v++) out[v] = 0.0;
+    /* acoustic waves r = (1, u -+ c e_k, H -+ c u_k) */
+    out[0] += l1 * a1 + l5 * a5;
+    for (int j = 0; j < d; j++) out[1 + j] += l1 * a1 * (u[j] - (j == k ? c : 0.0)) + l5 * a5 * (u[j] + (j == k ? c : 0.0));
+    out[d + 1] += l1 * a1 * (H - c * un) + l5 * a5 * (H + c * un);
+    /* entropy wave r = (1, u, |u|^2/2) and shear waves r = (0, e_j, u_j), j != k */
+    out[0] += l2 * a2;
+    for (int j = 0; j < d; j++) out[1 + j] += l2 * a2 * u[j];
+    out[d + 1] += l2 * a2 * 0.5 * q2;
+    for (int j = 0; j < d; j++) {
+        if (j == k) continue;
+        double at = rho * du[j];
+        out[1 + j] += l2 * at;
+        out[d + 1] += l2 * at * u[j];
+    }
+}
+
+/* Osher-type flux of the universal form (reading: the paper names the flux of its
+ * reference without giving formulas): G = (F(qL) + F(qR))/2 - 1/2 int_0^1 |A(psi(s))| ds
+ * (qR - qL) along the straight path psi(s) = qL + s (qR - qL), integrated with the
+ * 3-point Gauss-Legendre rule (xi3, w3). */
+static void osher(int d, int k, double g, const double *xi3, const double *w3, const double *qL, const double *qR,
+                  double *G) {
+    int nv = d + 2;
+    double FL[5], FR[5], dQ[5], acc[5] = {0, 0, 0, 0, 0};
+    euler_flux(d, k, g, qL, FL);
+    euler_flux(d, k, g, qR, FR);
+    for (int v = 0; v < nv; v++) dQ[v] = qR[v] - qL[v];
+    for (int j = 0; j < 3; j++) {
+        double psi[5], o[5];
+        for (int v = 0; v < nv; v++) psi[v] = qL[v] + xi3[j] * dQ[v];
+        or_abs_jacobian(d, k, g, psi, dQ, o);
+        for (int v = 0; v < nv; v++) acc[v] += w3[j] * o[v];
+    }
+    for (int v = 0; v < nv; v++) G[v] = 0.5 * (FL[v] + FR[v]) - 0.5 * acc[v];
+}
+
+/* Numerical flux of the scheme: Rusanov (0) or Osher-type (1). */
+static void num_flux(const or_solver *S, int k, const double *qL, const double *qR, double *G) {
+    if (S->c.flux == 1) osher(S->d, k, S->c.gamma, S->B3.xi, S->B3.w, qL, qR, G);
+    else rusanov(S->d, k, S->c.gamma, qL, qR, G);
+}
+
+/* Test entry: the numerical flux with the 3-point rule computed here. */
+void or_numerical_flux(int d, int k, double g, int flux, const double *qL, const double *qR, double *G) {
+    if (flux == 1) {
+        double xi[3], w[3];
+        gauss_legendre(3, xi, w);
+        osher(d, k, g, xi, w, qL, qR, G);
+    } else {
+        rusanov(d, k, g, qL, qR, G);
+    }
+}
+
 /* --------------------------------------------------------- boundary conditions */
 /* reading: the paper names its boundary conditions without formulas.  A ghost state
  * is made from the interior state at the same point: transmissive copies it,
@@ -1017,7 +1086,9 @@ static void subcell_update(const or_solver *S, const double *vn, long c, double 
                             if (bside == 0) bc_ghost(S, k, 0, qR, x, tn, qL);
                             else if (bside == 1) bc_ghost(S, k, 1, qL, x, tn, qR);
                             if (!pass && !(all_physical(d, g, qL, 1) && all_physical(d, g, qR, 1))) { ok = 0; break; }
-                            rusanov(d, k, g, qL, qR, G);
+                            /* the scheme's flux on the traces; first-order fallbacks use Rusanov */
+                            if (pass) rusanov(d, k, g, qL, qR, G);
+                            else num_flux(S, k, qL, qR, G);
                             for (int v = 0; v < nv; v++) Fbar[v] += wt * G[v];
                         }
                     if (ok) break;
@@ -1144,8 +1215,8 @@ int or_step(or_solver *S, double dt) {
                             for (int v = 0; v < nv; v++)
                                 qout[v] = tr[cn * trsz + ((2 * k + 1 - side) * nv + v) * nfn * n + ap + nfn * s];
                         }
-                        if (side == 0) rusanov(d, k, g, qout, qin, G);
-                        else rusanov(d, k, g, qin, qout, G);
+                        if (side == 0) num_flux(S, k, qout, qin, G);
+                        else num_flux(S, k, qin, qout, G);
                         for (int v = 0; v < nv; v++) acc[v] += B->w[s] * G[v];
                     }
                     for (int v = 0; v < nv; v++) gbar[c * gsz + ((2 * k + side) * nv + v) * nfn + ap] = acc[v];

@@ -44,6 +44,7 @@ typedef struct {
     double gamma, eps, delta0;
     or_bc bc[3][2];
     int mood;             /* 1: one more MOOD layer after the subcell WENO3 scheme (first order) */
+    int flux;             /* 0: Rusanov, 1: Osher-type (universal form) */
 } or_config;
 
 typedef struct or_solver or_solver;
@@ -69,6 +70,9 @@ void or_force_troubled(or_solver *s, const uint8_t *mask);
 int or_poison(or_solver *s, long cell, int var, double value);
 /* MOOD layer of the last step: subcells whose WENO3 candidate failed, cells recomputed. */
 void or_mood_stats(const or_solver *s, long *flagged, long *redone);
+/* Test entries: numerical flux (0 Rusanov, 1 Osher-type) along axis k, and |A(Q)| dQ. */
+void or_numerical_flux(int d, int k, double g, int flux, const double *qL, const double *qR, double *G);
+void or_abs_jacobian(int d, int k, double g, const double *Q, const double *dQ, double *out);
 double or_time(const or_solver *s);
 void or_set_time(or_solver *s, double t);
 double or_cfl_dt(const or_solver *s, double cfl);

@@ -24,7 +24,7 @@ class _Config(C.Structure):
     _fields_ = [("dim", C.c_int), ("N", C.c_int), ("Ns", C.c_int), ("picard_iters", C.c_int),
                 ("limiter", C.c_int), ("ncell", C.c_int * 3), ("lo", C.c_double * 3),
                 ("hi", C.c_double * 3), ("gamma", C.c_double), ("eps", C.c_double),
-                ("delta0", C.c_double), ("bc", (_BC * 2) * 3), ("mood", C.c_int)]
+                ("delta0", C.c_double), ("bc", (_BC * 2) * 3), ("mood", C.c_int), ("flux", C.c_int)]
 
 
 _lib = None
@@ -54,6 +54,8 @@ def lib():
         L.or_force_troubled.argtypes = [C.c_void_p, C.POINTER(C.c_uint8)]
         L.or_poison.argtypes = [C.c_void_p, C.c_long, C.c_int, C.c_double]
         L.or_mood_stats.argtypes = [C.c_void_p, C.POINTER(C.c_long), C.POINTER(C.c_long)]
+        L.or_numerical_flux.argtypes = [C.c_int, C.c_int, C.c_double, C.c_int, dp, dp, dp]
+        L.or_abs_jacobian.argtypes = [C.c_int, C.c_int, C.c_double, dp, dp, dp]
         L.or_time.restype = C.c_double
         L.or_time.argtypes = [C.c_void_p]
         L.or_set_time.argtypes = [C.c_void_p, C.c_double]
@@ -123,9 +125,10 @@ def get_threads() -> int:
     return lib().or_get_threads()
 
 
-def make_config(wl, limiter: bool = True, picard_iters: int = 0, mood: bool = False) -> _Config:
+def make_config(wl, limiter: bool = True, picard_iters: int = 0, mood: bool = False, flux: int = 0) -> _Config:
     c = _Config()
     c.mood = 1 if mood else 0
+    c.flux = flux
     c.dim, c.N = wl.dim, wl.N
     c.Ns = wl.Ns if wl.Ns else 2 * wl.N + 1
     c.picard_iters = picard_iters if picard_iters else wl.N + 1
@@ -150,9 +153,9 @@ def make_config(wl, limiter: bool = True, picard_iters: int = 0, mood: bool = Fa
 class Oracle:
     """One problem advanced by the CPU oracle."""
 
-    def __init__(self, wl, limiter: bool = True, picard_iters: int = 0, mood: bool = False):
+    def __init__(self, wl, limiter: bool = True, picard_iters: int = 0, mood: bool = False, flux: int = 0):
         self.wl = wl
-        self.cfg = make_config(wl, limiter, picard_iters, mood)
+        self.cfg = make_config(wl, limiter, picard_iters, mood, flux)
         self.h = lib().or_create(C.byref(self.cfg))
         if not self.h:
             raise ValueError("oracle rejected the configuration")
@@ -257,3 +260,23 @@ class Oracle:
 
     def nonphysical(self) -> int:
         return lib().or_nonphysical(self.h)
+
+
+def numerical_flux(d, k, gamma, flux, qL, qR):
+    """Numerical flux (0 Rusanov, 1 Osher-type) along axis k between conserved states."""
+    dp = C.POINTER(C.c_double)
+    qL = np.ascontiguousarray(qL, dtype=np.float64)
+    qR = np.ascontiguousarray(qR, dtype=np.float64)
+    G = np.zeros(d + 2)
+    lib().or_numerical_flux(d, k, gamma, flux, qL.ctypes.data_as(dp), qR.ctypes.data_as(dp), G.ctypes.data_as(dp))
+    return G
+
+
+def abs_jacobian(d, k, gamma, Q, dQ):
+    """|A(Q)| dQ for the Euler flux Jacobian along axis k."""
+    dp = C.POINTER(C.c_double)
+    Q = np.ascontiguousarray(Q, dtype=np.float64)
+    dQ = np.ascontiguousarray(dQ, dtype=np.float64)
+    out = np.zeros(d + 2)
+    lib().or_abs_jacobian(d, k, gamma, Q.ctypes.data_as(dp), dQ.ctypes.data_as(dp), out.ctypes.data_as(dp))
+    return out

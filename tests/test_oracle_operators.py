@@ -105,3 +105,75 @@ def test_weno3_non_oscillatory_on_a_step():
     assert out.min() > -1e-6 and out.max() < 1 + 1e-6
     out = O.weno3([0.0, 0.0, 1.0, 1.0, 1.0])
     assert out.min() > -1e-6 and out.max() < 1 + 1e-6
+
+
+# ---------------------------------------------------------------- Osher-type flux
+def _euler_flux(d, k, g, Q):
+    p = (g - 1) * (Q[d + 1] - 0.5 * sum(Q[1 + j] ** 2 for j in range(d)) / Q[0])
+    un = Q[1 + k] / Q[0]
+    F = np.zeros(d + 2)
+    F[0] = Q[1 + k]
+    for j in range(d):
+        F[1 + j] = Q[1 + j] * un + (p if j == k else 0)
+    F[d + 1] = un * (Q[d + 1] + p)
+    return F
+
+
+def _state(d, g, rho, u, p):
+    return np.array([rho] + [rho * x for x in u] + [p / (g - 1) + 0.5 * rho * sum(x * x for x in u)])
+
+
+def _jac(d, k, g, Q, y, eps=1e-6):
+    """A(Q) y by a centred difference of the Euler flux (independent of the eigen-split)."""
+    return (_euler_flux(d, k, g, Q + eps * y) - _euler_flux(d, k, g, Q - eps * y)) / (2 * eps)
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_osher_flux_consistent(d):
+    rng = np.random.default_rng(11)
+    for _ in range(5):
+        q = _state(d, 1.4, rng.uniform(0.2, 2), rng.uniform(-1, 1, d), rng.uniform(0.2, 2))
+        for k in range(d):
+            G = O.numerical_flux(d, k, 1.4, 1, q, q)
+            assert np.abs(G - _euler_flux(d, k, 1.4, q)).max() < 1e-14 * max(1, np.abs(G).max())
+
+
+def test_osher_flux_resolves_stationary_contact():
+    """Zero normal velocity, equal pressure, different densities: the Osher-type flux gives
+    the exact flux (0, p, 0, 0); Rusanov adds dissipation."""
+    g, p = 1.4, 0.7
+    qL, qR = _state(2, g, 1.0, [0, 0], p), _state(2, g, 0.2, [0, 0], p)
+    G = O.numerical_flux(2, 0, g, 1, qL, qR)
+    assert np.abs(G - np.array([0, p, 0, 0])).max() < 1e-14
+    Gr = O.numerical_flux(2, 0, g, 0, qL, qR)
+    assert abs(Gr[0]) > 1e-2
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_abs_jacobian_matches_jacobian(d):
+    """Supersonic along k: |A| dq = A dq; any state: |A| |A| dq = A A dq (A by finite
+    differences of the flux, so a wrong eigenvector or wave strength shows)."""
+    g = 1.4
+    rng = np.random.default_rng(5)
+    for k in range(d):
+        u = list(rng.uniform(-0.5, 0.5, d))
+        u[k] = 3.0
+        Q = _state(d, g, 1.1, u, 0.9)            # c ~ 1.06 < u_k
+        dq = rng.normal(size=d + 2)
+        a = O.abs_jacobian(d, k, g, Q, dq)
+        assert np.abs(a - _jac(d, k, g, Q, dq)).max() < 1e-7 * np.abs(a).max()
+        Q2 = _state(d, g, 0.8, list(rng.uniform(-0.4, 0.4, d)), 1.3)   # subsonic
+        aa = O.abs_jacobian(d, k, g, Q2, O.abs_jacobian(d, k, g, Q2, dq))
+        AA = _jac(d, k, g, Q2, _jac(d, k, g, Q2, dq), eps=1e-5)
+        assert np.abs(aa - AA).max() < 1e-6 * np.abs(AA).max()
+
+
+def test_osher_flux_upwind_when_supersonic():
+    """All eigenvalues positive along the path: the flux is F(qL) up to the error of the
+    3-point rule on the path integral (small for a small jump)."""
+    g = 1.4
+    qL = _state(2, g, 1.0, [3.0, 0.2], 1.0)
+    qR = _state(2, g, 1.03, [3.05, 0.21], 1.04)
+    G = O.numerical_flux(2, 0, g, 1, qL, qR)
+    FL = _euler_flux(2, 0, g, qL)
+    assert np.abs(G - FL).max() < 1e-7 * np.abs(FL).max()

@@ -84,6 +84,10 @@ typedef struct {
                              algo2): subcells whose WENO3 result fails PAD or the relaxed DMP
                              against their cell's bounds get the first-order flux of the subcell
                              averages on all their sub-faces (reading); 0: off (default) */
+    int flux;             /* numerical flux at element faces and sub-faces (Sec. 2.3): 0 Rusanov
+                             (default), 1 Osher-type in the universal form (straight path, 3-point
+                             Gauss-Legendre, |A| from the Euler eigen-split; reading); the
+                             first-order fallbacks of the subcell scheme stay Rusanov */
 } adg_params;
 
 typedef struct adg_problem adg_problem;

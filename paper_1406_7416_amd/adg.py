@@ -45,7 +45,8 @@ class _Grid(C.Structure):
 
 class _Params(C.Structure):
     _fields_ = [("Ns", C.c_int), ("picard_iters", C.c_int), ("precision", C.c_int), ("limiter", C.c_int),
-                ("eps", C.c_double), ("delta0", C.c_double), ("pool_capacity", C.c_int64), ("mood", C.c_int)]
+                ("eps", C.c_double), ("delta0", C.c_double), ("pool_capacity", C.c_int64), ("mood", C.c_int),
+                ("flux", C.c_int)]
 
 
 _lib = None
@@ -127,7 +128,8 @@ class Problem:
     """One problem on one GPU: owns a torch workspace, drives the C ABI."""
 
     def __init__(self, wl, precision: int = ADG_FP64, limiter: bool = True, pool_capacity: int = 0,
-                 picard_iters: int = 0, device: str = "cuda:0", stream=None, mood: bool = False):
+                 picard_iters: int = 0, device: str = "cuda:0", stream=None, mood: bool = False,
+                 flux: int = 0):
         import torch
         L = load()
         self.wl = wl
@@ -144,6 +146,7 @@ class Problem:
         prm.eps, prm.delta0 = wl.eps, wl.delta0
         prm.pool_capacity = pool_capacity
         prm.mood = 1 if mood else 0
+        prm.flux = flux
         self._grid = _grid(wl)
         h = C.c_void_p()
         _check(L.adg_create(C.byref(self._grid), wl.N, wl.gamma, C.byref(prm), C.byref(h)))

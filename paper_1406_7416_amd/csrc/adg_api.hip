@@ -248,6 +248,7 @@ int adg_create(const adg_grid_desc *g, int N, double gamma, const adg_params *p,
     if (prm.delta0 == 0) prm.delta0 = 1e-4;
     if (prm.precision != ADG_FP64 && prm.precision != ADG_MIXED) return fail(ADG_EINVAL, "unknown precision mode");
     if (prm.mood != 0 && prm.mood != 1) return fail(ADG_EINVAL, "mood must be 0 or 1");
+    if (prm.flux != 0 && prm.flux != 1) return fail(ADG_EINVAL, "flux must be 0 (Rusanov) or 1 (Osher-type)");
     adg_problem *pb = new (std::nothrow) adg_problem();
     if (!pb) return fail(ADG_ENOMEM, "host allocation failed");
     Prob &P = pb->P;
@@ -280,6 +281,7 @@ int adg_create(const adg_grid_desc *g, int N, double gamma, const adg_params *p,
     }
     P.gamma = gamma;
     P.eps = prm.eps;
+    P.flux = prm.flux;
     P.delta0 = prm.delta0;
     for (int k = 0; k < g->dim; k++) {
         const int p0 = g->bc[k][0].kind[0] == ADG_PERIODIC, p1 = g->bc[k][1].kind[0] == ADG_PERIODIC;

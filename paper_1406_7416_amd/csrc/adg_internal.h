@@ -32,7 +32,7 @@ struct Tables {
     float fD[MAXN][MAXN], fKw[MAXN][MAXN], fDvol[MAXN][MAXN], fL[MAXN], fR[MAXN], fw[MAXN];
     float fDE[MAXN / 2][MAXN / 2 + 1], fDO[MAXN / 2 + 1][MAXN / 2];
     // FP32 copies of the degree-2 subcell operators (mixed form)
-    float fD3[3][3], fKw3[3][3], fL3[3], fR3[3], fw3[3];
+    float fD3[3][3], fKw3[3][3], fL3[3], fR3[3], fw3[3], fxi3[3];
 };
 
 struct BCDev {
@@ -51,6 +51,7 @@ struct Prob {
     double gamma, eps, delta0;
     BCDev bc[3][2];
     int periodic[3];
+    int flux;              // 0 Rusanov, 1 Osher-type
 };
 
 // Device buffers of one problem, carved out of the caller's workspace.

@@ -67,6 +67,81 @@ __device__ __forceinline__ void rusanov(int k, const R *qL, const R *qR, R *G, R
     for (int v = 0; v < NV; v++) G[v] = R(0.5) * (FL[v] + FR[v]) - R(0.5) * s * (qR[v] - qL[v]);
 }
 
+// |A(Q)| dQ for the Euler flux Jacobian along axis k: dQ split into the waves of A at Q
+// (acoustic, entropy, shear), each scaled by |u_k - c|, |u_k| or |u_k + c|.
+template <int DIM, typename R>
+__device__ __forceinline__ void abs_jacobian(int k, const R *Q, const R *dQ, R g, R *out) {
+    constexpr int NV = DIM + 2;
+    const R rho = Q[0], ir = R(1) / Q[0];
+    R u[DIM], du[DIM], q2 = 0, mdq = 0, un = 0, duk = 0;
+#pragma unroll
+    for (int j = 0; j < DIM; j++) {
+        u[j] = Q[1 + j] * ir;
+        q2 += u[j] * u[j];
+        du[j] = (dQ[1 + j] - u[j] * dQ[0]) * ir;
+        mdq += u[j] * dQ[1 + j];
+        if (j == k) { un = u[j]; duk = du[j]; }
+    }
+    const R p = pressure<DIM, R>(Q, g);
+    const R c2 = g * p * ir, c = sqrt(c2), H = (Q[NV - 1] + p) * ir;
+    const R dp = (g - R(1)) * (dQ[NV - 1] - mdq + R(0.5) * q2 * dQ[0]);
+    const R a1 = (dp - rho * c * duk) / (R(2) * c2), a5 = (dp + rho * c * duk) / (R(2) * c2);
+    const R a2 = dQ[0] - dp / c2;
+    const R l1 = fabs(un - c), l2 = fabs(un), l5 = fabs(un + c);
+    out[0] = l1 * a1 + l5 * a5 + l2 * a2;
+    R e = l1 * a1 * (H - c * un) + l5 * a5 * (H + c * un) + l2 * a2 * R(0.5) * q2;
+#pragma unroll
+    for (int j = 0; j < DIM; j++) {
+        const bool nk = j != k;
+        out[1 + j] = l1 * a1 * (u[j] - (nk ? R(0) : c)) + l5 * a5 * (u[j] + (nk ? R(0) : c)) + l2 * a2 * u[j] +
+                     (nk ? l2 * rho * du[j] : R(0));
+        if (nk) e += l2 * rho * du[j] * u[j];
+    }
+    out[NV - 1] = e;
+}
+
+// Osher-type flux in the universal form: (F(qL) + F(qR))/2 - 1/2 int_0^1 |A(psi(s))| ds
+// (qR - qL) on the straight path psi(s) = qL + s (qR - qL), 3-point Gauss-Legendre (xs, ws).
+template <int DIM, typename R>
+__device__ __forceinline__ void osher(int k, const R *qL, const R *qR, R *G, R g, const R *xs, const R *ws) {
+    constexpr int NV = DIM + 2;
+    R FL[NV], FR[NV], dQ[NV], acc[NV];
+    euler_flux<DIM, R>(k, qL, FL, g);
+    euler_flux<DIM, R>(k, qR, FR, g);
+#pragma unroll
+    for (int v = 0; v < NV; v++) {
+        dQ[v] = qR[v] - qL[v];
+        acc[v] = 0;
+    }
+#pragma unroll
+    for (int j = 0; j < 3; j++) {
+        R psi[NV], o[NV];
+#pragma unroll
+        for (int v = 0; v < NV; v++) psi[v] = qL[v] + xs[j] * dQ[v];
+        abs_jacobian<DIM, R>(k, psi, dQ, g, o);
+#pragma unroll
+        for (int v = 0; v < NV; v++) acc[v] += ws[j] * o[v];
+    }
+#pragma unroll
+    for (int v = 0; v < NV; v++) G[v] = R(0.5) * (FL[v] + FR[v]) - R(0.5) * acc[v];
+}
+
+// The scheme's numerical flux (Sec. 2.3): Rusanov or Osher-type.
+template <int DIM, typename R>
+__device__ __forceinline__ void num_flux(const Prob &P, const Tables *T, int k, const R *qL, const R *qR, R *G) {
+    if (P.flux == 1) {
+        R xs[3], ws[3];
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            xs[j] = sizeof(R) == 4 ? (R)T->fxi3[j] : (R)T->xi3[j];
+            ws[j] = sizeof(R) == 4 ? (R)T->fw3[j] : (R)T->w3[j];
+        }
+        osher<DIM, R>(k, qL, qR, G, (R)P.gamma, xs, ws);
+    } else {
+        rusanov<DIM, R>(k, qL, qR, G, (R)P.gamma);
+    }
+}
+
 template <int DIM, typename R = double>
 __device__ __forceinline__ bool physical(const R *q, R g) {
 #pragma unroll
@@ -590,7 +665,7 @@ __global__ __launch_bounds__((FaceShape<DIM, N>::BS)) void k_face(const Tables *
                 else qL[v] = (R)qo[v];
             }
         }
-        rusanov<DIM, R>(k, qL, qR, G, (R)P.gamma);
+        num_flux<DIM, R>(P, T, k, qL, qR, G);
         const R ws = std::is_same<R, double>::value ? (R)T->w[s] : (R)T->fw[s];
 #pragma unroll
         for (int v = 0; v < NV; v++) part[(lf * PER + j) * NV + v] = ws * G[v];
@@ -1562,7 +1637,9 @@ __device__ __forceinline__ void sub_update_cell(const Tables *__restrict__ T, co
                         ok = false;
                         break;
                     }
-                    rusanov<DIM, R>(k, qL, qR, G, gam);
+                    // the scheme's flux on the traces; the first-order fallback uses Rusanov
+                    if (pass) rusanov<DIM, R>(k, qL, qR, G, gam);
+                    else num_flux<DIM, R>(P, T, k, qL, qR, G);
 #pragma unroll
                     for (int v = 0; v < NV; v++) Fbar[v] += (R)wt * G[v];
                 }

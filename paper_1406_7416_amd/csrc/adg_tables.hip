@@ -201,6 +201,7 @@ void build_tables(int N, int Ns, Tables *T) {
         T->fL3[a] = (float)T->L3[a];
         T->fR3[a] = (float)T->R3[a];
         T->fw3[a] = (float)T->w3[a];
+        T->fxi3[a] = (float)T->xi3[a];
         for (int b = 0; b < 3; b++) {
             T->fD3[a][b] = (float)T->D3[a][b];
             T->fKw3[a][b] = (float)T->Kw3[a][b];

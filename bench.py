@@ -123,8 +123,10 @@ def main():
     forms = {}
     finals = {}
     u0 = None
-    for form, prec in (("fp64", adg.ADG_FP64), ("mixed", adg.ADG_MIXED)):
-        prob = adg.Problem(wl, precision=prec)
+    # the Osher-type flux (the paper's flux for its vortex runs) alongside Rusanov
+    for form, prec, flux in (("fp64", adg.ADG_FP64, 0), ("mixed", adg.ADG_MIXED, 0),
+                             ("fp64_osher", adg.ADG_FP64, 1), ("mixed_osher", adg.ADG_MIXED, 1)):
+        prob = adg.Problem(wl, precision=prec, flux=flux)
         if u0 is None:
             u0, _ = prob.project(wl.ic, 0)      # nodal values of the initial condition
         prob.set_state(u0)
@@ -210,6 +212,7 @@ def main():
         },
         "forms": forms,
         "speedup_mixed_vs_fp64": forms["mixed"]["value"] / forms["fp64"]["value"],
+        "speedup_mixed_vs_fp64_osher": forms["mixed_osher"]["value"] / forms["fp64_osher"]["value"],
         "rho_mixed_minus_fp64": {"max": float(drho.max()), "mean": float(drho.mean())},
         # both forms after the same steps, against the exact (advected) vortex
         "matched_l1_rho": {"fp64": forms["fp64"]["l1_rho_vs_exact"], "mixed": forms["mixed"]["l1_rho_vs_exact"],

@@ -224,6 +224,7 @@ def main():
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, u0, args.cpu_seconds)
+        out["cpu_baseline_single_thread"] = cpu_baseline(wl, u0, args.cpu_seconds / 2, threads=1)
 
     print(json.dumps(out), flush=True)
 
@@ -313,12 +314,15 @@ def batch_measurement(count, steps):
     return res
 
 
-def cpu_baseline(wl, u0, budget_s):
+def cpu_baseline(wl, u0, budget_s, threads=None):
     """The FP64 CPU oracle, as it stands, on the same workload: whole steps until the
-    time budget is used (at least one)."""
+    time budget is used (at least one); all host threads, or the number given."""
     from oracle import oracle as O
     o = O.Oracle(wl)
     o.set_state(u0)
+    saved = O.get_threads()
+    if threads:
+        O.set_threads(threads)
     threads = O.get_threads()
     steps, t0 = 0, time.perf_counter()
     while True:
@@ -327,6 +331,7 @@ def cpu_baseline(wl, u0, budget_s):
         el = time.perf_counter() - t0
         if el >= budget_s or steps >= 50:
             break
+    O.set_threads(saved)
     return {
         "value": wl.st_dof_per_step() * steps / el,
         "unit": "st-dof/s",

@@ -30,8 +30,9 @@ PEAK_HBM_GBS = 8000.0
 
 # HBM bytes per launch of k_predictor<2, 9, true, float> on the N=9, 64x64 vortex: rocprofv3
 # FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (the factors that make a plain 256 MiB copy read its
-# own size), taken on the kernel source whose SHA-256 starts with the prefix below; reported
-# as null once that source has changed.
+# own size), taken on the predictor source (the files below, concatenated) whose SHA-256 starts
+# with the prefix below; reported as null once that source has changed.
+PREDICTOR_SOURCES = ("adg_internal.h", "adg_device.h", "adg_predictor.h")
 PREDICTOR_TRAFFIC_BYTES = 84526924
 PREDICTOR_TRAFFIC_SOURCE = "e8d20c60c382cf6b"
 
@@ -64,9 +65,11 @@ def traffic_bytes(N, grid):
     """Measured HBM traffic of the dominant kernel, if it was measured on this workload and
     on the kernel source as it stands."""
     import hashlib
-    src = os.path.join(ROOT, "paper_1406_7416_amd", "csrc", "adg_kernels.hip")
-    with open(src, "rb") as f:
-        h = hashlib.sha256(f.read()).hexdigest()
+    h = hashlib.sha256()
+    for name in PREDICTOR_SOURCES:
+        with open(os.path.join(ROOT, "paper_1406_7416_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    h = h.hexdigest()
     if N != 9 or grid != 64 or not h.startswith(PREDICTOR_TRAFFIC_SOURCE):
         return None
     return PREDICTOR_TRAFFIC_BYTES

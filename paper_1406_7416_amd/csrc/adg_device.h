@@ -1,0 +1,178 @@
+// Device helpers shared by the kernels: Euler physics, numerical fluxes, boundary
+// ghost states and cell indexing.
+#pragma once
+#include <cmath>
+#include <type_traits>
+#include "adg_internal.h"
+
+namespace adg {
+
+// ------------------------------------------------------------------ small helpers
+template <int B, int E> struct Pow { static constexpr int v = B * Pow<B, E - 1>::v; };
+template <int B> struct Pow<B, 0> { static constexpr int v = 1; };
+
+__host__ __device__ constexpr int cpow(int b, int e) { return e == 0 ? 1 : b * cpow(b, e - 1); }
+
+template <int DIM, typename R = double>
+__device__ __forceinline__ R pressure(const R *q, R g) {
+    R ke = 0;
+#pragma unroll
+    for (int j = 0; j < DIM; j++) ke += q[1 + j] * q[1 + j];
+    return (g - R(1)) * (q[DIM + 1] - R(0.5) * ke / q[0]);
+}
+
+// a[1 + k] for a runtime axis k, by selection: a dynamic index would place the
+// register array in scratch memory
+template <int DIM, typename R>
+__device__ __forceinline__ R along(const R *a, int k) {
+    R r = a[1];
+#pragma unroll
+    for (int j = 1; j < DIM; j++)
+        if (k == j) r = a[1 + j];
+    return r;
+}
+
+// Euler flux along axis k (Sec. 5).
+template <int DIM, typename R = double>
+__device__ __forceinline__ void euler_flux(int k, const R *q, R *F, R g) {
+    const R p = pressure<DIM, R>(q, g);
+    const R qk = along<DIM, R>(q, k);
+    const R un = qk / q[0];
+    F[0] = qk;
+#pragma unroll
+    for (int j = 0; j < DIM; j++) F[1 + j] = q[1 + j] * un + (j == k ? p : R(0));
+    F[DIM + 1] = un * (q[DIM + 1] + p);
+}
+
+// Rusanov flux; wave speed per quadrature node: max over both sides of |u_n| + c.
+template <int DIM, typename R = double>
+__device__ __forceinline__ void rusanov(int k, const R *qL, const R *qR, R *G, R g) {
+    constexpr int NV = DIM + 2;
+    R FL[NV], FR[NV];
+    euler_flux<DIM, R>(k, qL, FL, g);
+    euler_flux<DIM, R>(k, qR, FR, g);
+    const R sL = fabs(along<DIM, R>(qL, k) / qL[0]) + sqrt(g * pressure<DIM, R>(qL, g) / qL[0]);
+    const R sR = fabs(along<DIM, R>(qR, k) / qR[0]) + sqrt(g * pressure<DIM, R>(qR, g) / qR[0]);
+    const R s = fmax(sL, sR);
+#pragma unroll
+    for (int v = 0; v < NV; v++) G[v] = R(0.5) * (FL[v] + FR[v]) - R(0.5) * s * (qR[v] - qL[v]);
+}
+
+// |A(Q)| dQ for the Euler flux Jacobian along axis k: dQ split into the waves of A at Q
+// (acoustic, entropy, shear), each scaled by |u_k - c|, |u_k| or |u_k + c|.
+template <int DIM, typename R>
+__device__ __forceinline__ void abs_jacobian(int k, const R *Q, const R *dQ, R g, R *out) {
+    constexpr int NV = DIM + 2;
+    const R rho = Q[0], ir = R(1) / Q[0];
+    R u[DIM], du[DIM], q2 = 0, mdq = 0, un = 0, duk = 0;
+#pragma unroll
+    for (int j = 0; j < DIM; j++) {
+        u[j] = Q[1 + j] * ir;
+        q2 += u[j] * u[j];
+        du[j] = (dQ[1 + j] - u[j] * dQ[0]) * ir;
+        mdq += u[j] * dQ[1 + j];
+        if (j == k) { un = u[j]; duk = du[j]; }
+    }
+    const R p = pressure<DIM, R>(Q, g);
+    const R c2 = g * p * ir, c = sqrt(c2), H = (Q[NV - 1] + p) * ir;
+    const R dp = (g - R(1)) * (dQ[NV - 1] - mdq + R(0.5) * q2 * dQ[0]);
+    const R a1 = (dp - rho * c * duk) / (R(2) * c2), a5 = (dp + rho * c * duk) / (R(2) * c2);
+    const R a2 = dQ[0] - dp / c2;
+    const R l1 = fabs(un - c), l2 = fabs(un), l5 = fabs(un + c);
+    out[0] = l1 * a1 + l5 * a5 + l2 * a2;
+    R e = l1 * a1 * (H - c * un) + l5 * a5 * (H + c * un) + l2 * a2 * R(0.5) * q2;
+#pragma unroll
+    for (int j = 0; j < DIM; j++) {
+        const bool nk = j != k;
+        out[1 + j] = l1 * a1 * (u[j] - (nk ? R(0) : c)) + l5 * a5 * (u[j] + (nk ? R(0) : c)) + l2 * a2 * u[j] +
+                     (nk ? l2 * rho * du[j] : R(0));
+        if (nk) e += l2 * rho * du[j] * u[j];
+    }
+    out[NV - 1] = e;
+}
+
+// Osher-type flux in the universal form: (F(qL) + F(qR))/2 - 1/2 int_0^1 |A(psi(s))| ds
+// (qR - qL) on the straight path psi(s) = qL + s (qR - qL), 3-point Gauss-Legendre (xs, ws).
+template <int DIM, typename R>
+__device__ __forceinline__ void osher(int k, const R *qL, const R *qR, R *G, R g, const R *xs, const R *ws) {
+    constexpr int NV = DIM + 2;
+    R FL[NV], FR[NV], dQ[NV], acc[NV];
+    euler_flux<DIM, R>(k, qL, FL, g);
+    euler_flux<DIM, R>(k, qR, FR, g);
+#pragma unroll
+    for (int v = 0; v < NV; v++) {
+        dQ[v] = qR[v] - qL[v];
+        acc[v] = 0;
+    }
+#pragma unroll
+    for (int j = 0; j < 3; j++) {
+        R psi[NV], o[NV];
+#pragma unroll
+        for (int v = 0; v < NV; v++) psi[v] = qL[v] + xs[j] * dQ[v];
+        abs_jacobian<DIM, R>(k, psi, dQ, g, o);
+#pragma unroll
+        for (int v = 0; v < NV; v++) acc[v] += ws[j] * o[v];
+    }
+#pragma unroll
+    for (int v = 0; v < NV; v++) G[v] = R(0.5) * (FL[v] + FR[v]) - R(0.5) * acc[v];
+}
+
+// The scheme's numerical flux (Sec. 2.3): Rusanov or Osher-type.
+template <int DIM, typename R>
+__device__ __forceinline__ void num_flux(const Prob &P, const Tables *T, int k, const R *qL, const R *qR, R *G) {
+    if (P.flux == 1) {
+        R xs[3], ws[3];
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            xs[j] = sizeof(R) == 4 ? (R)T->fxi3[j] : (R)T->xi3[j];
+            ws[j] = sizeof(R) == 4 ? (R)T->fw3[j] : (R)T->w3[j];
+        }
+        osher<DIM, R>(k, qL, qR, G, (R)P.gamma, xs, ws);
+    } else {
+        rusanov<DIM, R>(k, qL, qR, G, (R)P.gamma);
+    }
+}
+
+template <int DIM, typename R = double>
+__device__ __forceinline__ bool physical(const R *q, R g) {
+#pragma unroll
+    for (int v = 0; v < DIM + 2; v++)
+        if (!isfinite(q[v])) return false;
+    return q[0] > R(0) && pressure<DIM, R>(q, g) > R(0);
+}
+
+// Ghost state of one boundary side (transmissive / reflective / Dirichlet with split).
+template <int DIM>
+__device__ __forceinline__ void bc_ghost(const Prob &P, int k, int side, const double *qin, const double *x,
+                                         double t, double *qout) {
+    constexpr int NV = DIM + 2;
+    const BCDev &b = P.bc[k][side];
+    int which = 0;
+    if (b.split_axis >= 0) {
+        double xs = x[0];
+#pragma unroll
+        for (int j = 1; j < DIM; j++)
+            if (b.split_axis == j) xs = x[j];
+        which = (xs < b.split0 + b.split_speed * t) ? 0 : 1;
+    }
+    const int kind = b.kind[which];
+    if (kind == ADG_DIRICHLET) {
+#pragma unroll
+        for (int v = 0; v < NV; v++) qout[v] = b.state[which][v];
+        return;
+    }
+    const bool refl = kind == ADG_REFLECTIVE;
+#pragma unroll
+    for (int v = 0; v < NV; v++) qout[v] = (refl && v == 1 + k) ? -qin[v] : qin[v];
+}
+
+__device__ __forceinline__ int64_t cell_of(const Prob &P, const int *ci) {
+    return ci[0] + (int64_t)P.nc[0] * (ci[1] + (int64_t)P.nc[1] * ci[2]);
+}
+__device__ __forceinline__ void coords_of(const Prob &P, int64_t c, int *ci) {
+    ci[0] = (int)(c % P.nc[0]);
+    ci[1] = (int)((c / P.nc[0]) % P.nc[1]);
+    ci[2] = (int)(c / ((int64_t)P.nc[0] * P.nc[1]));
+}
+
+}  // namespace adg

@@ -13,565 +13,10 @@
 #include <type_traits>
 #include "adg_internal.h"
 #include "adg_kernels.h"
+#include "adg_device.h"
+#include "adg_predictor.h"
 
 namespace adg {
-
-// ------------------------------------------------------------------ small helpers
-template <int B, int E> struct Pow { static constexpr int v = B * Pow<B, E - 1>::v; };
-template <int B> struct Pow<B, 0> { static constexpr int v = 1; };
-
-__host__ __device__ constexpr int cpow(int b, int e) { return e == 0 ? 1 : b * cpow(b, e - 1); }
-
-template <int DIM, typename R = double>
-__device__ __forceinline__ R pressure(const R *q, R g) {
-    R ke = 0;
-#pragma unroll
-    for (int j = 0; j < DIM; j++) ke += q[1 + j] * q[1 + j];
-    return (g - R(1)) * (q[DIM + 1] - R(0.5) * ke / q[0]);
-}
-
-// a[1 + k] for a runtime axis k, by selection: a dynamic index would place the
-// register array in scratch memory
-template <int DIM, typename R>
-__device__ __forceinline__ R along(const R *a, int k) {
-    R r = a[1];
-#pragma unroll
-    for (int j = 1; j < DIM; j++)
-        if (k == j) r = a[1 + j];
-    return r;
-}
-
-// Euler flux along axis k (Sec. 5).
-template <int DIM, typename R = double>
-__device__ __forceinline__ void euler_flux(int k, const R *q, R *F, R g) {
-    const R p = pressure<DIM, R>(q, g);
-    const R qk = along<DIM, R>(q, k);
-    const R un = qk / q[0];
-    F[0] = qk;
-#pragma unroll
-    for (int j = 0; j < DIM; j++) F[1 + j] = q[1 + j] * un + (j == k ? p : R(0));
-    F[DIM + 1] = un * (q[DIM + 1] + p);
-}
-
-// Rusanov flux; wave speed per quadrature node: max over both sides of |u_n| + c.
-template <int DIM, typename R = double>
-__device__ __forceinline__ void rusanov(int k, const R *qL, const R *qR, R *G, R g) {
-    constexpr int NV = DIM + 2;
-    R FL[NV], FR[NV];
-    euler_flux<DIM, R>(k, qL, FL, g);
-    euler_flux<DIM, R>(k, qR, FR, g);
-    const R sL = fabs(along<DIM, R>(qL, k) / qL[0]) + sqrt(g * pressure<DIM, R>(qL, g) / qL[0]);
-    const R sR = fabs(along<DIM, R>(qR, k) / qR[0]) + sqrt(g * pressure<DIM, R>(qR, g) / qR[0]);
-    const R s = fmax(sL, sR);
-#pragma unroll
-    for (int v = 0; v < NV; v++) G[v] = R(0.5) * (FL[v] + FR[v]) - R(0.5) * s * (qR[v] - qL[v]);
-}
-
-// |A(Q)| dQ for the Euler flux Jacobian along axis k: dQ split into the waves of A at Q
-// (acoustic, entropy, shear), each scaled by |u_k - c|, |u_k| or |u_k + c|.
-template <int DIM, typename R>
-__device__ __forceinline__ void abs_jacobian(int k, const R *Q, const R *dQ, R g, R *out) {
-    constexpr int NV = DIM + 2;
-    const R rho = Q[0], ir = R(1) / Q[0];
-    R u[DIM], du[DIM], q2 = 0, mdq = 0, un = 0, duk = 0;
-#pragma unroll
-    for (int j = 0; j < DIM; j++) {
-        u[j] = Q[1 + j] * ir;
-        q2 += u[j] * u[j];
-        du[j] = (dQ[1 + j] - u[j] * dQ[0]) * ir;
-        mdq += u[j] * dQ[1 + j];
-        if (j == k) { un = u[j]; duk = du[j]; }
-    }
-    const R p = pressure<DIM, R>(Q, g);
-    const R c2 = g * p * ir, c = sqrt(c2), H = (Q[NV - 1] + p) * ir;
-    const R dp = (g - R(1)) * (dQ[NV - 1] - mdq + R(0.5) * q2 * dQ[0]);
-    const R a1 = (dp - rho * c * duk) / (R(2) * c2), a5 = (dp + rho * c * duk) / (R(2) * c2);
-    const R a2 = dQ[0] - dp / c2;
-    const R l1 = fabs(un - c), l2 = fabs(un), l5 = fabs(un + c);
-    out[0] = l1 * a1 + l5 * a5 + l2 * a2;
-    R e = l1 * a1 * (H - c * un) + l5 * a5 * (H + c * un) + l2 * a2 * R(0.5) * q2;
-#pragma unroll
-    for (int j = 0; j < DIM; j++) {
-        const bool nk = j != k;
-        out[1 + j] = l1 * a1 * (u[j] - (nk ? R(0) : c)) + l5 * a5 * (u[j] + (nk ? R(0) : c)) + l2 * a2 * u[j] +
-                     (nk ? l2 * rho * du[j] : R(0));
-        if (nk) e += l2 * rho * du[j] * u[j];
-    }
-    out[NV - 1] = e;
-}
-
-// Osher-type flux in the universal form: (F(qL) + F(qR))/2 - 1/2 int_0^1 |A(psi(s))| ds
-// (qR - qL) on the straight path psi(s) = qL + s (qR - qL), 3-point Gauss-Legendre (xs, ws).
-template <int DIM, typename R>
-__device__ __forceinline__ void osher(int k, const R *qL, const R *qR, R *G, R g, const R *xs, const R *ws) {
-    constexpr int NV = DIM + 2;
-    R FL[NV], FR[NV], dQ[NV], acc[NV];
-    euler_flux<DIM, R>(k, qL, FL, g);
-    euler_flux<DIM, R>(k, qR, FR, g);
-#pragma unroll
-    for (int v = 0; v < NV; v++) {
-        dQ[v] = qR[v] - qL[v];
-        acc[v] = 0;
-    }
-#pragma unroll
-    for (int j = 0; j < 3; j++) {
-        R psi[NV], o[NV];
-#pragma unroll
-        for (int v = 0; v < NV; v++) psi[v] = qL[v] + xs[j] * dQ[v];
-        abs_jacobian<DIM, R>(k, psi, dQ, g, o);
-#pragma unroll
-        for (int v = 0; v < NV; v++) acc[v] += ws[j] * o[v];
-    }
-#pragma unroll
-    for (int v = 0; v < NV; v++) G[v] = R(0.5) * (FL[v] + FR[v]) - R(0.5) * acc[v];
-}
-
-// The scheme's numerical flux (Sec. 2.3): Rusanov or Osher-type.
-template <int DIM, typename R>
-__device__ __forceinline__ void num_flux(const Prob &P, const Tables *T, int k, const R *qL, const R *qR, R *G) {
-    if (P.flux == 1) {
-        R xs[3], ws[3];
-#pragma unroll
-        for (int j = 0; j < 3; j++) {
-            xs[j] = sizeof(R) == 4 ? (R)T->fxi3[j] : (R)T->xi3[j];
-            ws[j] = sizeof(R) == 4 ? (R)T->fw3[j] : (R)T->w3[j];
-        }
-        osher<DIM, R>(k, qL, qR, G, (R)P.gamma, xs, ws);
-    } else {
-        rusanov<DIM, R>(k, qL, qR, G, (R)P.gamma);
-    }
-}
-
-template <int DIM, typename R = double>
-__device__ __forceinline__ bool physical(const R *q, R g) {
-#pragma unroll
-    for (int v = 0; v < DIM + 2; v++)
-        if (!isfinite(q[v])) return false;
-    return q[0] > R(0) && pressure<DIM, R>(q, g) > R(0);
-}
-
-// Ghost state of one boundary side (transmissive / reflective / Dirichlet with split).
-template <int DIM>
-__device__ __forceinline__ void bc_ghost(const Prob &P, int k, int side, const double *qin, const double *x,
-                                         double t, double *qout) {
-    constexpr int NV = DIM + 2;
-    const BCDev &b = P.bc[k][side];
-    int which = 0;
-    if (b.split_axis >= 0) {
-        double xs = x[0];
-#pragma unroll
-        for (int j = 1; j < DIM; j++)
-            if (b.split_axis == j) xs = x[j];
-        which = (xs < b.split0 + b.split_speed * t) ? 0 : 1;
-    }
-    const int kind = b.kind[which];
-    if (kind == ADG_DIRICHLET) {
-#pragma unroll
-        for (int v = 0; v < NV; v++) qout[v] = b.state[which][v];
-        return;
-    }
-    const bool refl = kind == ADG_REFLECTIVE;
-#pragma unroll
-    for (int v = 0; v < NV; v++) qout[v] = (refl && v == 1 + k) ? -qin[v] : qin[v];
-}
-
-__device__ __forceinline__ int64_t cell_of(const Prob &P, const int *ci) {
-    return ci[0] + (int64_t)P.nc[0] * (ci[1] + (int64_t)P.nc[1] * ci[2]);
-}
-__device__ __forceinline__ void coords_of(const Prob &P, int64_t c, int *ci) {
-    ci[0] = (int)(c % P.nc[0]);
-    ci[1] = (int)((c / P.nc[0]) % P.nc[1]);
-    ci[2] = (int)(c / ((int64_t)P.nc[0] * P.nc[1]));
-}
-
-// ------------------------------------------------------------- space-time predictor
-// Eq. (pde.nc.dg2) in nodal form (spatial weights divided out, K1^{-1} L = 1):
-//   q^{r+1}(a,s) = u(a) - sum_t Kw[s][t] S(a,t),
-//   S(a,t) = sum_k (dt/h_k) sum_b D[a_k][b] F_k(q^r(a|b, t))
-// Thread mapping: a "point owner" thread holds one spatial node of one cell with its
-// whole time pencil (NV x n values) in registers.  It evaluates the fluxes of the pencil
-// and stores them in LDS; "line owner" threads do the length-n spatial contractions
-// (n loads -> n outputs each, in place); the point owner accumulates S over the d axes
-// and applies the time contraction in registers: d + 1 contractions per sweep.
-template <int DIM, int N, typename R = double, int TB = 256>
-struct PredShape;
-
-// 1/x: correctly rounded division in FP64; the hardware reciprocal (within 1 ulp) in
-// the FP32 working precision of the mixed form.
-__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
-__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
-
-// TB: thread budget of a workgroup (cells per block = TB / n^d)
-template <int DIM, int N, typename R, int TB>
-struct PredShape {
-    static constexpr int n = N + 1;
-    static constexpr int NV = DIM + 2;
-    static constexpr int NN = cpow(n, DIM);
-    static constexpr int NST = NN * n;
-    static constexpr int NFN = cpow(n, DIM - 1);
-    static constexpr int CPB = NN <= TB ? TB / NN : 1;
-    static constexpr int ACT = CPB * NN;                           // active point owners
-    static constexpr int BS = ((ACT + 63) / 64) * 64;
-    static constexpr int VCMAX = 65536 / (CPB * NST * (int)sizeof(R));
-    static constexpr int VC = VCMAX < 1 ? 1 : (VCMAX > NV ? NV : VCMAX);  // vars per LDS chunk
-};
-
-template <typename R>
-struct PredArgs {
-    const double *in;      // input nodal values
-    int64_t in_cstride;    // stride between cells
-    int64_t in_vstride;    // stride between variables
-    R *trace;              // [cell][2d][v][nfn*n]
-    double *vol_out;       // candidate with volume term [v][cell][node] (main scheme only)
-    int64_t ncell;         // cells (or subcell positions) in this launch
-    int64_t cell0;         // first cell index (for vol_out addressing)
-    int iters;
-    double dth[3];         // dt/h_k multipliers (without dt)
-    const double *dt;      // device scalar
-    // operators of the n-node basis used by this launch (row stride MAXN)
-    const R *D, *Kw, *Lb, *Rb, *w, *Dvol;
-    const R *DE, *DO;      // even / odd parts of D (row strides MAXN/2 + 1 and MAXN/2)
-    // if set, the number of cells is min(*dcount, dcap) * dmult (read on the device)
-    const int *dcount;
-    int64_t dcap;
-    int dmult;
-};
-
-// Contraction along axis k of every line held in LDS: line[i] <- c * sum_b M[i][b] line[b]
-// (c only if SCALE).  One work item handles the same line of LV variables (independent FMA
-// chains sharing each operator entry; for long lines LV is 2 (FP32) or 1 (FP64) to bound
-// register use).
-// EO: M is the derivative matrix on symmetric nodes, applied through its even / odd parts
-// E, O (half-size products on x_b +- x_{n-1-b}: n^2/2 + 2n operations instead of n^2).
-template <int DIM, int N, int CPB, int VC, int BS, typename R, bool EO = false, bool SCALE = true>
-__device__ __forceinline__ void lds_lines(R *X, int k, int nlines_per_var, int lstride_s, const R (*M)[MAXN], R c,
-                                          int tid, int nvalid, const R (*E)[MAXN / 2 + 1] = nullptr,
-                                          const R (*O)[MAXN / 2] = nullptr) {
-    constexpr int n = N + 1, NN = cpow(n, DIM), NST = NN * n;
-    constexpr int LV = (n >= 8) ? (sizeof(R) == 8 ? 1 : 2) : VC;
-    constexpr int NG = (VC + LV - 1) / LV;   // variable groups per line
-    const int st = (k == 0) ? 1 : (k == 1 ? n : n * n);
-    const int nitems = CPB * NG * nlines_per_var;
-    for (int it = tid; it < nitems; it += BS) {
-        // compiler barrier: keeps the operator rows from being hoisted into registers
-        __asm__ volatile("" ::: "memory");
-        const int lcl = it / (NG * nlines_per_var);
-        const int grp = (it / nlines_per_var) % NG;
-        const int j = it % nlines_per_var;          // (a_perp, s) flattened, a_perp fastest
-        const int s = j / (NN / n), ap = j % (NN / n);
-        int base = 0, rem = ap, mul = 1;
-#pragma unroll
-        for (int jj = 0; jj < DIM; jj++) {
-            if (jj == k) { mul *= n; continue; }
-            base += (rem % n) * mul;
-            rem /= n;
-            mul *= n;
-        }
-        const int v0 = grp * LV;
-        R *line0 = &X[(lcl * VC + v0) * NST + lstride_s * s + base];
-        R xb[LV][n];
-#pragma unroll
-        for (int vv = 0; vv < LV; vv++)
-#pragma unroll
-            for (int b = 0; b < n; b++) xb[vv][b] = (v0 + vv < nvalid) ? line0[vv * NST + b * st] : R(0);
-        if constexpr (EO) {
-            constexpr int h = n / 2;
-            R e[LV][h], o[LV][h];
-#pragma unroll
-            for (int vv = 0; vv < LV; vv++)
-#pragma unroll
-                for (int b = 0; b < h; b++) {
-                    e[vv][b] = xb[vv][b] + xb[vv][n - 1 - b];
-                    o[vv][b] = xb[vv][b] - xb[vv][n - 1 - b];
-                }
-#pragma unroll
-            for (int i = 0; i < h; i++) {
-                R pe[LV], po[LV];
-#pragma unroll
-                for (int vv = 0; vv < LV; vv++) pe[vv] = po[vv] = 0;
-#pragma unroll
-                for (int b = 0; b < h; b++) {
-                    const R me = E[i][b], mo = O[i][b];
-#pragma unroll
-                    for (int vv = 0; vv < LV; vv++) {
-                        pe[vv] += me * e[vv][b];
-                        po[vv] += mo * o[vv][b];
-                    }
-                }
-                if constexpr (n % 2) {
-                    const R mm = E[i][h];
-#pragma unroll
-                    for (int vv = 0; vv < LV; vv++) pe[vv] += mm * xb[vv][h];
-                }
-#pragma unroll
-                for (int vv = 0; vv < LV; vv++)
-                    if (v0 + vv < nvalid) {
-                        const R yi = po[vv] + pe[vv], yr = po[vv] - pe[vv];
-                        line0[vv * NST + i * st] = SCALE ? c * yi : yi;
-                        line0[vv * NST + (n - 1 - i) * st] = SCALE ? c * yr : yr;
-                    }
-            }
-            if constexpr (n % 2) {
-                R acc[LV];
-#pragma unroll
-                for (int vv = 0; vv < LV; vv++) acc[vv] = 0;
-#pragma unroll
-                for (int b = 0; b < h; b++) {
-                    const R mo = O[h][b];
-#pragma unroll
-                    for (int vv = 0; vv < LV; vv++) acc[vv] += mo * o[vv][b];
-                }
-#pragma unroll
-                for (int vv = 0; vv < LV; vv++)
-                    if (v0 + vv < nvalid) line0[vv * NST + h * st] = SCALE ? c * acc[vv] : acc[vv];
-            }
-        } else {
-#pragma unroll
-            for (int i = 0; i < n; i++) {
-                R acc[LV];
-#pragma unroll
-                for (int vv = 0; vv < LV; vv++) acc[vv] = 0;
-#pragma unroll
-                for (int b = 0; b < n; b++) {
-                    const R m = M[i][b];
-#pragma unroll
-                    for (int vv = 0; vv < LV; vv++) acc[vv] += m * xb[vv][b];
-                }
-#pragma unroll
-                for (int vv = 0; vv < LV; vv++)
-                    if (v0 + vv < nvalid) line0[vv * NST + i * st] = SCALE ? c * acc[vv] : acc[vv];
-            }
-        }
-    }
-}
-
-// Blocks vb = vb0, vb0 + vbs, ... of CPB cells each, out of ncell cells.
-template <int DIM, int N, bool VOL, typename R, int TB = 256>
-__device__ void pred_cells(const PredArgs<R> &A, double gamma_d, int64_t ncell, int64_t vb0, int64_t vbs) {
-    using S = PredShape<DIM, N, R, TB>;
-    const R gamma = (R)gamma_d;
-    constexpr int n = S::n, NV = S::NV, NN = S::NN, NST = S::NST, NFN = S::NFN, CPB = S::CPB, VC = S::VC;
-    __shared__ R X[CPB * VC * NST];
-    // operators staged in LDS and read as wave-uniform broadcasts inside the loops (kept
-    // out of registers: the n x n matrices would otherwise be hoisted into VGPRs)
-    __shared__ R Ds[n][MAXN], Kws[n][MAXN], Dvs[n][MAXN];
-    // the spatial contractions use the even / odd form where it saves work (n >= 6)
-    constexpr bool EO = n >= 6;
-    __shared__ R Es[EO ? MAXN / 2 : 1][MAXN / 2 + 1], Os[EO ? MAXN / 2 + 1 : 1][MAXN / 2];
-
-    const int tid = threadIdx.x;
-    const int lc = tid / NN, a = tid % NN;
-    const double dt = *A.dt;
-    for (int i = tid; i < n * n; i += S::BS) {
-        const int r = i / n, cc = i % n;
-        Ds[r][cc] = A.D[r * MAXN + cc];
-        Kws[r][cc] = A.Kw[r * MAXN + cc];
-        Dvs[r][cc] = VOL ? A.Dvol[r * MAXN + cc] : R(0);
-    }
-    if constexpr (EO) {
-        for (int i = tid; i < (MAXN / 2) * (MAXN / 2 + 1); i += S::BS) {
-            Es[i / (MAXN / 2 + 1)][i % (MAXN / 2 + 1)] = A.DE[i];
-            Os[i / (MAXN / 2)][i % (MAXN / 2)] = A.DO[i];
-        }
-    }
-    __syncthreads();
-    const R(*D)[MAXN] = Ds;
-    const R(*Kw)[MAXN] = Kws;
-    const R(*Dvol)[MAXN] = Dvs;
-    // persistent over blocks of CPB cells (uniform per block: barriers stay legal)
-    for (int64_t vb = vb0; vb * CPB < ncell; vb += vbs) {
-    const int64_t c = vb * CPB + lc;
-    const bool owner = (tid < S::ACT) && (c < ncell);
-
-    double u0d[NV];
-    R u0[NV], q[NV][n], Sacc[NV][n];
-    if (owner) {
-#pragma unroll
-        for (int v = 0; v < NV; v++) u0d[v] = A.in[c * A.in_cstride + v * A.in_vstride + a];
-    } else {
-        // idle lanes carry a valid constant state so that they never produce NaN
-#pragma unroll
-        for (int v = 0; v < NV; v++) u0d[v] = (v == 0) ? 1.0 : 0.0;
-        u0d[NV - 1] = 2.5;
-    }
-#pragma unroll
-    for (int v = 0; v < NV; v++) u0[v] = (R)u0d[v];
-#pragma unroll
-    for (int v = 0; v < NV; v++)
-#pragma unroll
-        for (int s = 0; s < n; s++) q[v][s] = u0[v];
-
-    for (int r = 0; r < A.iters; r++) {
-        // 1/rho of every node of the pencil, shared by the fluxes of all axes (for long
-        // FP64 pencils recomputed per axis instead, to stay within 256 registers)
-        constexpr bool CACHE_IRHO = n < 8 || sizeof(R) == 4;
-        R irho[CACHE_IRHO ? n : 1];
-        if constexpr (CACHE_IRHO) {
-#pragma unroll
-            for (int t = 0; t < n; t++) irho[t] = recip(q[0][t]);
-        }
-#pragma unroll
-        for (int k = 0; k < DIM; k++) {
-            const R ck = (R)(dt * A.dth[k]);
-            for (int v0 = 0; v0 < NV; v0 += VC) {
-                // point phase: fluxes of the time pencil straight into LDS
-                if (tid < S::ACT) {
-#pragma unroll
-                    for (int t = 0; t < n; t++) {
-                        R ir;
-                        if constexpr (CACHE_IRHO) ir = irho[t];
-                        else ir = recip(q[0][t]);
-                        const R un = q[1 + k][t] * ir;
-                        R ke = 0;
-#pragma unroll
-                        for (int j = 0; j < DIM; j++) ke += q[1 + j][t] * q[1 + j][t];
-                        const R prt = (gamma - R(1)) * (q[NV - 1][t] - R(0.5) * ke * ir);
-                        R F[NV];
-                        F[0] = q[1 + k][t];
-#pragma unroll
-                        for (int j = 0; j < DIM; j++) F[1 + j] = q[1 + j][t] * un + (j == k ? prt : R(0));
-                        F[NV - 1] = un * (q[NV - 1][t] + prt);
-#pragma unroll
-                        for (int vv = 0; vv < VC; vv++)
-                            if (v0 + vv < NV) X[(lc * VC + vv) * NST + a + NN * t] = F[v0 + vv];
-                    }
-                }
-                __syncthreads();
-                lds_lines<DIM, N, CPB, VC, S::BS, R, EO, false>(X, k, NN, NN, D, R(1), tid,
-                                                                NV - v0 < VC ? NV - v0 : VC, Es, Os);
-                __syncthreads();
-                // S = sum_k (dt/h_k) D_k F_k, the factor applied while accumulating
-                if (tid < S::ACT) {
-#pragma unroll
-                    for (int vv = 0; vv < VC; vv++)
-                        if (v0 + vv < NV)
-#pragma unroll
-                            for (int t = 0; t < n; t++) {
-                                const R xk = X[(lc * VC + vv) * NST + a + NN * t];
-                                Sacc[v0 + vv][t] = (k == 0) ? ck * xk : Sacc[v0 + vv][t] + ck * xk;
-                            }
-                } else if (k == 0) {
-#pragma unroll
-                    for (int vv = 0; vv < VC; vv++)
-                        if (v0 + vv < NV)
-#pragma unroll
-                            for (int t = 0; t < n; t++) Sacc[v0 + vv][t] = 0;
-                }
-                __syncthreads();
-            }
-        }
-        // time contraction in registers (Kw row s broadcast from LDS, shared by the variables)
-#pragma unroll
-        for (int s = 0; s < n; s++) {
-            __asm__ volatile("" ::: "memory");
-            R acc[NV];
-#pragma unroll
-            for (int v = 0; v < NV; v++) acc[v] = 0;
-#pragma unroll
-            for (int t = 0; t < n; t++) {
-                const R kst = Kw[s][t];
-#pragma unroll
-                for (int v = 0; v < NV; v++) acc[v] += kst * Sacc[v][t];
-            }
-#pragma unroll
-            for (int v = 0; v < NV; v++) q[v][s] = u0[v] - acc[v];
-        }
-    }
-
-    // ---- volume term of eq. (pde.nc.gw2), divided by the diagonal mass:
-    //   (dt/h_k) sum_b [w_b D[b][a_k] / w_{a_k}] sum_s w_s F_k(q(a|b, s))
-    if constexpr (VOL) {
-        R vol[NV];
-#pragma unroll
-        for (int v = 0; v < NV; v++) vol[v] = 0;
-#pragma unroll
-        for (int k = 0; k < DIM; k++) {
-            const R ck = (R)(dt * A.dth[k]);
-            R Fi[NV];
-#pragma unroll
-            for (int v = 0; v < NV; v++) Fi[v] = 0;
-#pragma unroll
-            for (int t = 0; t < n; t++) {
-                R qt[NV], F[NV];
-#pragma unroll
-                for (int v = 0; v < NV; v++) qt[v] = q[v][t];
-                euler_flux<DIM, R>(k, qt, F, gamma);
-#pragma unroll
-                for (int v = 0; v < NV; v++) Fi[v] += A.w[t] * F[v];
-            }
-            for (int v0 = 0; v0 < NV; v0 += VC) {
-                if (tid < S::ACT) {
-#pragma unroll
-                    for (int vv = 0; vv < VC; vv++)
-                        if (v0 + vv < NV) X[(lc * VC + vv) * NST + a] = Fi[v0 + vv];
-                }
-                __syncthreads();
-                lds_lines<DIM, N, CPB, VC, S::BS, R>(X, k, NN / n, 0, Dvol, ck, tid, NV - v0 < VC ? NV - v0 : VC);
-                __syncthreads();
-                if (tid < S::ACT) {
-#pragma unroll
-                    for (int vv = 0; vv < VC; vv++)
-                        if (v0 + vv < NV) vol[v0 + vv] += X[(lc * VC + vv) * NST + a];
-                }
-                __syncthreads();
-            }
-        }
-        if (owner) {
-#pragma unroll
-            for (int v = 0; v < NV; v++)
-                A.vol_out[(A.cell0 + c) * NN + (int64_t)v * A.in_vstride + a] = u0d[v] + (double)vol[v];
-        }
-    }
-
-    // ---- face traces: q at xi_k = 0 / 1 per tangential node and time node
-    for (int v0 = 0; v0 < NV; v0 += VC) {
-        if (tid < S::ACT) {
-#pragma unroll
-            for (int vv = 0; vv < VC; vv++)
-                if (v0 + vv < NV)
-#pragma unroll
-                    for (int s = 0; s < n; s++) X[(lc * VC + vv) * NST + a + NN * s] = q[v0 + vv][s];
-        }
-        __syncthreads();
-        const int nitems = CPB * VC * 2 * DIM * NFN * n;
-        for (int it = tid; it < nitems; it += S::BS) {
-            const int lcl = it / (VC * 2 * DIM * NFN * n);
-            int rem0 = it % (VC * 2 * DIM * NFN * n);
-            const int vv = rem0 / (2 * DIM * NFN * n);
-            rem0 %= 2 * DIM * NFN * n;
-            const int face = rem0 / (NFN * n);
-            const int j = rem0 % (NFN * n);   // ap + NFN*s
-            const int s = j / NFN, ap = j % NFN;
-            const int k = face >> 1, side = face & 1;
-            const int64_t cc = vb * CPB + lcl;
-            if (cc >= ncell || v0 + vv >= NV) continue;
-            int base = 0, rem = ap, mul = 1;
-#pragma unroll
-            for (int jj = 0; jj < DIM; jj++) {
-                if (jj == k) { mul *= n; continue; }
-                base += (rem % n) * mul;
-                rem /= n;
-                mul *= n;
-            }
-            const R *line = &X[(lcl * VC + vv) * NST + NN * s + base];
-            const int st = (k == 0) ? 1 : (k == 1 ? n : n * n);
-            const R *Bv = side ? A.Rb : A.Lb;
-            R acc = 0;
-#pragma unroll
-            for (int b = 0; b < n; b++) acc += Bv[b] * line[b * st];
-            A.trace[((cc * 2 * DIM + face) * NV + v0 + vv) * (NFN * n) + j] = acc;
-        }
-        __syncthreads();
-    }
-    }  // persistent loop
-}
-
-template <int DIM, int N, bool VOL, typename R>
-// FP32: at most 128 registers, four waves per SIMD; FP64: two waves per SIMD
-__global__ __launch_bounds__((PredShape<DIM, N, R>::BS), (sizeof(R) == 4 ? 4 : 2)) void k_predictor(PredArgs<R> A,
-                                                                                                   double gamma_d) {
-    pred_cells<DIM, N, VOL, R>(A, gamma_d, A.ncell, blockIdx.x, gridDim.x);
-}
 
 // ------------------------------------------------------------------- face fluxes
 // One thread per (face, tangential node, time node): Rusanov flux weighted by the time

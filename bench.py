@@ -89,6 +89,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the four-quadrant batch measurement")
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=20)
+    ap.add_argument("--no-3d", action="store_true", help="skip the 3D explosion measurement (128^3, N=3)")
+    ap.add_argument("--steps-3d", type=int, default=6)
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device-to-device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -225,11 +227,74 @@ def main():
     if not args.no_batch:
         out["batch"] = batch_measurement(args.batch_count, args.batch_steps)
 
+    if not args.no_3d:
+        out["explosion3d"] = explosion3d_measurement(args.steps_3d)
+
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, u0, args.cpu_seconds)
         out["cpu_baseline_single_thread"] = cpu_baseline(wl, u0, args.cpu_seconds / 2, threads=1)
 
     print(json.dumps(out), flush=True)
+
+
+def explosion3d_measurement(steps, warmup=2, breakdown=2, ncell=128, N=3):
+    """The 3D explosion at its full size (128^3 cells on [-1,1]^3, N = 3): both precision
+    forms stepped at the CFL time step from the initial data (nodal interpolant, initial
+    detection against the subcell-centre values), `warmup` untimed steps, then `steps`
+    timed steps."""
+    import torch
+    from paper_1406_7416_amd import adg
+    from paper_1406_7416_amd import workloads as W
+    wl = W.explosion_3d(ncell, N)
+    t0 = time.perf_counter()
+    u0 = adg.project(wl, 0)[0]
+    v0 = adg.project(wl, 1)[1]
+    t_init = time.perf_counter() - t0
+    print(f"# explosion3d {ncell}^3 N={N}: initial data {t_init:.1f} s", file=sys.stderr, flush=True)
+    st_dof = wl.st_dof_per_step()
+    res = {"workload": f"3D explosion (Sec. 5), N={N}, {ncell}^3 cells on [-1,1]^3, transmissive, "
+                       f"CFL factor {wl.cfl}, Ns={2 * N + 1}",
+           "cells": wl.num_cells, "st_dof_per_step": st_dof, "steps": steps, "warmup": warmup}
+    for form, prec in (("fp64", adg.ADG_FP64), ("mixed", adg.ADG_MIXED)):
+        prob = adg.Problem(wl, precision=prec, pool_capacity=wl.num_cells // 8)
+        prob.set_state(u0, v0)
+        troubled0 = int(prob.troubled().sum())
+        for _ in range(warmup):
+            prob.step_cfl()
+        torch.cuda.synchronize()
+        prob.profile(True, groups=["predictor"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            prob.step_cfl()
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        pred_ms, pred_n = prob.profile_read()["predictor"]
+        prob.profile(True)
+        for _ in range(breakdown):
+            prob.step_cfl()
+        prof = prob.profile_read()
+        prob.profile(False)
+        pred_s = pred_ms * 1e-3 / max(1, pred_n)
+        res[form] = {
+            "value": st_dof * steps / elapsed,
+            "unit": "st-dof/s",
+            "ms_per_step": 1e3 * elapsed / steps,
+            "predictor_avg_us": 1e6 * pred_s,
+            "predictor_tflops": predictor_flops_per_cell(3, N) * wl.num_cells / pred_s / 1e12,
+            "kernels": {g: {"ms_total": round(ms, 4), "launches": n, "avg_us": round(1e3 * ms / n, 3) if n else None}
+                        for g, (ms, n) in prof.items()},
+            "troubled_initial": troubled0,
+            "troubled_last_step": prob.stats()["troubled"],
+            "t_simulated": prob.time,
+        }
+        prob.close()
+        del prob
+        torch.cuda.empty_cache()
+        print(f"# explosion3d {form}: {res[form]['value']:.3e} st-dof/s, {res[form]['ms_per_step']:.2f} ms/step, "
+              f"troubled {res[form]['troubled_last_step']}", file=sys.stderr, flush=True)
+    res["speedup_mixed_vs_fp64"] = res["mixed"]["value"] / res["fp64"]["value"]
+    return res
 
 
 def batch_measurement(count, steps):

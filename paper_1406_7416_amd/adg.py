@@ -124,6 +124,42 @@ def _grid(wl) -> _Grid:
     return g
 
 
+def _axis_points(h, wl, axis: int, m: int, n: int, Ns: int) -> np.ndarray:
+    per = n if m == 0 else Ns * m
+    out = np.zeros(wl.ncell[axis] * per)
+    _check(load().adg_axis_points(h, axis, m, _dp(out)))
+    return out
+
+
+def _project(h, wl, ic, m: int, t: float, Ns: int):
+    from .workloads import sample_grid
+    d, n = wl.dim, wl.N + 1
+    axes = [_axis_points(h, wl, k, m, n, Ns) for k in range(d)]
+    samples = np.ascontiguousarray(sample_grid(ic, axes, t))
+    u = np.zeros((d + 2, wl.num_cells, n ** d))
+    v = np.zeros((d + 2, wl.num_cells, Ns ** d)) if m > 0 else None
+    _check(load().adg_project_samples(h, _dp(samples), m, _dp(u), _dp(v) if v is not None else None))
+    return u, v
+
+
+def project(wl, m: int, ic=None, t: float = 0.0):
+    """Initial data of workload `wl` without a GPU: nodal values u (m = 0: samples at the
+    nodes; m > 0: L2 projection with an m-point rule per subcell) and, for m > 0, the
+    rule's subcell averages v, for Problem.set_state."""
+    L = load()
+    Ns = wl.Ns if wl.Ns else 2 * wl.N + 1
+    prm = _Params()
+    prm.Ns = Ns
+    prm.eps, prm.delta0 = wl.eps, wl.delta0
+    g = _grid(wl)
+    h = C.c_void_p()
+    _check(L.adg_create(C.byref(g), wl.N, wl.gamma, C.byref(prm), C.byref(h)))
+    try:
+        return _project(h, wl, wl.ic if ic is None else ic, m, t, Ns)
+    finally:
+        L.adg_destroy(h)
+
+
 class Problem:
     """One problem on one GPU: owns a torch workspace, drives the C ABI."""
 
@@ -173,19 +209,10 @@ class Problem:
 
     # ---- initial data
     def axis_points(self, axis: int, m: int) -> np.ndarray:
-        per = self.n if m == 0 else self.Ns * m
-        out = np.zeros(self.wl.ncell[axis] * per)
-        _check(load().adg_axis_points(self.h, axis, m, _dp(out)))
-        return out
+        return _axis_points(self.h, self.wl, axis, m, self.n, self.Ns)
 
     def project(self, ic, m: int, t: float = 0.0):
-        from .workloads import sample_grid
-        axes = [self.axis_points(k, m) for k in range(self.dim)]
-        samples = np.ascontiguousarray(sample_grid(ic, axes, t))
-        u = np.zeros((self.nv, self.ncell, self.nn))
-        v = np.zeros((self.nv, self.ncell, self.nsub)) if m > 0 else None
-        _check(load().adg_project_samples(self.h, _dp(samples), m, _dp(u), _dp(v) if v is not None else None))
-        return u, v
+        return _project(self.h, self.wl, ic, m, t, self.Ns)
 
     def set_state(self, u, v_exact: Optional[np.ndarray] = None):
         ve = None if v_exact is None else np.ascontiguousarray(v_exact, dtype=np.float64)

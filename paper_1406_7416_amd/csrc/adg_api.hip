@@ -3,8 +3,10 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 #include "adg_kernels.h"
 
@@ -21,6 +23,32 @@ static int fail(int code, const char *fmt, ...) {
     va_end(ap);
     g_err = buf;
     return code;
+}
+
+// Worker threads of the host-side set-up loops (projection of initial data, initial
+// detection): OMP_NUM_THREADS if set, else the hardware's, at most 16.
+static int host_threads() {
+    const char *e = std::getenv("OMP_NUM_THREADS");
+    int n = e ? std::atoi(e) : 0;
+    if (n <= 0) n = (int)std::thread::hardware_concurrency();
+    return std::max(1, std::min(n, 16));
+}
+
+// fn(lo, hi) on contiguous chunks of [0, n), one per worker thread.
+template <class F>
+static void parallel_for(int64_t n, F &&fn) {
+    const int nt = (int)std::min<int64_t>(host_threads(), std::max<int64_t>(n / 64, 1));
+    if (nt <= 1) {
+        fn((int64_t)0, n);
+        return;
+    }
+    std::vector<std::thread> th;
+    th.reserve(nt);
+    for (int t = 0; t < nt; t++) {
+        const int64_t lo = n * t / nt, hi = n * (t + 1) / nt;
+        th.emplace_back([&fn, lo, hi] { fn(lo, hi); });
+    }
+    for (auto &x : th) x.join();
 }
 
 #define HIPCHK(call)                                                                                 \
@@ -400,6 +428,42 @@ int adg_axis_points(const adg_problem *pb, int axis, int m, double *out) {
     return ADG_OK;
 }
 
+// out = (M x M (x M)) in: M is mo x mi with row stride ld, in holds mi^d values (x fastest),
+// out mo^d; applied axis by axis (sum factorisation), t1 / t2 hold the intermediate stages.
+static void tensor_host(int d, int mo, int mi, const double *M, int ld, const double *in, double *out,
+                        std::vector<double> &t1, std::vector<double> &t2) {
+    int dims[3] = {mi, mi, mi};
+    const double *src = in;
+    for (int k = 0; k < d; k++) {
+        int dn[3] = {dims[0], dims[1], dims[2]};
+        dn[k] = mo;
+        int64_t tot = 1, stride = 1;
+        for (int j = 0; j < d; j++) tot *= dn[j];
+        for (int j = 0; j < k; j++) stride *= dims[j];
+        std::vector<double> &buf = (k % 2 == 0) ? t1 : t2;
+        if (k < d - 1 && (int64_t)buf.size() < tot) buf.resize(tot);
+        double *dst = (k == d - 1) ? out : buf.data();
+        for (int64_t e = 0; e < tot; e++) {
+            int mm[3] = {0, 0, 0};
+            int64_t r = e, base = 0, mul = 1;
+            for (int j = 0; j < d; j++) {
+                mm[j] = (int)(r % dn[j]);
+                r /= dn[j];
+            }
+            for (int j = 0; j < d; j++) {
+                if (j != k) base += mm[j] * mul;
+                mul *= dims[j];
+            }
+            const double *row = M + (int64_t)mm[k] * ld;
+            double acc = 0.0;
+            for (int b = 0; b < mi; b++) acc += row[b] * src[base + b * stride];
+            dst[e] = acc;
+        }
+        dims[k] = mo;
+        src = dst;
+    }
+}
+
 int adg_project_samples(const adg_problem *pb, const double *samples, int m, double *u, double *v) {
     if (!pb || !samples || !u || m < 0 || m > 16) return fail(ADG_EINVAL, "bad argument");
     const Prob &P = pb->P;
@@ -410,63 +474,72 @@ int adg_project_samples(const adg_problem *pb, const double *samples, int m, dou
     for (int k = 0; k < d; k++) ext[k] = (int64_t)P.nc[k] * per;
     const int64_t npts = ext[0] * ext[1] * ext[2];
     if (m == 0) {
-        for (int64_t c = 0; c < nc; c++) {
-            int ci[3] = {(int)(c % P.nc[0]), (int)((c / P.nc[0]) % P.nc[1]), (int)(c / ((int64_t)P.nc[0] * P.nc[1]))};
-            for (int64_t a = 0; a < nn; a++) {
-                int ma[3] = {(int)(a % n), (int)((a / n) % n), (int)(a / (n * n))};
-                int64_t gi[3] = {0, 0, 0};
-                for (int k = 0; k < d; k++) gi[k] = (int64_t)ci[k] * per + ma[k];
-                const int64_t pidx = gi[0] + ext[0] * (gi[1] + ext[1] * gi[2]);
-                for (int vv = 0; vv < nv; vv++) u[((int64_t)vv * nc + c) * nn + a] = samples[vv * npts + pidx];
-            }
-        }
-        return ADG_OK;
-    }
-    // composite m-point rule on every subcell; per-axis basis values at the points
-    double xq[16], wq[16];
-    gl_nodes(m, xq, wq);
-    std::vector<double> phi((size_t)Ns * m * n);
-    for (int s = 0; s < Ns; s++)
-        for (int q = 0; q < m; q++) lagrange_values(n, pb->tab_host.xi, (s + xq[q]) / Ns, &phi[((size_t)s * m + q) * n]);
-    const int64_t nq = ipow64(m, d);
-    std::vector<double> acc((size_t)nv * nn);
-    for (int64_t c = 0; c < nc; c++) {
-        int ci[3] = {(int)(c % P.nc[0]), (int)((c / P.nc[0]) % P.nc[1]), (int)(c / ((int64_t)P.nc[0] * P.nc[1]))};
-        std::fill(acc.begin(), acc.end(), 0.0);
-        for (int64_t sg = 0; sg < nsub; sg++) {
-            int ms[3] = {(int)(sg % Ns), (int)((sg / Ns) % Ns), (int)(sg / (Ns * Ns))};
-            double avg[5] = {0, 0, 0, 0, 0};
-            for (int64_t qi = 0; qi < nq; qi++) {
-                int mq[3] = {(int)(qi % m), (int)((qi / m) % m), (int)(qi / (m * m))};
-                int64_t gi[3] = {0, 0, 0};
-                double w = 1.0;
-                for (int k = 0; k < d; k++) {
-                    gi[k] = ((int64_t)ci[k] * Ns + ms[k]) * m + mq[k];
-                    w *= wq[mq[k]];
-                }
-                const int64_t pidx = gi[0] + ext[0] * (gi[1] + ext[1] * gi[2]);
-                double f[5];
-                for (int vv = 0; vv < nv; vv++) {
-                    f[vv] = samples[vv * npts + pidx];
-                    avg[vv] += w * f[vv];
-                }
+        parallel_for(nc, [&](int64_t c0, int64_t c1) {
+            for (int64_t c = c0; c < c1; c++) {
+                int ci[3] = {(int)(c % P.nc[0]), (int)((c / P.nc[0]) % P.nc[1]), (int)(c / ((int64_t)P.nc[0] * P.nc[1]))};
                 for (int64_t a = 0; a < nn; a++) {
                     int ma[3] = {(int)(a % n), (int)((a / n) % n), (int)(a / (n * n))};
-                    double ph = w;
-                    for (int k = 0; k < d; k++) ph *= phi[((size_t)ms[k] * m + mq[k]) * n + ma[k]];
-                    for (int vv = 0; vv < nv; vv++) acc[vv * nn + a] += ph * f[vv];
+                    int64_t gi[3] = {0, 0, 0};
+                    for (int k = 0; k < d; k++) gi[k] = (int64_t)ci[k] * per + ma[k];
+                    const int64_t pidx = gi[0] + ext[0] * (gi[1] + ext[1] * gi[2]);
+                    for (int vv = 0; vv < nv; vv++) u[((int64_t)vv * nc + c) * nn + a] = samples[vv * npts + pidx];
                 }
             }
-            if (v)
-                for (int vv = 0; vv < nv; vv++) v[((int64_t)vv * nc + c) * nsub + sg] = avg[vv];
-        }
-        for (int64_t a = 0; a < nn; a++) {
-            int ma[3] = {(int)(a % n), (int)((a / n) % n), (int)(a / (n * n))};
-            double W = 1.0;
-            for (int k = 0; k < d; k++) W *= pb->tab_host.w[ma[k]];
-            for (int vv = 0; vv < nv; vv++) u[((int64_t)vv * nc + c) * nn + a] = acc[vv * nn + a] / (W * nsub);
-        }
+        });
+        return ADG_OK;
     }
+    // composite m-point rule on every subcell.  u: the L2 projection onto the nodal basis,
+    // u_a = sum over points of w * phi_a * f / (w_a Ns^d) (mass matrix diagonal in the GL
+    // nodal basis), applied axis by axis with the per-axis matrix w_q phi_a(x_q); v: the
+    // rule's subcell averages.
+    double xq[16], wq[16];
+    gl_nodes(m, xq, wq);
+    const int pa = Ns * m;   // points per axis and cell
+    std::vector<double> phw((size_t)n * pa), phi(n);
+    for (int s = 0; s < Ns; s++)
+        for (int q = 0; q < m; q++) {
+            lagrange_values(n, pb->tab_host.xi, (s + xq[q]) / Ns, phi.data());
+            for (int a = 0; a < n; a++) phw[(size_t)a * pa + s * m + q] = wq[q] * phi[a];
+        }
+    const int64_t nq = ipow64(m, d), npc = ipow64(pa, d);
+    parallel_for(nc, [&](int64_t c0, int64_t c1) {
+        std::vector<double> f((size_t)npc), out((size_t)nn), t1, t2;
+        for (int64_t c = c0; c < c1; c++) {
+            int ci[3] = {(int)(c % P.nc[0]), (int)((c / P.nc[0]) % P.nc[1]), (int)(c / ((int64_t)P.nc[0] * P.nc[1]))};
+            for (int vv = 0; vv < nv; vv++) {
+                // the cell's points, x fastest
+                for (int64_t e = 0; e < npc; e++) {
+                    const int64_t me[3] = {e % pa, (e / pa) % pa, e / ((int64_t)pa * pa)};
+                    int64_t gi[3] = {0, 0, 0};
+                    for (int k = 0; k < d; k++) gi[k] = (int64_t)ci[k] * pa + me[k];
+                    f[e] = samples[vv * npts + gi[0] + ext[0] * (gi[1] + ext[1] * gi[2])];
+                }
+                if (v)
+                    for (int64_t sg = 0; sg < nsub; sg++) {
+                        const int ms[3] = {(int)(sg % Ns), (int)((sg / Ns) % Ns), (int)(sg / (Ns * Ns))};
+                        double avg = 0.0;
+                        for (int64_t qi = 0; qi < nq; qi++) {
+                            const int mq[3] = {(int)(qi % m), (int)((qi / m) % m), (int)(qi / (m * m))};
+                            double w = 1.0;
+                            int64_t e = 0;
+                            for (int k = d - 1; k >= 0; k--) {
+                                w *= wq[mq[k]];
+                                e = e * pa + ms[k] * m + mq[k];
+                            }
+                            avg += w * f[e];
+                        }
+                        v[((int64_t)vv * nc + c) * nsub + sg] = avg;
+                    }
+                tensor_host(d, n, pa, phw.data(), pa, f.data(), out.data(), t1, t2);
+                for (int64_t a = 0; a < nn; a++) {
+                    const int ma[3] = {(int)(a % n), (int)((a / n) % n), (int)(a / (n * n))};
+                    double W = 1.0;
+                    for (int k = 0; k < d; k++) W *= pb->tab_host.w[ma[k]];
+                    u[((int64_t)vv * nc + c) * nn + a] = out[a] / (W * nsub);
+                }
+            }
+        }
+    });
     return ADG_OK;
 }
 
@@ -481,8 +554,9 @@ static int initial_detection(adg_problem *pb, std::vector<double> &u, const doub
     beta.assign(nc, 0);
     slot.assign(nc, -1);
     count = 0;
-    // per (possibly ghost) subcell value of the exact data
-    auto value = [&](const int *gci, const int *gs, double *q) {
+    // value of one subcell of a ghost cell (outside a non-periodic side): the boundary rule
+    // applied to the mirrored interior subcell
+    auto ghost_value = [&](const int *gci, const int *gs, double *q) {
         int src[3] = {0, 0, 0}, ss[3] = {0, 0, 0}, gside[3] = {-1, -1, -1};
         for (int j = 0; j < d; j++) {
             src[j] = gci[j];
@@ -515,83 +589,116 @@ static int initial_detection(adg_problem *pb, std::vector<double> &u, const doub
             }
         }
     };
-    std::vector<double> vstar((size_t)nv * nsub);
-    for (int64_t c = 0; c < nc; c++) {
-        int ci[3] = {(int)(c % P.nc[0]), (int)((c / P.nc[0]) % P.nc[1]), (int)(c / ((int64_t)P.nc[0] * P.nc[1]))};
-        double lo[5], hi[5];
-        for (int vv = 0; vv < nv; vv++) {
-            lo[vv] = INFINITY;
-            hi[vv] = -INFINITY;
-        }
-        const int nb = (int)ipow64(3, d);
-        for (int o = 0; o < nb; o++) {
-            int gci[3] = {ci[0], ci[1], ci[2]};
-            int off[3] = {o % 3, (o / 3) % 3, o / 9};
-            for (int j = 0; j < d; j++) gci[j] += off[j] - 1;
-            for (int64_t sg = 0; sg < nsub; sg++) {
-                int gs[3] = {(int)(sg % Ns), (int)((sg / Ns) % Ns), (int)(sg / (Ns * Ns))};
-                double q[5];
-                value(gci, gs, q);
-                for (int vv = 0; vv < nv; vv++) {
-                    lo[vv] = std::fmin(lo[vv], q[vv]);
-                    hi[vv] = std::fmax(hi[vv], q[vv]);
-                }
-            }
-        }
-        // candidate subcell averages P(u0)
-        for (int vv = 0; vv < nv; vv++)
-            for (int64_t sg = 0; sg < nsub; sg++) {
-                int ms[3] = {(int)(sg % Ns), (int)((sg / Ns) % Ns), (int)(sg / (Ns * Ns))};
-                double acc = 0;
-                for (int64_t a = 0; a < nn; a++) {
-                    int ma[3] = {(int)(a % n), (int)((a / n) % n), (int)(a / (n * n))};
-                    double wgt = 1;
-                    for (int j = 0; j < d; j++) wgt *= T.P[ms[j]][ma[j]];
-                    acc += wgt * u[((int64_t)vv * nc + c) * nn + a];
-                }
-                vstar[vv * nsub + sg] = acc;
-            }
-        bool bad = false;
-        for (int64_t sg = 0; sg < nsub && !bad; sg++) {
-            double q[5];
-            bool finite = true;
+    // per-cell extrema of the exact subcell data
+    std::vector<double> cmin((size_t)nc * nv), cmax((size_t)nc * nv);
+    parallel_for(nc, [&](int64_t c0, int64_t c1) {
+        for (int64_t c = c0; c < c1; c++)
             for (int vv = 0; vv < nv; vv++) {
-                q[vv] = vstar[vv * nsub + sg];
-                finite = finite && std::isfinite(q[vv]);
+                double lo = INFINITY, hi = -INFINITY;
+                const double *x = vex + ((int64_t)vv * nc + c) * nsub;
+                for (int64_t sg = 0; sg < nsub; sg++) {
+                    lo = std::fmin(lo, x[sg]);
+                    hi = std::fmax(hi, x[sg]);
+                }
+                cmin[(size_t)c * nv + vv] = lo;
+                cmax[(size_t)c * nv + vv] = hi;
             }
-            if (!finite) { bad = true; break; }
-            double ke = 0;
-            for (int j = 0; j < d; j++) ke += q[1 + j] * q[1 + j];
-            const double p = (P.gamma - 1.0) * (q[d + 1] - 0.5 * ke / q[0]);
-            if (!(q[0] > 0) || !(p > 0)) bad = true;
+    });
+    std::vector<uint8_t> flag(nc, 0);
+    parallel_for(nc, [&](int64_t c0, int64_t c1) {
+        std::vector<double> vstar((size_t)nsub), t1, t2;
+        std::vector<double> vs((size_t)nv * nsub);
+        for (int64_t c = c0; c < c1; c++) {
+            int ci[3] = {(int)(c % P.nc[0]), (int)((c / P.nc[0]) % P.nc[1]), (int)(c / ((int64_t)P.nc[0] * P.nc[1]))};
+            double lo[5], hi[5];
             for (int vv = 0; vv < nv; vv++) {
-                const double delta = std::fmax(P.delta0, P.eps * (hi[vv] - lo[vv]));
-                if (q[vv] < lo[vv] - delta || q[vv] > hi[vv] + delta) bad = true;
+                lo[vv] = INFINITY;
+                hi[vv] = -INFINITY;
             }
-        }
-        if (bad) {
-            if (count >= pb->cap) return fail(ADG_ECAPACITY, "initial detection flags more cells than the pool holds");
-            beta[c] = 1;
-            slot[c] = (int)count;
-            for (int vv = 0; vv < nv; vv++)
-                for (int64_t sg = 0; sg < nsub; sg++)
-                    pool[((size_t)count * nv + vv) * nsub + sg] = vex[((int64_t)vv * nc + c) * nsub + sg];
-            // u := R(v_exact)
-            for (int vv = 0; vv < nv; vv++)
-                for (int64_t a = 0; a < nn; a++) {
-                    int ma[3] = {(int)(a % n), (int)((a / n) % n), (int)(a / (n * n))};
-                    double acc = 0;
-                    for (int64_t sg = 0; sg < nsub; sg++) {
-                        int ms[3] = {(int)(sg % Ns), (int)((sg / Ns) % Ns), (int)(sg / (Ns * Ns))};
-                        double wgt = 1;
-                        for (int j = 0; j < d; j++) wgt *= T.Rg[ma[j]][ms[j]];
-                        acc += wgt * vex[((int64_t)vv * nc + c) * nsub + sg];
+            // bounds over the 3^d neighbourhood: stored extrema of interior (or periodically
+            // wrapped) cells, subcell by subcell for ghost cells
+            const int nb = (int)ipow64(3, d);
+            for (int o = 0; o < nb; o++) {
+                int gci[3] = {ci[0], ci[1], ci[2]};
+                const int off[3] = {o % 3, (o / 3) % 3, o / 9};
+                bool ghost = false;
+                int src[3] = {0, 0, 0};
+                for (int j = 0; j < d; j++) {
+                    gci[j] += off[j] - 1;
+                    src[j] = gci[j];
+                    if (gci[j] < 0 || gci[j] >= P.nc[j]) {
+                        if (P.periodic[j]) src[j] = (gci[j] + P.nc[j]) % P.nc[j];
+                        else ghost = true;
                     }
-                    u[((int64_t)vv * nc + c) * nn + a] = acc;
                 }
-            count++;
+                if (!ghost) {
+                    const int64_t cs = src[0] + (int64_t)P.nc[0] * (src[1] + (int64_t)P.nc[1] * src[2]);
+                    for (int vv = 0; vv < nv; vv++) {
+                        lo[vv] = std::fmin(lo[vv], cmin[(size_t)cs * nv + vv]);
+                        hi[vv] = std::fmax(hi[vv], cmax[(size_t)cs * nv + vv]);
+                    }
+                    continue;
+                }
+                for (int64_t sg = 0; sg < nsub; sg++) {
+                    const int gs[3] = {(int)(sg % Ns), (int)((sg / Ns) % Ns), (int)(sg / (Ns * Ns))};
+                    double q[5];
+                    ghost_value(gci, gs, q);
+                    for (int vv = 0; vv < nv; vv++) {
+                        lo[vv] = std::fmin(lo[vv], q[vv]);
+                        hi[vv] = std::fmax(hi[vv], q[vv]);
+                    }
+                }
+            }
+            // candidate subcell averages P(u0)
+            for (int vv = 0; vv < nv; vv++)
+                tensor_host(d, Ns, n, &T.P[0][0], MAXN, &u[((int64_t)vv * nc + c) * nn], &vs[(size_t)vv * nsub], t1, t2);
+            bool bad = false;
+            for (int64_t sg = 0; sg < nsub && !bad; sg++) {
+                double q[5];
+                bool finite = true;
+                for (int vv = 0; vv < nv; vv++) {
+                    q[vv] = vs[(size_t)vv * nsub + sg];
+                    finite = finite && std::isfinite(q[vv]);
+                }
+                if (!finite) {
+                    bad = true;
+                    break;
+                }
+                double ke = 0;
+                for (int j = 0; j < d; j++) ke += q[1 + j] * q[1 + j];
+                const double p = (P.gamma - 1.0) * (q[d + 1] - 0.5 * ke / q[0]);
+                if (!(q[0] > 0) || !(p > 0)) bad = true;
+                for (int vv = 0; vv < nv; vv++) {
+                    const double delta = std::fmax(P.delta0, P.eps * (hi[vv] - lo[vv]));
+                    if (q[vv] < lo[vv] - delta || q[vv] > hi[vv] + delta) bad = true;
+                }
+            }
+            flag[c] = bad;
         }
+    });
+    // pool slots in cell order
+    std::vector<int64_t> list;
+    for (int64_t c = 0; c < nc; c++) {
+        if (!flag[c]) continue;
+        if (count >= pb->cap) return fail(ADG_ECAPACITY, "initial detection flags more cells than the pool holds");
+        beta[c] = 1;
+        slot[c] = (int)count;
+        list.push_back(c);
+        count++;
     }
+    // troubled cells: the exact subcell data into the pool, u := R(v_exact)
+    pool.assign((size_t)count * nv * nsub, 0.0);
+    parallel_for(count, [&](int64_t i0, int64_t i1) {
+        std::vector<double> t1, t2;
+        for (int64_t i = i0; i < i1; i++) {
+            const int64_t c = list[i];
+            for (int vv = 0; vv < nv; vv++) {
+                const double *vc = vex + ((int64_t)vv * nc + c) * nsub;
+                std::copy(vc, vc + nsub, pool.begin() + ((size_t)i * nv + vv) * nsub);
+                tensor_host(d, n, Ns, &T.Rg[0][0], MAXNS, vc, &u[((int64_t)vv * nc + c) * nn], t1, t2);
+            }
+        }
+    });
     return ADG_OK;
 }
 
@@ -614,7 +721,6 @@ int adg_set_state(adg_problem *pb, const double *u, int on_device, const double 
             std::memcpy(uh.data(), u, ubytes);
         }
         std::vector<double> pool;
-        pool.resize((size_t)pb->cap * P.nv * nsub);
         int rc = initial_detection(pb, uh, v_exact, beta, slot, pool, count);
         if (rc != ADG_OK) return rc;
         HIPCHK(hipMemcpyAsync(pb->B.u[0], uh.data(), ubytes, hipMemcpyHostToDevice, pb->stream));

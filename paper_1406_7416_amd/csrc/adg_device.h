@@ -142,17 +142,16 @@ __device__ __forceinline__ bool physical(const R *q, R g) {
 }
 
 // Ghost state of one boundary side (transmissive / reflective / Dirichlet with split).
+// The point's coordinates come as values (x0, x1, x2): a selection among the elements of
+// an array would become a dynamic index into it.
 template <int DIM>
-__device__ __forceinline__ void bc_ghost(const Prob &P, int k, int side, const double *qin, const double *x,
-                                         double t, double *qout) {
+__device__ __forceinline__ void bc_ghost(const Prob &P, int k, int side, const double *qin, double x0, double x1,
+                                         double x2, double t, double *qout) {
     constexpr int NV = DIM + 2;
     const BCDev &b = P.bc[k][side];
     int which = 0;
     if (b.split_axis >= 0) {
-        double xs = x[0];
-#pragma unroll
-        for (int j = 1; j < DIM; j++)
-            if (b.split_axis == j) xs = x[j];
+        const double xs = b.split_axis == 0 ? x0 : (b.split_axis == 1 ? x1 : x2);
         which = (xs < b.split0 + b.split_speed * t) ? 0 : 1;
     }
     const int kind = b.kind[which];

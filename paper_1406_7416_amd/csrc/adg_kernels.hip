@@ -29,17 +29,14 @@ struct FaceShape {
     static constexpr int BS = ((FPB * PER + 63) / 64) * 64;
 };
 
-template <int DIM, int N, typename R>
-__global__ __launch_bounds__((FaceShape<DIM, N>::BS)) void k_face(const Tables *__restrict__ T, Prob P,
-                                                                 const R *__restrict__ trace, R *__restrict__ gbar,
-                                                                 const double *__restrict__ scal, int64_t kb1,
-                                                                 int64_t kb2) {
-    // one launch for the faces of every axis: blocks [0, kb1) axis 0, [kb1, kb2) axis 1, then axis 2
-    const int k = (blockIdx.x < kb1) ? 0 : ((blockIdx.x < kb2) ? 1 : 2);
-    const int64_t blk = (int64_t)blockIdx.x - (k == 0 ? 0 : (k == 1 ? kb1 : kb2));
+// The faces normal to axis K handled by one workgroup (block blk of that axis); K is a
+// compile-time constant so that no per-thread array is indexed dynamically.
+template <int DIM, int N, typename R, int K>
+__device__ __forceinline__ void face_axis(const Tables *__restrict__ T, const Prob &P, const R *__restrict__ trace,
+                                          R *__restrict__ gbar, const double *__restrict__ scal, int64_t blk, R *part) {
     using FS = FaceShape<DIM, N>;
     constexpr int n = N + 1, NV = DIM + 2, NFN = FS::NFN, PER = FS::PER, FPB = FS::FPB;
-    __shared__ R part[FPB * PER * NV];
+    constexpr int k = K;
     const int nk = P.nc[k];
     const int nfk = P.periodic[k] ? nk : nk + 1;           // faces along k per line
     int64_t nlines = 1;
@@ -101,13 +98,18 @@ __global__ __launch_bounds__((FaceShape<DIM, N>::BS)) void k_face(const Tables *
         if (!hasL || !hasR) {
             const double ts = t0 + T->xi[s] * dt;
             double qi[NV], qo[NV];
+            if (hasL) {
 #pragma unroll
-            for (int v = 0; v < NV; v++) qi[v] = hasL ? (double)qL[v] : (double)qR[v];
-            bc_ghost<DIM>(P, k, hasL ? 1 : 0, qi, x, ts, qo);
+                for (int v = 0; v < NV; v++) qi[v] = (double)qL[v];
+                bc_ghost<DIM>(P, k, 1, qi, x[0], x[1], x[2], ts, qo);
 #pragma unroll
-            for (int v = 0; v < NV; v++) {
-                if (hasL) qR[v] = (R)qo[v];
-                else qL[v] = (R)qo[v];
+                for (int v = 0; v < NV; v++) qR[v] = (R)qo[v];
+            } else {
+#pragma unroll
+                for (int v = 0; v < NV; v++) qi[v] = (double)qR[v];
+                bc_ghost<DIM>(P, k, 0, qi, x[0], x[1], x[2], ts, qo);
+#pragma unroll
+                for (int v = 0; v < NV; v++) qL[v] = (R)qo[v];
             }
         }
         num_flux<DIM, R>(P, T, k, qL, qR, G);
@@ -131,6 +133,23 @@ __global__ __launch_bounds__((FaceShape<DIM, N>::BS)) void k_face(const Tables *
 #pragma unroll
             for (int v = 0; v < NV; v++) gbar[((cR * 2 * DIM + 2 * k) * NV + v) * NFN + ap] = acc[v];
         }
+    }
+}
+
+template <int DIM, int N, typename R>
+__global__ __launch_bounds__((FaceShape<DIM, N>::BS)) void k_face(const Tables *__restrict__ T, Prob P,
+                                                                 const R *__restrict__ trace, R *__restrict__ gbar,
+                                                                 const double *__restrict__ scal, int64_t kb1,
+                                                                 int64_t kb2) {
+    // one launch for the faces of every axis: blocks [0, kb1) axis 0, [kb1, kb2) axis 1, then axis 2
+    using FS = FaceShape<DIM, N>;
+    __shared__ R part[FS::FPB * FS::PER * (DIM + 2)];
+    const int k = (blockIdx.x < kb1) ? 0 : ((blockIdx.x < kb2) ? 1 : 2);
+    const int64_t blk = (int64_t)blockIdx.x - (k == 0 ? 0 : (k == 1 ? kb1 : kb2));
+    switch (k) {
+    case 0: face_axis<DIM, N, R, 0>(T, P, trace, gbar, scal, blk, part); break;
+    case 1: face_axis<DIM, N, R, 1>(T, P, trace, gbar, scal, blk, part); break;
+    default: face_axis<DIM, N, R, DIM - 1>(T, P, trace, gbar, scal, blk, part); break;
     }
 }
 
@@ -559,7 +578,7 @@ __global__ __launch_bounds__(128) void k_cell_bounds(const Tables *__restrict__ 
         for (int j = 0; j < DIM; j++) {
             if (gside[j] < 0) continue;
             double qo[NV];
-            bc_ghost<DIM>(P, j, gside[j], q, x, t0, qo);
+            bc_ghost<DIM>(P, j, gside[j], q, x[0], x[1], x[2], t0, qo);
 #pragma unroll
             for (int v = 0; v < NV; v++) q[v] = qo[v];
         }
@@ -812,7 +831,7 @@ __device__ __forceinline__ void sub_halo_cell(const Tables *__restrict__ T, cons
         for (int j = 0; j < DIM; j++) {
             if (gside[j] < 0) continue;
             double qo[NV];
-            bc_ghost<DIM>(P, j, gside[j], q, x, t0, qo);
+            bc_ghost<DIM>(P, j, gside[j], q, x[0], x[1], x[2], t0, qo);
 #pragma unroll
             for (int v = 0; v < NV; v++) q[v] = qo[v];
         }
@@ -861,7 +880,6 @@ template <int DIM, int N>
 __device__ __forceinline__ void sub_recon_cell(const Tables *__restrict__ T, const Bufs &B, int sidx, const double *halo) {
     constexpr int NV = DIM + 2, NS = 2 * N + 1, HN = NS + 6, HSZ = cpow(HN, DIM);
     constexpr int NPOS = cpow(NS, DIM) + 2 * DIM * cpow(NS, DIM - 1), N3 = cpow(3, DIM);
-    constexpr int W5 = cpow(5, DIM);
     for (int item = threadIdx.x; item < NPOS * NV; item += blockDim.x) {
         const int v = item / NPOS, pos = item % NPOS;
         int L[3];
@@ -888,50 +906,40 @@ __device__ __forceinline__ void sub_recon_cell(const Tables *__restrict__ T, con
                 for (int qy = 0; qy < 3; qy++) Y[qy * 3 + qx] = o3[qy];
             }
         } else {
-            double w0[W5], w1[W5];
-            for (int e = 0; e < W5; e++) {
-                int mo[3] = {e % 5, (e / 5) % 5, e / 25};
-                int hidx = 0;
-                for (int j = DIM - 1; j >= 0; j--) hidx = hidx * HN + (L[j] + mo[j] - 2 + 3);
-                w0[e] = h[hidx];
-            }
-            double *src = w0, *dst = w1;
-            for (int k = 0; k < DIM; k++) {
-                int dimsb[3], dimsa[3], na = 1;
-                for (int j = 0; j < DIM; j++) {
-                    dimsb[j] = j < k ? 3 : 5;
-                    dimsa[j] = j <= k ? 3 : 5;
-                    na *= dimsa[j];
+            // plane by plane in z: x sweep on the five rows of the plane, y sweep per x node;
+            // then the z sweep per (y node, x node)
+            double w2[5][3][3];   // [z][qy][qx]
+#pragma unroll
+            for (int z = 0; z < 5; z++) {
+                double w1[5][3];
+#pragma unroll
+                for (int y = 0; y < 5; y++) {
+                    double a5[5];
+#pragma unroll
+                    for (int o = 0; o < 5; o++) a5[o] = h[((L[2] + z + 1) * HN + (L[1] + y + 1)) * HN + (L[0] + o + 1)];
+                    weno3(T, a5, w1[y]);
                 }
-                for (int e = 0; e < na; e++) {
-                    int ma[3] = {0, 0, 0}, r = e;
-                    for (int j = 0; j < DIM; j++) {
-                        ma[j] = r % dimsa[j];
-                        r /= dimsa[j];
-                    }
-                    if (ma[k] != 0) continue;
+#pragma unroll
+                for (int qx = 0; qx < 3; qx++) {
                     double a5[5], o3[3];
-                    for (int o = 0; o < 5; o++) {
-                        int mb[3] = {ma[0], ma[1], ma[2]};
-                        mb[k] = o;
-                        int ib = 0;
-                        for (int j = DIM - 1; j >= 0; j--) ib = ib * dimsb[j] + mb[j];
-                        a5[o] = src[ib];
-                    }
+#pragma unroll
+                    for (int y = 0; y < 5; y++) a5[y] = w1[y][qx];
                     weno3(T, a5, o3);
-                    for (int qn = 0; qn < 3; qn++) {
-                        int mc[3] = {ma[0], ma[1], ma[2]};
-                        mc[k] = qn;
-                        int ic = 0;
-                        for (int j = DIM - 1; j >= 0; j--) ic = ic * dimsa[j] + mc[j];
-                        dst[ic] = o3[qn];
-                    }
+#pragma unroll
+                    for (int qy = 0; qy < 3; qy++) w2[z][qy][qx] = o3[qy];
                 }
-                double *t = src;
-                src = dst;
-                dst = t;
             }
-            for (int a = 0; a < N3; a++) Y[a] = src[a];
+#pragma unroll
+            for (int qy = 0; qy < 3; qy++)
+#pragma unroll
+                for (int qx = 0; qx < 3; qx++) {
+                    double a5[5], o3[3];
+#pragma unroll
+                    for (int z = 0; z < 5; z++) a5[z] = w2[z][qy][qx];
+                    weno3(T, a5, o3);
+#pragma unroll
+                    for (int qz = 0; qz < 3; qz++) Y[(qz * 3 + qy) * 3 + qx] = o3[qz];
+                }
         }
     }
 }
@@ -950,9 +958,12 @@ __device__ __forceinline__ void sub_update_cell(const Tables *__restrict__ T, co
     constexpr int NPOS = NSUB + 2 * DIM * NSF, NF3 = cpow(3, DIM - 1);
     constexpr int TRS = 2 * DIM * NV * NF3 * 3;   // trace size per position
     constexpr int BIG = NSUB > NN ? NSUB : NN;
-    __shared__ double Fb[DIM * (NS + 1) * NSF * NV];
+    // sub-face fluxes (working precision), later the gather's intermediate stage
+    constexpr int FBB = DIM * (NS + 1) * NSF * NV * (int)sizeof(R), TMB = NV * BIG * 8;
+    __shared__ __align__(16) unsigned char fbt[FBB > TMB ? FBB : TMB];
+    R *Fb = reinterpret_cast<R *>(fbt);
+    double *tmp = reinterpret_cast<double *>(fbt);
     __shared__ double vn[NV * BIG];
-    __shared__ double tmp[NV * BIG];
     __shared__ double ug[NV * BIG];
     __shared__ double red[2 * NV * (SUB_BS / 64)];
     __shared__ int badc;
@@ -964,134 +975,139 @@ __device__ __forceinline__ void sub_update_cell(const Tables *__restrict__ T, co
     const R *tr = reinterpret_cast<const R *>(B.strace) + (int64_t)ch * NPOS * TRS;
     const R gam = (R)P.gamma;
     if (threadIdx.x == 0) badc = 0;
-    // neighbour existence per face of the cell
-    bool nbex[3][2];
+    // neighbour existence per face of the cell: bit 2k + side
+    int nbex = 0;
+#pragma unroll
     for (int k = 0; k < DIM; k++)
+#pragma unroll
         for (int side = 0; side < 2; side++) {
             const int nb = ci[k] + (side ? 1 : -1);
-            nbex[k][side] = P.periodic[k] || (nb >= 0 && nb < P.nc[k]);
+            if (P.periodic[k] || (nb >= 0 && nb < P.nc[k])) nbex |= 1 << (2 * k + side);
         }
-    const int nfaces = DIM * (NS + 1) * NSF;
-    for (int it = threadIdx.x; it < nfaces; it += SUB_BS) {
-        const int k = it / ((NS + 1) * NSF);
-        const int f = (it / NSF) % (NS + 1);
-        const int sp = it % NSF;
-        int mp[2] = {sp % NS, sp / NS};
-        // positions left (f-1) and right (f) of the sub-face
-        auto pos_of = [&](int Lk) -> int {
-            int Lv[3] = {0, 0, 0}, j2 = 0;
-            for (int j = 0; j < DIM; j++) {
-                if (j == k) Lv[j] = Lk;
-                else Lv[j] = mp[j2++];
-            }
-            if (Lk >= 0 && Lk < NS) {
-                int idx = 0;
-                for (int j = DIM - 1; j >= 0; j--) idx = idx * NS + Lv[j];
-                return idx;
-            }
-            return NSUB + (2 * k + (Lk >= NS ? 1 : 0)) * NSF + sp;
-        };
-        const int pL = pos_of(f - 1), pR = pos_of(f);
-        int low = 0;
-        if constexpr (REDO) {
-            // flags of the subcells on both sides: own subcells, or the neighbour's layer
-            const int own = B.slot[1][B.tlist[w]];
-            auto flag_at = [&](int Lk) -> int {
-                int Lv[3] = {0, 0, 0}, j2 = 0, sl = own, side = -1;
+    // sub-faces of all axes in one range (threads stay busy for small Ns); the body is
+    // instantiated per axis (compile-time k: no dynamic indexing of per-thread arrays)
+    for (int it = threadIdx.x; it < DIM * (NS + 1) * NSF; it += SUB_BS) {
+        auto subface = [&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            const int it2 = it - k * (NS + 1) * NSF;
+            const int f = it2 / NSF;
+            const int sp = it2 % NSF;
+            // subcell coordinate along axis j of the sub-face's tangential position (j != k):
+            // the first tangential axis takes sp % NS, the second sp / NS
+            const int mp0 = sp % NS, mp1 = sp / NS;
+            auto tang = [&](int j) -> int { return (j < k ? j : j - 1) == 0 ? mp0 : mp1; };
+            // positions left (f-1) and right (f) of the sub-face
+            auto pos_of = [&](int Lk) -> int {
+                if (Lk >= 0 && Lk < NS) {
+                    int idx = 0;
 #pragma unroll
-                for (int j = 0; j < DIM; j++) {
-                    if (j == k) Lv[j] = Lk;
-                    else Lv[j] = mp[j2++];
+                    for (int j = DIM - 1; j >= 0; j--) idx = idx * NS + (j == k ? Lk : tang(j));
+                    return idx;
                 }
-                if (Lk < 0) { side = 0; Lk += NS; }
-                if (Lk >= NS) { side = 1; Lk -= NS; }
-                if (side >= 0) sl = nslot[k][side];
-                if (sl < 0) return 0;
-                int idx = 0;
-#pragma unroll
-                for (int j = DIM - 1; j >= 0; j--) idx = idx * NS + (j == k ? Lk : Lv[j]);
-                return B.mflag[(int64_t)sl * NSUB + idx];
+                return NSUB + (2 * k + (Lk >= NS ? 1 : 0)) * NSF + sp;
             };
-            low = flag_at(f - 1) | flag_at(f);
-        }
-        const int bside = (f == 0 && !nbex[k][0]) ? 0 : ((f == NS && !nbex[k][1]) ? 1 : -1);
-        // subcell averages of both sides (halo coordinates: local subcell + 3)
-        double avL[NV], avR[NV];
-        {
-            int hL = 0, hR = 0;
-            int j2 = 0;
-            int Lv[3] = {0, 0, 0}, Rv[3] = {0, 0, 0};
-            for (int j = 0; j < DIM; j++) {
-                if (j == k) { Lv[j] = f - 1; Rv[j] = f; }
-                else { Lv[j] = Rv[j] = mp[j2++]; }
-            }
-            for (int j = DIM - 1; j >= 0; j--) {
-                hL = hL * HN + (Lv[j] + 3);
-                hR = hR * HN + (Rv[j] + 3);
-            }
+            const int pL = pos_of(f - 1), pR = pos_of(f);
+            int low = 0;
+            if constexpr (REDO) {
+                // flags of the subcells on both sides: own subcells, or the neighbour's layer
+                const int own = B.slot[1][B.tlist[w]];
+                auto flag_at = [&](int Lk) -> int {
+                    int sl = own, side = -1;
+                    if (Lk < 0) { side = 0; Lk += NS; }
+                    if (Lk >= NS) { side = 1; Lk -= NS; }
+                    if (side >= 0) sl = nslot[k][side];
+                    if (sl < 0) return 0;
+                    int idx = 0;
 #pragma unroll
-            for (int v = 0; v < NV; v++) {
-                avL[v] = halo[v * HSZ + hL];
-                avR[v] = halo[v * HSZ + hR];
+                    for (int j = DIM - 1; j >= 0; j--) idx = idx * NS + (j == k ? Lk : tang(j));
+                    return B.mflag[(int64_t)sl * NSUB + idx];
+                };
+                low = flag_at(f - 1) | flag_at(f);
             }
-        }
-        // Positivity safeguard: if any predictor trace on either side is not a physical
-        // state, the sub-face takes the first-order flux of the two subcell averages.
-        R Fbar[NV];
-        for (int pass = low; pass < 2; pass++) {
-            bool ok = true;
+            const int bside = (f == 0 && !((nbex >> (2 * k)) & 1)) ? 0 : ((f == NS && !((nbex >> (2 * k + 1)) & 1)) ? 1 : -1);
+            // subcell averages of both sides (halo coordinates: local subcell + 3)
+            double avL[NV], avR[NV];
+            {
+                int hL = 0, hR = 0;
 #pragma unroll
-            for (int v = 0; v < NV; v++) Fbar[v] = 0;
-            for (int s = 0; s < 3 && ok; s++)
-                for (int ap = 0; ap < NF3; ap++) {
-                    R qL[NV], qR[NV], G[NV];
-                    int ma[2] = {ap % 3, ap / 3};
-                    double wt = T->w3[s];
-                    double x[3] = {0, 0, 0};
-                    int j3 = 0;
-                    for (int j = 0; j < DIM; j++) {
-                        if (j == k) {
-                            x[j] = P.lo[j] + P.h[j] * (ci[j] + (double)f / NS);
-                        } else {
-                            wt *= T->w3[ma[j3]];
-                            x[j] = P.lo[j] + P.h[j] * (ci[j] + (mp[j3] + T->xi3[ma[j3]]) / NS);
-                            j3++;
+                for (int j = DIM - 1; j >= 0; j--) {
+                    hL = hL * HN + ((j == k ? f - 1 : tang(j)) + 3);
+                    hR = hR * HN + ((j == k ? f : tang(j)) + 3);
+                }
+#pragma unroll
+                for (int v = 0; v < NV; v++) {
+                    avL[v] = halo[v * HSZ + hL];
+                    avR[v] = halo[v * HSZ + hR];
+                }
+            }
+            // Positivity safeguard: if any predictor trace on either side is not a physical
+            // state, the sub-face takes the first-order flux of the two subcell averages.
+            R Fbar[NV];
+            for (int pass = low; pass < 2; pass++) {
+                bool ok = true;
+#pragma unroll
+                for (int v = 0; v < NV; v++) Fbar[v] = 0;
+                for (int s = 0; s < 3 && ok; s++)
+                    for (int ap = 0; ap < NF3; ap++) {
+                        R qL[NV], qR[NV], G[NV];
+                        const int ma0 = ap % 3, ma1 = ap / 3;
+                        double wt = T->w3[s];
+                        double x[3] = {0, 0, 0};
+#pragma unroll
+                        for (int j = 0; j < DIM; j++) {
+                            if (j == k) {
+                                x[j] = P.lo[j] + P.h[j] * (ci[j] + (double)f / NS);
+                            } else {
+                                const bool first = (j < k ? j : j - 1) == 0;
+                                const int ma = first ? ma0 : ma1;
+                                wt *= T->w3[ma];
+                                x[j] = P.lo[j] + P.h[j] * (ci[j] + ((first ? mp0 : mp1) + T->xi3[ma]) / NS);
+                            }
                         }
-                    }
-                    const double ts = t0 + T->xi3[s] * dt;
-                    const R *trL = tr + (int64_t)pL * TRS + (2 * k + 1) * NV * NF3 * 3;
-                    const R *trR = tr + (int64_t)pR * TRS + (2 * k + 0) * NV * NF3 * 3;
-#pragma unroll
-                    for (int v = 0; v < NV; v++) {
-                        qL[v] = pass ? (R)avL[v] : trL[v * NF3 * 3 + ap + NF3 * s];
-                        qR[v] = pass ? (R)avR[v] : trR[v * NF3 * 3 + ap + NF3 * s];
-                    }
-                    if (bside >= 0) {
-                        // ghost state of the boundary rule, evaluated in FP64
-                        double qi[NV], qo[NV];
-#pragma unroll
-                        for (int v = 0; v < NV; v++) qi[v] = (double)(bside == 0 ? qR[v] : qL[v]);
-                        bc_ghost<DIM>(P, k, bside, qi, x, ts, qo);
+                        const double ts = t0 + T->xi3[s] * dt;
+                        const R *trL = tr + (int64_t)pL * TRS + (2 * k + 1) * NV * NF3 * 3;
+                        const R *trR = tr + (int64_t)pR * TRS + (2 * k + 0) * NV * NF3 * 3;
 #pragma unroll
                         for (int v = 0; v < NV; v++) {
-                            if (bside == 0) qL[v] = (R)qo[v];
-                            else qR[v] = (R)qo[v];
+                            qL[v] = pass ? (R)avL[v] : trL[v * NF3 * 3 + ap + NF3 * s];
+                            qR[v] = pass ? (R)avR[v] : trR[v * NF3 * 3 + ap + NF3 * s];
                         }
-                    }
-                    if (!pass && !(physical<DIM, R>(qL, gam) && physical<DIM, R>(qR, gam))) {
-                        ok = false;
-                        break;
-                    }
-                    // the scheme's flux on the traces; the first-order fallback uses Rusanov
-                    if (pass) rusanov<DIM, R>(k, qL, qR, G, gam);
-                    else num_flux<DIM, R>(P, T, k, qL, qR, G);
+                        if (bside >= 0) {
+                            // ghost state of the boundary rule, evaluated in FP64
+                            double qi[NV], qo[NV];
+                            if (bside == 0) {
 #pragma unroll
-                    for (int v = 0; v < NV; v++) Fbar[v] += (R)wt * G[v];
-                }
-            if (ok) break;
-        }
+                                for (int v = 0; v < NV; v++) qi[v] = (double)qR[v];
+                                bc_ghost<DIM>(P, k, 0, qi, x[0], x[1], x[2], ts, qo);
 #pragma unroll
-        for (int v = 0; v < NV; v++) Fb[it * NV + v] = (double)Fbar[v];
+                                for (int v = 0; v < NV; v++) qL[v] = (R)qo[v];
+                            } else {
+#pragma unroll
+                                for (int v = 0; v < NV; v++) qi[v] = (double)qL[v];
+                                bc_ghost<DIM>(P, k, 1, qi, x[0], x[1], x[2], ts, qo);
+#pragma unroll
+                                for (int v = 0; v < NV; v++) qR[v] = (R)qo[v];
+                            }
+                        }
+                        if (!pass && !(physical<DIM, R>(qL, gam) && physical<DIM, R>(qR, gam))) {
+                            ok = false;
+                            break;
+                        }
+                        // the scheme's flux on the traces; the first-order fallback uses Rusanov
+                        if (pass) rusanov<DIM, R>(k, qL, qR, G, gam);
+                        else num_flux<DIM, R>(P, T, k, qL, qR, G);
+#pragma unroll
+                        for (int v = 0; v < NV; v++) Fbar[v] += (R)wt * G[v];
+                    }
+                if (ok) break;
+            }
+#pragma unroll
+            for (int v = 0; v < NV; v++) Fb[it * NV + v] = Fbar[v];
+        };
+        const int kk = it / ((NS + 1) * NSF);
+        if (kk == 0) subface(std::integral_constant<int, 0>{});
+        else if (kk == 1) subface(std::integral_constant<int, 1>{});
+        else subface(std::integral_constant<int, DIM - 1>{});
     }
     __syncthreads();
     // FV update of the cell's own subcells
@@ -1356,12 +1372,17 @@ __global__ __launch_bounds__(SUB_BS, 2) void k_subcell(const Tables *__restrict_
                 const int k = threadIdx.x >> 1, side = threadIdx.x & 1;
                 int ci[3];
                 coords_of(P, c, ci);
-                int nb[3] = {ci[0], ci[1], ci[2]};
-                nb[k] += side ? 1 : -1;
+                // the neighbour's coordinate along k, then its cell (selections, no dynamic index)
+                const int cik = k == 0 ? ci[0] : (k == 1 ? ci[1] : ci[2]);
+                const int nck = P.nc[k];
+                int nbk = cik + (side ? 1 : -1);
                 int sl = -1;
-                if (nb[k] >= 0 && nb[k] < P.nc[k]) sl = 0;
-                else if (P.periodic[k]) { nb[k] = (nb[k] + P.nc[k]) % P.nc[k]; sl = 0; }
+                if (nbk >= 0 && nbk < nck) sl = 0;
+                else if (P.periodic[k]) { nbk = (nbk + nck) % nck; sl = 0; }
                 if (sl == 0) {
+                    int nb[3];
+#pragma unroll
+                    for (int j = 0; j < 3; j++) nb[j] = (j == k) ? nbk : ci[j];
                     const int64_t cn = cell_of(P, nb);
                     sl = B.beta[1][cn] ? B.slot[1][cn] : -1;
                 }
@@ -1379,9 +1400,11 @@ __global__ __launch_bounds__(SUB_BS, 2) void k_subcell(const Tables *__restrict_
                     const int sl = nslot[k][side];
                     if (sl >= 0) {
                         // the neighbour's subcell layer facing this cell
-                        int mp[2] = {sp % NS, sp / NS}, idx = 0, j2 = 0, L[3];
-                        for (int j = 0; j < DIM; j++) L[j] = (j == k) ? (side ? 0 : NS - 1) : mp[j2++];
-                        for (int j = DIM - 1; j >= 0; j--) idx = idx * NS + L[j];
+                        const int mp0 = sp % NS, mp1 = sp / NS;
+                        int idx = 0;
+#pragma unroll
+                        for (int j = DIM - 1; j >= 0; j--)
+                            idx = idx * NS + ((j == k) ? (side ? 0 : NS - 1) : ((j < k ? j : j - 1) == 0 ? mp0 : mp1));
                         any |= B.mflag[(int64_t)sl * NSUB + idx];
                     }
                 }
@@ -1448,8 +1471,10 @@ __global__ __launch_bounds__(128) void k_fluxcorr(const Tables *__restrict__ T, 
         const int v = it / NN, a = it % NN;
         int m[3] = {a % n, (a / n) % n, a / (n * n)};
         double val = B.u[cur ^ 1][((int64_t)v * P.ncell + c) * NN + a];
+#pragma unroll
         for (int k = 0; k < DIM; k++) {
             int ap = 0, mul = 1;
+#pragma unroll
             for (int j = 0; j < DIM; j++) {
                 if (j == k) continue;
                 ap += m[j] * mul;
@@ -1463,13 +1488,13 @@ __global__ __launch_bounds__(128) void k_fluxcorr(const Tables *__restrict__ T, 
                 const double *fs = B.sflux + ((int64_t)slot * 2 * DIM + 2 * k + (1 - side)) * NV * NSF + v * NSF;
                 double Fsub = 0.0;
                 for (int sp = 0; sp < NSF; sp++) {
-                    int ms[2] = {sp % NS, sp / NS};
+                    // tangential subcell coordinates: sp % NS on the first axis, sp / NS on the second
+                    const int ms0 = sp % NS, ms1 = sp / NS;
                     double wgt = 1.0;
-                    int j2 = 0;
+#pragma unroll
                     for (int j = 0; j < DIM; j++) {
                         if (j == k) continue;
-                        wgt *= T->Pt[ms[j2]][m[j]];
-                        j2++;
+                        wgt *= T->Pt[(j < k ? j : j - 1) == 0 ? ms0 : ms1][m[j]];
                     }
                     Fsub += wgt * fs[sp];
                 }

@@ -102,16 +102,29 @@ def prim_to_cons(gamma: float, rho, vel: Sequence, p) -> list:
 
 def sample_grid(ic: Callable, axes: Sequence[np.ndarray], t: float = 0.0) -> np.ndarray:
     """Evaluate ``ic`` on the tensor grid spanned by the per-axis coordinates ``axes``
-    (x fastest in the result).  Returns float64 [nv][...z, y, x] flattened per variable."""
+    (x fastest in the result).  Returns float64 [nv][...z, y, x] flattened per variable.
+    The grid is evaluated in slabs along the slowest axis (``ic`` acts point by point), so
+    the temporaries stay small next to the result."""
     d = len(axes)
-    mesh = []
-    for k, a in enumerate(axes):
-        shape = [1] * d
-        shape[d - 1 - k] = len(a)
-        mesh.append(np.asarray(a, dtype=np.float64).reshape(shape))
-    vals = ic(mesh, t)
-    full = np.broadcast_shapes(*[np.shape(m) for m in mesh])
-    return np.stack([np.broadcast_to(np.asarray(v, dtype=np.float64), full).ravel() for v in vals])
+    axes = [np.asarray(a, dtype=np.float64) for a in axes]
+    sizes = [len(a) for a in axes]
+    per_slab = int(np.prod(sizes[:-1]))
+    slab = max(1, min(sizes[-1], (1 << 22) // max(per_slab, 1)))
+    out = None
+    for z0 in range(0, sizes[-1], slab):
+        z1 = min(sizes[-1], z0 + slab)
+        mesh = []
+        for k, a in enumerate(axes):
+            shape = [1] * d
+            shape[d - 1 - k] = len(a) if k < d - 1 else z1 - z0
+            mesh.append((a if k < d - 1 else a[z0:z1]).reshape(shape))
+        vals = ic(mesh, t)
+        full = np.broadcast_shapes(*[np.shape(m) for m in mesh])
+        if out is None:
+            out = np.empty((len(vals), int(np.prod(sizes))))
+        for v, val in enumerate(vals):
+            out[v, z0 * per_slab:z1 * per_slab] = np.broadcast_to(np.asarray(val, dtype=np.float64), full).ravel()
+    return out
 
 
 # ----------------------------------------------------------------- explosions

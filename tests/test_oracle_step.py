@@ -424,3 +424,38 @@ def test_osher_scheme_contact_wave_and_conservation():
         o.step(o.cfl_dt())
         assert np.abs(totals(o) - m0).max() < 1e-13 * np.abs(m0).max()
     assert np.isfinite(o.state()).all()
+
+
+def test_one_step_depends_on_two_cells_around():
+    """Locality of one limited step (Sec. 4: the detection of a cell needs its candidate and
+    the old data of its 3^d block; a troubled cell's subcell scheme needs its neighbours'
+    old data; an unlimited cell's faces need the troubled status of its face neighbours):
+    a box cut out of a larger grid, stepped with its own transmissive sides, agrees exactly
+    with the larger grid on every cell at least three cells inside the box.  The 3D
+    explosion at full size is checked on the GPU through such boxes."""
+    nc, N, wn, origin = 18, 3, 12, (6, 3, 3)
+    h = 2.0 / nc
+    dt = W.stable_cfl(N) * h / (3 * (2 * N + 1) * math.sqrt(1.4))
+
+    def stepped(wl):
+        o = O.Oracle(wl)
+        o.set_state(o.project(wl.ic, 0)[0], o.project(wl.ic, 1)[1])
+        o.step(dt)
+        return o
+
+    full = stepped(W.explosion_3d(nc, N))
+    lo = tuple(-1.0 + i * h for i in origin)
+    bc = (W.BC.simple(W.TRANSMISSIVE), W.BC.simple(W.TRANSMISSIVE))
+    box = stepped(W.Workload("box", 3, N, (wn,) * 3, lo, tuple(x + wn * h for x in lo), [bc] * 3, W.explosion_ic(3)))
+    i = np.arange(wn)
+    z, y, x = np.meshgrid(i + origin[2], i + origin[1], i + origin[0], indexing="ij")
+    cells = (x + nc * (y + nc * z)).ravel()
+    for depth, exact in ((0, False), (3, True)):
+        ok = (i >= depth) & (i < wn - depth)
+        m = (ok[:, None, None] & ok[None, :, None] & ok[None, None, :]).ravel()
+        same = np.array_equal(box.state()[:, m], full.state()[:, cells[m]]) and \
+            np.array_equal(box.troubled()[m], full.troubled()[cells[m]])
+        assert same == exact
+    ok = (i >= 3) & (i < wn - 3)
+    m = (ok[:, None, None] & ok[None, :, None] & ok[None, None, :]).ravel()
+    assert box.troubled()[m].sum() > 0

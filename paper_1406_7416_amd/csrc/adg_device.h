@@ -154,15 +154,16 @@ __device__ __forceinline__ void bc_ghost(const Prob &P, int k, int side, const d
         const double xs = b.split_axis == 0 ? x0 : (b.split_axis == 1 ? x1 : x2);
         which = (xs < b.split0 + b.split_speed * t) ? 0 : 1;
     }
+    // value selections only: a branch per kind would merge pointers into the kernel
+    // argument and into the caller's arrays, which moves both to scratch memory
     const int kind = b.kind[which];
-    if (kind == ADG_DIRICHLET) {
+    const bool dir = kind == ADG_DIRICHLET, refl = kind == ADG_REFLECTIVE;
 #pragma unroll
-        for (int v = 0; v < NV; v++) qout[v] = b.state[which][v];
-        return;
+    for (int v = 0; v < NV; v++) {
+        const double st = which ? b.state[1][v] : b.state[0][v];
+        const double in = (refl && v == 1 + k) ? -qin[v] : qin[v];
+        qout[v] = dir ? st : in;
     }
-    const bool refl = kind == ADG_REFLECTIVE;
-#pragma unroll
-    for (int v = 0; v < NV; v++) qout[v] = (refl && v == 1 + k) ? -qin[v] : qin[v];
 }
 
 __device__ __forceinline__ int64_t cell_of(const Prob &P, const int *ci) {

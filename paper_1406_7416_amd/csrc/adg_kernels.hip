@@ -574,13 +574,16 @@ __global__ __launch_bounds__(128) void k_cell_bounds(const Tables *__restrict__ 
 #pragma unroll
         for (int v = 0; v < NV; v++) q[v] = vs[v * NSUB + sidx];
         double x[3] = {0, 0, 0};
-        for (int j = 0; j < DIM; j++) x[j] = P.lo[j] + P.h[j] * (ei[j] + (gs[j] + 0.5) / NS);
-        for (int j = 0; j < DIM; j++) {
-            if (gside[j] < 0) continue;
-            double qo[NV];
-            bc_ghost<DIM>(P, j, gside[j], q, x[0], x[1], x[2], t0, qo);
 #pragma unroll
-            for (int v = 0; v < NV; v++) q[v] = qo[v];
+        for (int j = 0; j < DIM; j++) x[j] = P.lo[j] + P.h[j] * (ei[j] + (gs[j] + 0.5) / NS);
+#pragma unroll
+        for (int j = 0; j < DIM; j++) {
+            if (gside[j] >= 0) {
+                double qo[NV];
+                bc_ghost<DIM>(P, j, gside[j], q, x[0], x[1], x[2], t0, qo);
+#pragma unroll
+                for (int v = 0; v < NV; v++) q[v] = qo[v];
+            }
         }
 #pragma unroll
         for (int v = 0; v < NV; v++) {
@@ -985,11 +988,17 @@ __device__ __forceinline__ void sub_update_cell(const Tables *__restrict__ T, co
             if (P.periodic[k] || (nb >= 0 && nb < P.nc[k])) nbex |= 1 << (2 * k + side);
         }
     // sub-faces of all axes in one range (threads stay busy for small Ns); the body is
-    // instantiated per axis (compile-time k: no dynamic indexing of per-thread arrays)
-    for (int it = threadIdx.x; it < DIM * (NS + 1) * NSF; it += SUB_BS) {
+    // instantiated per axis (compile-time k: no dynamic indexing of per-thread arrays).
+    // Each axis's range is padded to whole waves (no wave runs two axes' bodies) unless
+    // that would take more rounds of the workgroup.
+    constexpr int PA = (NS + 1) * NSF, PA64 = (PA + 63) / 64 * 64;
+    constexpr int STRIDE = (DIM * PA64 + SUB_BS - 1) / SUB_BS <= (DIM * PA + SUB_BS - 1) / SUB_BS ? PA64 : PA;
+    for (int i0 = threadIdx.x; i0 < DIM * STRIDE; i0 += SUB_BS) {
+        const int kk = i0 / STRIDE, it2 = i0 % STRIDE;
+        if (it2 >= PA) continue;
+        const int it = kk * PA + it2;   // sub-face index: axis-major, then face, then tangential
         auto subface = [&](auto kc) {
             constexpr int k = decltype(kc)::value;
-            const int it2 = it - k * (NS + 1) * NSF;
             const int f = it2 / NSF;
             const int sp = it2 % NSF;
             // subcell coordinate along axis j of the sub-face's tangential position (j != k):
@@ -1104,7 +1113,6 @@ __device__ __forceinline__ void sub_update_cell(const Tables *__restrict__ T, co
 #pragma unroll
             for (int v = 0; v < NV; v++) Fb[it * NV + v] = Fbar[v];
         };
-        const int kk = it / ((NS + 1) * NSF);
         if (kk == 0) subface(std::integral_constant<int, 0>{});
         else if (kk == 1) subface(std::integral_constant<int, 1>{});
         else subface(std::integral_constant<int, DIM - 1>{});

@@ -32,9 +32,9 @@ PEAK_HBM_GBS = 8000.0
 # FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (the factors that make a plain 256 MiB copy read its
 # own size), taken on the predictor source (the files below, concatenated) whose SHA-256 starts
 # with the prefix below; reported as null once that source has changed.
-PREDICTOR_SOURCES = ("adg_internal.h", "adg_device.h", "adg_predictor.h")
-PREDICTOR_TRAFFIC_BYTES = 84526924
-PREDICTOR_TRAFFIC_SOURCE = "e8d20c60c382cf6b"
+PREDICTOR_SOURCES = ("adg_internal.h", "adg_physics.h", "adg_predictor.h")
+PREDICTOR_TRAFFIC_BYTES = 86733995
+PREDICTOR_TRAFFIC_SOURCE = "e4f91cbc9d995a98"
 
 
 def predictor_flops_per_cell(d: int, N: int) -> float:

@@ -24,6 +24,7 @@ struct Tables {
     double xi3[3], w3[3];
     double D3[MAXN][MAXN], L3[MAXN], R3[MAXN], Kw3[MAXN][MAXN];
     double weno[3][3][3];        // [stencil][monomial][cell]: averages -> coefficients
+    float fweno[3][3][3];        // the same in FP32 (mixed form)
     // Even / odd parts of D on the symmetric nodes, where D[n-1-a][n-1-b] = -D[a][b]:
     //   DE[a][b] = (D[a][b] + D[a][n-1-b]) / 2,  DO[a][b] = (D[a][b] - D[a][n-1-b]) / 2
     // for a, b < n/2; odd n adds DE[a][n/2] = D[a][n/2] and the middle row DO[n/2][b] = D[n/2][b].

@@ -1,6 +1,6 @@
 // Local space-time predictor (a point-owner / line-owner LDS design, see below).
 #pragma once
-#include "adg_device.h"
+#include "adg_physics.h"
 
 namespace adg {
 
@@ -203,19 +203,16 @@ __device__ void pred_cells(const PredArgs<R> &A, double gamma_d, int64_t ncell, 
     const int64_t c = vb * CPB + lc;
     const bool owner = (tid < S::ACT) && (c < ncell);
 
-    double u0d[NV];
     R u0[NV], q[NV][n], Sacc[NV][n];
     if (owner) {
 #pragma unroll
-        for (int v = 0; v < NV; v++) u0d[v] = A.in[c * A.in_cstride + v * A.in_vstride + a];
+        for (int v = 0; v < NV; v++) u0[v] = (R)A.in[c * A.in_cstride + v * A.in_vstride + a];
     } else {
         // idle lanes carry a valid constant state so that they never produce NaN
 #pragma unroll
-        for (int v = 0; v < NV; v++) u0d[v] = (v == 0) ? 1.0 : 0.0;
-        u0d[NV - 1] = 2.5;
+        for (int v = 0; v < NV; v++) u0[v] = (v == 0) ? R(1) : R(0);
+        u0[NV - 1] = R(2.5);
     }
-#pragma unroll
-    for (int v = 0; v < NV; v++) u0[v] = (R)u0d[v];
 #pragma unroll
     for (int v = 0; v < NV; v++)
 #pragma unroll
@@ -337,9 +334,11 @@ __device__ void pred_cells(const PredArgs<R> &A, double gamma_d, int64_t ncell, 
             }
         }
         if (owner) {
+            // u^n is read again here rather than held in registers through the sweeps
 #pragma unroll
             for (int v = 0; v < NV; v++)
-                A.vol_out[(A.cell0 + c) * NN + (int64_t)v * A.in_vstride + a] = u0d[v] + (double)vol[v];
+                A.vol_out[(A.cell0 + c) * NN + (int64_t)v * A.in_vstride + a] =
+                    A.in[c * A.in_cstride + v * A.in_vstride + a] + (double)vol[v];
         }
     }
 

@@ -228,7 +228,10 @@ void build_tables(int N, int Ns, Tables *T) {
         }
         lu_solve(3, A, Bm, 3);
         for (int p = 0; p < 3; p++)
-            for (int j = 0; j < 3; j++) T->weno[st][p][j] = Bm[p * 3 + j];
+            for (int j = 0; j < 3; j++) {
+                T->weno[st][p][j] = Bm[p * 3 + j];
+                T->fweno[st][p][j] = (float)Bm[p * 3 + j];
+            }
     }
 }
 

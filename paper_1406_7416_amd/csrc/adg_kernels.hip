@@ -876,10 +876,50 @@ __device__ __forceinline__ void weno3(const Tables *__restrict__ T, const double
     }
 }
 
+// FP32 variant (mixed form): the same weights, each scaled by (sigma_min + eps)^8, i.e.
+// lambda_k ((sigma_min + eps) / (sigma_k + eps))^8 before normalisation, so that they stay in
+// FP32 range (the unscaled (sigma + eps)^-8 overflows for eps = 1e-14); reciprocals by the
+// hardware reciprocal.
+__device__ __forceinline__ void weno3(const Tables *__restrict__ T, const float *a, float *out) {
+    float c[3][3], sg[3];
+    const float lam[3] = {1.0f, 1.0e5f, 1.0f};
+#pragma unroll
+    for (int st = 0; st < 3; st++) {
+#pragma unroll
+        for (int p = 0; p < 3; p++) {
+            float acc = 0.0f;
+#pragma unroll
+            for (int m = 0; m < 3; m++) acc += T->fweno[st][p][m] * a[st + m];
+            c[st][p] = acc;
+        }
+        sg[st] = c[st][1] * c[st][1] + 2.0f * c[st][1] * c[st][2] + (16.0f / 3.0f) * c[st][2] * c[st][2] + 1e-14f;
+    }
+    const float smin = fminf(sg[0], fminf(sg[1], sg[2]));
+    float wt[3], sum = 0.0f;
+#pragma unroll
+    for (int st = 0; st < 3; st++) {
+        float r = smin * __builtin_amdgcn_rcpf(sg[st]);
+        r = r * r;
+        r = r * r;
+        r = r * r;
+        wt[st] = lam[st] * r;
+        sum += wt[st];
+    }
+    const float isum = __builtin_amdgcn_rcpf(sum);
+#pragma unroll
+    for (int qn = 0; qn < 3; qn++) {
+        const float x = T->fxi3[qn];
+        float acc = 0.0f;
+#pragma unroll
+        for (int st = 0; st < 3; st++) acc += (wt[st] * isum) * (c[st][0] + c[st][1] * x + c[st][2] * x * x);
+        out[qn] = acc;
+    }
+}
+
 // S2: dimension-by-dimension WENO3 reconstruction at every position -> nodal values at
 // the 3^d GL points of the subcell (x sweep on the averages, then y (then z) sweeps on
 // the nodal values of the previous sweep).  One work item per (position, variable).
-template <int DIM, int N>
+template <int DIM, int N, typename R>
 __device__ __forceinline__ void sub_recon_cell(const Tables *__restrict__ T, const Bufs &B, int sidx, const double *halo) {
     constexpr int NV = DIM + 2, NS = 2 * N + 1, HN = NS + 6, HSZ = cpow(HN, DIM);
     constexpr int NPOS = cpow(NS, DIM) + 2 * DIM * cpow(NS, DIM - 1), N3 = cpow(3, DIM);
@@ -888,20 +928,20 @@ __device__ __forceinline__ void sub_recon_cell(const Tables *__restrict__ T, con
         int L[3];
         position_coords<DIM>(pos, NS, L);
         const double *h = halo + v * HSZ;
-        double *Y = B.Y + ((int64_t)sidx * NPOS + pos) * NV * N3 + v * N3;
+        R *Y = reinterpret_cast<R *>(B.Y) + ((int64_t)sidx * NPOS + pos) * NV * N3 + v * N3;
         if constexpr (DIM == 2) {
             // x sweep on the five rows of the 5 x 5 stencil, then y sweep per x node
-            double w1[5][3];
+            R w1[5][3];
 #pragma unroll
             for (int r = 0; r < 5; r++) {
-                double a5[5];
+                R a5[5];
 #pragma unroll
-                for (int o = 0; o < 5; o++) a5[o] = h[(L[1] + r + 1) * HN + (L[0] + o + 1)];
+                for (int o = 0; o < 5; o++) a5[o] = (R)h[(L[1] + r + 1) * HN + (L[0] + o + 1)];
                 weno3(T, a5, w1[r]);
             }
 #pragma unroll
             for (int qx = 0; qx < 3; qx++) {
-                double a5[5], o3[3];
+                R a5[5], o3[3];
 #pragma unroll
                 for (int r = 0; r < 5; r++) a5[r] = w1[r][qx];
                 weno3(T, a5, o3);
@@ -911,20 +951,20 @@ __device__ __forceinline__ void sub_recon_cell(const Tables *__restrict__ T, con
         } else {
             // plane by plane in z: x sweep on the five rows of the plane, y sweep per x node;
             // then the z sweep per (y node, x node)
-            double w2[5][3][3];   // [z][qy][qx]
+            R w2[5][3][3];   // [z][qy][qx]
 #pragma unroll
             for (int z = 0; z < 5; z++) {
-                double w1[5][3];
+                R w1[5][3];
 #pragma unroll
                 for (int y = 0; y < 5; y++) {
-                    double a5[5];
+                    R a5[5];
 #pragma unroll
-                    for (int o = 0; o < 5; o++) a5[o] = h[((L[2] + z + 1) * HN + (L[1] + y + 1)) * HN + (L[0] + o + 1)];
+                    for (int o = 0; o < 5; o++) a5[o] = (R)h[((L[2] + z + 1) * HN + (L[1] + y + 1)) * HN + (L[0] + o + 1)];
                     weno3(T, a5, w1[y]);
                 }
 #pragma unroll
                 for (int qx = 0; qx < 3; qx++) {
-                    double a5[5], o3[3];
+                    R a5[5], o3[3];
 #pragma unroll
                     for (int y = 0; y < 5; y++) a5[y] = w1[y][qx];
                     weno3(T, a5, o3);
@@ -936,7 +976,7 @@ __device__ __forceinline__ void sub_recon_cell(const Tables *__restrict__ T, con
             for (int qy = 0; qy < 3; qy++)
 #pragma unroll
                 for (int qx = 0; qx < 3; qx++) {
-                    double a5[5], o3[3];
+                    R a5[5], o3[3];
 #pragma unroll
                     for (int z = 0; z < 5; z++) a5[z] = w2[z][qy][qx];
                     weno3(T, a5, o3);
@@ -1188,7 +1228,7 @@ __device__ __forceinline__ void sub_update_cell(const Tables *__restrict__ T, co
 // Output: the face traces of every position, [pos][2d][v][3^(d-1) tangential x 3 time],
 // in the working precision R (FP32 in the mixed form).
 template <int DIM, typename R>
-__device__ void sub_predictor(const Tables *__restrict__ T, const double *__restrict__ Y, R *__restrict__ tr,
+__device__ void sub_predictor(const Tables *__restrict__ T, const R *__restrict__ Y, R *__restrict__ tr,
                               int npos, double dt, const double *dth, double gamma_d) {
     constexpr int NV = DIM + 2, NN = cpow(3, DIM), NF = cpow(3, DIM - 1), PPW = 64 / NN;
     constexpr int TRS = 2 * DIM * NV * NF * 3;
@@ -1322,8 +1362,8 @@ __device__ void sub_predictor(const Tables *__restrict__ T, const double *__rest
 // troubled cell and runs its halo (eq. (ader.icbc)), WENO3 reconstruction, degree-2
 // space-time predictor, sub-face fluxes, FV update and gather, using its own scratch
 // slot (blockIdx.x), so the scratch scales with the grid, not with the worklist.
-// R: working precision of the degree-2 predictor and the sub-face fluxes (FP32 in the mixed
-// form); halo, WENO3, FV update, gather and pool stay FP64.  flagging: also flag the WENO3
+// R: working precision of the WENO3 reconstruction, the degree-2 predictor and the sub-face
+// fluxes (FP32 in the mixed form); halo, FV update, gather and pool stay FP64.  flagging: also flag the WENO3
 // result for the MOOD layer; REDO: the MOOD layer's recompute (only cells with a flag on or
 // next to their sub-faces).
 template <int DIM, int N, typename R, bool REDO>
@@ -1337,7 +1377,7 @@ __global__ __launch_bounds__(SUB_BS, 2) void k_subcell(const Tables *__restrict_
     const double dt = B.scal[0];
     double dth[3] = {0.0, 0.0, 0.0};
     for (int k = 0; k < DIM; k++) dth[k] = (double)NS / P.h[k];
-    const double *Ys = B.Y + (int64_t)sidx * NPOS * NV * N3;
+    const R *Ys = reinterpret_cast<const R *>(B.Y) + (int64_t)sidx * NPOS * NV * N3;
     R *trs = reinterpret_cast<R *>(B.strace) + (int64_t)sidx * NPOS * TRS;
     // 2D: the halo and the source cells' coefficients live in LDS; 3D: halo in HBM scratch
     constexpr int HSZ = cpow(NS + 6, DIM), NNS = cpow(N + 1, DIM);
@@ -1422,7 +1462,7 @@ __global__ __launch_bounds__(SUB_BS, 2) void k_subcell(const Tables *__restrict_
         }
         sub_halo_cell<DIM, N>(T, P, B, cur, w, halo, nbu);
         __syncthreads();
-        sub_recon_cell<DIM, N>(T, B, sidx, halo);
+        sub_recon_cell<DIM, N, R>(T, B, sidx, halo);
         __syncthreads();
         sub_predictor<DIM, R>(T, Ys, trs, NPOS, dt, dth, P.gamma);
         __syncthreads();

@@ -1238,13 +1238,21 @@ __device__ void sub_predictor(const Tables *__restrict__ T, const R *__restrict_
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const int slot = lane / NN, a = lane % NN;
     const int ia[3] = {a % 3, (a / 3) % 3, a / 9};
-    // this lane's rows of the derivative matrix, per axis, and dt/h_k
+    // Along each axis a lane needs the values of the two other nodes of its line: it reads
+    // them from the lanes of line nodes (ia + 1) % 3 and (ia + 2) % 3 (two lane permutations
+    // per value; its own node's value it has).  Dk[k][j]: this lane's derivative-matrix row
+    // in that order (own node first); src1/src2: the two source lanes.
     R Dk[DIM][3], ck[DIM];
+    int src1[DIM], src2[DIM];
 #pragma unroll
     for (int k = 0; k < DIM; k++) {
         ck[k] = (R)(dt * dth[k]);
-#pragma unroll
-        for (int b = 0; b < 3; b++) Dk[k][b] = F32 ? (R)T->fD3[ia[k]][b] : (R)T->D3[ia[k]][b];
+        const int r = ia[k], n1 = (r + 1) % 3, n2 = (r + 2) % 3;
+        Dk[k][0] = F32 ? (R)T->fD3[r][r] : (R)T->D3[r][r];
+        Dk[k][1] = F32 ? (R)T->fD3[r][n1] : (R)T->D3[r][n1];
+        Dk[k][2] = F32 ? (R)T->fD3[r][n2] : (R)T->D3[r][n2];
+        src1[k] = lane + (n1 - r) * ST[k];
+        src2[k] = lane + (n2 - r) * ST[k];
     }
     for (int base = wv * PPW; base < npos; base += nw * PPW) {
         const int pos = base + slot;
@@ -1281,20 +1289,20 @@ __device__ void sub_predictor(const Tables *__restrict__ T, const R *__restrict_
                     for (int j = 0; j < DIM; j++) F[1 + j][t] = q[1 + j][t] * un + (j == k ? prt : R(0));
                     F[NV - 1][t] = un * (q[NV - 1][t] + prt);
                 }
-                // sum_b D[a_k][b] F(node b of the line), b ascending
-                R x[NV][3];
+                // sum_b D[a_k][b] F(node b of the line): own node, then (ia + 1) % 3, (ia + 2) % 3
+                // all lane permutations of the axis first (independent, in flight together)
+                R g1[NV][3], g2[NV][3], x[NV][3];
 #pragma unroll
                 for (int v = 0; v < NV; v++)
 #pragma unroll
-                    for (int t = 0; t < 3; t++) x[v][t] = 0;
+                    for (int t = 0; t < 3; t++) {
+                        g1[v][t] = __shfl(F[v][t], src1[k]);
+                        g2[v][t] = __shfl(F[v][t], src2[k]);
+                    }
 #pragma unroll
-                for (int b = 0; b < 3; b++) {
-                    const int src = lane + (b - ia[k]) * ST[k];
+                for (int v = 0; v < NV; v++)
 #pragma unroll
-                    for (int v = 0; v < NV; v++)
-#pragma unroll
-                        for (int t = 0; t < 3; t++) x[v][t] += Dk[k][b] * __shfl(F[v][t], src);
-                }
+                    for (int t = 0; t < 3; t++) x[v][t] = Dk[k][0] * F[v][t] + Dk[k][1] * g1[v][t] + Dk[k][2] * g2[v][t];
 #pragma unroll
                 for (int v = 0; v < NV; v++)
 #pragma unroll
@@ -1320,21 +1328,23 @@ __device__ void sub_predictor(const Tables *__restrict__ T, const R *__restrict_
         // at the high end the xi_k = 1 trace
 #pragma unroll
         for (int k = 0; k < DIM; k++) {
+            // the line's three nodes in this lane's order: own, (ia + 1) % 3, (ia + 2) % 3
             R qb[3][NV][3];
 #pragma unroll
-            for (int b = 0; b < 3; b++) {
-                const int src = lane + (b - ia[k]) * ST[k];
+            for (int v = 0; v < NV; v++)
 #pragma unroll
-                for (int v = 0; v < NV; v++)
-#pragma unroll
-                    for (int s = 0; s < 3; s++) qb[b][v][s] = __shfl(q[v][s], src);
-            }
+                for (int s = 0; s < 3; s++) {
+                    qb[0][v][s] = q[v][s];
+                    qb[1][v][s] = __shfl(q[v][s], src1[k]);
+                    qb[2][v][s] = __shfl(q[v][s], src2[k]);
+                }
             if (valid && ia[k] != 1) {
                 const int side = ia[k] == 2;
+                const int r = ia[k], nb[3] = {r, (r + 1) % 3, (r + 2) % 3};
                 R Bv[3];
 #pragma unroll
                 for (int b = 0; b < 3; b++)
-                    Bv[b] = F32 ? (R)(side ? T->fR3[b] : T->fL3[b]) : (R)(side ? T->R3[b] : T->L3[b]);
+                    Bv[b] = F32 ? (R)(side ? T->fR3[nb[b]] : T->fL3[nb[b]]) : (R)(side ? T->R3[nb[b]] : T->L3[nb[b]]);
                 int ap = 0, mul = 1;
 #pragma unroll
                 for (int j = 0; j < DIM; j++) {

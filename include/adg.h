@@ -116,13 +116,16 @@ int adg_axis_points(const adg_problem *pb, int axis, int m, double *out);
 /* Host-side projection of samples taken on the tensor grid of adg_axis_points(m):
  * samples[var][z][y][x].  m = 0: nodal interpolation (u only).  m > 0: L2 projection
  * onto the DG basis by the composite m-point rule on every subcell, and (if v != NULL)
- * the subcell averages of the samples.  u, v: host, state / subcell layouts. */
+ * the subcell averages of the samples.  u, v: host, state / subcell layouts.  Runs on
+ * host threads (OMP_NUM_THREADS if set, else the hardware's, at most 16). */
 int adg_project_samples(const adg_problem *pb, const double *samples, int m, double *u, double *v);
 
 /* Sets the DG state u (layout above; device pointer if on_device, else host) and time 0.
  * If v_exact (host, subcell layout) is given, applies the initial detection of Sec. 4.4:
  * PAD + DMP of P(u) against the bounds of v_exact over each cell's neighbourhood;
- * troubled cells start from v_exact and u := R(v_exact).  Synchronising. */
+ * troubled cells start from v_exact and u := R(v_exact).  The detection runs on host
+ * threads like adg_project_samples; the pool must hold every cell it flags
+ * (ADG_ECAPACITY otherwise).  Synchronising. */
 int adg_set_state(adg_problem *pb, const double *u, int on_device, const double *v_exact);
 
 /* Copies the DG state out (device pointer if to_device).  Synchronising for host copies. */

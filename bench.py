@@ -33,7 +33,7 @@ PEAK_HBM_GBS = 8000.0
 # own size), taken on the predictor source (the files below, concatenated) whose SHA-256 starts
 # with the prefix below; reported as null once that source has changed.
 PREDICTOR_SOURCES = ("adg_internal.h", "adg_physics.h", "adg_predictor.h")
-PREDICTOR_TRAFFIC_BYTES = 86733995
+PREDICTOR_TRAFFIC_BYTES = 86605232
 PREDICTOR_TRAFFIC_SOURCE = "e4f91cbc9d995a98"
 
 

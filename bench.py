@@ -216,6 +216,10 @@ def main():
             "avg_launch_us": h["predictor_avg_us"],
         },
         "forms": forms,
+        # memory-bound kernel of the step against a measured copy bandwidth: the face fluxes
+        # read every cell's face traces once and write one time-integrated flux per face node
+        # and adjacent cell (FP32 in the mixed form)
+        "memory_bound": face_bandwidth(wl, forms["mixed"]["kernels"]["faces"]["avg_us"]),
         "speedup_mixed_vs_fp64": forms["mixed"]["value"] / forms["fp64"]["value"],
         "speedup_mixed_vs_fp64_osher": forms["mixed_osher"]["value"] / forms["fp64_osher"]["value"],
         "rho_mixed_minus_fp64": {"max": float(drho.max()), "mean": float(drho.mean())},
@@ -284,6 +288,8 @@ def explosion3d_measurement(steps, warmup=2, breakdown=2, ncell=128, N=3):
             "predictor_tflops": predictor_flops_per_cell(3, N) * wl.num_cells / pred_s / 1e12,
             "kernels": {g: {"ms_total": round(ms, 4), "launches": n, "avg_us": round(1e3 * ms / n, 3) if n else None}
                         for g, (ms, n) in prof.items()},
+            "face_kernel_gbs": (wl.num_cells * 2 * 3 * 5 * ((N + 1) ** 3 + (N + 1) ** 2) * (4 if prec == adg.ADG_MIXED else 8)
+                                / (prof["faces"][0] * 1e-3 / max(1, prof["faces"][1])) / 1e9) if prof["faces"][1] else None,
             "troubled_initial": troubled0,
             "troubled_last_step": prob.stats()["troubled"],
             "t_simulated": prob.time,
@@ -295,6 +301,35 @@ def explosion3d_measurement(steps, warmup=2, breakdown=2, ncell=128, N=3):
               f"troubled {res[form]['troubled_last_step']}", file=sys.stderr, flush=True)
     res["speedup_mixed_vs_fp64"] = res["mixed"]["value"] / res["fp64"]["value"]
     return res
+
+
+def copy_bandwidth_gbs(nbytes=1 << 30, reps=5):
+    """Device-to-device copy of nbytes (read + write counted), HIP events around `reps`
+    copies: the achievable HBM bandwidth the memory-bound kernels are compared with."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2.0 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return gbs
+
+
+def face_bandwidth(wl, avg_us):
+    d, n, nv = wl.dim, wl.N + 1, wl.dim + 2
+    nbytes = wl.num_cells * 2 * d * nv * (n ** d + n ** (d - 1)) * 4
+    copy = copy_bandwidth_gbs()
+    gbs = nbytes / (avg_us * 1e-6) / 1e9
+    return {"kernel": "k_face (mixed form)", "algorithmic_bytes": nbytes, "avg_launch_us": avg_us,
+            "achieved_gbs": gbs, "copy_gbs_measured": copy, "frac_of_copy": gbs / copy,
+            "frac_of_peak": gbs / PEAK_HBM_GBS}
 
 
 def batch_measurement(count, steps):

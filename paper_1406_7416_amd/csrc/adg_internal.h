@@ -80,7 +80,7 @@ struct Bufs {
     int64_t *ring;         // extended-grid indices of the ghost ring
     // subcell chunk scratch
     double *halo;          // [chunk][v][(Ns+6)^d]
-    double *Y;             // [chunk][pos][v][3^d]
+    double *Y;             // [chunk][pos][v][3^d] reconstructed nodal values (float in the mixed form)
     double *strace;        // [chunk][pos][2d][v][3^(d-1)*3]
 };
 

@@ -222,10 +222,16 @@ __device__ void pred_cells(const PredArgs<R> &A, double gamma_d, int64_t ncell, 
         // 1/rho of every node of the pencil, shared by the fluxes of all axes (for long
         // FP64 pencils recomputed per axis instead, to stay within 256 registers)
         constexpr bool CACHE_IRHO = n < 8 || sizeof(R) == 4;
-        R irho[CACHE_IRHO ? n : 1];
+        R irho[CACHE_IRHO ? n : 1], pr[CACHE_IRHO ? n : 1];
         if constexpr (CACHE_IRHO) {
 #pragma unroll
-            for (int t = 0; t < n; t++) irho[t] = recip(q[0][t]);
+            for (int t = 0; t < n; t++) {
+                irho[t] = recip(q[0][t]);
+                R ke = 0;
+#pragma unroll
+                for (int j = 0; j < DIM; j++) ke += q[1 + j][t] * q[1 + j][t];
+                pr[t] = (gamma - R(1)) * (q[NV - 1][t] - R(0.5) * ke * irho[t]);
+            }
         }
 #pragma unroll
         for (int k = 0; k < DIM; k++) {
@@ -239,10 +245,14 @@ __device__ void pred_cells(const PredArgs<R> &A, double gamma_d, int64_t ncell, 
                         if constexpr (CACHE_IRHO) ir = irho[t];
                         else ir = recip(q[0][t]);
                         const R un = q[1 + k][t] * ir;
-                        R ke = 0;
+                        R prt;
+                        if constexpr (CACHE_IRHO) prt = pr[t];
+                        else {
+                            R ke = 0;
 #pragma unroll
-                        for (int j = 0; j < DIM; j++) ke += q[1 + j][t] * q[1 + j][t];
-                        const R prt = (gamma - R(1)) * (q[NV - 1][t] - R(0.5) * ke * ir);
+                            for (int j = 0; j < DIM; j++) ke += q[1 + j][t] * q[1 + j][t];
+                            prt = (gamma - R(1)) * (q[NV - 1][t] - R(0.5) * ke * ir);
+                        }
                         R F[NV];
                         F[0] = q[1 + k][t];
 #pragma unroll

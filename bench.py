@@ -33,7 +33,7 @@ PEAK_HBM_GBS = 8000.0
 # own size), taken on the predictor source (the files below, concatenated) whose SHA-256 starts
 # with the prefix below; reported as null once that source has changed.
 PREDICTOR_SOURCES = ("adg_internal.h", "adg_physics.h", "adg_predictor.h")
-PREDICTOR_TRAFFIC_BYTES = 86015315
+PREDICTOR_TRAFFIC_BYTES = 86021798
 PREDICTOR_TRAFFIC_SOURCE = "09aa0e2b73ff9b3c"
 
 
@@ -91,6 +91,7 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=20)
     ap.add_argument("--no-3d", action="store_true", help="skip the 3D explosion measurement (128^3, N=3)")
     ap.add_argument("--steps-3d", type=int, default=6)
+    ap.add_argument("--no-small", action="store_true", help="skip the 2D explosion and double Mach measurements")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device-to-device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -234,11 +235,46 @@ def main():
     if not args.no_3d:
         out["explosion3d"] = explosion3d_measurement(args.steps_3d)
 
+    if not args.no_small:
+        # the two other 2D workloads: the 2D explosion (40 x 40, N = 3) and the double Mach
+        # reflection at its full size (400 x 100, N = 5)
+        out["explosion2d"] = form_pair_measurement(W.explosion_2d(40, 3), 4, steps=50)
+        out["double_mach"] = form_pair_measurement(W.double_mach(400, 100, 5), 1, steps=20)
+
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, u0, args.cpu_seconds)
         out["cpu_baseline_single_thread"] = cpu_baseline(wl, u0, args.cpu_seconds / 2, threads=1)
 
     print(json.dumps(out), flush=True)
+
+
+def form_pair_measurement(wl, m, steps, warmup=3):
+    """Both precision forms on one workload at the CFL time step: initial data by the
+    m-point rule per subcell with the initial detection, `warmup` untimed steps, then
+    `steps` timed steps."""
+    import torch
+    from paper_1406_7416_amd import adg
+    u0, v0 = adg.project(wl, m)
+    res = {"workload": f"{wl.name}, N={wl.N}, {wl.ncell[0]}x{wl.ncell[1]} cells", "cells": wl.num_cells,
+           "st_dof_per_step": wl.st_dof_per_step(), "steps": steps}
+    for form, prec in (("fp64", adg.ADG_FP64), ("mixed", adg.ADG_MIXED)):
+        prob = adg.Problem(wl, precision=prec)
+        prob.set_state(u0, v0)
+        for _ in range(warmup):
+            prob.step_cfl()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            prob.step_cfl()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        res[form] = {"value": wl.st_dof_per_step() * steps / el, "ms_per_step": 1e3 * el / steps,
+                     "troubled_last_step": prob.stats()["troubled"]}
+        prob.close()
+    res["speedup_mixed_vs_fp64"] = res["mixed"]["value"] / res["fp64"]["value"]
+    print(f"# {wl.name}: fp64 {res['fp64']['value']:.3e}, mixed {res['mixed']['value']:.3e} st-dof/s, "
+          f"troubled {res['mixed']['troubled_last_step']}", file=sys.stderr, flush=True)
+    return res
 
 
 def explosion3d_measurement(steps, warmup=2, breakdown=2, ncell=128, N=3):

@@ -91,7 +91,7 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=20)
     ap.add_argument("--no-3d", action="store_true", help="skip the 3D explosion measurement (128^3, N=3)")
     ap.add_argument("--steps-3d", type=int, default=6)
-    ap.add_argument("--no-small", action="store_true", help="skip the 2D explosion and double Mach measurements")
+    ap.add_argument("--no-small", action="store_true", help="skip the 2D explosion, double Mach and shock-vortex measurements")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device-to-device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -236,10 +236,11 @@ def main():
         out["explosion3d"] = explosion3d_measurement(args.steps_3d)
 
     if not args.no_small:
-        # the two other 2D workloads: the 2D explosion (40 x 40, N = 3) and the double Mach
-        # reflection at its full size (400 x 100, N = 5)
+        # the other 2D workloads: the 2D explosion (40 x 40, N = 3), the double Mach reflection
+        # at its full size (400 x 100, N = 5) and the shock-vortex interaction (200 x 100, N = 5)
         out["explosion2d"] = form_pair_measurement(W.explosion_2d(40, 3), 4, steps=50)
         out["double_mach"] = form_pair_measurement(W.double_mach(400, 100, 5), 1, steps=20)
+        out["shock_vortex"] = form_pair_measurement(W.shock_vortex(200, 100, 5), 3, steps=20)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, u0, args.cpu_seconds)

@@ -230,6 +230,82 @@ def double_mach(nx: int = 400, ny: int = 100, N: int = 5, gamma: float = 1.4, Lx
                     [(left, right), (bottom, top)], ic, t_end=0.2)
 
 
+# --------------------------------------------------- shock-vortex interaction
+SVI = dict(gamma=1.4, a=0.075, b=0.175, Ms=1.5, Mv=0.7, p0=1.0, rho0=1.0, xc=0.25, yc=0.5, xs=0.5)
+
+
+def normal_shock_downstream(gamma: float, rho0: float, u0: float, p0: float):
+    """Rankine-Hugoniot state behind a stationary normal shock for the upstream state
+    (rho0, u0 > 0, p0) (flow in +x)."""
+    M2 = u0 * u0 * rho0 / (gamma * p0)
+    rho1 = rho0 * (gamma + 1.0) * M2 / ((gamma - 1.0) * M2 + 2.0)
+    p1 = p0 * (1.0 + 2.0 * gamma / (gamma + 1.0) * (M2 - 1.0))
+    return rho1, u0 * rho0 / rho1, p1
+
+
+def svi_vphi(r, vm: float, a: float, b: float):
+    """Angular velocity of the vortex (Sec. 5, shock-vortex interaction)."""
+    r = np.asarray(r, dtype=np.float64)
+    rs = np.maximum(r, 1e-300)
+    inner = vm * r / a
+    ring = vm * a / (a * a - b * b) * (r - b * b / rs)
+    return np.where(r <= a, inner, np.where(r <= b, ring, 0.0))
+
+
+def svi_temperature(r, T0: float, vm: float, a: float, b: float, gamma: float, R: float = 1.0):
+    """T(r) of the vortex: dT/dr = (gamma-1)/(R gamma) v_phi^2 / r with T = T0 for r >= b,
+    integrated in closed form (v_phi^2/r is r vm^2/a^2 inside a and A^2 (r - 2 b^2/r + b^4/r^3)
+    on the ring, A = vm a/(a^2 - b^2))."""
+    r = np.asarray(r, dtype=np.float64)
+    K = (gamma - 1.0) / (R * gamma)
+    A2 = (vm * a / (a * a - b * b)) ** 2
+
+    def ring_primitive(s):
+        return A2 * (0.5 * s * s - 2.0 * b * b * np.log(s) - 0.5 * b ** 4 / (s * s))
+
+    # integral of v^2/s from r to b
+    ring_part_a = ring_primitive(b) - ring_primitive(a)
+    rr = np.clip(r, a, b)
+    I_ring = ring_primitive(b) - ring_primitive(rr)
+    I_inner = vm * vm / (2.0 * a * a) * (a * a - np.minimum(r, a) ** 2) + ring_part_a
+    I = np.where(r >= b, 0.0, np.where(r >= a, I_ring, I_inner))
+    return T0 - K * I
+
+
+def shock_vortex(nx: int = 200, ny: int = 100, N: int = 5) -> Workload:
+    """Sec. 5 shock-vortex interaction on [0,2] x [0,1]: stationary normal shock at x = 0.5
+    (upstream rho0 = p0 = 1, Mach Ms = 1.5 in +x; downstream by Rankine-Hugoniot) and a vortex
+    of Mach Mv = 0.7 at (0.25, 0.5), superposed on the upstream flow.  Boundaries (not given
+    in the paper; reading): the upstream state flows in on the left, transmissive elsewhere.
+    The paper's mesh size h = 1/100 is the default grid."""
+    c = SVI
+    g, rho0, p0 = c["gamma"], c["rho0"], c["p0"]
+    c0 = math.sqrt(g * p0 / rho0)
+    u0 = c["Ms"] * c0
+    vm = c["Mv"] * c0
+    T0 = p0 / rho0
+    rho1, u1, p1 = normal_shock_downstream(g, rho0, u0, p0)
+
+    def ic(x, t=0.0):
+        X, Y = x[0], x[1]
+        dx, dy = X - c["xc"], Y - c["yc"]
+        r = np.sqrt(dx * dx + dy * dy)
+        vphi = svi_vphi(r, vm, c["a"], c["b"])
+        rs = np.maximum(r, 1e-300)
+        T = svi_temperature(r, T0, vm, c["a"], c["b"], g)
+        up = X < c["xs"]
+        rho = np.where(up, rho0 * (T / T0) ** (1.0 / (g - 1.0)), rho1)
+        p = np.where(up, p0 * (T / T0) ** (g / (g - 1.0)), p1)
+        u = np.where(up, u0 - vphi * dy / rs, u1)
+        v = np.where(up, vphi * dx / rs, 0.0 * X)
+        return prim_to_cons(g, rho, [u, v], p)
+
+    inflow = BC.simple(DIRICHLET, _cons_tuple(g, (rho0, u0, 0.0, p0)))
+    out = BC.simple(TRANSMISSIVE)
+    return Workload("shock_vortex", 2, N, (nx, ny), (0.0, 0.0), (2.0, 1.0),
+                    [(inflow, out), (out, out)], ic, gamma=g, t_end=0.7)
+
+
 # ------------------------------------------------------- four-quadrant RPs
 def quadrant_ic(states, gamma: float = 1.4):
     """Sec. 5 2D Riemann problem: u1 for x>0,y>0; u2 for x<=0,y>0; u3 for x<=0,y<=0;

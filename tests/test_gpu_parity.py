@@ -243,6 +243,23 @@ def test_config_explosion_3d_16cubed():
     assert o.troubled().sum() > 0
 
 
+def test_shock_vortex_small():
+    """Shock-vortex interaction (Sec. 5) on a coarse grid, N = 3: standing shock, vortex
+    upstream, inflow on the left."""
+    o, g = paired(W.shock_vortex(40, 20, 3), m=4)
+    run_parity(o, g, 5)
+    assert o.troubled().sum() > 0
+
+
+def test_config_shock_vortex_full_size():
+    """Shock-vortex interaction at the paper's mesh size h = 1/100 (200 x 100 cells on
+    [0,2] x [0,1], N = 5), initial detection against 3-point subcell averages (exact for the
+    uniform states), two steps."""
+    o, g = paired(W.shock_vortex(200, 100, 5), m=3)
+    run_parity(o, g, 2)
+    assert o.troubled().sum() > 0
+
+
 def test_pool_overflow_is_reported_and_cleared():
     """More troubled cells than the subcell pool holds: the initial detection refuses at
     once; a step that overflows is reported by the following call (the counts stay on the

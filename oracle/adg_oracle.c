@@ -647,8 +647,8 @@ static void neighbourhood_bounds(const or_solver *S, const double *vn, double t,
 }
 
 /* PAD eq. (positivity) + relaxed DMP eqs. (relax),(dmp) on one cell's candidate subcell
- * averages.  reading: PAD is checked on the candidate subcell averages (the detection is
- * "on a subcell basis"), plus a finiteness check; delta = max(delta0, eps (M - m)).
+ * averages.  reading: PAD is checked on the candidate subcell averages (the detection runs
+ * subcell by subcell), plus a finiteness check; delta = max(delta0, eps (M - m)).
  * Returns 1 if troubled; *margin = smallest normalised slack over all tests. */
 static int detect_cell(const or_solver *S, const double *vstar /*[v][nsub]*/, const double *m,
                        const double *M, double *margin) {

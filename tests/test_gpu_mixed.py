@@ -75,3 +75,36 @@ def test_mixed_forced_troubled_conservation():
 def test_mixed_3d_explosion():
     o, g = paired_mixed(W.explosion_3d(6, 2))
     run_mixed(o, g, 2)
+
+
+def test_mixed_config_explosion_2d_full_size():
+    """The 2D explosion at its full size (40 x 40, N = 3) in the mixed form, 5 steps."""
+    o, g = paired_mixed(W.explosion_2d(40, 3))
+    run_mixed(o, g, 5)
+    assert o.troubled().sum() > 0
+
+
+def test_mixed_config_double_mach_full_size():
+    """The double Mach reflection at its full size (400 x 100, N = 5) in the mixed form,
+    initial detection against one-point subcell averages, 2 steps."""
+    o, g = paired_mixed(W.double_mach(400, 100, 5), m=1)
+    run_mixed(o, g, 2)
+    assert o.troubled().sum() > 0
+
+
+def test_mixed_config_shock_vortex_full_size():
+    """The shock-vortex interaction at the paper's mesh size (200 x 100, N = 5) in the mixed
+    form, 2 steps."""
+    o, g = paired_mixed(W.shock_vortex(200, 100, 5), m=3)
+    run_mixed(o, g, 2)
+    assert o.troubled().sum() > 0
+
+
+def test_mixed_vortex_full_size():
+    """The benchmark's headline workload and form: the N = 9 vortex on 64 x 64 cells in the
+    mixed form, initial data by nodal interpolation, 2 steps, every output against the
+    oracle."""
+    o, g = paired_mixed(W.vortex(64, 9), m=0)
+    worst, steps = run_mixed(o, g, 2)
+    assert steps == 2 and worst > 0
+    assert o.troubled().sum() == 0 and g.troubled().sum() == 0

@@ -41,3 +41,17 @@ def test_osher_mixed_form():
         g.step(dt)
         assert rel_err(g.state(), o.state()) < 2e-6
     assert np.array_equal(o.troubled(), g.troubled())
+
+
+@pytest.mark.parametrize("prec_name", ["fp64", "mixed"])
+def test_osher_vortex_full_size(prec_name):
+    """The benchmark's vortex (N = 9, 64 x 64) with the Osher-type flux in the launch
+    configuration the benchmark times, one step, both forms."""
+    from paper_1406_7416_amd import adg
+    prec = adg.ADG_MIXED if prec_name == "mixed" else adg.ADG_FP64
+    o, g = paired_osher(W.vortex(64, 9), m=0, precision=prec)
+    dt = o.cfl_dt()
+    o.step(dt)
+    g.step(dt)
+    assert rel_err(g.state(), o.state()) < (2e-6 if prec_name == "mixed" else 1e-12)
+    assert np.array_equal(o.troubled(), g.troubled())

@@ -1229,7 +1229,7 @@ __device__ __forceinline__ void sub_update_cell(const Tables *__restrict__ T, co
 // in the working precision R (FP32 in the mixed form).
 template <int DIM, typename R>
 __device__ void sub_predictor(const Tables *__restrict__ T, const R *__restrict__ Y, R *__restrict__ tr,
-                              int npos, double dt, const double *dth, double gamma_d) {
+                              int npos, int nsub, int nsf, double dt, const double *dth, double gamma_d) {
     constexpr int NV = DIM + 2, NN = cpow(3, DIM), NF = cpow(3, DIM - 1), PPW = 64 / NN;
     constexpr int TRS = 2 * DIM * NV * NF * 3;
     constexpr int ST[3] = {1, 3, 9};
@@ -1338,7 +1338,11 @@ __device__ void sub_predictor(const Tables *__restrict__ T, const R *__restrict_
                     qb[1][v][s] = __shfl(q[v][s], src1[k]);
                     qb[2][v][s] = __shfl(q[v][s], src2[k]);
                 }
-            if (valid && ia[k] != 1) {
+            // a neighbour-layer position (pos >= nsub) only needs the trace on its face toward
+            // the cell: the + face of the low layer, the - face of the high layer
+            const int layer = pos >= nsub ? (pos - nsub) / nsf : -1;
+            const bool needed = layer < 0 || ((layer >> 1) == k && (layer & 1) == (ia[k] == 0));
+            if (valid && ia[k] != 1 && needed) {
                 const int side = ia[k] == 2;
                 const int r = ia[k], nb[3] = {r, (r + 1) % 3, (r + 2) % 3};
                 R Bv[3];
@@ -1474,7 +1478,7 @@ __global__ __launch_bounds__(SUB_BS, 2) void k_subcell(const Tables *__restrict_
         __syncthreads();
         sub_recon_cell<DIM, N, R>(T, B, sidx, halo);
         __syncthreads();
-        sub_predictor<DIM, R>(T, Ys, trs, NPOS, dt, dth, P.gamma);
+        sub_predictor<DIM, R>(T, Ys, trs, NPOS, NSUB, NSF, dt, dth, P.gamma);
         __syncthreads();
         sub_update_cell<DIM, N, R, REDO>(T, P, B, cur, w, sidx, nonphys, halo, REDO ? 0 : flagging, mb, nslot);
     }

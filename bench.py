@@ -33,7 +33,7 @@ PEAK_HBM_GBS = 8000.0
 # own size), taken on the predictor source (the files below, concatenated) whose SHA-256 starts
 # with the prefix below; reported as null once that source has changed.
 PREDICTOR_SOURCES = ("adg_internal.h", "adg_physics.h", "adg_predictor.h")
-PREDICTOR_TRAFFIC_BYTES = 86021798
+PREDICTOR_TRAFFIC_BYTES = 86023925
 PREDICTOR_TRAFFIC_SOURCE = "09aa0e2b73ff9b3c"
 
 

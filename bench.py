@@ -9,7 +9,7 @@ reduction (eq. (cfl)) + old-time bounds + space-time predictor + face fluxes + c
 flagged).  Metric: space-time degrees of freedom updated per second, counted per
 conserved variable as the paper does ((N+1)^(d+1) per cell and step).
 
-Prints one JSON line.  With --gpus above 1 it exits: this build runs on one GPU.
+Prints one JSON line.  With --gpus above 1 it exits: the benchmark runs on one GPU.
 """
 import argparse
 import json
@@ -107,7 +107,7 @@ def main():
         return
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported",
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus above 1 is not supported",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 

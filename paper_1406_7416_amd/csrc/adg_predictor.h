@@ -1,5 +1,7 @@
 // Local space-time predictor (a point-owner / line-owner LDS design, see below).
 #pragma once
+#include <type_traits>
+
 #include "adg_physics.h"
 
 namespace adg {
@@ -218,14 +220,20 @@ __device__ void pred_cells(const PredArgs<R> &A, double gamma_d, int64_t ncell, 
 #pragma unroll
         for (int s = 0; s < n; s++) q[v][s] = u0[v];
 
-    for (int r = 0; r < A.iters; r++) {
+    // One Picard sweep.  In the first the iterate is u^n at every time node, so every time slice
+    // of the fluxes and of their spatial derivatives is the same: only slice 0 is computed and
+    // it stands for all of them (equal to the full sweep in exact arithmetic; the compiled code
+    // may round differently, by a few units in the last place).
+    auto sweep = [&](auto first_c) __attribute__((always_inline)) {
+        constexpr bool FIRST = decltype(first_c)::value;
+        constexpr int NT = FIRST ? 1 : n;   // time slices computed
         // 1/rho of every node of the pencil, shared by the fluxes of all axes (for long
         // FP64 pencils recomputed per axis instead, to stay within 256 registers)
         constexpr bool CACHE_IRHO = n < 8 || sizeof(R) == 4;
         R irho[CACHE_IRHO ? n : 1], pr[CACHE_IRHO ? n : 1];
         if constexpr (CACHE_IRHO) {
 #pragma unroll
-            for (int t = 0; t < n; t++) {
+            for (int t = 0; t < NT; t++) {
                 irho[t] = recip(q[0][t]);
                 R ke = 0;
 #pragma unroll
@@ -240,7 +248,7 @@ __device__ void pred_cells(const PredArgs<R> &A, double gamma_d, int64_t ncell, 
                 // point phase: fluxes of the time pencil straight into LDS
                 if (tid < S::ACT) {
 #pragma unroll
-                    for (int t = 0; t < n; t++) {
+                    for (int t = 0; t < NT; t++) {
                         R ir;
                         if constexpr (CACHE_IRHO) ir = irho[t];
                         else ir = recip(q[0][t]);
@@ -264,8 +272,8 @@ __device__ void pred_cells(const PredArgs<R> &A, double gamma_d, int64_t ncell, 
                     }
                 }
                 __syncthreads();
-                lds_lines<DIM, N, CPB, VC, S::BS, R, EO, false>(X, k, NN, NN, D, R(1), tid,
-                                                                NV - v0 < VC ? NV - v0 : VC, Es, Os);
+                lds_lines<DIM, N, CPB, VC, S::BS, R, EO, false>(X, k, FIRST ? NN / n : NN, FIRST ? 0 : NN, D, R(1),
+                                                                tid, NV - v0 < VC ? NV - v0 : VC, Es, Os);
                 __syncthreads();
                 // S = sum_k (dt/h_k) D_k F_k, the factor applied while accumulating
                 if (tid < S::ACT) {
@@ -274,7 +282,7 @@ __device__ void pred_cells(const PredArgs<R> &A, double gamma_d, int64_t ncell, 
                         if (v0 + vv < NV)
 #pragma unroll
                             for (int t = 0; t < n; t++) {
-                                const R xk = X[(lc * VC + vv) * NST + a + NN * t];
+                                const R xk = X[(lc * VC + vv) * NST + a + NN * (FIRST ? 0 : t)];
                                 Sacc[v0 + vv][t] = (k == 0) ? ck * xk : Sacc[v0 + vv][t] + ck * xk;
                             }
                 } else if (k == 0) {
@@ -303,7 +311,9 @@ __device__ void pred_cells(const PredArgs<R> &A, double gamma_d, int64_t ncell, 
 #pragma unroll
             for (int v = 0; v < NV; v++) q[v][s] = u0[v] - acc[v];
         }
-    }
+    };
+    if (A.iters > 0) sweep(std::true_type{});
+    for (int r = 1; r < A.iters; r++) sweep(std::false_type{});
 
     // ---- volume term of eq. (pde.nc.gw2), divided by the diagonal mass:
     //   (dt/h_k) sum_b [w_b D[b][a_k] / w_{a_k}] sum_s w_s F_k(q(a|b, s))

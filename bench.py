@@ -50,6 +50,38 @@ def predictor_flops_per_cell(d: int, N: int) -> float:
     return (n - 1) * sweep + first
 
 
+def vortex_convergence(N: int = 9, grids=(16, 32, 64), t_end: float = 10.0) -> dict:
+    """L1 density error against the exact isentropic vortex at t_end (10: the vortex crosses
+    the periodic box once and is back at its start), per grid and precision form, and the
+    observed orders between successive grids.  Initial data by nodal interpolation; CFL
+    time steps, the last one shortened to land on t_end."""
+    import numpy as np
+    from paper_1406_7416_amd import adg
+    from paper_1406_7416_amd import workloads as W
+    out = {"workload": f"isentropic vortex, N={N}, t_end={t_end}", "grids": list(grids)}
+    for form, prec in (("fp64", adg.ADG_FP64), ("mixed", adg.ADG_MIXED)):
+        errs, nsteps = [], []
+        for g in grids:
+            wl = W.vortex(g, N)
+            prob = adg.Problem(wl, precision=prec)
+            u0, _ = prob.project(wl.ic, 0)
+            prob.set_state(u0)
+            steps = 0
+            while prob.time < t_end * (1 - 1e-14):
+                prob.step(min(prob.cfl_dt(), t_end - prob.time))
+                steps += 1
+            ue, _ = prob.project(lambda x, t: wl.ic(x, t_end), 0)
+            errs.append(l1_norm(prob.state()[0] - ue[0], wl))
+            nsteps.append(steps)
+            prob.close()
+            print(f"# convergence {form} {g}^2: L1(rho) {errs[-1]:.3e} after {steps} steps", file=sys.stderr,
+                  flush=True)
+        orders = [float(np.log2(errs[i] / errs[i + 1]) / np.log2(grids[i + 1] / grids[i]))
+                  for i in range(len(grids) - 1)]
+        out[form] = {"l1_rho": errs, "steps": nsteps, "orders": orders}
+    return out
+
+
 def l1_norm(f, wl):
     """L1 norm over the domain of a nodal field f[cell][node] (tensor Gauss-Legendre
     quadrature of the cells' nodes)."""
@@ -98,7 +130,13 @@ def main():
     ap.add_argument("--no-small", action="store_true", help="skip the 2D explosion, double Mach and shock-vortex measurements")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device-to-device copy of this size (counter calibration)")
+    ap.add_argument("--convergence", action="store_true",
+                    help="only measure the vortex's L1 error at t = 10 on 16^2, 32^2, 64^2 cells (degree --N)")
     args = ap.parse_args()
+
+    if args.convergence:
+        print(json.dumps(vortex_convergence(args.N)))
+        return
 
     if args.copy_bytes:
         import torch

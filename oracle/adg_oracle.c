@@ -874,6 +874,7 @@ typedef struct {
     double *tr;     /* [(Ns+2)^d][2d][v][3^{d-1}*3]     subcell predictor face traces */
     uint8_t *have;  /* [(Ns+2)^d]                       trace computed */
     double *F;      /* [d][(Ns+1)][Ns^{d-1}][v]         time/face averaged sub-face fluxes */
+    double *Fq;     /* [d][(Ns+1)][Ns^{d-1}][3^{d-1}][v] time-averaged flux at each tangential point */
 } sc_work;
 
 static void sc_alloc(const or_solver *S, sc_work *W) {
@@ -882,8 +883,9 @@ static void sc_alloc(const or_solver *S, sc_work *W) {
     W->tr = malloc(sizeof(double) * ipow(Ns + 2, d) * 2 * d * nv * ipow(3, d));
     W->have = malloc(ipow(Ns + 2, d));
     W->F = malloc(sizeof(double) * d * (Ns + 1) * ipow(Ns, d - 1) * nv);
+    W->Fq = malloc(sizeof(double) * d * (Ns + 1) * ipow(Ns, d - 1) * ipow(3, d - 1) * nv);
 }
-static void sc_free(sc_work *W) { free(W->halo); free(W->tr); free(W->have); free(W->F); }
+static void sc_free(sc_work *W) { free(W->halo); free(W->tr); free(W->have); free(W->F); free(W->Fq); }
 
 /* 1 if every point of q[v*npts + i] has finite values, rho > 0 and p > 0 */
 static int all_physical(int d, double g, const double *q, int npts) {
@@ -908,8 +910,9 @@ static int floordiv(int a, int b) { return (a >= 0) ? a / b : -((-a + b - 1) / b
  *   5. one-step FV update of the subcell averages.
  * reading (scheme details are given in the paper's references, not in the paper):
  * steps 2-4 as stated; sub-faces on the domain boundary take the boundary ghost state of
- * the DG scheme.  Outputs vnew [v][nsub] and the averaged fluxes on the cell's own faces
- * sf[(2k+side)][v][nsubf]. */
+ * the DG scheme.  Outputs vnew [v][nsub] and, on the cell's own faces, the time-averaged
+ * flux at each tangential quadrature point of each sub-face,
+ * sf[(2k+side)][v][nsubf][3^{d-1}] (consumed by the flux correction of Sec. 4.4). */
 /* 1 if subcell (global cell gci, local subcell ms) carries a MOOD flag; cells outside a
  * non-periodic boundary and untroubled cells carry none. */
 static int mood_flag(const or_solver *S, const uint8_t *flag, const uint8_t *troubled, const int *gci, const int *ms) {
@@ -1058,9 +1061,11 @@ static void subcell_update(const or_solver *S, const double *vn, long c, double 
                     low = mood_flag(S, flag, troubled, gL, mL) || mood_flag(S, flag, troubled, gR, mR);
                 }
                 double Fbar[5] = {0, 0, 0, 0, 0};
+                double *Fq = W->Fq + (((long)k * (Ns + 1) + f) * nsf + sp) * nfn3 * nv;
                 for (int pass = low; pass < 2; pass++) {
                     int ok = 1;
                     for (int v = 0; v < nv; v++) Fbar[v] = 0.0;
+                    for (int i = 0; i < nfn3 * nv; i++) Fq[i] = 0.0;
                     for (int s = 0; s < 3 && ok; s++)
                         for (int ap = 0; ap < nfn3; ap++) {
                             double qL[5], qR[5], G[5];
@@ -1089,7 +1094,10 @@ static void subcell_update(const or_solver *S, const double *vn, long c, double 
                             /* the scheme's flux on the traces; first-order fallbacks use Rusanov */
                             if (pass) rusanov(d, k, g, qL, qR, G);
                             else num_flux(S, k, qL, qR, G);
-                            for (int v = 0; v < nv; v++) Fbar[v] += wt * G[v];
+                            for (int v = 0; v < nv; v++) {
+                                Fbar[v] += wt * G[v];
+                                Fq[ap * nv + v] += S->B3.w[s] * G[v];
+                            }
                         }
                     if (ok) break;
                 }
@@ -1116,7 +1124,9 @@ static void subcell_update(const or_solver *S, const double *vn, long c, double 
         for (int side = 0; side < 2; side++)
             for (int v = 0; v < nv; v++)
                 for (int sp = 0; sp < nsf; sp++)
-                    sf[((2 * k + side) * nv + v) * nsf + sp] = W->F[(((long)k * (Ns + 1) + (side ? Ns : 0)) * nsf + sp) * nv + v];
+                    for (int ap = 0; ap < nfn3; ap++)
+                        sf[(((2 * k + side) * nv + v) * nsf + sp) * nfn3 + ap] =
+                            W->Fq[((((long)k * (Ns + 1) + (side ? Ns : 0)) * nsf + sp) * nfn3 + ap) * nv + v];
 }
 
 /* --------------------------------------------------------------- the step */
@@ -1291,8 +1301,10 @@ int or_step(or_solver *S, double dt) {
 
     /* step 4: subcell recompute */
     long nsf = S->nsubf;
+    const int nfn3 = ipow(3, d - 1);
+    const long sfsz = 2L * d * nv * nsf * nfn3;   /* per cell: [2d][v][sub-face][tangential point] */
     double *vnew = malloc(sizeof(double) * nv * ncell * S->nsub);
-    double *sf = malloc(sizeof(double) * ncell * 2 * d * nv * nsf);
+    double *sf = malloc(sizeof(double) * ncell * sfsz);
     long nonphys = 0;
 #pragma omp parallel
     {
@@ -1302,7 +1314,7 @@ int or_step(or_solver *S, double dt) {
 #pragma omp for schedule(dynamic, 1)
         for (long c = 0; c < ncell; c++) {
             if (!bnew[c]) continue;
-            subcell_update(S, vn, c, dt, &W, vc, sf + c * 2 * d * nv * nsf, NULL, NULL);
+            subcell_update(S, vn, c, dt, &W, vc, sf + c * sfsz, NULL, NULL);
             for (int v = 0; v < nv; v++)
                 memcpy(vnew + ((long)v * ncell + c) * S->nsub, vc + v * S->nsub, sizeof(double) * S->nsub);
         }
@@ -1368,7 +1380,7 @@ int or_step(or_solver *S, double dt) {
 #pragma omp for schedule(dynamic, 1)
             for (long c = 0; c < ncell; c++) {
                 if (!redo[c]) continue;
-                subcell_update(S, vn, c, dt, &W, vc, sf + c * 2 * d * nv * nsf, flag, bnew);
+                subcell_update(S, vn, c, dt, &W, vc, sf + c * sfsz, flag, bnew);
                 for (int v = 0; v < nv; v++)
                     memcpy(vnew + ((long)v * ncell + c) * nsub, vc + v * nsub, sizeof(double) * nsub);
             }
@@ -1394,10 +1406,18 @@ int or_step(or_solver *S, double dt) {
     }
     S->nonphys += nonphys;
 
-    /* flux correction of unlimited cells next to troubled cells (Sec. 4.4): remove the DG
-     * face flux and add the subcell fluxes integrated against each basis function.
-     * reading: the sub-face flux is constant on its sub-face; its integral against the
-     * tangential basis is P[sigma][a]/Ns per tangential axis. */
+    /* flux correction of unlimited cells next to troubled cells (Sec. 4.4): the DG face
+     * integral becomes the sum of the integrals over the sub-faces, with the subcell
+     * scheme's flux.  Remove the DG face flux and add, for each basis function, the
+     * integral over each sub-face of the subcell flux times that basis function: the flux
+     * at the 3 Gauss-Legendre points per tangential axis (time-averaged) times the
+     * tangential basis there, with the quadrature weights (w3/Ns per axis).  The mean
+     * moment receives the sub-face averages that the troubled cell's update used, so the
+     * step stays conservative. */
+    double phi3[MAXNS][3][MAXN];   /* phi3[sigma][g][m] = phi_m((sigma + xi3_g)/Ns) */
+    for (int sg = 0; sg < Ns; sg++)
+        for (int gq = 0; gq < 3; gq++)
+            for (int m = 0; m < n; m++) phi3[sg][gq][m] = lagrange(n, B->xi, m, (sg + S->B3.xi[gq]) / Ns);
 #pragma omp parallel for schedule(static)
     for (long c = 0; c < ncell; c++) {
         if (bnew[c]) continue;
@@ -1413,7 +1433,7 @@ int or_step(or_solver *S, double dt) {
                 }
                 long cn = cell_index(S, nb);
                 if (!bnew[cn]) continue;
-                const double *fs = sf + cn * 2 * d * nv * nsf + (long)(2 * k + (1 - side)) * nv * nsf;
+                const double *fs = sf + cn * sfsz + (long)(2 * k + (1 - side)) * nv * nsf * nfn3;
                 for (int a = 0; a < nn; a++) {
                     int m[3];
                     unflat(a, n, d, m);
@@ -1424,14 +1444,18 @@ int or_step(or_solver *S, double dt) {
                         for (int sp = 0; sp < nsf; sp++) {
                             int ms[3] = {0, 0, 0};
                             unflat(sp, Ns, d - 1, ms);
-                            double wgt = 1;
-                            int j2 = 0;
-                            for (int j = 0; j < d; j++) {
-                                if (j == k) continue;
-                                wgt *= S->P[ms[j2]][m[j]] / (Ns * B->w[m[j]]);
-                                j2++;
+                            for (int gp = 0; gp < nfn3; gp++) {
+                                int mg[3] = {0, 0, 0};
+                                unflat(gp, 3, d - 1, mg);
+                                double wgt = 1;
+                                int j2 = 0;
+                                for (int j = 0; j < d; j++) {
+                                    if (j == k) continue;
+                                    wgt *= S->B3.w[mg[j2]] / Ns * phi3[ms[j2]][mg[j2]][m[j]] / B->w[m[j]];
+                                    j2++;
+                                }
+                                Fsub += wgt * fs[(v * nsf + sp) * nfn3 + gp];
                             }
-                            Fsub += wgt * fs[v * nsf + sp];
                         }
                         double Gdg = gbar[c * gsz + ((2 * k + side) * nv + v) * nfn + ap];
                         double corr = side ? dth[k] * B->R[ak] / B->w[ak] * (Gdg - Fsub)

@@ -70,7 +70,7 @@ struct adg_problem {
     struct Off {
         size_t tab, u0, u1, emin0, emax0, emin1, emax1, trace, gbar, beta0, beta1, force, mflag, margin, tlist, clist,
             slot0,
-            slot1, pool0, pool1, sflux, blk, counts, scal, lampart, ring, halo, Y, strace, end;
+            slot1, pool0, pool1, sflux, blk, counts, scal, lampart, ring, halo, Y, strace, fpts, end;
     } off;
     int64_t ring_cap = 0;    // ghost-ring cells of the extended grid
     int64_t nring = 0;       // of which the detection reads (non-periodic sides)
@@ -143,7 +143,7 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 static void plan(adg_problem *pb) {
     const Prob &P = pb->P;
     const int d = P.dim, nv = P.nv, n = P.n, Ns = P.Ns;
-    const int64_t nn = ipow64(n, d), nfn = ipow64(n, d - 1), nsub = ipow64(Ns, d), nsf = ipow64(Ns, d - 1);
+    const int64_t nn = ipow64(n, d), nfn = ipow64(n, d - 1), nsub = ipow64(Ns, d);
     int64_t next = 1;
     for (int j = 0; j < d; j++) next *= P.nc[j] + 2;
     const int64_t nc = P.ncell;
@@ -183,7 +183,7 @@ static void plan(adg_problem *pb) {
     f.slot1 = take(4ull * nc);
     f.pool0 = take(8ull * pb->cap * nv * nsub);
     f.pool1 = take(8ull * pb->cap * nv * nsub);
-    f.sflux = take(8ull * pb->cap * 2 * d * nv * nsf);
+    f.sflux = take(8ull * pb->cap * 2 * d * nv * nfn);
     f.blk = take(4ull * 2 * nblk);
     f.counts = take(4ull * 8);
     f.scal = take(8ull * 8);
@@ -197,6 +197,7 @@ static void plan(adg_problem *pb) {
     f.halo = take(8ull * chunk * nv * hsz);
     f.Y = take(8ull * chunk * pb->npos * nv * n3);
     f.strace = take(8ull * chunk * pb->npos * 2 * d * nv * nf3 * 3);
+    f.fpts = take(8ull * chunk * 2 * d * nv * ipow64(3 * Ns, d - 1));
     f.end = o;
     pb->ws_bytes = o;
 }
@@ -234,6 +235,7 @@ static void carve(adg_problem *pb) {
     B.halo = (double *)(w + f.halo);
     B.Y = (double *)(w + f.Y);
     B.strace = (double *)(w + f.strace);
+    B.fpts = (double *)(w + f.fpts);
     pb->tab_dev = B.tab;
 }
 

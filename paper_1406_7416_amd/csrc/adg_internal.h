@@ -19,7 +19,8 @@ struct Tables {
     double Dvol[MAXN][MAXN];     // w_b D[b][a] / w_a : volume-term operator
     double P[MAXNS][MAXN];       // subcell projection, eq. (subcell.p)
     double Rg[MAXN][MAXNS];      // subcell reconstruction (gather), eq. (subcell.r)
-    double Pt[MAXNS][MAXN];      // P[s][a] / (Ns w_a): sub-face integral of phi_a over face w_a
+    double Pq[3 * MAXNS][MAXN];  // (w3_g / Ns) phi_a((s + xi3_g) / Ns) / w_a at row s*3+g:
+                                 // sub-face quadrature of phi_a over the face weight w_a
     // degree-2 subcell scheme (3 Gauss-Legendre nodes)
     double xi3[3], w3[3];
     double D3[MAXN][MAXN], L3[MAXN], R3[MAXN], Kw3[MAXN][MAXN];
@@ -70,7 +71,8 @@ struct Bufs {
     int *tlist, *clist;    // troubled cells, corrected cells
     int *slot[2];          // cell -> pool slot (old / new), -1 if none
     double *pool[2];       // [slot][v][sub]
-    double *sflux;         // [slot][2d][v][subf]
+    double *sflux;         // [slot][2d][v][n^(d-1)] subcell fluxes integrated against the face basis
+    double *fpts;          // [chunk][2d][v][(3 Ns)^(d-1)] time-averaged sub-face fluxes per point
     int *blk;              // block partial counts for compaction [2][nblk]
     int *counts;           // [0] troubled [1] corrected [2] nonphysical cumulative [3] capacity overflow
                            // [4] block ticket of the compaction [5] MOOD-flagged subcells

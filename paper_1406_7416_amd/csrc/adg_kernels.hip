@@ -1001,6 +1001,8 @@ __device__ __forceinline__ void sub_update_cell(const Tables *__restrict__ T, co
     constexpr int NPOS = NSUB + 2 * DIM * NSF, NF3 = cpow(3, DIM - 1);
     constexpr int TRS = 2 * DIM * NV * NF3 * 3;   // trace size per position
     constexpr int BIG = NSUB > NN ? NSUB : NN;
+    constexpr int QF = cpow(3 * NS, DIM - 1);     // tangential quadrature points of one face
+    constexpr int NFN = cpow(n, DIM - 1);
     // sub-face fluxes (working precision), later the gather's intermediate stage
     constexpr int FBB = DIM * (NS + 1) * NSF * NV * (int)sizeof(R), TMB = NV * BIG * 8;
     __shared__ __align__(16) unsigned char fbt[FBB > TMB ? FBB : TMB];
@@ -1091,28 +1093,35 @@ __device__ __forceinline__ void sub_update_cell(const Tables *__restrict__ T, co
             }
             // Positivity safeguard: if any predictor trace on either side is not a physical
             // state, the sub-face takes the first-order flux of the two subcell averages.
+            // A sub-face on the cell's own face also keeps its time-averaged flux at each
+            // tangential quadrature point for the flux correction of the neighbour.
             R Fbar[NV];
+            const bool own_face = (f == 0 || f == NS);
+            double *fp = B.fpts + ((int64_t)ch * 2 * DIM + 2 * k + (f == NS ? 1 : 0)) * NV * QF;
             for (int pass = low; pass < 2; pass++) {
                 bool ok = true;
 #pragma unroll
                 for (int v = 0; v < NV; v++) Fbar[v] = 0;
-                for (int s = 0; s < 3 && ok; s++)
-                    for (int ap = 0; ap < NF3; ap++) {
-                        R qL[NV], qR[NV], G[NV];
-                        const int ma0 = ap % 3, ma1 = ap / 3;
-                        double wt = T->w3[s];
-                        double x[3] = {0, 0, 0};
+                for (int ap = 0; ap < NF3 && ok; ap++) {
+                    const int ma0 = ap % 3, ma1 = ap / 3;
+                    double wtan = 1.0;
+                    double x[3] = {0, 0, 0};
 #pragma unroll
-                        for (int j = 0; j < DIM; j++) {
-                            if (j == k) {
-                                x[j] = P.lo[j] + P.h[j] * (ci[j] + (double)f / NS);
-                            } else {
-                                const bool first = (j < k ? j : j - 1) == 0;
-                                const int ma = first ? ma0 : ma1;
-                                wt *= T->w3[ma];
-                                x[j] = P.lo[j] + P.h[j] * (ci[j] + ((first ? mp0 : mp1) + T->xi3[ma]) / NS);
-                            }
+                    for (int j = 0; j < DIM; j++) {
+                        if (j == k) {
+                            x[j] = P.lo[j] + P.h[j] * (ci[j] + (double)f / NS);
+                        } else {
+                            const bool first = (j < k ? j : j - 1) == 0;
+                            const int ma = first ? ma0 : ma1;
+                            wtan *= T->w3[ma];
+                            x[j] = P.lo[j] + P.h[j] * (ci[j] + ((first ? mp0 : mp1) + T->xi3[ma]) / NS);
                         }
+                    }
+                    R Gt[NV];
+#pragma unroll
+                    for (int v = 0; v < NV; v++) Gt[v] = 0;
+                    for (int s = 0; s < 3; s++) {
+                        R qL[NV], qR[NV], G[NV];
                         const double ts = t0 + T->xi3[s] * dt;
                         const R *trL = tr + (int64_t)pL * TRS + (2 * k + 1) * NV * NF3 * 3;
                         const R *trR = tr + (int64_t)pR * TRS + (2 * k + 0) * NV * NF3 * 3;
@@ -1146,8 +1155,17 @@ __device__ __forceinline__ void sub_update_cell(const Tables *__restrict__ T, co
                         if (pass) rusanov<DIM, R>(k, qL, qR, G, gam);
                         else num_flux<DIM, R>(P, T, k, qL, qR, G);
 #pragma unroll
-                        for (int v = 0; v < NV; v++) Fbar[v] += (R)wt * G[v];
+                        for (int v = 0; v < NV; v++) Gt[v] += (R)T->w3[s] * G[v];
                     }
+                    if (!ok) break;
+#pragma unroll
+                    for (int v = 0; v < NV; v++) Fbar[v] += (R)wtan * Gt[v];
+                    if (own_face) {
+                        const int q = (mp0 * 3 + ma0) + 3 * NS * (mp1 * 3 + ma1);
+#pragma unroll
+                        for (int v = 0; v < NV; v++) fp[v * QF + q] = (double)Gt[v];
+                    }
+                }
                 if (ok) break;
             }
 #pragma unroll
@@ -1202,11 +1220,26 @@ __device__ __forceinline__ void sub_update_cell(const Tables *__restrict__ T, co
             if (bad) atomicAdd(&B.counts[5], 1);
         }
     }
-    // boundary fluxes of the cell's faces for the flux correction
-    for (int it = threadIdx.x; it < 2 * DIM * NV * NSF; it += SUB_BS) {
-        const int face = it / (NV * NSF), v = (it / NSF) % NV, sp = it % NSF;
-        const int k = face >> 1, side = face & 1;
-        B.sflux[(int64_t)slot * 2 * DIM * NV * NSF + it] = Fb[((k * (NS + 1) + (side ? NS : 0)) * NSF + sp) * NV + v];
+    // Flux correction data (Sec. 4.4: the face integral of the unlimited neighbour becomes
+    // the sum of the integrals over the sub-faces): for each face, variable and tangential
+    // node a of the DG basis, the integral of the subcell flux times phi_a over the face,
+    // divided by the face weight w_a, from the per-point fluxes (3 Gauss-Legendre points per
+    // sub-face and tangential axis; Pq[s*3+g][a] = (w3_g / Ns) phi_a((s + xi3_g) / Ns) / w_a).
+    for (int it = threadIdx.x; it < 2 * DIM * NV * NFN; it += SUB_BS) {
+        const int face = it / (NV * NFN), v = (it / NFN) % NV, a = it % NFN;
+        const int a0 = a % n, a1 = a / n;
+        const double *fq = B.fpts + ((int64_t)ch * 2 * DIM + face) * NV * QF + v * QF;
+        double acc = 0.0;
+        for (int ms1 = 0; ms1 < (DIM == 3 ? NS : 1); ms1++)
+            for (int ms0 = 0; ms0 < NS; ms0++)
+                for (int g1 = 0; g1 < (DIM == 3 ? 3 : 1); g1++)
+                    for (int g0 = 0; g0 < 3; g0++) {
+                        const int q0 = ms0 * 3 + g0, q1 = ms1 * 3 + g1;
+                        double wgt = T->Pq[q0][a0];
+                        if (DIM == 3) wgt *= T->Pq[q1][a1];
+                        acc += wgt * fq[q0 + 3 * NS * q1];
+                    }
+        B.sflux[(int64_t)slot * 2 * DIM * NV * NFN + it] = acc;
     }
     __syncthreads();
     store_cell_bounds<NV>(P, B, c, vn, NSUB, threadIdx.x, SUB_BS, red);
@@ -1486,7 +1519,8 @@ __global__ __launch_bounds__(SUB_BS, 2) void k_subcell(const Tables *__restrict_
 
 // Flux correction of unlimited cells next to troubled cells (Sec. 4.4): the DG face
 // flux of each face shared with a troubled cell is replaced by the subcell fluxes of
-// that face, each integrated against the basis (P[sigma][a] / (Ns w_a) per tangential axis).
+// that face integrated against the basis (the troubled cell's kernel stores those
+// integrals per tangential node).
 template <int DIM, int N, typename R>
 __global__ __launch_bounds__(128) void k_fluxcorr(const Tables *__restrict__ T, Prob P, Bufs B, int cur, int count,
                                                   int advance) {
@@ -1498,7 +1532,7 @@ __global__ __launch_bounds__(128) void k_fluxcorr(const Tables *__restrict__ T, 
     __shared__ double tmp[NV_ * TMP_];
     __shared__ double red[2 * NV_ * 2];
     constexpr int n = N + 1, NV = DIM + 2, NN = cpow(n, DIM), NFN = cpow(n, DIM - 1);
-    constexpr int NS = 2 * N + 1, NSF = cpow(NS, DIM - 1);
+    constexpr int NS = 2 * N + 1;
     // the step's last kernel also advances t (no other workgroup reads t here) and ends a
     // one-step debug poison of the candidate
     if (advance && blockIdx.x == 0 && threadIdx.x == 0) {
@@ -1547,19 +1581,7 @@ __global__ __launch_bounds__(128) void k_fluxcorr(const Tables *__restrict__ T, 
             for (int side = 0; side < 2; side++) {
                 if (nbc[k][side] < 0) continue;
                 const int slot = nslot[k][side];
-                const double *fs = B.sflux + ((int64_t)slot * 2 * DIM + 2 * k + (1 - side)) * NV * NSF + v * NSF;
-                double Fsub = 0.0;
-                for (int sp = 0; sp < NSF; sp++) {
-                    // tangential subcell coordinates: sp % NS on the first axis, sp / NS on the second
-                    const int ms0 = sp % NS, ms1 = sp / NS;
-                    double wgt = 1.0;
-#pragma unroll
-                    for (int j = 0; j < DIM; j++) {
-                        if (j == k) continue;
-                        wgt *= T->Pt[(j < k ? j : j - 1) == 0 ? ms0 : ms1][m[j]];
-                    }
-                    Fsub += wgt * fs[sp];
-                }
+                const double Fsub = B.sflux[(((int64_t)slot * 2 * DIM + 2 * k + (1 - side)) * NV + v) * NFN + ap];
                 const double Gdg = (double)gbar[((c * 2 * DIM + 2 * k + side) * NV + v) * NFN + ap];
                 val += side ? ck * T->R[ak] * (Gdg - Fsub) : ck * T->L[ak] * (Fsub - Gdg);
             }

@@ -170,10 +170,14 @@ void build_tables(int N, int Ns, Tables *T) {
         for (int i = 0; i < n; i++)
             for (int q = 0; q < Ns; q++) T->Rg[i][q] = Pt[i * Ns + q];
     }
-    for (int s = 0; s < Ns; s++)
-        for (int a = 0; a < n; a++) T->Pt[s][a] = T->P[s][a] / (Ns * T->w[a]);
     // degree-2 scheme on the subgrid
     gl_newton(3, T->xi3, T->w3);
+    for (int s = 0; s < Ns; s++)
+        for (int g = 0; g < 3; g++) {
+            double phi[MAXN];
+            B.eval((s + T->xi3[g]) / Ns, phi);
+            for (int a = 0; a < n; a++) T->Pq[s * 3 + g][a] = T->w3[g] / Ns * phi[a] / T->w[a];
+        }
     Bary B3;
     B3.init(3, T->xi3);
     B3.diff(T->D3);

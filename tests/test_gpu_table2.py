@@ -4,10 +4,11 @@ against the L1 density errors the paper prints (tests/golden/table2_vortex_order
 
 The time steps differ from the paper's (CFL factor 0.3 here: the stability reading of the
 CFL rule), and the time error is of the same order as the space error, so the errors are
-compared within a factor of 1.5.  On 8^2, 10^2 and 12^2 cells the limiter is on and stays
-idle.  On 4^2 cells (the vortex core narrower than a cell) the limiter is off: with it,
-the relaxed DMP flags cells of the under-resolved vortex from the first step and the error
-grows far above the paper's, an open difference in the reading of the detection."""
+compared within a factor of 1.5.  The limiter is on in every row, as in the paper.  On 8^2,
+10^2 and 12^2 cells it stays idle.  On 4^2 cells (the vortex core narrower than a cell) the
+relaxed DMP flags a cell now and then (at most one at a time); the flagged cell and its
+unlimited neighbours then exchange fluxes through the sub-face integrals of Sec. 4.4, and
+the error stays at the paper's level (the FP64 oracle gives 4.7e-3 against 3.95e-3)."""
 import json
 import os
 
@@ -28,27 +29,31 @@ def l1_density_error(nx, limiter):
     p = adg.Problem(wl, precision=adg.ADG_FP64, flux=1, limiter=limiter)
     u0, _ = p.project(wl.ic, 0)
     p.set_state(u0)
+    max_troubled = 0
     while p.time < T_END * (1 - 1e-14):
         p.step(min(p.cfl_dt(), T_END - p.time))
+        max_troubled = max(max_troubled, int(p.troubled().sum()))
     ue, _ = p.project(lambda x, t: wl.ic(x, T_END), 0)
     n = wl.N + 1
     w1 = np.polynomial.legendre.leggauss(n)[1] / 2.0
     w = np.multiply.outer(w1, w1).ravel()
     h2 = (10.0 / nx) ** 2
     err = float((np.abs(p.state()[0] - ue[0]) @ w).sum() * h2)
-    troubled = int(p.troubled().sum())
     p.close()
-    return err, troubled
+    return err, max_troubled
 
 
-@pytest.mark.parametrize("nx,limiter", [(4, False), (8, True), (10, True), (12, True)])
-def test_vortex_p9_l1_error_against_table2(nx, limiter):
+@pytest.mark.parametrize("nx", [4, 8, 10, 12])
+def test_vortex_p9_l1_error_against_table2(nx):
     import torch
     assert torch.cuda.is_available()
     row = json.load(open(GOLDEN))["rows"]["9"]
     paper = row["L1"][row["Nx"].index(nx)]
-    err, troubled = l1_density_error(nx, limiter)
-    print(f"vortex N=9 {nx}^2 limiter={limiter}: L1 {err:.3e}, Table 2 {paper:.2e}, ratio {err / paper:.2f}",
-          flush=True)
+    err, max_troubled = l1_density_error(nx, True)
+    print(f"vortex N=9 {nx}^2 limited: L1 {err:.3e}, Table 2 {paper:.2e}, ratio {err / paper:.2f}, "
+          f"most troubled cells in a step {max_troubled}", flush=True)
     assert paper / 1.5 < err < paper * 1.5
-    assert troubled == 0
+    if nx >= 8:
+        assert max_troubled == 0   # resolved vortex: the limiter stays idle
+    else:
+        assert max_troubled <= 2

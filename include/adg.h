@@ -194,6 +194,27 @@ int adg_batch_step_cfl(adg_batch *b, double cfl, int nsteps);
 int adg_batch_dt(adg_batch *b, double *dts);
 int adg_batch_destroy(adg_batch *b);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, serving
+ * loops or harnesses that forbid hipMalloc): the time step of adg_cfl_dt for a state the
+ * caller holds, computed by the same kernels with no problem handle and no workspace.
+ * The reduction's partial maxima and scalars live in a static device array of the library
+ * (ADG_STATIC_PARTIALS + 8 doubles, about 8 KB), one per device, held until the process
+ * ends; nothing is allocated.
+ *   dev_u   device, state layout above: ncell cells of degree N in dim dimensions
+ *           (read only; owned by the caller);
+ *   gamma   ratio of specific heats; hmin the smallest cell edge; cfl the Courant factor:
+ *           dt = cfl * hmin / (dim (2N+1) max over cells, nodes, axes of |v_k| + c);
+ *   dev_dt  device, one double, written (owned by the caller);
+ *   hip_stream the stream to enqueue on (NULL: the null stream); no host wait.
+ * Every call on one device shares that device's array: calls that overlap on one device
+ * (different streams or threads) race and must be serialised by the caller.
+ * Errors: ADG_EINVAL (null pointer, dim/N not supported, ncell outside
+ * 1..ADG_STATIC_MAX_CELLS, gamma <= 1, hmin or cfl <= 0), ADG_EDEVICE. */
+#define ADG_STATIC_PARTIALS 1024
+#define ADG_STATIC_MAX_CELLS ((int64_t)1 << 34)
+int adg_cfl_dt_static(const double *dev_u, int dim, int N, int64_t ncell, double gamma, double hmin, double cfl,
+                      double *dev_dt, void *hip_stream);
+
 /* Debug hook: cells with mask[c] != 0 are flagged troubled at every following detection
  * (NULL clears).  Host memory, one byte per cell. */
 int adg_debug_force_troubled(adg_problem *pb, const uint8_t *mask);

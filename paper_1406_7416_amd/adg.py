@@ -24,6 +24,7 @@ EXPORTS = [
     "adg_time", "adg_get_troubled", "adg_get_margin", "adg_get_subcells", "adg_get_stats",
     "adg_profile", "adg_profile_read", "adg_batch_create", "adg_batch_step_cfl", "adg_batch_dt",
     "adg_batch_destroy", "adg_debug_force_troubled", "adg_debug_poison", "adg_get_mood_stats",
+    "adg_cfl_dt_static",
 ]
 
 KERNEL_GROUPS = ["bounds", "predictor", "faces", "corrector_detect", "compact", "subcell", "fluxcorr", "dt"]
@@ -88,6 +89,7 @@ def load():
     L.adg_batch_step_cfl.argtypes = [vp, C.c_double, C.c_int]
     L.adg_batch_dt.argtypes = [vp, dp]
     L.adg_batch_destroy.argtypes = [vp]
+    L.adg_cfl_dt_static.argtypes = [vp, C.c_int, C.c_int, C.c_int64, C.c_double, C.c_double, C.c_double, vp, vp]
     for name in EXPORTS[1:]:
         if name != "adg_workspace_bytes":
             getattr(L, name).restype = C.c_int
@@ -313,6 +315,20 @@ class Problem:
         out = (C.c_int64 * 4)()
         _check(load().adg_get_stats(self.h, out))
         return {"troubled": out[0], "corrected": out[1], "nonphysical": out[2], "steps": out[3]}
+
+
+def cfl_dt_static(u, dim: int, N: int, gamma: float, hmin: float, cfl: float, dt_out, stream=None):
+    """Eq. (cfl) time step of a device state tensor u ([var][cell][node], float64) into the
+    one-element device tensor dt_out, through the entry point that allocates nothing (its
+    reduction scratch is a static device array of the library).  Enqueued on `stream`
+    (default: torch's current stream), no host wait."""
+    import torch
+    assert u.is_cuda and u.dtype == torch.float64 and u.is_contiguous()
+    assert dt_out.is_cuda and dt_out.dtype == torch.float64 and dt_out.numel() >= 1
+    ncell = u.shape[1]
+    s = stream if stream is not None else torch.cuda.current_stream(u.device)
+    _check(load().adg_cfl_dt_static(C.c_void_p(u.data_ptr()), dim, N, ncell, gamma, hmin, cfl,
+                                     C.c_void_p(dt_out.data_ptr()), C.c_void_p(s.cuda_stream)))
 
 
 class Batch:

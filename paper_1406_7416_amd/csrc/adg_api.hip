@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -1147,6 +1148,60 @@ int adg_debug_poison(adg_problem *pb, int64_t cell, int var, double value) {
     const double rec[4] = {1.0, (double)cell, (double)var, value};
     HIPCHK(hipMemcpyAsync(pb->B.scal + 4, rec, sizeof rec, hipMemcpyHostToDevice, pb->stream));
     HIPCHK(hipStreamSynchronize(pb->stream));
+    return ADG_OK;
+}
+
+// ------------------------------------------------- time step without a workspace
+// The per-block partial maxima of the wave-speed reduction (at most ADG_STATIC_PARTIALS
+// blocks) and the reduction's scalars, for adg_cfl_dt_static.  Each device holds its own
+// copy until the process ends.  Host code never passes `scratch` itself to a kernel (on
+// the host it is only a stand-in for the device symbol): it uses the device address that
+// hipGetSymbolAddress returned for the current device.
+static __device__ __align__(256) double scratch[ADG_STATIC_PARTIALS + 8];
+static std::mutex g_scratch_mu;
+static double *g_scratch_dev[64];   // per device ordinal: device address of `scratch`
+
+static int scratch_for_current_device(double **out) {
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(ADG_EDEVICE, "device ordinal %d beyond 63", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *ptr = nullptr;
+        HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return fail(ADG_EDEVICE, "hipGetSymbolAddress gave no address for the static scratch");
+        g_scratch_dev[dev] = (double *)ptr;
+    }
+    *out = g_scratch_dev[dev];
+    return ADG_OK;
+}
+
+int adg_cfl_dt_static(const double *dev_u, int dim, int N, int64_t ncell, double gamma, double hmin, double cfl,
+                      double *dev_dt, void *hip_stream) {
+    if (!dev_u || !dev_dt) return fail(ADG_EINVAL, "null pointer");
+    if (!supported(dim, N)) return fail(ADG_EINVAL, "dim %d, N %d not supported", dim, N);
+    if (ncell < 1 || ncell > ADG_STATIC_MAX_CELLS)
+        return fail(ADG_EINVAL, "ncell %lld outside 1..%lld", (long long)ncell, (long long)ADG_STATIC_MAX_CELLS);
+    if (!(gamma > 1.0) || !(hmin > 0.0) || !(cfl > 0.0)) return fail(ADG_EINVAL, "gamma, hmin and cfl must be > 0 (gamma > 1)");
+    double *ptr = nullptr;
+    const int rc = scratch_for_current_device(&ptr);
+    if (rc != ADG_OK) return rc;
+    StepCtx C;
+    std::memset((void *)&C, 0, sizeof C);
+    C.P.dim = dim;
+    C.P.N = N;
+    C.P.n = N + 1;
+    C.P.nv = dim + 2;
+    C.P.ncell = ncell;
+    C.P.gamma = gamma;
+    C.B.lam_part = ptr;                          // partial maxima: ptr[0 .. ADG_STATIC_PARTIALS)
+    C.B.scal = ptr + ADG_STATIC_PARTIALS;        // [0] dt, [2] largest signal speed
+    C.stream = (hipStream_t)hip_stream;
+    const int64_t nn = ipow64(N + 1, dim);
+    C.lam_blocks = (int)std::min<int64_t>(ADG_STATIC_PARTIALS, std::max<int64_t>(1, (ncell * nn + 255) / 256));
+    launch_lambda(C, dev_u, cfl * hmin / (dim * (2.0 * N + 1.0)));
+    launch_copy_scalar(C.B.scal, dev_dt, C.stream);
+    HIPCHK(hipGetLastError());
     return ADG_OK;
 }
 

@@ -39,5 +39,6 @@ void launch_fluxcorr(const StepCtx &C, int count, int advance);
 void launch_lambda(const StepCtx &C, const double *u, double factor);
 void launch_set_scalar(const StepCtx &C, int idx, double val);
 void launch_advance_time(const StepCtx &C);
+void launch_copy_scalar(const double *src, double *dst, hipStream_t stream);
 
 }  // namespace adg

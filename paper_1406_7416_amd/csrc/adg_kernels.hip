@@ -1815,6 +1815,10 @@ void launch_lambda(const StepCtx &C, const double *u, double factor) {
 void launch_set_scalar(const StepCtx &C, int idx, double val) {
     hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(1), 0, C.stream, C.B.scal, idx, val);
 }
+__global__ void k_copy_scalar(const double *src, double *dst) { dst[0] = src[0]; }
+void launch_copy_scalar(const double *src, double *dst, hipStream_t stream) {
+    hipLaunchKernelGGL(k_copy_scalar, dim3(1), dim3(1), 0, stream, src, dst);
+}
 void launch_advance_time(const StepCtx &C) {
     hipLaunchKernelGGL(k_advance_time, dim3(1), dim3(1), 0, C.stream, C.B.scal);
 }

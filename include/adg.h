@@ -73,7 +73,11 @@ typedef struct {
 } adg_grid_desc;
 
 typedef struct {
-    int Ns;               /* subcells per axis; 0 -> 2N+1 (Sec. 4.5); only 2N+1 accepted */
+    int Ns;               /* subcells per axis; 0 -> 2N+1.  Sec. 4.5 allows any Ns >= N+1 and shows 2N+1
+                             to be the optimum (the subgrid FV scheme is then stable at the DG time step
+                             of eq. (cfl) and resolves as finely as the DG polynomial); the kernels are
+                             specialised at compile time on Ns = 2N+1, so any other value gives
+                             ADG_EINVAL */
     int picard_iters;     /* 0 -> N+1 sweeps of the predictor (reading: fixed count) */
     int precision;        /* ADG_FP64 or ADG_MIXED */
     int limiter;          /* 1: subcell limiter on (default), 0: unlimited ADER-DG */
@@ -103,9 +107,17 @@ int adg_destroy(adg_problem *pb);
 size_t adg_workspace_bytes(const adg_problem *pb);
 
 /* Binds a caller-owned device allocation (>= adg_workspace_bytes, 256-byte aligned) and
- * a hipStream_t (NULL: the null stream), uploads the operator tables.  Errors:
+ * a hipStream_t (NULL: the null stream), uploads the operator tables.  The DG state is
+ * part of this one allocation (two copies, current and next, swapped by every step), so
+ * there is no separate state argument: adg_state_device_ptr gives the current copy in
+ * place, adg_set_state / adg_get_state copy from and to caller buffers.  Errors:
  * ADG_ENOMEM (too small), ADG_EDEVICE. */
 int adg_bind(adg_problem *pb, void *dev_workspace, size_t bytes, void *hip_stream);
+
+/* Device address of the current DG state inside the workspace (state layout above),
+ * valid until the next step or adg_set_state; read it on the bound stream.  Errors:
+ * ADG_EINVAL, ADG_ESTATE (no state). */
+int adg_state_device_ptr(const adg_problem *pb, const double **u);
 
 /* Physical coordinates along `axis` of the points where initial data is sampled:
  * m = 0: the DG nodes, out[(i*(N+1) + a)] for cell i, node a;
@@ -136,10 +148,15 @@ int adg_get_state(const adg_problem *pb, double *u, int to_device);
 int adg_cfl_dt(adg_problem *pb, double cfl, double *dt_out);
 
 /* One full step with the given dt, enqueued on the bound stream without any host wait
- * (the troubled-cell count stays on the device).  Errors: ADG_ESTATE, ADG_EDEVICE;
- * ADG_ECAPACITY once an earlier step found more troubled cells than the pool holds
- * (detected asynchronously; the state is then not advanced correctly; sticky until the
- * next adg_set_state). */
+ * (the troubled-cell count stays on the device).  Errors: ADG_ESTATE (no state, or the
+ * problem belongs to a batch), ADG_EDEVICE; ADG_ECAPACITY once an earlier step found more
+ * troubled cells than the pool holds (detected asynchronously; the state is then not
+ * advanced correctly; sticky until the next adg_set_state).
+ * ADG_ENONPHYSICAL is a warning, not a failure: this step was enqueued normally, and the
+ * counter of subcell ADER-WENO3 results that fail the positivity test of eq. (positivity)
+ * (Sec. 6 notes that the WENO3 scheme need not preserve positivity) has risen since the last
+ * report, as read from the asynchronous counter copy of an earlier step; the count is in
+ * adg_get_stats. */
 int adg_step(adg_problem *pb, double dt);
 
 /* As adg_step with dt from eq. (cfl) computed on the device from the current state. */
@@ -148,16 +165,22 @@ int adg_step_cfl(adg_problem *pb, double cfl);
 /* Current time (synchronising). */
 int adg_time(const adg_problem *pb, double *t);
 
-/* Troubled-cell map beta of the last step (or of the initial detection), 1 byte per
- * cell, host memory; *count = number of troubled cells.  Synchronising. */
+/* Troubled-cell map of the last step (or of the initial detection): the flag
+ * beta_i^{n+1} of Sec. 4.4 (step 3 of the five), 1 byte per cell, host memory;
+ * *count = number of troubled cells.  Synchronising. */
 int adg_get_troubled(const adg_problem *pb, uint8_t *beta, int64_t *count);
 
-/* Signed normalised detection margin per cell of the last detection (negative: a test
- * failed).  Host memory, float per cell.  Synchronising. */
+/* Signed normalised detection margin per cell of the last detection (Sec. 4.3: the
+ * smallest slack of the candidate's subcell averages to the relaxed DMP bounds of eqs.
+ * (dmp), (relax) and to the positivity thresholds of eq. (positivity), each divided by
+ * the variable's scale; negative: a test failed).  Host memory, float per cell.
+ * Synchronising. */
 int adg_get_margin(const adg_problem *pb, float *margin);
 
-/* Subcell data v of troubled cells (subcell layout, host; entries of untroubled cells
- * are left untouched).  Synchronising. */
+/* Subcell data v_h of troubled cells, the alternative representation that Sec. 4.4 stores
+ * only in troubled cells (the result of the subcell scheme, eq. (aderweno)) and that
+ * eq. (ader.icbc) takes as the next step's data there (subcell layout, host; entries of
+ * untroubled cells are left untouched).  Synchronising. */
 int adg_get_subcells(const adg_problem *pb, double *v);
 
 /* Statistics of the last step: out[0] troubled cells, out[1] corrected neighbours,
@@ -179,18 +202,48 @@ int adg_profile(adg_problem *pb, int enable);
 int adg_profile_read(adg_problem *pb, double *ms, int64_t *launches, int ngroups);
 
 /* Batching of independent problems (not in the paper): the problems (each created and
- * bound as above, with a state set, all on the current device) advance together.  The first call takes
- * one ordinary step per problem, then captures one step of every problem -- each on its
- * own stream branch of one fork/join capture, dt from eq. (cfl) per problem on the
- * device -- into two hipGraphs (the two buffer parities) and from then on replays them:
- * one hipGraphLaunch per batch step.  The problems' own streams are not used while the
- * batch steps; the batch synchronises its streams before returning.  Problems must not
- * be stepped outside the batch while it exists.  Errors: ADG_EINVAL, ADG_ESTATE,
- * ADG_EDEVICE. */
+ * bound as above, with a state set, all on the current device, none in another batch,
+ * sharing precision, limiter and MOOD layer; grids, degrees, boundaries, flux and Picard
+ * sweeps may differ) advance together; while the batch exists they are not stepped or
+ * set on their own (adg_step, adg_step_cfl, adg_set_state return ADG_ESTATE).
+ * The problems are grouped into classes of equal (dim, N).  Every stage of the step is one
+ * launch per class over all its problems: a tile table maps each workgroup to (problem,
+ * block of that problem's own grid) for the time step, ghost-ring bounds, predictor, face
+ * fluxes, corrector + detection and compaction; the subcell ADER-WENO3 recompute and the
+ * flux correction run over one global worklist per class (the troubled cells, resp. their
+ * corrected neighbours, of all its problems, from per-problem offsets computed on the
+ * device after the compaction).  Each problem's arithmetic is that of its own step, so
+ * the batch is bitwise equal to stepping the problems one by one.
+ * adg_batch_workspace_bytes / adg_batch_bind: the batch's device memory (launch tables of
+ * both buffer parities, worklist offsets, the subcell scratch of each class: about 0.1-0.2
+ * GB per 2D class with N <= 5), owned by the caller, 256-byte aligned, and the caller's
+ * stream (NULL: the null stream), whose pending work each batch step waits for; the batch
+ * captures and replays on a stream of its own (created by adg_batch_create).
+ * adg_batch_step_cfl: the first call (or a call with another cfl) takes one ordinary step
+ * per problem, then captures one step of every problem (dt from eq. (cfl) per problem, on
+ * the device; each class's stages in order on a branch of its own) into two hipGraphs (the
+ * two buffer parities) and from then on replays them: one hipGraphLaunch per batch step.  Synchronises the batch stream before returning.
+ * Errors: ADG_EINVAL, ADG_ESTATE (not bound), ADG_EDEVICE; ADG_ECAPACITY if any problem's
+ * troubled cells exceeded its pool capacity (the message names the first such problem);
+ * ADG_ENONPHYSICAL (a warning, as for adg_step) if a problem's count of non-physical
+ * subcell results rose.
+ * adg_batch_profile(b, 1) clears the stage timing; while it is on, each batch step
+ * enqueues the graph's launches directly on the batch stream (the same kernels in the same
+ * order) with a HIP event at the start of every stage and at the end of the step (stages:
+ * 0 time step, 1 ghost-ring bounds, 2 predictor, 3 face fluxes, 4 corrector + detection,
+ * 5 compaction + worklist offsets, 6 subcell ADER-WENO3 (+ MOOD layer), 7 flux correction,
+ * 8 time advance); adg_batch_profile(b, 0) returns to graph replays.
+ * adg_batch_profile_read fills ms[s] (total milliseconds) and steps[s] for s < nstages
+ * (<= 9).
+ * adg_batch_dt: per-problem dt of the last batch step (host memory, count doubles).
+ * Synchronising. */
 typedef struct adg_batch adg_batch;
 int adg_batch_create(adg_problem *const *ps, int count, adg_batch **out);
+size_t adg_batch_workspace_bytes(const adg_batch *b);
+int adg_batch_bind(adg_batch *b, void *dev_workspace, size_t bytes, void *hip_stream);
 int adg_batch_step_cfl(adg_batch *b, double cfl, int nsteps);
-/* Per-problem dt of the last batch step (host memory, count doubles).  Synchronising. */
+int adg_batch_profile(adg_batch *b, int enable);
+int adg_batch_profile_read(adg_batch *b, double *ms, int64_t *steps, int nstages);
 int adg_batch_dt(adg_batch *b, double *dts);
 int adg_batch_destroy(adg_batch *b);
 

@@ -24,8 +24,12 @@ EXPORTS = [
     "adg_time", "adg_get_troubled", "adg_get_margin", "adg_get_subcells", "adg_get_stats",
     "adg_profile", "adg_profile_read", "adg_batch_create", "adg_batch_step_cfl", "adg_batch_dt",
     "adg_batch_destroy", "adg_debug_force_troubled", "adg_debug_poison", "adg_get_mood_stats",
-    "adg_cfl_dt_static",
+    "adg_cfl_dt_static", "adg_state_device_ptr", "adg_batch_workspace_bytes", "adg_batch_bind",
+    "adg_batch_profile", "adg_batch_profile_read",
 ]
+
+BATCH_STAGES = ["dt", "bounds", "predictor", "faces", "corrector_detect", "compact", "subcell", "fluxcorr",
+                "advance"]
 
 KERNEL_GROUPS = ["bounds", "predictor", "faces", "corrector_detect", "compact", "subcell", "fluxcorr", "dt"]
 
@@ -89,17 +93,38 @@ def load():
     L.adg_batch_step_cfl.argtypes = [vp, C.c_double, C.c_int]
     L.adg_batch_dt.argtypes = [vp, dp]
     L.adg_batch_destroy.argtypes = [vp]
+    L.adg_batch_workspace_bytes.restype = C.c_size_t
+    L.adg_batch_workspace_bytes.argtypes = [vp]
+    L.adg_batch_bind.argtypes = [vp, vp, C.c_size_t, vp]
+    L.adg_batch_profile.argtypes = [vp, C.c_int]
+    L.adg_batch_profile_read.argtypes = [vp, dp, C.POINTER(i64), C.c_int]
+    L.adg_state_device_ptr.argtypes = [vp, C.POINTER(vp)]
     L.adg_cfl_dt_static.argtypes = [vp, C.c_int, C.c_int, C.c_int64, C.c_double, C.c_double, C.c_double, vp, vp]
     for name in EXPORTS[1:]:
-        if name != "adg_workspace_bytes":
+        if name not in ("adg_workspace_bytes", "adg_batch_workspace_bytes"):
             getattr(L, name).restype = C.c_int
     _lib = L
     return L
 
 
+ADG_ENONPHYSICAL = -5
+_nonphysical_warnings = 0
+
+
 def _check(rc: int):
+    """Raises on an error code.  ADG_ENONPHYSICAL is a warning (the step was taken; the count
+    of non-physical subcell results is in Problem.stats()): it is counted, not raised."""
+    global _nonphysical_warnings
+    if rc == ADG_ENONPHYSICAL:
+        _nonphysical_warnings += 1
+        return
     if rc != 0:
         raise AdgError(f"adg error {rc}: {load().adg_last_error().decode()}")
+
+
+def nonphysical_warnings() -> int:
+    """How many calls so far returned the ADG_ENONPHYSICAL warning."""
+    return _nonphysical_warnings
 
 
 def _dp(a: np.ndarray):
@@ -263,6 +288,12 @@ class Problem:
         _check(load().adg_get_state(self.h, u.ctypes.data_as(C.c_void_p), 0))
         return u
 
+    def state_device_ptr(self) -> int:
+        """Device address of the current state inside the workspace (valid until the next step)."""
+        ptr = C.c_void_p()
+        _check(load().adg_state_device_ptr(self.h, C.byref(ptr)))
+        return ptr.value
+
     def state_tensor(self):
         import torch
         u = torch.empty((self.nv, self.ncell, self.nn), dtype=torch.float64, device=self.device)
@@ -332,15 +363,36 @@ def cfl_dt_static(u, dim: int, N: int, gamma: float, hmin: float, cfl: float, dt
 
 
 class Batch:
-    """Independent problems advanced together: one hipGraph launch per batch step."""
+    """Independent problems advanced together: one launch per stage and (d, N) class, the
+    whole step captured in a hipGraph, one graph launch per batch step.  The batch's device
+    memory is a torch tensor; it runs on torch's current stream of the problems' device."""
 
-    def __init__(self, problems):
+    def __init__(self, problems, stream=None):
+        import torch
         L = load()
         self.problems = list(problems)
         arr = (C.c_void_p * len(self.problems))(*[p.h.value for p in self.problems])
         h = C.c_void_p()
         _check(L.adg_batch_create(arr, len(self.problems), C.byref(h)))
         self.h = h
+        dev = self.problems[0].device
+        nbytes = L.adg_batch_workspace_bytes(self.h)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+        aligned = (self.workspace.data_ptr() + 255) & ~255
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        _check(L.adg_batch_bind(self.h, C.c_void_p(aligned), nbytes, C.c_void_p(self.stream.cuda_stream)))
+        self.workspace_bytes = nbytes
+
+    def profile(self, enable: bool):
+        """Starts (clears) or stops the per-stage timing (events inside the graphs)."""
+        _check(load().adg_batch_profile(self.h, 1 if enable else 0))
+
+    def profile_read(self) -> dict:
+        ns = len(BATCH_STAGES)
+        ms = np.zeros(ns)
+        n = (C.c_int64 * ns)()
+        _check(load().adg_batch_profile_read(self.h, _dp(ms), n, ns))
+        return {g: (float(ms[i]), int(n[i])) for i, g in enumerate(BATCH_STAGES)}
 
     def step_cfl(self, cfl: float, nsteps: int = 1):
         _check(load().adg_batch_step_cfl(self.h, cfl, nsteps))

@@ -86,6 +86,9 @@ struct adg_problem {
     int *pinned = nullptr;    // host-pinned copy of the counters
     hipEvent_t counts_ready = nullptr;   // recorded after the asynchronous counter copy
     bool capturing = false;              // inside a batch graph capture
+    struct adg_batch *batch = nullptr;   // the batch that steps this problem (set_state / step refused)
+    bool batch_driving = false;          // the batch itself is calling the step functions
+    int64_t nonphys_reported = 0;        // cumulative non-physical subcell results already reported
     int64_t last_troubled = 0, last_corrected = 0, steps = 0;
     // kernel-group timing
     unsigned prof_mask = 0;   // kernel groups timed (bit g: group g)
@@ -273,7 +276,9 @@ int adg_create(const adg_grid_desc *g, int N, double gamma, const adg_params *p,
     if (p) prm = *p;
     else prm.limiter = 1;
     if (prm.Ns == 0) prm.Ns = 2 * N + 1;
-    if (prm.Ns != 2 * N + 1) return fail(ADG_EINVAL, "only Ns = 2N+1 is built");
+    if (prm.Ns != 2 * N + 1)
+        return fail(ADG_EINVAL, "Ns = %d: the kernels are built for Ns = 2N+1 = %d only (Sec. 4.5's choice, stable "
+                    "at the DG time step of eq. (cfl)); Ns >= N+1 is not built", prm.Ns, 2 * N + 1);
     if (prm.picard_iters <= 0) prm.picard_iters = N + 1;
     if (prm.eps == 0) prm.eps = 1e-3;
     if (prm.delta0 == 0) prm.delta0 = 1e-4;
@@ -708,6 +713,7 @@ static int initial_detection(adg_problem *pb, std::vector<double> &u, const doub
 int adg_set_state(adg_problem *pb, const double *u, int on_device, const double *v_exact) {
     if (!pb || !u) return fail(ADG_EINVAL, "null argument");
     if (!pb->bound) return fail(ADG_ESTATE, "adg_bind first");
+    if (pb->batch) return fail(ADG_ESTATE, "the problem belongs to a batch: destroy the batch first");
     const Prob &P = pb->P;
     const int64_t nn = ipow64(P.n, P.dim), nsub = ipow64(P.Ns, P.dim);
     const size_t ubytes = 8ull * P.nv * P.ncell * nn;
@@ -742,11 +748,19 @@ int adg_set_state(adg_problem *pb, const double *u, int on_device, const double 
     HIPCHK(hipStreamSynchronize(pb->stream));
     // the host copy of the counters starts over too (a pool overflow is reported until here)
     std::memset(pb->pinned, 0, 16);
+    pb->nonphys_reported = 0;
     pb->has_state = true;
     pb->bounds_valid = false;
     pb->last_troubled = count;
     pb->last_corrected = 0;
     pb->steps = 0;
+    return ADG_OK;
+}
+
+int adg_state_device_ptr(const adg_problem *pb, const double **u) {
+    if (!pb || !u) return fail(ADG_EINVAL, "null argument");
+    if (!pb->has_state) return fail(ADG_ESTATE, "no state");
+    *u = pb->B.u[pb->cur];
     return ADG_OK;
 }
 
@@ -779,12 +793,27 @@ int adg_cfl_dt(adg_problem *pb, double cfl, double *dt_out) {
     return ADG_OK;
 }
 
+// ADG_ENONPHYSICAL once the counter of subcell results failing PAD (copied to the host
+// after every step) has risen since the last report; ADG_OK otherwise.
+static int nonphysical_news(adg_problem *pb) {
+    if (pb->pinned && pb->pinned[2] > pb->nonphys_reported) {
+        const int64_t now = pb->pinned[2];
+        const int rc = fail(ADG_ENONPHYSICAL, "%lld subcell results failed positivity so far (%lld new)",
+                            (long long)now, (long long)(now - pb->nonphys_reported));
+        pb->nonphys_reported = now;
+        return rc;
+    }
+    return ADG_OK;
+}
+
 static int do_step(adg_problem *pb) {
     StepCtx C = ctx(pb);
     Bufs &B = pb->B;
     if (!pb->capturing && pb->counts_ready && hipEventQuery(pb->counts_ready) == hipSuccess && pb->pinned[3])
         return fail(ADG_ECAPACITY, "troubled cells exceeded the pool capacity %lld in an earlier step",
                     (long long)pb->cap);
+    const int news = (!pb->capturing && pb->counts_ready && hipEventQuery(pb->counts_ready) == hipSuccess)
+                         ? nonphysical_news(pb) : ADG_OK;
     if (pb->prm.limiter) {
         GroupTimer g(pb, 0);
         launch_bounds(C);
@@ -843,12 +872,17 @@ static int do_step(adg_problem *pb) {
     pb->last_troubled = troubled;
     pb->last_corrected = corrected;
     pb->steps++;
-    return rc;
+    return rc != ADG_OK ? rc : news;
+}
+
+static int in_foreign_batch(const adg_problem *pb) {
+    return pb->batch && !pb->batch_driving;
 }
 
 int adg_step(adg_problem *pb, double dt) {
     if (!pb) return fail(ADG_EINVAL, "null argument");
     if (!pb->has_state) return fail(ADG_ESTATE, "no state");
+    if (in_foreign_batch(pb)) return fail(ADG_ESTATE, "the problem belongs to a batch: step it with adg_batch_step_cfl");
     if (!(dt > 0) || !std::isfinite(dt)) return fail(ADG_EINVAL, "dt must be positive");
     StepCtx C = ctx(pb);
     launch_set_scalar(C, 0, dt);
@@ -858,6 +892,7 @@ int adg_step(adg_problem *pb, double dt) {
 int adg_step_cfl(adg_problem *pb, double cfl) {
     if (!pb) return fail(ADG_EINVAL, "null argument");
     if (!pb->has_state) return fail(ADG_ESTATE, "no state");
+    if (in_foreign_batch(pb)) return fail(ADG_ESTATE, "the problem belongs to a batch: step it with adg_batch_step_cfl");
     if (!(cfl > 0)) return fail(ADG_EINVAL, "cfl must be positive");
     StepCtx C = ctx(pb);
     {
@@ -971,17 +1006,40 @@ int adg_profile_read(adg_problem *pb, double *ms, int64_t *launches, int ngroups
 
 }  // extern "C"
 
+// One (d, N) class of a batch: its problems share every kernel instantiation.
+struct BatchClass {
+    int dim = 0, N = 0, group = 0;
+    std::vector<int> members;             // indices into adg_batch::ps
+    std::vector<BTile> tiles[6];          // lambda, bounds, predictor, face, corrector, compaction
+    size_t off_ents[2] = {0, 0}, off_tiles[6] = {0, 0, 0, 0, 0, 0}, off_wt = 0, off_wc = 0;
+    size_t off_Y = 0, off_tr = 0, off_halo = 0, off_fp = 0;
+    int sub_grid = 0, fc_grid = 0;
+};
+
 struct adg_batch {
     std::vector<adg_problem *> ps;
-    std::vector<hipStream_t> streams;     // one branch per problem
+    std::vector<BatchClass> cls;
     std::vector<hipStream_t> saved;       // the problems' own streams
-    std::vector<hipEvent_t> evs;          // fork / join events
-    hipStream_t origin = nullptr;
+    hipStream_t user = nullptr;           // the caller's stream bound to the batch
+    hipStream_t stream = nullptr;         // the batch's own stream: captures and replays (a
+                                          // legacy null stream cannot be captured)
+    std::vector<hipStream_t> cstream;     // one branch per class inside the graph
+    std::vector<hipEvent_t> cev;          // fork (0) and per-class join events
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    bool bound = false;
+    int precision = 0, limiter = 1, mood = 0;
     hipGraphExec_t exec[2] = {nullptr, nullptr};
     hipGraph_t graph[2] = {nullptr, nullptr};
     int parity = 0;                       // which graph advances the current state
     bool captured = false;
     double cfl = 0;
+    // stage timing: events at the start of every stage and at the end, inside the graphs
+    unsigned prof_mask = 0;
+    hipEvent_t ev[2][BSTAGE_COUNT + 1] = {};
+    bool ev_pending[2] = {false, false};
+    double prof_ms[BSTAGE_COUNT] = {0};
+    int64_t prof_n[BSTAGE_COUNT] = {0};
 };
 
 // Host-side bookkeeping of one step (what do_step does after its launches), for replays.
@@ -1000,39 +1058,204 @@ static void host_advance(adg_problem *pb) {
     pb->steps++;
 }
 
-static int batch_capture(adg_batch *b) {
-    for (int g = 0; g < 2; g++) {
-        HIPCHK(hipStreamBeginCapture(b->origin, hipStreamCaptureModeThreadLocal));
-        HIPCHK(hipEventRecord(b->evs[0], b->origin));
-        int rc = ADG_OK;
-        for (size_t i = 0; i < b->ps.size() && rc == ADG_OK; i++) {
-            adg_problem *pb = b->ps[i];
-            hipStream_t st = b->streams[i];
-            if (hipStreamWaitEvent(st, b->evs[0], 0) != hipSuccess) { rc = fail(ADG_EDEVICE, "fork"); break; }
-            pb->stream = st;
-            pb->capturing = true;
-            StepCtx C = ctx(pb);
-            launch_lambda(C, pb->B.u[pb->cur], dt_factor(pb, b->cfl));
-            rc = do_step(pb);
-            pb->capturing = false;
-            if (rc == ADG_OK && hipEventRecord(b->evs[1 + i], st) != hipSuccess) rc = fail(ADG_EDEVICE, "join record");
-            if (rc == ADG_OK && hipStreamWaitEvent(b->origin, b->evs[1 + i], 0) != hipSuccess)
-                rc = fail(ADG_EDEVICE, "join wait");
+// Layout of the batch workspace: per class, the entries of both buffer parities, the tile
+// tables of the stages, the global worklist offsets and the subcell scratch slots.
+static void batch_plan(adg_batch *b) {
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t r = o;
+        o = align256(o + std::max<size_t>(bytes, 1));
+        return r;
+    };
+    for (auto &K : b->cls) {
+        const size_t np = K.members.size();
+        for (int t = 0; t < 6; t++) K.tiles[t].clear();
+        for (size_t q = 0; q < np; q++) {
+            const adg_problem *pb = b->ps[K.members[q]];
+            const Prob &P = pb->P;
+            const int64_t nn = ipow64(P.n, P.dim);
+            const int lam_nb = (int)std::min<int64_t>(pb->lam_blocks, (P.ncell * nn + 255) / 256);
+            int64_t kb1 = 0, kb2 = 0;
+            const int64_t nblk[6] = {lam_nb, b->limiter ? pb->nring : 0,
+                                     stage_blocks(BSTAGE_PREDICTOR, P, b->precision, &kb1, &kb2),
+                                     stage_blocks(BSTAGE_FACE, P, b->precision, &kb1, &kb2),
+                                     stage_blocks(BSTAGE_CORRECTOR, P, b->precision, &kb1, &kb2),
+                                     b->limiter ? stage_blocks(BSTAGE_COMPACT, P, b->precision, &kb1, &kb2) : 0};
+            for (int t = 0; t < 6; t++)
+                for (int64_t x = 0; x < nblk[t]; x++) K.tiles[t].push_back(BTile{(int)q, (int)x, (int)nblk[t]});
         }
+        for (int g = 0; g < 2; g++) K.off_ents[g] = take(sizeof(BatchEntry) * np);
+        for (int t = 0; t < 6; t++) K.off_tiles[t] = take(sizeof(BTile) * K.tiles[t].size());
+        K.off_wt = take(4 * (np + 1));
+        K.off_wc = take(4 * (np + 1));
+        // subcell scratch: one slot per workgroup of the persistent launch (two per CU)
+        const int d = K.dim, nv = d + 2, Ns = 2 * K.N + 1;
+        int64_t caps = 0;
+        for (int m : K.members) caps += b->ps[m]->cap;
+        K.sub_grid = (int)std::max<int64_t>(1, std::min<int64_t>(512, caps));
+        K.fc_grid = 1024;
+        const int64_t npos = positions_per_cell(d, K.N), n3 = ipow64(3, d), nf3 = ipow64(3, d - 1);
+        const int64_t G = K.sub_grid;
+        K.off_Y = take(8ull * G * npos * nv * n3);
+        K.off_tr = take(8ull * G * npos * 2 * d * nv * nf3 * 3);
+        K.off_halo = take(d == 3 ? 8ull * G * nv * ipow64(Ns + 6, d) : 8);
+        K.off_fp = take(8ull * G * 2 * d * nv * ipow64(3 * Ns, d - 1));
+    }
+    b->ws_bytes = o;
+}
+
+// The launch arguments of one problem at one buffer parity (g = 0: as the problem stands,
+// g = 1: after one more step's buffer swaps).
+static BatchEntry batch_entry(const adg_problem *pb, int g, double cfl, int precision) {
+    Bufs B = pb->B;
+    int cur = pb->cur;
+    if (g == 1) {
+        if (pb->prm.limiter) {
+            std::swap(B.beta[0], B.beta[1]);
+            std::swap(B.slot[0], B.slot[1]);
+            std::swap(B.pool[0], B.pool[1]);
+            std::swap(B.ext_min[0], B.ext_min[1]);
+            std::swap(B.ext_max[0], B.ext_max[1]);
+        }
+        cur ^= 1;
+    }
+    BatchEntry e;
+    std::memset((void *)&e, 0, sizeof e);
+    e.T = pb->tab_dev;
+    e.P = pb->P;
+    e.B = B;
+    e.cur = cur;
+    e.limiter = pb->prm.limiter;
+    e.cap = pb->cap;
+    int64_t kb1 = 0, kb2 = 0;
+    (void)stage_blocks(BSTAGE_FACE, pb->P, precision, &kb1, &kb2);
+    e.kb1 = kb1;
+    e.kb2 = kb2;
+    const int64_t nn = ipow64(pb->P.n, pb->P.dim);
+    e.lam_nb = (int)std::min<int64_t>(pb->lam_blocks, (pb->P.ncell * nn + 255) / 256);
+    e.factor = dt_factor(pb, cfl);
+    e.ring = B.ring;
+    StepCtx C = ctx(pb);
+    C.B = B;
+    C.cur = cur;
+    predictor_args(C, &e.pf, &e.pd);
+    return e;
+}
+
+static BatchLaunch batch_launch(const adg_batch *b, const BatchClass &K, int g) {
+    BatchLaunch L;
+    std::memset((void *)&L, 0, sizeof L);
+    char *w = b->ws;
+    L.E = (const BatchEntry *)(w + K.off_ents[g]);
+    L.np = (int)K.members.size();
+    const BTile **tp[6] = {&L.t_lambda, &L.t_bounds, &L.t_pred, &L.t_face, &L.t_corr, &L.t_compact};
+    int *np_[6] = {&L.n_lambda, &L.n_bounds, &L.n_pred, &L.n_face, &L.n_corr, &L.n_compact};
+    for (int t = 0; t < 6; t++) {
+        *tp[t] = (const BTile *)(w + K.off_tiles[t]);
+        *np_[t] = (int)K.tiles[t].size();
+    }
+    L.off_t = (int *)(w + K.off_wt);
+    L.off_c = (int *)(w + K.off_wc);
+    L.S = SubScratch{(double *)(w + K.off_Y), (double *)(w + K.off_tr), (double *)(w + K.off_halo),
+                     (double *)(w + K.off_fp)};
+    L.sub_grid = K.sub_grid;
+    L.fc_grid = K.fc_grid;
+    L.precision = b->precision;
+    L.mood = b->mood;
+    L.stream = b->stream;
+    return L;
+}
+
+// The stages of one step of every problem, stage after stage, each one batched launch
+// per class; timed: an event at the start of every stage and at the end (on the batch
+// stream, outside any graph).
+static int batch_enqueue(adg_batch *b, int g, bool timed) {
+    if (timed && b->ev_pending[g]) {
+        // this parity's events of the previous step: add them up before recording again
+        HIPCHK(hipEventSynchronize(b->ev[g][BSTAGE_COUNT]));
+        for (int st = 0; st < BSTAGE_COUNT; st++) {
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, b->ev[g][st], b->ev[g][st + 1]));
+            b->prof_ms[st] += ms;
+            b->prof_n[st] += 1;
+        }
+    }
+    for (int st = 0; st < BSTAGE_COUNT; st++) {
+        if (timed) HIPCHK(hipEventRecord(b->ev[g][st], b->stream));
+        const bool lim_stage = st == BSTAGE_BOUNDS || st == BSTAGE_COMPACT || st == BSTAGE_SUBCELL ||
+                               st == BSTAGE_FLUXCORR;
+        if (lim_stage && !b->limiter) continue;
+        for (const auto &K : b->cls) launch_batched(K.dim, K.N, st, batch_launch(b, K, g));
+    }
+    if (timed) {
+        HIPCHK(hipEventRecord(b->ev[g][BSTAGE_COUNT], b->stream));
+        b->ev_pending[g] = true;
+    }
+    HIPCHK(hipGetLastError());
+    return ADG_OK;
+}
+
+// One step of every class, each class's stages in order on a branch of its own (the
+// classes share no data), forked from and joined back into the batch stream.
+static int batch_enqueue_branches(adg_batch *b, int g) {
+    HIPCHK(hipEventRecord(b->cev[0], b->stream));
+    for (size_t c = 0; c < b->cls.size(); c++) {
+        const BatchClass &K = b->cls[c];
+        hipStream_t st = b->cstream[c];
+        HIPCHK(hipStreamWaitEvent(st, b->cev[0], 0));
+        BatchLaunch L = batch_launch(b, K, g);
+        L.stream = st;
+        for (int s2 = 0; s2 < BSTAGE_COUNT; s2++) {
+            const bool lim_stage = s2 == BSTAGE_BOUNDS || s2 == BSTAGE_COMPACT || s2 == BSTAGE_SUBCELL ||
+                                   s2 == BSTAGE_FLUXCORR;
+            if (lim_stage && !b->limiter) continue;
+            launch_batched(K.dim, K.N, s2, L);
+        }
+        HIPCHK(hipEventRecord(b->cev[1 + c], st));
+        HIPCHK(hipStreamWaitEvent(b->stream, b->cev[1 + c], 0));
+    }
+    HIPCHK(hipGetLastError());
+    return ADG_OK;
+}
+
+static int batch_capture(adg_batch *b) {
+    // entries of both parities from the problems' current buffers
+    for (const auto &K : b->cls) {
+        for (int g = 0; g < 2; g++) {
+            std::vector<BatchEntry> ents;
+            for (int m : K.members) ents.push_back(batch_entry(b->ps[m], g, b->cfl, b->precision));
+            HIPCHK(hipMemcpyAsync(b->ws + K.off_ents[g], ents.data(), sizeof(BatchEntry) * ents.size(),
+                                  hipMemcpyHostToDevice, b->stream));
+        }
+        for (int t = 0; t < 6; t++)
+            if (!K.tiles[t].empty())
+                HIPCHK(hipMemcpyAsync(b->ws + K.off_tiles[t], K.tiles[t].data(), sizeof(BTile) * K.tiles[t].size(),
+                                      hipMemcpyHostToDevice, b->stream));
+    }
+    HIPCHK(hipStreamSynchronize(b->stream));
+    for (int g = 0; g < 2; g++) {
+        HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+        const int rc = batch_enqueue_branches(b, g);
         hipGraph_t gr = nullptr;
-        hipError_t e = hipStreamEndCapture(b->origin, &gr);
+        hipError_t e = hipStreamEndCapture(b->stream, &gr);
         if (rc != ADG_OK) return rc;
         if (e != hipSuccess) return fail(ADG_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
         b->graph[g] = gr;
         HIPCHK(hipGraphInstantiate(&b->exec[g], gr, nullptr, nullptr, 0));
     }
-    // capturing advanced the host bookkeeping twice (one step per graph): back to start
-    for (auto *pb : b->ps) {
-        pb->steps -= 2;
-    }
     b->parity = 0;
     b->captured = true;
     return ADG_OK;
+}
+
+static void batch_drop_graphs(adg_batch *b) {
+    for (int g = 0; g < 2; g++) {
+        if (b->exec[g]) (void)hipGraphExecDestroy(b->exec[g]);
+        if (b->graph[g]) (void)hipGraphDestroy(b->graph[g]);
+        b->exec[g] = nullptr;
+        b->graph[g] = nullptr;
+    }
+    b->captured = false;
 }
 
 extern "C" {
@@ -1043,72 +1266,176 @@ int adg_batch_create(adg_problem *const *ps, int count, adg_batch **out) {
     for (int i = 0; i < count; i++) {
         adg_problem *pb = ps[i];
         if (!pb || !pb->has_state) return fail(ADG_ESTATE, "problem %d has no state", i);
+        if (pb->batch) return fail(ADG_ESTATE, "problem %d already belongs to a batch", i);
         for (int j = 0; j < i; j++)
             if (ps[j] == pb) return fail(ADG_EINVAL, "problem listed twice");
+        const adg_params &a = ps[0]->prm, &c = pb->prm;
+        if (c.precision != a.precision || c.limiter != a.limiter || c.mood != a.mood)
+            return fail(ADG_EINVAL, "problem %d: the problems of a batch share precision, limiter and MOOD layer", i);
     }
     adg_batch *b = new (std::nothrow) adg_batch();
     if (!b) return fail(ADG_ENOMEM, "host allocation failed");
     b->ps.assign(ps, ps + count);
-    b->streams.resize(count, nullptr);
-    b->evs.resize(count + 1, nullptr);
+    b->precision = ps[0]->prm.precision;
+    b->limiter = ps[0]->prm.limiter;
+    b->mood = ps[0]->prm.mood;
+    // classes of equal (dim, N), each split into `groups` launch groups (problems dealt out
+    // in turn) that run on branches of their own, so that stages of different groups overlap
+    const char *ge = std::getenv("ADG_BATCH_GROUPS");
+    const int groups = std::max(1, std::min(64, ge ? std::atoi(ge) : 4));
+    std::vector<int> seen;   // problems of each (dim, N) so far, per class index of its group 0
     for (int i = 0; i < count; i++) {
         b->saved.push_back(ps[i]->stream);
-        if (hipStreamCreateWithFlags(&b->streams[i], hipStreamNonBlocking) != hipSuccess) {
-            adg_batch_destroy(b);
-            return fail(ADG_EDEVICE, "hipStreamCreate failed");
+        int k0 = -1;
+        for (size_t j = 0; j < b->cls.size(); j += 1)
+            if (b->cls[j].dim == ps[i]->P.dim && b->cls[j].N == ps[i]->P.N && b->cls[j].group == 0) k0 = (int)j;
+        if (k0 < 0) {
+            k0 = (int)b->cls.size();
+            for (int gi = 0; gi < groups; gi++) {
+                b->cls.emplace_back();
+                b->cls.back().dim = ps[i]->P.dim;
+                b->cls.back().N = ps[i]->P.N;
+                b->cls.back().group = gi;
+            }
+            seen.resize(b->cls.size(), 0);
         }
+        const int gi = seen[k0]++ % groups;
+        b->cls[k0 + gi].members.push_back(i);
     }
-    for (int i = 0; i <= count; i++)
-        if (hipEventCreateWithFlags(&b->evs[i], hipEventDisableTiming) != hipSuccess) {
-            adg_batch_destroy(b);
-            return fail(ADG_EDEVICE, "hipEventCreate failed");
-        }
-    if (hipStreamCreateWithFlags(&b->origin, hipStreamNonBlocking) != hipSuccess) {
+    // drop empty groups
+    b->cls.erase(std::remove_if(b->cls.begin(), b->cls.end(), [](const BatchClass &K) { return K.members.empty(); }),
+                 b->cls.end());
+    for (int g = 0; g < 2; g++)
+        for (int st = 0; st <= BSTAGE_COUNT; st++)
+            if (hipEventCreate(&b->ev[g][st]) != hipSuccess) {
+                adg_batch_destroy(b);
+                return fail(ADG_EDEVICE, "hipEventCreate failed");
+            }
+    if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
         adg_batch_destroy(b);
         return fail(ADG_EDEVICE, "hipStreamCreate failed");
     }
+    b->cstream.assign(b->cls.size(), nullptr);
+    b->cev.assign(b->cls.size() + 1, nullptr);
+    for (size_t c = 0; c < b->cls.size(); c++)
+        if (hipStreamCreateWithFlags(&b->cstream[c], hipStreamNonBlocking) != hipSuccess) {
+            adg_batch_destroy(b);
+            return fail(ADG_EDEVICE, "hipStreamCreate failed");
+        }
+    for (auto &e : b->cev)
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+            adg_batch_destroy(b);
+            return fail(ADG_EDEVICE, "hipEventCreate failed");
+        }
+    batch_plan(b);
+    for (auto *pb : b->ps) pb->batch = b;
     *out = b;
+    return ADG_OK;
+}
+
+size_t adg_batch_workspace_bytes(const adg_batch *b) { return b ? b->ws_bytes : 0; }
+
+int adg_batch_bind(adg_batch *b, void *dev_workspace, size_t bytes, void *hip_stream) {
+    if (!b || !dev_workspace) return fail(ADG_EINVAL, "null argument");
+    if (((uintptr_t)dev_workspace) & 255) return fail(ADG_EINVAL, "workspace must be 256-byte aligned");
+    if (bytes < b->ws_bytes) return fail(ADG_ENOMEM, "batch workspace %zu bytes, %zu needed", bytes, b->ws_bytes);
+    batch_drop_graphs(b);
+    b->ws = (char *)dev_workspace;
+    b->user = (hipStream_t)hip_stream;
+    b->bound = true;
     return ADG_OK;
 }
 
 int adg_batch_step_cfl(adg_batch *b, double cfl, int nsteps) {
     if (!b || !(cfl > 0) || nsteps < 0) return fail(ADG_EINVAL, "bad argument");
-    // make the problems' pending work visible to the batch streams
+    if (!b->bound) return fail(ADG_ESTATE, "adg_batch_bind first");
+    // make the caller's and the problems' pending work visible to the batch stream
+    HIPCHK(hipStreamSynchronize(b->user));
     for (size_t i = 0; i < b->ps.size(); i++) HIPCHK(hipStreamSynchronize(b->saved[i]));
     int done = 0;
     if (!b->captured || b->cfl != cfl) {
-        if (b->captured) {
-            for (int g = 0; g < 2; g++) {
-                if (b->exec[g]) (void)hipGraphExecDestroy(b->exec[g]);
-                if (b->graph[g]) (void)hipGraphDestroy(b->graph[g]);
-                b->exec[g] = nullptr;
-                b->graph[g] = nullptr;
-            }
-            b->captured = false;
-        }
+        batch_drop_graphs(b);
         b->cfl = cfl;
         // one ordinary step per problem (initialises the old-time bounds), then capture
         if (nsteps > 0) {
             for (size_t i = 0; i < b->ps.size(); i++) {
                 adg_problem *pb = b->ps[i];
-                pb->stream = b->streams[i];
+                pb->stream = b->stream;
+                pb->batch_driving = true;
                 int rc = adg_step_cfl(pb, cfl);
+                pb->batch_driving = false;
                 pb->stream = b->saved[i];
-                if (rc != ADG_OK) return rc;
+                if (rc != ADG_OK && rc != ADG_ENONPHYSICAL) return rc;
             }
             done = 1;
         }
-        for (size_t i = 0; i < b->ps.size(); i++) HIPCHK(hipStreamSynchronize(b->streams[i]));
+        HIPCHK(hipStreamSynchronize(b->stream));
+        for (auto *pb : b->ps)
+            if (!pb->bounds_valid && b->limiter)
+                return fail(ADG_ESTATE, "batch capture needs one step taken (nsteps >= 1)");
         int rc = batch_capture(b);
-        for (size_t i = 0; i < b->ps.size(); i++) b->ps[i]->stream = b->saved[i];
         if (rc != ADG_OK) return rc;
     }
+    const bool timed = b->prof_mask != 0;
     for (int s = done; s < nsteps; s++) {
-        HIPCHK(hipGraphLaunch(b->exec[b->parity], b->origin));
+        const int g = b->parity;
+        if (timed) {
+            // the same launches as the graph, enqueued directly with an event at every stage
+            // boundary (events recorded inside a graph give no elapsed times here)
+            int rc = batch_enqueue(b, g, true);
+            if (rc != ADG_OK) return rc;
+        } else {
+            HIPCHK(hipGraphLaunch(b->exec[g], b->stream));
+        }
         for (auto *pb : b->ps) host_advance(pb);
         b->parity ^= 1;
     }
-    HIPCHK(hipStreamSynchronize(b->origin));
+    if (timed && nsteps > done) {
+        HIPCHK(hipStreamSynchronize(b->stream));
+        for (int g = 0; g < 2; g++)
+            for (int st = 0; st < BSTAGE_COUNT; st++) {
+                float ms = 0.f;
+                if (b->ev_pending[g] && hipEventElapsedTime(&ms, b->ev[g][st], b->ev[g][st + 1]) == hipSuccess) {
+                    b->prof_ms[st] += ms;
+                    b->prof_n[st] += 1;
+                }
+            }
+        b->ev_pending[0] = b->ev_pending[1] = false;
+    }
+    HIPCHK(hipStreamSynchronize(b->stream));
+    // the replays do not copy the counters to the host: read every problem's pool
+    // overflow flag (sticky) and its count of non-physical subcell results now
+    for (auto *pb : b->ps) HIPCHK(hipMemcpyAsync(pb->pinned, pb->B.counts, 16, hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    int news = ADG_OK;
+    for (size_t i = 0; i < b->ps.size(); i++) {
+        adg_problem *pb = b->ps[i];
+        if (pb->pinned[3])
+            return fail(ADG_ECAPACITY, "problem %d: troubled cells exceeded the pool capacity %lld", (int)i,
+                        (long long)pb->cap);
+        if (nonphysical_news(pb) != ADG_OK) news = ADG_ENONPHYSICAL;
+    }
+    if (news != ADG_OK) return fail(ADG_ENONPHYSICAL, "subcell results failed positivity in the batch");
+    return ADG_OK;
+}
+
+int adg_batch_profile(adg_batch *b, int enable) {
+    if (!b) return fail(ADG_EINVAL, "null argument");
+    b->prof_mask = enable ? 1u : 0u;
+    b->ev_pending[0] = b->ev_pending[1] = false;
+    for (int st = 0; st < BSTAGE_COUNT; st++) {
+        b->prof_ms[st] = 0;
+        b->prof_n[st] = 0;
+    }
+    return ADG_OK;
+}
+
+int adg_batch_profile_read(adg_batch *b, double *ms, int64_t *steps, int nstages) {
+    if (!b || !ms || !steps || nstages < 0 || nstages > BSTAGE_COUNT) return fail(ADG_EINVAL, "bad argument");
+    for (int st = 0; st < nstages; st++) {
+        ms[st] = b->prof_ms[st];
+        steps[st] = b->prof_n[st];
+    }
     return ADG_OK;
 }
 
@@ -1124,17 +1451,20 @@ int adg_batch_dt(adg_batch *b, double *dts) {
 
 int adg_batch_destroy(adg_batch *b) {
     if (!b) return ADG_OK;
-    if (b->origin) (void)hipStreamSynchronize(b->origin);
-    for (int g = 0; g < 2; g++) {
-        if (b->exec[g]) (void)hipGraphExecDestroy(b->exec[g]);
-        if (b->graph[g]) (void)hipGraphDestroy(b->graph[g]);
-    }
-    for (size_t i = 0; i < b->streams.size(); i++)
-        if (b->streams[i]) (void)hipStreamDestroy(b->streams[i]);
-    for (auto e : b->evs)
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    batch_drop_graphs(b);
+    if (b->stream) (void)hipStreamDestroy(b->stream);
+    for (auto st : b->cstream)
+        if (st) (void)hipStreamDestroy(st);
+    for (auto e : b->cev)
         if (e) (void)hipEventDestroy(e);
-    if (b->origin) (void)hipStreamDestroy(b->origin);
-    for (size_t i = 0; i < b->ps.size(); i++) b->ps[i]->stream = b->saved[i];
+    for (int g = 0; g < 2; g++)
+        for (int st = 0; st <= BSTAGE_COUNT; st++)
+            if (b->ev[g][st]) (void)hipEventDestroy(b->ev[g][st]);
+    for (size_t i = 0; i < b->ps.size(); i++) {
+        b->ps[i]->stream = b->saved[i];
+        if (b->ps[i]->batch == b) b->ps[i]->batch = nullptr;
+    }
     delete b;
     return ADG_OK;
 }

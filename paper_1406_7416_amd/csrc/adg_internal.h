@@ -86,6 +86,53 @@ struct Bufs {
     double *strace;        // [chunk][pos][2d][v][3^(d-1)*3]
 };
 
+// Arguments of one launch of the space-time predictor.
+template <typename R>
+struct PredArgs {
+    const double *in;      // input nodal values
+    int64_t in_cstride;    // stride between cells
+    int64_t in_vstride;    // stride between variables
+    R *trace;              // [cell][2d][v][nfn*n]
+    double *vol_out;       // candidate with volume term [v][cell][node] (main scheme only)
+    int64_t ncell;         // cells (or subcell positions) in this launch
+    int64_t cell0;         // first cell index (for vol_out addressing)
+    int iters;
+    double dth[3];         // dt/h_k multipliers (without dt)
+    const double *dt;      // device scalar
+    // operators of the n-node basis used by this launch (row stride MAXN)
+    const R *D, *Kw, *Lb, *Rb, *w, *Dvol;
+    const R *DE, *DO;      // even / odd parts of D (row strides MAXN/2 + 1 and MAXN/2)
+    // if set, the number of cells is min(*dcount, dcap) * dmult (read on the device)
+    const int *dcount;
+    int64_t dcap;
+    int dmult;
+};
+
+// Batched launches: one launch per stage of the step covers every problem of one (d, N)
+// class.  A BatchEntry holds what the per-problem launch passes as arguments (one entry
+// per problem and buffer parity, in device memory); a BTile names the problem and the
+// block within that problem's own grid for one workgroup of a batched launch.
+struct BatchEntry {
+    const Tables *T;
+    Prob P;
+    Bufs B;
+    int cur;               // current state buffer
+    int limiter;
+    int64_t cap;           // pool slots
+    int64_t kb1, kb2;      // face kernel: first block of axis 1 and of axis 2
+    int lam_nb;            // blocks of the wave-speed reduction
+    double factor;         // dt = factor / lambda_max  (cfl * hmin / (d (2N+1)))
+    const int64_t *ring;   // ghost-ring cells of the extended grid (null: every extended cell)
+    PredArgs<float> pf;    // predictor arguments in the mixed form
+    PredArgs<double> pd;   // and in the FP64 form
+};
+
+struct BTile {
+    int p;                 // problem within the class
+    int b;                 // block index within that problem's grid
+    int n;                 // that problem's grid size for this stage
+};
+
 int64_t ipow64(int64_t b, int e);
 
 }  // namespace adg

@@ -21,6 +21,39 @@ struct StepCtx {
     int mood;              // MOOD layer after the subcell scheme
 };
 
+// Scratch of the subcell scheme, one slot per workgroup (sidx): reconstructed nodal values,
+// predictor traces, the 3D halo and the per-point boundary fluxes.
+struct SubScratch {
+    double *Y, *strace, *halo, *fpts;
+};
+
+// Stages of one step in a batch, each one batched launch (or a few) per (d, N) class.
+enum {
+    BSTAGE_DT = 0,         // wave speed reduction and dt (eq. (cfl))
+    BSTAGE_BOUNDS,         // old-time bounds of the ghost ring
+    BSTAGE_PREDICTOR,      // predictor + volume term + face traces
+    BSTAGE_FACE,           // face fluxes
+    BSTAGE_CORRECTOR,      // corrector + scatter + detection
+    BSTAGE_COMPACT,        // compaction + the class's global worklist offsets
+    BSTAGE_SUBCELL,        // subcell ADER-WENO3 over the global troubled worklist (+ MOOD layer)
+    BSTAGE_FLUXCORR,       // flux correction over the global list of corrected neighbours
+    BSTAGE_ADVANCE,        // t += dt
+    BSTAGE_COUNT
+};
+
+// One (d, N) class of a batch at one buffer parity (device pointers).
+struct BatchLaunch {
+    const BatchEntry *E;
+    int np;
+    const BTile *t_lambda, *t_bounds, *t_pred, *t_face, *t_corr, *t_compact;
+    int n_lambda, n_bounds, n_pred, n_face, n_corr, n_compact;
+    int *off_t, *off_c;    // np + 1 each: global troubled / corrected worklist offsets
+    SubScratch S;          // sub_grid scratch slots for the subcell scheme
+    int sub_grid, fc_grid;
+    int precision, mood;
+    hipStream_t stream;
+};
+
 bool supported(int dim, int N);
 int positions_per_cell(int dim, int N);
 void build_tables(int N, int Ns, Tables *T);
@@ -40,5 +73,10 @@ void launch_lambda(const StepCtx &C, const double *u, double factor);
 void launch_set_scalar(const StepCtx &C, int idx, double val);
 void launch_advance_time(const StepCtx &C);
 void launch_copy_scalar(const double *src, double *dst, hipStream_t stream);
+// blocks of one problem's launch of a batch stage (predictor, face, corrector, compaction)
+int64_t stage_blocks(int stage, const Prob &P, int precision, int64_t *kb1, int64_t *kb2);
+void launch_batched(int dim, int N, int stage, const BatchLaunch &L);
+// the predictor's launch arguments of C in both precisions (batch entries)
+void predictor_args(const StepCtx &C, PredArgs<float> *pf, PredArgs<double> *pd);
 
 }  // namespace adg

@@ -38,27 +38,6 @@ struct PredShape {
     static constexpr int VC = VCMAX < 1 ? 1 : (VCMAX > NV ? NV : VCMAX);  // vars per LDS chunk
 };
 
-template <typename R>
-struct PredArgs {
-    const double *in;      // input nodal values
-    int64_t in_cstride;    // stride between cells
-    int64_t in_vstride;    // stride between variables
-    R *trace;              // [cell][2d][v][nfn*n]
-    double *vol_out;       // candidate with volume term [v][cell][node] (main scheme only)
-    int64_t ncell;         // cells (or subcell positions) in this launch
-    int64_t cell0;         // first cell index (for vol_out addressing)
-    int iters;
-    double dth[3];         // dt/h_k multipliers (without dt)
-    const double *dt;      // device scalar
-    // operators of the n-node basis used by this launch (row stride MAXN)
-    const R *D, *Kw, *Lb, *Rb, *w, *Dvol;
-    const R *DE, *DO;      // even / odd parts of D (row strides MAXN/2 + 1 and MAXN/2)
-    // if set, the number of cells is min(*dcount, dcap) * dmult (read on the device)
-    const int *dcount;
-    int64_t dcap;
-    int dmult;
-};
-
 // Contraction along axis k of every line held in LDS: line[i] <- c * sum_b M[i][b] line[b]
 // (c only if SCALE).  One work item handles the same line of LV variables (independent FMA
 // chains sharing each operator entry; for long lines LV is 2 (FP32) or 1 (FP64) to bound

@@ -11,7 +11,7 @@ pytestmark = pytest.mark.gpu
 
 def make(wl, prec):
     from paper_1406_7416_amd import adg
-    g = adg.Problem(wl, precision=prec, pool_capacity=max(16, wl.num_cells // 4))
+    g = adg.Problem(wl, precision=prec, pool_capacity=wl.num_cells)
     u, _ = g.project(wl.ic, 0)
     g.set_state(u)
     return g
@@ -44,3 +44,36 @@ def test_batch_equals_individual_steps(prec_name):
     dts = b.dts()
     assert np.all(dts > 0)
     b.close()
+
+
+def test_batch_reports_pool_overflow_and_locks_its_problems():
+    """A problem whose troubled cells exceed its pool makes adg_batch_step_cfl fail with
+    ADG_ECAPACITY (the replays themselves copy no counters); while the batch exists its
+    problems are not stepped or set on their own."""
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1406_7416_amd import adg
+    wls = W.quadrant_batch(3)
+    for wl in wls:
+        wl.ncell = (16, 16)
+    ps = []
+    for i, wl in enumerate(wls):
+        g = adg.Problem(wl, precision=adg.ADG_FP64, pool_capacity=1 if i == 1 else 256)
+        u, _ = g.project(wl.ic, 0)
+        g.set_state(u)
+        ps.append(g)
+    b = adg.Batch(ps)
+    with pytest.raises(adg.AdgError, match="-6"):
+        ps[0].step_cfl(0.5)
+    with pytest.raises(adg.AdgError, match="-6"):
+        ps[2].set_state(ps[2].state())
+    with pytest.raises(adg.AdgError, match="-6"):
+        adg.Batch([ps[0]])
+    with pytest.raises(adg.AdgError, match="-4"):
+        for _ in range(4):
+            b.step_cfl(0.5, 2)
+    b.close()
+    # after the batch: stepping on their own works again (problem 0 has a large pool)
+    ps[0].step_cfl(0.5)
+    for g in ps:
+        g.close()

@@ -1,13 +1,16 @@
 #!/usr/bin/env python3
-"""Benchmark of one full ADER-DG step with the a-posteriori subcell limiter on one MI355X.
+"""Benchmark of the ADER-DG step with the a-posteriori subcell limiter on one MI355X.
 
-Workload: the smooth isentropic vortex of Sec. 5 (beta = 5, rho = p = 1, u = v = 1
-background, periodic [0,10]^2) with N = 9 on 64 x 64 cells, limiter active (detection
-runs every step; the resolved vortex triggers no troubled cell).  One step = Delta t
-reduction (eq. (cfl)) + old-time bounds + space-time predictor + face fluxes + corrector
-+ scatter/detection + compaction (+ subcell recompute and flux correction when cells are
-flagged).  Metric: space-time degrees of freedom updated per second, counted per
-conserved variable as the paper does ((N+1)^(d+1) per cell and step).
+Headline workload: a batch of 256 independent four-quadrant Riemann problems (Sec. 5, 2D
+Riemann problems; random quadrant states rho, p ~ U[0.1, 2], u, v ~ U[-1, 1], seed
+20140627), grids drawn from {32, 64, 128, 256}^2 and degrees from N = 3, 4, 5 (6.1M cells),
+transmissive boundaries, every problem at the batch's smallest CFL factor.  One step of the
+batch = one step of every problem: Delta t (eq. (cfl)), old-time bounds, space-time
+predictor, face fluxes, corrector + scatter + detection, compaction, subcell ADER-WENO3
+recompute of the troubled cells, flux correction.  The mixed form runs batched (one launch
+per stage and (d, N) class, the step captured in a hipGraph); the plain FP64 form is
+stepped problem by problem.  Metric: space-time degrees of freedom updated per second,
+counted per conserved variable as the paper does ((N+1)^(d+1) per cell and step).
 
 Prints one JSON line.  With --gpus above 1 it exits: the benchmark runs on one GPU.
 """
@@ -22,19 +25,29 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # MI355X published peaks used for the roofline fraction
-PEAK_FP64_VALU_TFLOPS = 78.6
-# FP32 vector work compiled without packed-FP32 instructions issues at the FP64 vector
-# rate (one FMA per lane per cycle); the 157.3 TFLOP/s FP32 figure needs packed FP32.
-PEAK_FP32_VALU_TFLOPS = 78.6
+PEAK_FP64_TFLOPS = 78.6
+PEAK_FP32_TFLOPS = 157.3
+# FP32 vector work compiled without packed-FP32 instructions issues one FMA per lane and
+# clock: 256 CUs x 2.4 GHz x 128 flop per clock = 78.6 TFLOP/s, the FP64 vector rate (a
+# secondary ceiling, reported beside the published FP32 figure)
+PEAK_FP32_NONPACKED_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 
-# HBM bytes per launch of k_predictor<2, 9, true, float> on the N=9, 64x64 vortex: rocprofv3
-# FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (the factors that make a plain 256 MiB copy read its
-# own size), taken on the predictor source (the files below, concatenated) whose SHA-256 starts
-# with the prefix below; reported as null once that source has changed.
-PREDICTOR_SOURCES = ("adg_internal.h", "adg_physics.h", "adg_predictor.h")
-PREDICTOR_TRAFFIC_BYTES = 74257524
-PREDICTOR_TRAFFIC_SOURCE = "19eedc28bf47549f"
+# HBM traffic of the dominant kernel family of the batch step, from rocprofv3 counter runs
+# (FETCH_SIZE x the factor that makes a plain copy read its own size, plus WRITE_SIZE),
+# summed over the family's launches of one batch step, keyed to the SHA-256 prefix of the
+# kernel sources it was measured on (null once they change).
+TRAFFIC = {}   # stage -> (bytes per batch step, source hash prefix)
+KERNEL_SOURCES = ("adg_internal.h", "adg_physics.h", "adg_device.h", "adg_predictor.h", "adg_kernels_impl.h")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1406_7416_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def predictor_flops_per_cell(d: int, N: int) -> float:
@@ -97,41 +110,48 @@ def l1_norm(f, wl):
     return float((np.abs(f) * w[None, :]).sum() * vol)
 
 
-def traffic_bytes(N, grid):
-    """Measured HBM traffic of the dominant kernel, if it was measured on this workload and
-    on the kernel source as it stands."""
-    import hashlib
-    h = hashlib.sha256()
-    for name in PREDICTOR_SOURCES:
-        with open(os.path.join(ROOT, "paper_1406_7416_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
-    h = h.hexdigest()
-    if N != 9 or grid != 64 or not h.startswith(PREDICTOR_TRAFFIC_SOURCE):
-        return None
-    return PREDICTOR_TRAFFIC_BYTES
+def subcell_flops_per_cell(d: int, N: int) -> float:
+    """Algorithmic flops of the subcell ADER-WENO3 recompute of one troubled cell (Ns = 2N+1
+    subcells per axis, nu = d+2 variables).  Positions: the Ns^d subcells and the 2d Ns^(d-1)
+    face-adjacent subcells of the neighbours.  Per position: the dimension-by-dimension WENO3
+    reconstruction (2D: 5 + 3 one-dimensional reconstructions per variable, 3D: 25 + 15 + 9;
+    148 flops each: three stencil polynomials, indicators, weights, evaluation at 3 points),
+    the degree-2 space-time predictor (the predictor count with n = 3) and its face traces
+    (2d faces x nu x 3^(d-1) x 3 nodes, a length-3 contraction each).  Per sub-face: the
+    numerical flux at 3^(d-1) x 3 points (70 flops each).  The FV update and the gather R
+    (sum-factorised) are counted in full."""
+    Ns, nv, n = 2 * N + 1, d + 2, N + 1
+    pos = Ns ** d + 2 * d * Ns ** (d - 1)
+    weno_1d = {2: 8, 3: 49}[d] * nv * 148
+    pred = 3 * (2.0 * (d + 1) * nv * 3 ** (d + 2) + (10 + 8 * d) * 3 ** (d + 1))   # 3 full sweeps, n = 3
+    traces = 2 * d * nv * 3 ** (d - 1) * 3 * 3 * 2
+    subfaces = d * (Ns + 1) * Ns ** (d - 1) * 3 ** d * 70
+    update = Ns ** d * nv * d * 3
+    gather = 2 * nv * sum(n ** (j + 1) * Ns ** (d - j) for j in range(d))
+    return pos * (weno_1d + pred + traces) + subfaces + update + gather
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--grid", type=int, default=64)
-    ap.add_argument("--N", type=int, default=9)
-    ap.add_argument("--breakdown-steps", type=int, default=10,
-                    help="untimed steps with events around every kernel group (per-kernel breakdown)")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="bounded CPU-baseline sample")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-batch", action="store_true", help="skip the four-quadrant batch measurement")
+    ap.add_argument("--steps", type=int, default=20, help="timed batch steps")
+    ap.add_argument("--warmup", type=int, default=3, help="untimed batch steps before the timed region")
     ap.add_argument("--batch-count", type=int, default=256)
-    ap.add_argument("--batch-steps", type=int, default=20)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="bounded CPU-baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="only the headline batch (no vortex, 3D explosion, double Mach, 2D explosion, shock-vortex)")
     ap.add_argument("--no-3d", action="store_true", help="skip the 3D explosion measurement (128^3, N=3)")
     ap.add_argument("--steps-3d", type=int, default=6)
-    ap.add_argument("--no-small", action="store_true", help="skip the 2D explosion, double Mach and shock-vortex measurements")
+    ap.add_argument("--grid", type=int, default=64, help="vortex grid (extra measurement)")
+    ap.add_argument("--N", type=int, default=9, help="vortex degree (extra measurement)")
+    ap.add_argument("--vortex-steps", type=int, default=100)
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device-to-device copy of this size (counter calibration)")
     ap.add_argument("--convergence", action="store_true",
                     help="only measure the vortex's L1 error at t = 10 on 16^2, 32^2, 64^2 cells (degree --N)")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="only the batch in both forms, no CPU leg or extras (profiling runs)")
     args = ap.parse_args()
 
     if args.convergence:
@@ -153,142 +173,133 @@ def main():
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
-    import numpy as np
     import torch
-    from paper_1406_7416_amd import adg
     from paper_1406_7416_amd import workloads as W
 
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(1)
 
-    wl = W.vortex(args.grid, args.N)
-    d, N = wl.dim, wl.N
-    st_dof_step = wl.st_dof_per_step()
-    print(f"# workload vortex N={N} grid={args.grid}^2 cells={wl.num_cells} cfl={wl.cfl}", file=sys.stderr,
-          flush=True)
-
-    forms = {}
-    finals = {}
-    u0 = None
-    # the Osher-type flux (the paper's flux for its vortex runs) alongside Rusanov
-    for form, prec, flux in (("fp64", adg.ADG_FP64, 0), ("mixed", adg.ADG_MIXED, 0),
-                             ("fp64_osher", adg.ADG_FP64, 1), ("mixed_osher", adg.ADG_MIXED, 1)):
-        prob = adg.Problem(wl, precision=prec, flux=flux)
-        if u0 is None:
-            u0, _ = prob.project(wl.ic, 0)      # nodal values of the initial condition
-        prob.set_state(u0)
-        for _ in range(args.warmup):
-            prob.step_cfl()
-        torch.cuda.synchronize()
-        # timed region: HIP events around the dominant kernel only (two event records per
-        # step on the problem's stream)
-        prob.profile(True, groups=["predictor"])
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            prob.step_cfl()
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        pred_ms, pred_n = prob.profile_read()["predictor"]
-        prob.profile(False)
-        elapsed = t1 - t0
-        # per-kernel-group breakdown from a separate, untimed pass with events around
-        # every group
-        prob.profile(True)
-        for _ in range(args.breakdown_steps):
-            prob.step_cfl()
-        prof = prob.profile_read()
-        prob.profile(False)
-        t_sim = prob.time
-        u = prob.state()
-        ue, _ = prob.project(lambda x, t: wl.ic(x, t_sim), 0)
-        forms[form] = {
-            "value": st_dof_step * args.steps / elapsed,
-            "ms_per_step": 1e3 * elapsed / args.steps,
-            "predictor_avg_us": 1e3 * pred_ms / max(1, pred_n),
-            "kernels": {g: {"ms_total": round(ms, 4), "launches": n, "avg_us": round(1e3 * ms / n, 3) if n else None}
-                        for g, (ms, n) in prof.items()},
-            "troubled_last_step": prob.stats()["troubled"],
-            "t_simulated": t_sim,
-            "linf_rho_vs_exact": float(np.abs(u[0] - ue[0]).max()),
-            "l1_rho_vs_exact": l1_norm(u[0] - ue[0], wl),
-        }
-        finals[form] = u
-        prob.close()
-        print(f"# {form}: {forms[form]['value']:.3e} st-dof/s, predictor {forms[form]['predictor_avg_us']:.1f} us",
-              file=sys.stderr, flush=True)
-    # the two forms after the same number of steps: density difference (max and mean)
-    drho = np.abs(finals["mixed"][0] - finals["fp64"][0])
-    head = "mixed"
-    h = forms[head]
-    pred_avg_s = h["predictor_avg_us"] * 1e-6
-    flops_launch = predictor_flops_per_cell(d, N) * wl.num_cells
-    achieved_tflops = flops_launch / pred_avg_s / 1e12
-
+    wls = W.quadrant_batch(args.batch_count)
+    bres = batch_measurement(wls, args.steps, args.warmup, fp64_forms=True)
+    head = bres["mixed_batched"]
     out = {
         "metric": "space-time dof-updates/s",
-        "value": h["value"],
+        "value": head["value"],
         "unit": "st-dof/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": h["ms_per_step"],
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 predictor and face fluxes, f64 state/detection",
-        "data": "synthetic (analytic initial condition)",
+        "dtype": "f32 predictor, face fluxes and subcell reconstruction/predictor/fluxes; f64 state, detection, "
+                 "projection/gather, subcell halo and update",
+        "data": "synthetic (seeded random four-quadrant states, analytic initial data)",
         "config": {
-            "workload": f"isentropic vortex (Sec. 5), N={N}, {args.grid}x{args.grid} cells, periodic [0,10]^2, "
-                        f"limiter on, CFL factor {wl.cfl}, Ns={2 * N + 1}",
-            "cells": wl.num_cells,
-            "st_dof_per_step": st_dof_step,
-            "form": "mixed (headline); FP64 GPU form alongside",
+            "workload": f"batch of {len(wls)} four-quadrant Riemann problems (Sec. 5), grids 32^2..256^2, "
+                        f"N = 3..5, {bres['cells']} cells, transmissive, CFL factor {bres['cfl']}, Ns = 2N+1, "
+                        f"limiter on",
+            "problems": len(wls),
+            "cells": bres["cells"],
+            "st_dof_per_step": bres["st_dof_per_step"],
+            "form": "mixed precision, batched (one launch per stage and (d, N) class, hipGraph); "
+                    "the plain FP64 form stepped problem by problem alongside",
         },
-        "roofline": {
-            "bound": "alu",
-            "kernel": "k_predictor (FP32 space-time predictor + volume term + face traces)",
-            "achieved": achieved_tflops,
-            "peak": PEAK_FP32_VALU_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": achieved_tflops / PEAK_FP32_VALU_TFLOPS,
-            "traffic": traffic_bytes(args.N, args.grid),
-            "traffic_unit": "bytes per launch (HBM, calibrated rocprofv3 counters)",
-            "flops_per_launch": flops_launch,
-            "avg_launch_us": h["predictor_avg_us"],
-        },
-        "forms": forms,
-        # memory-bound kernel of the step against a measured copy bandwidth: the face fluxes
-        # read every cell's face traces once and write one time-integrated flux per face node
-        # and adjacent cell (FP32 in the mixed form)
-        "memory_bound": face_bandwidth(wl, forms["mixed"]["kernels"]["faces"]["avg_us"]),
-        "speedup_mixed_vs_fp64": forms["mixed"]["value"] / forms["fp64"]["value"],
-        "speedup_mixed_vs_fp64_osher": forms["mixed_osher"]["value"] / forms["fp64_osher"]["value"],
-        "rho_mixed_minus_fp64": {"max": float(drho.max()), "mean": float(drho.mean())},
-        # both forms after the same steps, against the exact (advected) vortex
-        "matched_l1_rho": {"fp64": forms["fp64"]["l1_rho_vs_exact"], "mixed": forms["mixed"]["l1_rho_vs_exact"],
-                           "mixed_over_fp64": forms["mixed"]["l1_rho_vs_exact"] / forms["fp64"]["l1_rho_vs_exact"]},
+        "roofline": bres["roofline"],
+        "batch": bres,
+        "speedup_mixed_batched_vs_fp64_per_problem": bres["speedup"],
     }
+    del bres
 
-    if not args.no_batch:
-        out["batch"] = batch_measurement(args.batch_count, args.batch_steps)
-
-    if not args.no_3d:
-        out["explosion3d"] = explosion3d_measurement(args.steps_3d)
-
-    if not args.no_small:
+    if not args.batch_only and not args.no_extra:
+        out["vortex"] = vortex_measurement(args.grid, args.N, args.vortex_steps)
+        if not args.no_3d:
+            out["explosion3d"] = explosion3d_measurement(args.steps_3d)
         # the other 2D workloads: the 2D explosion (40 x 40, N = 3), the double Mach reflection
         # at its full size (400 x 100, N = 5) and the shock-vortex interaction (200 x 100, N = 5)
         out["explosion2d"] = form_pair_measurement(W.explosion_2d(40, 3), 4, steps=50)
         out["double_mach"] = form_pair_measurement(W.double_mach(400, 100, 5), 1, steps=20)
         out["shock_vortex"] = form_pair_measurement(W.shock_vortex(200, 100, 5), 3, steps=20)
 
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, u0, args.cpu_seconds)
-        out["cpu_baseline_single_thread"] = cpu_baseline(wl, u0, args.cpu_seconds / 2, threads=1)
+    if not args.batch_only and not args.no_cpu_baseline:
+        cpu = cpu_baseline_leg(wls, min(wl.cfl for wl in wls), args.cpu_seconds)
+        out["cpu_baseline"] = cpu["cpu_baseline"]
+        out["l1_rho_vs_oracle"] = cpu["l1_rho_vs_oracle"]
 
     print(json.dumps(out), flush=True)
+
+
+def vortex_measurement(grid, N, steps, warmup=10, breakdown_steps=10):
+    """The isentropic vortex (Sec. 5, beta = 5, periodic [0,10]^2), degree N on grid^2 cells, in
+    both precision forms with both fluxes: throughput, the predictor's rate (its algorithmic
+    flops over its average launch time from HIP events around every predictor launch on the
+    problem's stream in the timed region), the face kernel's bandwidth, and the L1 density
+    error against the exact (translated) vortex after the steps taken."""
+    import numpy as np
+    import torch
+    from paper_1406_7416_amd import adg
+    from paper_1406_7416_amd import workloads as W
+    wl = W.vortex(grid, N)
+    d = wl.dim
+    st_dof_step = wl.st_dof_per_step()
+    forms, finals, u0 = {}, {}, None
+    for form, prec, flux in (("fp64", adg.ADG_FP64, 0), ("mixed", adg.ADG_MIXED, 0),
+                             ("fp64_osher", adg.ADG_FP64, 1), ("mixed_osher", adg.ADG_MIXED, 1)):
+        prob = adg.Problem(wl, precision=prec, flux=flux)
+        if u0 is None:
+            u0, _ = prob.project(wl.ic, 0)      # nodal values of the initial condition
+        prob.set_state(u0)
+        for _ in range(warmup):
+            prob.step_cfl()
+        torch.cuda.synchronize()
+        prob.profile(True, groups=["predictor"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            prob.step_cfl()
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        pred_ms, pred_n = prob.profile_read()["predictor"]
+        prob.profile(False)
+        prob.profile(True)
+        for _ in range(breakdown_steps):
+            prob.step_cfl()
+        prof = prob.profile_read()
+        prob.profile(False)
+        t_sim = prob.time
+        u = prob.state()
+        ue, _ = prob.project(lambda x, t: wl.ic(x, t_sim), 0)
+        pred_avg_s = 1e-3 * pred_ms / max(1, pred_n)
+        tflops = predictor_flops_per_cell(d, N) * wl.num_cells / pred_avg_s / 1e12
+        forms[form] = {
+            "value": st_dof_step * steps / elapsed,
+            "ms_per_step": 1e3 * elapsed / steps,
+            "predictor_avg_us": 1e6 * pred_avg_s,
+            "predictor_tflops": tflops,
+            "predictor_frac": tflops / (PEAK_FP32_TFLOPS if prec == adg.ADG_MIXED else PEAK_FP64_TFLOPS),
+            "kernels": {g: {"ms_total": round(ms, 4), "launches": n, "avg_us": round(1e3 * ms / n, 3) if n else None}
+                        for g, (ms, n) in prof.items()},
+            "troubled_last_step": prob.stats()["troubled"],
+            "t_simulated": t_sim,
+            "l1_rho_vs_exact": l1_norm(u[0] - ue[0], wl),
+        }
+        finals[form] = u
+        prob.close()
+        print(f"# vortex {form}: {forms[form]['value']:.3e} st-dof/s, predictor {forms[form]['predictor_avg_us']:.1f} us",
+              file=sys.stderr, flush=True)
+    drho = np.abs(finals["mixed"][0] - finals["fp64"][0])
+    return {
+        "workload": f"isentropic vortex (Sec. 5), N={N}, {grid}x{grid} cells, periodic [0,10]^2, limiter on, "
+                    f"CFL factor {wl.cfl}",
+        "cells": wl.num_cells, "st_dof_per_step": st_dof_step, "steps": steps, "forms": forms,
+        "speedup_mixed_vs_fp64": forms["mixed"]["value"] / forms["fp64"]["value"],
+        "speedup_mixed_vs_fp64_osher": forms["mixed_osher"]["value"] / forms["fp64_osher"]["value"],
+        "rho_mixed_minus_fp64": {"max": float(drho.max()), "mean": float(drho.mean())},
+        "l1_rho_vs_exact": {"fp64": forms["fp64"]["l1_rho_vs_exact"], "mixed": forms["mixed"]["l1_rho_vs_exact"]},
+        "memory_bound": face_bandwidth(wl, forms["mixed"]["kernels"]["faces"]["avg_us"]),
+    }
 
 
 def form_pair_measurement(wl, m, steps, warmup=3):
@@ -411,117 +422,211 @@ def face_bandwidth(wl, avg_us):
             "frac_of_peak": gbs / PEAK_HBM_GBS}
 
 
-def batch_measurement(count, steps):
-    """Independent four-quadrant Riemann problems (random states, grids from
-    {32,64,128,256}^2, N from {3,4,5}): the mixed form advanced as one batch (one hipGraph
-    launch per batch step) against the plain FP64 form stepped problem by problem."""
+def _make_batch_problems(wls, prec, mood=False):
+    from paper_1406_7416_amd import adg
+    ps = []
+    for wl in wls:
+        cap = wl.num_cells if wl.num_cells <= 4096 else wl.num_cells // 3
+        p = adg.Problem(wl, precision=prec, pool_capacity=cap, mood=mood)
+        u, _ = p.project(wl.ic, 0)
+        p.set_state(u)
+        ps.append(p)
+    return ps
+
+
+def _free(*objs):
     import gc
     import torch
+    for o in objs:
+        if isinstance(o, list):
+            for p in o:
+                p.close()
+        elif o is not None:
+            o.close()
+    gc.collect()
+    torch.cuda.empty_cache()
+
+
+def batch_measurement(wls, steps, warmup, fp64_forms=True):
+    """The batch in the mixed form, batched: `warmup` untimed batch steps, then `steps` timed
+    graph replays (the first call also takes one ordinary step per problem and captures).
+    Then the same number of steps with the stages timed (HIP events at every stage boundary
+    on the batch stream, the same launches enqueued directly): the per-stage times and the
+    roofline of the dominant stage.  Then the plain FP64 form problem after problem
+    (per-problem launches, no graph) and the FP64 form batched, and the mixed form batched
+    with the MOOD layer of Sec. 6."""
+    import numpy as np
+    import torch
     from paper_1406_7416_amd import adg
-    from paper_1406_7416_amd import workloads as W
-    wls = W.quadrant_batch(count)
     cfl = min(wl.cfl for wl in wls)
     st_dof = sum(wl.st_dof_per_step() for wl in wls)
-    res = {"problems": count, "cells": sum(wl.num_cells for wl in wls), "st_dof_per_step": st_dof,
-           "steps": steps, "cfl": cfl}
+    res = {"problems": len(wls), "cells": sum(wl.num_cells for wl in wls), "st_dof_per_step": st_dof,
+           "steps": steps, "warmup": warmup, "cfl": cfl}
 
-    def build(prec, mood=False):
-        ps = []
-        for wl in wls:
-            cap = wl.num_cells if wl.num_cells <= 4096 else wl.num_cells // 3
-            p = adg.Problem(wl, precision=prec, pool_capacity=cap, mood=mood)
-            u, _ = p.project(wl.ic, 0)
-            p.set_state(u)
-            ps.append(p)
-        return ps
+    def timed_batch(prec, mood=False, stages=True):
+        ps = _make_batch_problems(wls, prec, mood)
+        b = adg.Batch(ps)
+        b.step_cfl(cfl, max(1, warmup))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.step_cfl(cfl, steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        r = {"value": st_dof * steps / el, "ms_per_step": 1e3 * el / steps,
+             "troubled_last_step": int(sum(int(p.troubled().sum()) for p in ps))}
+        if stages:
+            b.profile(True)
+            b.step_cfl(cfl, steps)
+            pr = b.profile_read()
+            b.profile(False)
+            r["stages_ms_per_step"] = {g: ms / max(1, n) for g, (ms, n) in pr.items()}
+            r["troubled_per_class"] = {}
+            for p, wl in zip(ps, wls):
+                key = f"N{wl.N}"
+                r["troubled_per_class"][key] = r["troubled_per_class"].get(key, 0) + int(p.troubled().sum())
+        if mood:
+            fl = [p.mood_stats() for p in ps]
+            r["flagged_subcells_last_step"] = int(sum(f for f, _ in fl))
+            r["recomputed_cells_last_step"] = int(sum(x for _, x in fl))
+        r["workspace_bytes"] = int(b.workspace_bytes + sum(p.workspace_bytes for p in ps))
+        _free(b, ps)
+        return r
 
-    # mixed form, batched
-    ps = build(adg.ADG_MIXED)
-    b = adg.Batch(ps)
-    b.step_cfl(cfl, 3)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    b.step_cfl(cfl, steps)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    res["mixed_batched"] = {"value": st_dof * steps / el, "ms_per_batch_step": 1e3 * el / steps,
-                            "troubled_last_step": int(sum(int(p.troubled().sum()) for p in ps))}
-    b.close()
-    for p in ps:
-        p.close()
-    del ps, b
-    gc.collect()
-    torch.cuda.empty_cache()
-    # plain FP64 form, one problem after the other, per-problem launches
-    ps = build(adg.ADG_FP64)
-    for p in ps:
-        for _ in range(3):
-            p.step_cfl(cfl)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for p in ps:
-        for _ in range(steps):
-            p.step_cfl(cfl)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    res["fp64_per_problem"] = {"value": st_dof * steps / el, "ms_per_batch_step": 1e3 * el / steps}
-    res["speedup"] = res["mixed_batched"]["value"] / res["fp64_per_problem"]["value"]
-    for p in ps:
-        p.close()
-    del ps
-    gc.collect()
-    torch.cuda.empty_cache()
-    # the same batch with the MOOD layer after the subcell scheme (Sec. 6, Fig. algo2)
-    ps = build(adg.ADG_MIXED, mood=True)
-    b = adg.Batch(ps)
-    b.step_cfl(cfl, 3)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    b.step_cfl(cfl, steps)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    fl = [p.mood_stats() for p in ps]
-    res["mixed_batched_mood"] = {"value": st_dof * steps / el, "ms_per_batch_step": 1e3 * el / steps,
-                                 "flagged_subcells_last_step": int(sum(f for f, _ in fl)),
-                                 "recomputed_cells_last_step": int(sum(r for _, r in fl)),
-                                 "troubled_last_step": int(sum(int(p.troubled().sum()) for p in ps))}
-    b.close()
-    for p in ps:
-        p.close()
-    del ps, b
-    gc.collect()
-    torch.cuda.empty_cache()
-    print(f"# batch: mixed batched {res['mixed_batched']['value']:.3e}, fp64 per problem "
-          f"{res['fp64_per_problem']['value']:.3e} st-dof/s", file=sys.stderr, flush=True)
+    res["mixed_batched"] = timed_batch(adg.ADG_MIXED)
+    print(f"# batch mixed: {res['mixed_batched']['value']:.3e} st-dof/s, "
+          f"{res['mixed_batched']['ms_per_step']:.2f} ms/step", file=sys.stderr, flush=True)
+    if fp64_forms:
+        # the plain FP64 GPU form: per-problem launches, one problem after the other
+        ps = _make_batch_problems(wls, adg.ADG_FP64)
+        for p in ps:
+            for _ in range(max(1, warmup)):
+                p.step_cfl(cfl)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for p in ps:
+            for _ in range(steps):
+                p.step_cfl(cfl)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        res["fp64_per_problem"] = {"value": st_dof * steps / el, "ms_per_step": 1e3 * el / steps}
+        _free(ps)
+        res["fp64_batched"] = timed_batch(adg.ADG_FP64)
+        res["speedup"] = res["mixed_batched"]["value"] / res["fp64_per_problem"]["value"]
+        res["speedup_vs_fp64_batched"] = res["mixed_batched"]["value"] / res["fp64_batched"]["value"]
+        res["mixed_batched_mood"] = timed_batch(adg.ADG_MIXED, mood=True, stages=False)
+        print(f"# batch fp64 per problem {res['fp64_per_problem']['value']:.3e}, fp64 batched "
+              f"{res['fp64_batched']['value']:.3e} st-dof/s", file=sys.stderr, flush=True)
+    res["roofline"] = batch_roofline(wls, res["mixed_batched"])
     return res
 
 
-def cpu_baseline(wl, u0, budget_s, threads=None):
-    """The FP64 CPU oracle, as it stands, on the same workload: whole steps until the
-    time budget is used (at least one); all host threads, or the number given."""
-    from oracle import oracle as O
-    o = O.Oracle(wl)
-    o.set_state(u0)
-    saved = O.get_threads()
-    if threads:
-        O.set_threads(threads)
-    threads = O.get_threads()
-    steps, t0 = 0, time.perf_counter()
-    while True:
-        o.step(o.cfl_dt())
-        steps += 1
-        el = time.perf_counter() - t0
-        if el >= budget_s or steps >= 50:
-            break
-    O.set_threads(saved)
+def batch_roofline(wls, m):
+    """Roofline of the dominant stage of the mixed batched step: its algorithmic flops per batch
+    step (the predictor: predictor_flops_per_cell x cells of every problem; the subcell
+    recompute: subcell_flops_per_cell x the troubled cells of each degree) over its measured
+    time per step.  The stage's launches (one per class) run one after another on the batch
+    stream, so its event time is the sum of their durations."""
+    st = m["stages_ms_per_step"]
+    pred_flops = sum(predictor_flops_per_cell(wl.dim, wl.N) * wl.num_cells for wl in wls)
+    sub_flops = sum(subcell_flops_per_cell(2, int(k[1:])) * v for k, v in m["troubled_per_class"].items())
+    rates = {"predictor": pred_flops / (st["predictor"] * 1e-3) / 1e12,
+             "subcell": sub_flops / (st["subcell"] * 1e-3) / 1e12}
+    dom = max(("predictor", "subcell"), key=lambda g: st[g])
+    flops = pred_flops if dom == "predictor" else sub_flops
+    achieved = rates[dom]
+    tr = TRAFFIC.get(dom)
+    traffic = tr[0] if tr and tr[1] == kernel_source_hash() else None
+    kern = {"predictor": "kb_predictor<2, N, float> (FP32 space-time predictor + volume term + face traces), "
+                         "one launch per degree N = 3, 4, 5",
+            "subcell": "kb_subcell<2, N, float> (subcell ADER-WENO3 over the global troubled worklist), "
+                       "one launch per degree N = 3, 4, 5"}[dom]
     return {
-        "value": wl.st_dof_per_step() * steps / el,
-        "unit": "st-dof/s",
-        "cores": threads,
-        "kind": "oracle",
-        "sample": f"{steps} full steps of the same workload ({wl.num_cells} cells, N={wl.N}), {el:.1f} s, "
-                  f"OpenMP threads={threads}",
+        "bound": "alu",
+        "kernel": kern,
+        "achieved": achieved,
+        "peak": PEAK_FP32_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": achieved / PEAK_FP32_TFLOPS,
+        "frac_of_nonpacked_fp32": achieved / PEAK_FP32_NONPACKED_TFLOPS,
+        "traffic": traffic,
+        "traffic_unit": "HBM bytes per batch step of the stage (calibrated rocprofv3 counters)",
+        "flops_per_step": flops,
+        "ms_per_step": st[dom],
+        "share_of_step": st[dom] / sum(st.values()),
+        "other_stage_rates_tflops": {k: v for k, v in rates.items() if k != dom},
     }
+
+
+def cpu_baseline_leg(wls, cfl, budget_s, l1_steps=10):
+    """The FP64 CPU oracle on the headline workload.
+
+    Timing: the oracle as it stands, all host threads, whole steps of the batch's problems in
+    order (one step per problem, from its initial data) until the time budget is used; the
+    rate is the space-time dofs of those steps over their time.
+
+    L1 density error against the oracle: a sample of the batch (up to three 32^2 problems of
+    every degree and one 64^2 problem) stepped `l1_steps` times by the oracle and by both GPU
+    forms with the oracle's time steps; L1(rho_gpu - rho_oracle) relative to L1(rho_oracle)
+    per problem, worst over the sample."""
+    import numpy as np
+    from oracle import oracle as O
+    from paper_1406_7416_amd import adg
+    threads = O.get_threads()
+    done, st_dof, el, t0 = 0, 0, 0.0, time.perf_counter()
+    for wl in wls:
+        o = O.Oracle(wl)
+        u, _ = o.project(wl.ic, 0)
+        o.set_state(u)
+        t1 = time.perf_counter()
+        o.step(o.cfl_dt(cfl))
+        el += time.perf_counter() - t1
+        st_dof += wl.st_dof_per_step()
+        done += 1
+        del o
+        if el >= budget_s or time.perf_counter() - t0 >= 3 * budget_s:
+            break
+    cpu = {"value": st_dof / el, "unit": "st-dof/s", "cores": threads, "kind": "oracle",
+           "sample": f"one step (time step + step, timed) of each of the first {done} problems of the batch, "
+                     f"from their initial data; {el:.1f} s of stepping, OpenMP threads={threads}"}
+    # L1 against the oracle on a sample
+    idx, per_n = [], {}
+    for i, wl in enumerate(wls):
+        if wl.ncell[0] == 32 and per_n.get(wl.N, 0) < 3:
+            per_n[wl.N] = per_n.get(wl.N, 0) + 1
+            idx.append(i)
+    idx.append(next(i for i, wl in enumerate(wls) if wl.ncell[0] == 64))
+    worst = {"fp64": 0.0, "mixed": 0.0}
+    per = []
+    for i in idx:
+        wl = wls[i]
+        o = O.Oracle(wl)
+        u, _ = o.project(wl.ic, 0)
+        o.set_state(u)
+        gs = {}
+        for form, prec in (("fp64", adg.ADG_FP64), ("mixed", adg.ADG_MIXED)):
+            g = adg.Problem(wl, precision=prec)
+            g.set_state(u)
+            gs[form] = g
+        for _ in range(l1_steps):
+            dt = o.cfl_dt(cfl)
+            o.step(dt)
+            for g in gs.values():
+                g.step(dt)
+        ro = o.state()[0]
+        norm = l1_norm(ro, wl)
+        row = {"problem": i, "grid": wl.ncell[0], "N": wl.N}
+        for form, g in gs.items():
+            e = l1_norm(g.state()[0] - ro, wl) / norm
+            row[form] = e
+            worst[form] = max(worst[form], e)
+            g.close()
+        per.append(row)
+    l1 = {"steps": l1_steps, "sample": idx, "relative_l1_worst": worst, "per_problem": per,
+          "tolerance_mixed": 1e-5, "tolerance_fp64": 1e-12,
+          "within_tolerance": worst["mixed"] <= 1e-5 and worst["fp64"] <= 1e-12}
+    print(f"# cpu oracle {cpu['value']:.3e} st-dof/s on {threads} threads; L1 vs oracle: fp64 {worst['fp64']:.2e}, "
+          f"mixed {worst['mixed']:.2e}", file=sys.stderr, flush=True)
+    return {"cpu_baseline": cpu, "l1_rho_vs_oracle": l1}
 
 
 if __name__ == "__main__":

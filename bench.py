@@ -33,11 +33,16 @@ PEAK_FP32_TFLOPS = 157.3
 PEAK_FP32_NONPACKED_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 
-# HBM traffic of the dominant kernel family of the batch step, from rocprofv3 counter runs
-# (FETCH_SIZE x the factor that makes a plain copy read its own size, plus WRITE_SIZE),
-# summed over the family's launches of one batch step, keyed to the SHA-256 prefix of the
+# HBM traffic per launch of the batch step's dominant kernels, from rocprofv3 counter runs
+# (FETCH_SIZE x the factor that makes a plain copy read its own size, plus WRITE_SIZE, in
+# bytes; mean over the steady launches of the run), keyed to the SHA-256 prefix of the
 # kernel sources it was measured on (null once they change).
-TRAFFIC = {}   # stage -> (bytes per batch step, source hash prefix)
+# (launch "stage:N<degree>" -> (bytes per launch, source hash prefix)); copy calibration: a 256 MiB
+# copy reads FETCH_SIZE = 131,084 KiB (factor 2.0) and writes WRITE_SIZE = 262,144 KiB (factor 1.0)
+TRAFFIC = {
+    "subcell:N5": (22312457557, "1db78e76a962899b"),
+    "predictor:N5": (10808884736, "1db78e76a962899b"),
+}
 KERNEL_SOURCES = ("adg_internal.h", "adg_physics.h", "adg_device.h", "adg_predictor.h", "adg_kernels_impl.h")
 
 
@@ -151,7 +156,8 @@ def main():
     ap.add_argument("--convergence", action="store_true",
                     help="only measure the vortex's L1 error at t = 10 on 16^2, 32^2, 64^2 cells (degree --N)")
     ap.add_argument("--batch-only", action="store_true",
-                    help="only the batch in both forms, no CPU leg or extras (profiling runs)")
+                    help="only the mixed batched form of the batch: no FP64 forms, MOOD run, CPU leg or extras "
+                         "(profiling runs)")
     args = ap.parse_args()
 
     if args.convergence:
@@ -181,7 +187,7 @@ def main():
         sys.exit(1)
 
     wls = W.quadrant_batch(args.batch_count)
-    bres = batch_measurement(wls, args.steps, args.warmup, fp64_forms=True)
+    bres = batch_measurement(wls, args.steps, args.warmup, fp64_forms=not args.batch_only)
     head = bres["mixed_batched"]
     out = {
         "metric": "space-time dof-updates/s",
@@ -209,7 +215,7 @@ def main():
         },
         "roofline": bres["roofline"],
         "batch": bres,
-        "speedup_mixed_batched_vs_fp64_per_problem": bres["speedup"],
+        "speedup_mixed_batched_vs_fp64_per_problem": bres.get("speedup"),
     }
     del bres
 
@@ -479,7 +485,11 @@ def batch_measurement(wls, steps, warmup, fp64_forms=True):
             b.step_cfl(cfl, steps)
             pr = b.profile_read()
             b.profile(False)
+            launches = pr.pop("launches")
+            nst = max(1, next(iter(pr.values()))[1])
             r["stages_ms_per_step"] = {g: ms / max(1, n) for g, (ms, n) in pr.items()}
+            r["launch_ms"] = {f"{g}:N{cl[1]}": ms / nst for (g, cl), ms in launches.items()
+                              if g in ("predictor", "subcell", "corrector_detect", "faces")}
             r["troubled_per_class"] = {}
             for p, wl in zip(ps, wls):
                 key = f"N{wl.N}"
@@ -493,6 +503,7 @@ def batch_measurement(wls, steps, warmup, fp64_forms=True):
         return r
 
     res["mixed_batched"] = timed_batch(adg.ADG_MIXED)
+    res["roofline"] = batch_roofline(wls, res["mixed_batched"])
     print(f"# batch mixed: {res['mixed_batched']['value']:.3e} st-dof/s, "
           f"{res['mixed_batched']['ms_per_step']:.2f} ms/step", file=sys.stderr, flush=True)
     if fp64_forms:
@@ -516,30 +527,39 @@ def batch_measurement(wls, steps, warmup, fp64_forms=True):
         res["mixed_batched_mood"] = timed_batch(adg.ADG_MIXED, mood=True, stages=False)
         print(f"# batch fp64 per problem {res['fp64_per_problem']['value']:.3e}, fp64 batched "
               f"{res['fp64_batched']['value']:.3e} st-dof/s", file=sys.stderr, flush=True)
-    res["roofline"] = batch_roofline(wls, res["mixed_batched"])
     return res
 
 
 def batch_roofline(wls, m):
-    """Roofline of the dominant stage of the mixed batched step: its algorithmic flops per batch
-    step (the predictor: predictor_flops_per_cell x cells of every problem; the subcell
-    recompute: subcell_flops_per_cell x the troubled cells of each degree) over its measured
-    time per step.  The stage's launches (one per class) run one after another on the batch
-    stream, so its event time is the sum of their durations."""
-    st = m["stages_ms_per_step"]
-    pred_flops = sum(predictor_flops_per_cell(wl.dim, wl.N) * wl.num_cells for wl in wls)
-    sub_flops = sum(subcell_flops_per_cell(2, int(k[1:])) * v for k, v in m["troubled_per_class"].items())
-    rates = {"predictor": pred_flops / (st["predictor"] * 1e-3) / 1e12,
-             "subcell": sub_flops / (st["subcell"] * 1e-3) / 1e12}
-    dom = max(("predictor", "subcell"), key=lambda g: st[g])
-    flops = pred_flops if dom == "predictor" else sub_flops
-    achieved = rates[dom]
-    tr = TRAFFIC.get(dom)
+    """Roofline of the dominant kernel of the mixed batched step: the launch (stage, degree
+    class) with the largest time per step among the predictor and the subcell recompute,
+    its algorithmic flops (predictor_flops_per_cell x the class's cells, or
+    subcell_flops_per_cell x the class's troubled cells) over its average launch duration
+    (HIP events around that launch on the batch stream, the timed steps of the profiled
+    pass).  The other stage's rate is reported beside it."""
+    lm = m["launch_ms"]
+    cells = {}
+    for wl in wls:
+        cells[wl.N] = cells.get(wl.N, 0) + wl.num_cells
+    troubled = {int(k[1:]): v for k, v in m["troubled_per_class"].items()}
+    def flops(stage, N):
+        if stage == "predictor":
+            return predictor_flops_per_cell(2, N) * cells[N]
+        return subcell_flops_per_cell(2, N) * troubled.get(N, 0)
+    cand = [(k.split(":")[0], int(k.split(":N")[1])) for k in lm if k.startswith(("predictor:", "subcell:"))]
+    stage, N = max(cand, key=lambda x: lm[f"{x[0]}:N{x[1]}"])
+    dur_ms = lm[f"{stage}:N{N}"]
+    f = flops(stage, N)
+    achieved = f / (dur_ms * 1e-3) / 1e12
+    tr = TRAFFIC.get(f"{stage}:N{N}")
     traffic = tr[0] if tr and tr[1] == kernel_source_hash() else None
-    kern = {"predictor": "kb_predictor<2, N, float> (FP32 space-time predictor + volume term + face traces), "
-                         "one launch per degree N = 3, 4, 5",
-            "subcell": "kb_subcell<2, N, float> (subcell ADER-WENO3 over the global troubled worklist), "
-                       "one launch per degree N = 3, 4, 5"}[dom]
+    kern = {"predictor": f"kb_predictor<2, {N}, float> (FP32 space-time predictor + volume term + face traces, "
+                         f"all {cells[N]} cells of degree {N})",
+            "subcell": f"kb_subcell<2, {N}, float, false> (subcell ADER-WENO3 over the global worklist of the "
+                       f"{troubled.get(N, 0)} troubled cells of degree {N})"}[stage]
+    st = m["stages_ms_per_step"]
+    pred_all = sum(flops("predictor", n) for n in cells)
+    sub_all = sum(flops("subcell", n) for n in cells)
     return {
         "bound": "alu",
         "kernel": kern,
@@ -549,11 +569,11 @@ def batch_roofline(wls, m):
         "frac": achieved / PEAK_FP32_TFLOPS,
         "frac_of_nonpacked_fp32": achieved / PEAK_FP32_NONPACKED_TFLOPS,
         "traffic": traffic,
-        "traffic_unit": "HBM bytes per batch step of the stage (calibrated rocprofv3 counters)",
-        "flops_per_step": flops,
-        "ms_per_step": st[dom],
-        "share_of_step": st[dom] / sum(st.values()),
-        "other_stage_rates_tflops": {k: v for k, v in rates.items() if k != dom},
+        "traffic_unit": "HBM bytes per launch (calibrated rocprofv3 counters)",
+        "flops_per_launch": f,
+        "avg_launch_ms": dur_ms,
+        "stage_rates_tflops": {"predictor": pred_all / (st["predictor"] * 1e-3) / 1e12,
+                               "subcell": sub_all / (st["subcell"] * 1e-3) / 1e12},
     }
 
 

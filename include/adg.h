@@ -221,20 +221,21 @@ int adg_profile_read(adg_problem *pb, double *ms, int64_t *launches, int ngroups
  * captures and replays on a stream of its own (created by adg_batch_create).
  * adg_batch_step_cfl: the first call (or a call with another cfl) takes one ordinary step
  * per problem, then captures one step of every problem (dt from eq. (cfl) per problem, on
- * the device; each class's stages in order on a branch of its own) into two hipGraphs (the
- * two buffer parities) and from then on replays them: one hipGraphLaunch per batch step.  Synchronises the batch stream before returning.
+ * the device; stage after stage, the classes one after another) into two hipGraphs (the two
+ * buffer parities) and from then on replays them: one hipGraphLaunch per batch step.  Synchronises the batch stream before returning.
  * Errors: ADG_EINVAL, ADG_ESTATE (not bound), ADG_EDEVICE; ADG_ECAPACITY if any problem's
  * troubled cells exceeded its pool capacity (the message names the first such problem);
  * ADG_ENONPHYSICAL (a warning, as for adg_step) if a problem's count of non-physical
  * subcell results rose.
  * adg_batch_profile(b, 1) clears the stage timing; while it is on, each batch step
  * enqueues the graph's launches directly on the batch stream (the same kernels in the same
- * order) with a HIP event at the start of every stage and at the end of the step (stages:
- * 0 time step, 1 ghost-ring bounds, 2 predictor, 3 face fluxes, 4 corrector + detection,
- * 5 compaction + worklist offsets, 6 subcell ADER-WENO3 (+ MOOD layer), 7 flux correction,
- * 8 time advance); adg_batch_profile(b, 0) returns to graph replays.
- * adg_batch_profile_read fills ms[s] (total milliseconds) and steps[s] for s < nstages
- * (<= 9).
+ * order) with a HIP event before every launch group (stage, class) and one at the end of
+ * the step (stages: 0 time step, 1 ghost-ring bounds, 2 predictor, 3 face fluxes,
+ * 4 corrector + detection, 5 compaction + worklist offsets, 6 subcell ADER-WENO3 (+ MOOD
+ * layer), 7 flux correction, 8 time advance); adg_batch_profile(b, 0) returns to graph
+ * replays.  adg_batch_classes returns the number of classes and fills their dim and N (up
+ * to max_classes); adg_batch_profile_read fills ms[stage * nclasses + class] (total
+ * milliseconds; 9 x nclasses entries) and *steps (timed batch steps).
  * adg_batch_dt: per-problem dt of the last batch step (host memory, count doubles).
  * Synchronising. */
 typedef struct adg_batch adg_batch;
@@ -243,7 +244,8 @@ size_t adg_batch_workspace_bytes(const adg_batch *b);
 int adg_batch_bind(adg_batch *b, void *dev_workspace, size_t bytes, void *hip_stream);
 int adg_batch_step_cfl(adg_batch *b, double cfl, int nsteps);
 int adg_batch_profile(adg_batch *b, int enable);
-int adg_batch_profile_read(adg_batch *b, double *ms, int64_t *steps, int nstages);
+int adg_batch_classes(const adg_batch *b, int *dims, int *Ns, int max_classes);
+int adg_batch_profile_read(adg_batch *b, double *ms, int64_t *steps);
 int adg_batch_dt(adg_batch *b, double *dts);
 int adg_batch_destroy(adg_batch *b);
 

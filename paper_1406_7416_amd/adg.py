@@ -25,7 +25,7 @@ EXPORTS = [
     "adg_profile", "adg_profile_read", "adg_batch_create", "adg_batch_step_cfl", "adg_batch_dt",
     "adg_batch_destroy", "adg_debug_force_troubled", "adg_debug_poison", "adg_get_mood_stats",
     "adg_cfl_dt_static", "adg_state_device_ptr", "adg_batch_workspace_bytes", "adg_batch_bind",
-    "adg_batch_profile", "adg_batch_profile_read",
+    "adg_batch_profile", "adg_batch_profile_read", "adg_batch_classes",
 ]
 
 BATCH_STAGES = ["dt", "bounds", "predictor", "faces", "corrector_detect", "compact", "subcell", "fluxcorr",
@@ -97,7 +97,8 @@ def load():
     L.adg_batch_workspace_bytes.argtypes = [vp]
     L.adg_batch_bind.argtypes = [vp, vp, C.c_size_t, vp]
     L.adg_batch_profile.argtypes = [vp, C.c_int]
-    L.adg_batch_profile_read.argtypes = [vp, dp, C.POINTER(i64), C.c_int]
+    L.adg_batch_profile_read.argtypes = [vp, dp, C.POINTER(i64)]
+    L.adg_batch_classes.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.c_int]
     L.adg_state_device_ptr.argtypes = [vp, C.POINTER(vp)]
     L.adg_cfl_dt_static.argtypes = [vp, C.c_int, C.c_int, C.c_int64, C.c_double, C.c_double, C.c_double, vp, vp]
     for name in EXPORTS[1:]:
@@ -387,12 +388,27 @@ class Batch:
         """Starts (clears) or stops the per-stage timing (events inside the graphs)."""
         _check(load().adg_batch_profile(self.h, 1 if enable else 0))
 
+    def classes(self):
+        """The (dim, N) classes of the batch, in launch order."""
+        L = load()
+        nc = L.adg_batch_classes(self.h, None, None, 0)
+        if nc < 0:
+            _check(nc)
+        dims, Ns = (C.c_int * nc)(), (C.c_int * nc)()
+        L.adg_batch_classes(self.h, dims, Ns, nc)
+        return [(dims[i], Ns[i]) for i in range(nc)]
+
     def profile_read(self) -> dict:
+        """{stage: (total ms, timed steps)} and, under "launches", {(stage, (dim, N)): total ms}."""
+        cls = self.classes()
         ns = len(BATCH_STAGES)
-        ms = np.zeros(ns)
-        n = (C.c_int64 * ns)()
-        _check(load().adg_batch_profile_read(self.h, _dp(ms), n, ns))
-        return {g: (float(ms[i]), int(n[i])) for i, g in enumerate(BATCH_STAGES)}
+        ms = np.zeros(ns * len(cls))
+        n = C.c_int64()
+        _check(load().adg_batch_profile_read(self.h, _dp(ms), C.byref(n)))
+        out = {g: (float(ms[i * len(cls):(i + 1) * len(cls)].sum()), int(n.value)) for i, g in enumerate(BATCH_STAGES)}
+        out["launches"] = {(g, cls[c]): float(ms[i * len(cls) + c]) for i, g in enumerate(BATCH_STAGES)
+                           for c in range(len(cls))}
+        return out
 
     def step_cfl(self, cfl: float, nsteps: int = 1):
         _check(load().adg_batch_step_cfl(self.h, cfl, nsteps))

@@ -1008,7 +1008,7 @@ int adg_profile_read(adg_problem *pb, double *ms, int64_t *launches, int ngroups
 
 // One (d, N) class of a batch: its problems share every kernel instantiation.
 struct BatchClass {
-    int dim = 0, N = 0, group = 0;
+    int dim = 0, N = 0;
     std::vector<int> members;             // indices into adg_batch::ps
     std::vector<BTile> tiles[6];          // lambda, bounds, predictor, face, corrector, compaction
     size_t off_ents[2] = {0, 0}, off_tiles[6] = {0, 0, 0, 0, 0, 0}, off_wt = 0, off_wc = 0;
@@ -1023,8 +1023,6 @@ struct adg_batch {
     hipStream_t user = nullptr;           // the caller's stream bound to the batch
     hipStream_t stream = nullptr;         // the batch's own stream: captures and replays (a
                                           // legacy null stream cannot be captured)
-    std::vector<hipStream_t> cstream;     // one branch per class inside the graph
-    std::vector<hipEvent_t> cev;          // fork (0) and per-class join events
     char *ws = nullptr;
     size_t ws_bytes = 0;
     bool bound = false;
@@ -1036,10 +1034,10 @@ struct adg_batch {
     double cfl = 0;
     // stage timing: events at the start of every stage and at the end, inside the graphs
     unsigned prof_mask = 0;
-    hipEvent_t ev[2][BSTAGE_COUNT + 1] = {};
+    std::vector<hipEvent_t> ev[2];        // [stage * nclass + class], then one at the end
     bool ev_pending[2] = {false, false};
-    double prof_ms[BSTAGE_COUNT] = {0};
-    int64_t prof_n[BSTAGE_COUNT] = {0};
+    std::vector<double> prof_ms;          // [stage * nclass + class] total milliseconds
+    int64_t prof_n = 0;                   // timed steps
 };
 
 // Host-side bookkeeping of one step (what do_step does after its launches), for replays.
@@ -1167,52 +1165,38 @@ static BatchLaunch batch_launch(const adg_batch *b, const BatchClass &K, int g) 
 }
 
 // The stages of one step of every problem, stage after stage, each one batched launch
-// per class; timed: an event at the start of every stage and at the end (on the batch
-// stream, outside any graph).
-static int batch_enqueue(adg_batch *b, int g, bool timed) {
-    if (timed && b->ev_pending[g]) {
-        // this parity's events of the previous step: add them up before recording again
-        HIPCHK(hipEventSynchronize(b->ev[g][BSTAGE_COUNT]));
-        for (int st = 0; st < BSTAGE_COUNT; st++) {
-            float ms = 0.f;
-            HIPCHK(hipEventElapsedTime(&ms, b->ev[g][st], b->ev[g][st + 1]));
-            b->prof_ms[st] += ms;
-            b->prof_n[st] += 1;
-        }
+// per class, all on the batch stream; timed: an event before every launch group (stage,
+// class) and one at the end (outside any graph).
+static void batch_harvest(adg_batch *b, int g) {
+    const size_t nl = BSTAGE_COUNT * b->cls.size();
+    for (size_t i = 0; i < nl; i++) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, b->ev[g][i], b->ev[g][i + 1]) == hipSuccess) b->prof_ms[i] += ms;
     }
-    for (int st = 0; st < BSTAGE_COUNT; st++) {
-        if (timed) HIPCHK(hipEventRecord(b->ev[g][st], b->stream));
-        const bool lim_stage = st == BSTAGE_BOUNDS || st == BSTAGE_COMPACT || st == BSTAGE_SUBCELL ||
-                               st == BSTAGE_FLUXCORR;
-        if (lim_stage && !b->limiter) continue;
-        for (const auto &K : b->cls) launch_batched(K.dim, K.N, st, batch_launch(b, K, g));
-    }
-    if (timed) {
-        HIPCHK(hipEventRecord(b->ev[g][BSTAGE_COUNT], b->stream));
-        b->ev_pending[g] = true;
-    }
-    HIPCHK(hipGetLastError());
-    return ADG_OK;
+    b->prof_n += 1;
+    b->ev_pending[g] = false;
 }
 
-// One step of every class, each class's stages in order on a branch of its own (the
-// classes share no data), forked from and joined back into the batch stream.
-static int batch_enqueue_branches(adg_batch *b, int g) {
-    HIPCHK(hipEventRecord(b->cev[0], b->stream));
-    for (size_t c = 0; c < b->cls.size(); c++) {
-        const BatchClass &K = b->cls[c];
-        hipStream_t st = b->cstream[c];
-        HIPCHK(hipStreamWaitEvent(st, b->cev[0], 0));
-        BatchLaunch L = batch_launch(b, K, g);
-        L.stream = st;
-        for (int s2 = 0; s2 < BSTAGE_COUNT; s2++) {
-            const bool lim_stage = s2 == BSTAGE_BOUNDS || s2 == BSTAGE_COMPACT || s2 == BSTAGE_SUBCELL ||
-                                   s2 == BSTAGE_FLUXCORR;
+static int batch_enqueue(adg_batch *b, int g, bool timed) {
+    const int nc = (int)b->cls.size();
+    if (timed && b->ev_pending[g]) {
+        // this parity's events of the previous step: add them up before recording again
+        HIPCHK(hipEventSynchronize(b->ev[g][BSTAGE_COUNT * nc]));
+        batch_harvest(b, g);
+    }
+    for (int st = 0; st < BSTAGE_COUNT; st++) {
+        const bool lim_stage = st == BSTAGE_BOUNDS || st == BSTAGE_COMPACT || st == BSTAGE_SUBCELL ||
+                               st == BSTAGE_FLUXCORR;
+        for (int c = 0; c < nc; c++) {
+            if (timed) HIPCHK(hipEventRecord(b->ev[g][st * nc + c], b->stream));
             if (lim_stage && !b->limiter) continue;
-            launch_batched(K.dim, K.N, s2, L);
+            const BatchClass &K = b->cls[c];
+            launch_batched(K.dim, K.N, st, batch_launch(b, K, g));
         }
-        HIPCHK(hipEventRecord(b->cev[1 + c], st));
-        HIPCHK(hipStreamWaitEvent(b->stream, b->cev[1 + c], 0));
+    }
+    if (timed) {
+        HIPCHK(hipEventRecord(b->ev[g][BSTAGE_COUNT * nc], b->stream));
+        b->ev_pending[g] = true;
     }
     HIPCHK(hipGetLastError());
     return ADG_OK;
@@ -1235,7 +1219,7 @@ static int batch_capture(adg_batch *b) {
     HIPCHK(hipStreamSynchronize(b->stream));
     for (int g = 0; g < 2; g++) {
         HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-        const int rc = batch_enqueue_branches(b, g);
+        const int rc = batch_enqueue(b, g, false);
         hipGraph_t gr = nullptr;
         hipError_t e = hipStreamEndCapture(b->stream, &gr);
         if (rc != ADG_OK) return rc;
@@ -1279,54 +1263,32 @@ int adg_batch_create(adg_problem *const *ps, int count, adg_batch **out) {
     b->precision = ps[0]->prm.precision;
     b->limiter = ps[0]->prm.limiter;
     b->mood = ps[0]->prm.mood;
-    // classes of equal (dim, N), each split into `groups` launch groups (problems dealt out
-    // in turn) that run on branches of their own, so that stages of different groups overlap
-    const char *ge = std::getenv("ADG_BATCH_GROUPS");
-    const int groups = std::max(1, std::min(64, ge ? std::atoi(ge) : 4));
-    std::vector<int> seen;   // problems of each (dim, N) so far, per class index of its group 0
     for (int i = 0; i < count; i++) {
         b->saved.push_back(ps[i]->stream);
-        int k0 = -1;
-        for (size_t j = 0; j < b->cls.size(); j += 1)
-            if (b->cls[j].dim == ps[i]->P.dim && b->cls[j].N == ps[i]->P.N && b->cls[j].group == 0) k0 = (int)j;
-        if (k0 < 0) {
-            k0 = (int)b->cls.size();
-            for (int gi = 0; gi < groups; gi++) {
-                b->cls.emplace_back();
-                b->cls.back().dim = ps[i]->P.dim;
-                b->cls.back().N = ps[i]->P.N;
-                b->cls.back().group = gi;
-            }
-            seen.resize(b->cls.size(), 0);
+        int k = -1;
+        for (size_t j = 0; j < b->cls.size(); j++)
+            if (b->cls[j].dim == ps[i]->P.dim && b->cls[j].N == ps[i]->P.N) k = (int)j;
+        if (k < 0) {
+            b->cls.emplace_back();
+            b->cls.back().dim = ps[i]->P.dim;
+            b->cls.back().N = ps[i]->P.N;
+            k = (int)b->cls.size() - 1;
         }
-        const int gi = seen[k0]++ % groups;
-        b->cls[k0 + gi].members.push_back(i);
+        b->cls[k].members.push_back(i);
     }
-    // drop empty groups
-    b->cls.erase(std::remove_if(b->cls.begin(), b->cls.end(), [](const BatchClass &K) { return K.members.empty(); }),
-                 b->cls.end());
-    for (int g = 0; g < 2; g++)
-        for (int st = 0; st <= BSTAGE_COUNT; st++)
-            if (hipEventCreate(&b->ev[g][st]) != hipSuccess) {
+    for (int g = 0; g < 2; g++) {
+        b->ev[g].assign(BSTAGE_COUNT * b->cls.size() + 1, nullptr);
+        for (auto &e : b->ev[g])
+            if (hipEventCreate(&e) != hipSuccess) {
                 adg_batch_destroy(b);
                 return fail(ADG_EDEVICE, "hipEventCreate failed");
             }
+    }
+    b->prof_ms.assign(BSTAGE_COUNT * b->cls.size(), 0.0);
     if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
         adg_batch_destroy(b);
         return fail(ADG_EDEVICE, "hipStreamCreate failed");
     }
-    b->cstream.assign(b->cls.size(), nullptr);
-    b->cev.assign(b->cls.size() + 1, nullptr);
-    for (size_t c = 0; c < b->cls.size(); c++)
-        if (hipStreamCreateWithFlags(&b->cstream[c], hipStreamNonBlocking) != hipSuccess) {
-            adg_batch_destroy(b);
-            return fail(ADG_EDEVICE, "hipStreamCreate failed");
-        }
-    for (auto &e : b->cev)
-        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
-            adg_batch_destroy(b);
-            return fail(ADG_EDEVICE, "hipEventCreate failed");
-        }
     batch_plan(b);
     for (auto *pb : b->ps) pb->batch = b;
     *out = b;
@@ -1393,14 +1355,7 @@ int adg_batch_step_cfl(adg_batch *b, double cfl, int nsteps) {
     if (timed && nsteps > done) {
         HIPCHK(hipStreamSynchronize(b->stream));
         for (int g = 0; g < 2; g++)
-            for (int st = 0; st < BSTAGE_COUNT; st++) {
-                float ms = 0.f;
-                if (b->ev_pending[g] && hipEventElapsedTime(&ms, b->ev[g][st], b->ev[g][st + 1]) == hipSuccess) {
-                    b->prof_ms[st] += ms;
-                    b->prof_n[st] += 1;
-                }
-            }
-        b->ev_pending[0] = b->ev_pending[1] = false;
+            if (b->ev_pending[g]) batch_harvest(b, g);
     }
     HIPCHK(hipStreamSynchronize(b->stream));
     // the replays do not copy the counters to the host: read every problem's pool
@@ -1423,19 +1378,25 @@ int adg_batch_profile(adg_batch *b, int enable) {
     if (!b) return fail(ADG_EINVAL, "null argument");
     b->prof_mask = enable ? 1u : 0u;
     b->ev_pending[0] = b->ev_pending[1] = false;
-    for (int st = 0; st < BSTAGE_COUNT; st++) {
-        b->prof_ms[st] = 0;
-        b->prof_n[st] = 0;
-    }
+    std::fill(b->prof_ms.begin(), b->prof_ms.end(), 0.0);
+    b->prof_n = 0;
     return ADG_OK;
 }
 
-int adg_batch_profile_read(adg_batch *b, double *ms, int64_t *steps, int nstages) {
-    if (!b || !ms || !steps || nstages < 0 || nstages > BSTAGE_COUNT) return fail(ADG_EINVAL, "bad argument");
-    for (int st = 0; st < nstages; st++) {
-        ms[st] = b->prof_ms[st];
-        steps[st] = b->prof_n[st];
+int adg_batch_classes(const adg_batch *b, int *dims, int *Ns, int max_classes) {
+    if (!b) return fail(ADG_EINVAL, "null argument");
+    const int nc = (int)b->cls.size();
+    for (int c = 0; c < nc && c < max_classes; c++) {
+        if (dims) dims[c] = b->cls[c].dim;
+        if (Ns) Ns[c] = b->cls[c].N;
     }
+    return nc;
+}
+
+int adg_batch_profile_read(adg_batch *b, double *ms, int64_t *steps) {
+    if (!b || !ms || !steps) return fail(ADG_EINVAL, "null argument");
+    std::copy(b->prof_ms.begin(), b->prof_ms.end(), ms);
+    *steps = b->prof_n;
     return ADG_OK;
 }
 
@@ -1454,13 +1415,10 @@ int adg_batch_destroy(adg_batch *b) {
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     batch_drop_graphs(b);
     if (b->stream) (void)hipStreamDestroy(b->stream);
-    for (auto st : b->cstream)
-        if (st) (void)hipStreamDestroy(st);
-    for (auto e : b->cev)
-        if (e) (void)hipEventDestroy(e);
+
     for (int g = 0; g < 2; g++)
-        for (int st = 0; st <= BSTAGE_COUNT; st++)
-            if (b->ev[g][st]) (void)hipEventDestroy(b->ev[g][st]);
+        for (auto e : b->ev[g])
+            if (e) (void)hipEventDestroy(e);
     for (size_t i = 0; i < b->ps.size(); i++) {
         b->ps[i]->stream = b->saved[i];
         if (b->ps[i]->batch == b) b->ps[i]->batch = nullptr;

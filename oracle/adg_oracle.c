@@ -48,6 +48,7 @@ struct or_solver {
     double wenoinv[3][3][3];
     double *u, *vstore, *margin, *bmin, *bmax;
     uint8_t *beta, *force;
+    uint8_t *solid;            /* masked geometry: 1 = solid cell (NULL: none) */
     double t;
     long nonphys;
     long poison_cell;          /* test hook: cell whose next candidate is overwritten (-1: none) */
@@ -512,7 +513,19 @@ or_solver *or_create(const or_config *c) {
 void or_destroy(or_solver *S) {
     if (!S) return;
     free(S->u); free(S->vstore); free(S->margin); free(S->bmin); free(S->bmax);
-    free(S->beta); free(S->force); free(S);
+    free(S->beta); free(S->force); free(S->solid); free(S);
+}
+
+/* Masked geometry (reading: the paper's forward-facing step removes a rectangle from the
+ * domain and names its faces reflective walls, without saying how the scheme treats them):
+ * solid cells carry a fixed state, are never updated, troubled or corrected, and take no
+ * part in the time step; a face between a fluid and a solid cell is a reflective wall. */
+void or_set_mask(or_solver *S, const uint8_t *mask) {
+    free(S->solid);
+    S->solid = NULL;
+    if (!mask) return;
+    S->solid = malloc(S->ncell);
+    memcpy(S->solid, mask, S->ncell);
 }
 
 void or_set_threads(int nt) {
@@ -577,14 +590,51 @@ static void apply_R(const or_solver *S, const double *vcell, long vstride, doubl
         }
 }
 
+/* 1 if the cell at global coordinates g (possibly outside the domain) is solid: outside a
+ * periodic axis it wraps; outside another axis it is the cell whose interior it mirrors. */
+static int solid_at(const or_solver *S, const int *g) {
+    if (!S->solid) return 0;
+    int ci[3] = {0, 0, 0};
+    for (int k = 0; k < S->d; k++) {
+        int x = g[k], nk = S->nc[k];
+        if (x < 0 || x >= nk) {
+            if (S->c.bc[k][x >= nk].kind[0] == OR_PERIODIC) x = ((x % nk) + nk) % nk;
+            else x = x >= nk ? 2 * nk - 1 - x : -1 - x;
+        }
+        ci[k] = x;
+    }
+    return S->solid[cell_index(S, ci)];
+}
+
 /* Subcell value at global (cell, subcell) position, where the cell index may lie one
  * or more cells outside the domain.  reading (the paper is silent on boundaries of the
  * subgrid data): periodic axes wrap; other axes mirror the interior subcells across the
  * boundary and then apply the boundary rule at the ghost subcell centre (time t).
+ * A solid cell (masked geometry) holds the mirror image of the fluid across its walls: for
+ * every axis along which it has a fluid face neighbour (the lower one if both are fluid)
+ * its data is that neighbour's, mirrored along the axis (subcell index reversed, the axis's
+ * momentum negated); a solid cell at a convex corner of the obstacle, with fluid face
+ * neighbours along two axes, mirrors along both (the point reflection through the corner).
+ * The image depends on the solid cell alone, not on the cell that reads it, so two troubled
+ * cells see the same data and compute the same sub-face fluxes.
  * vn is [v][cell][sub]. */
-static void subcell_value(const or_solver *S, const double *vn, const int *gci, const int *gs, double t,
+static void subcell_value(const or_solver *S, const double *vn, const int *gci_in, const int *gs_in, double t,
                           double *out) {
     int d = S->d, Ns = S->Ns, nv = S->nv;
+    int gci[3] = {gci_in[0], gci_in[1], gci_in[2]}, gs[3] = {gs_in[0], gs_in[1], gs_in[2]};
+    int wall[3] = {0, 0, 0};
+    if (S->solid && solid_at(S, gci)) {
+        int step[3] = {0, 0, 0};
+        for (int k = 0; k < d; k++) {
+            int lo[3] = {gci[0], gci[1], gci[2]}, hi[3] = {gci[0], gci[1], gci[2]};
+            lo[k] -= 1;
+            hi[k] += 1;
+            if (!solid_at(S, lo)) step[k] = -1;
+            else if (!solid_at(S, hi)) step[k] = 1;
+        }
+        for (int k = 0; k < d; k++)
+            if (step[k]) { wall[k] = 1; gci[k] += step[k]; gs[k] = Ns - 1 - gs[k]; }
+    }
     int ci[3] = {0, 0, 0}, si[3] = {0, 0, 0};
     int ghost_axis[3], ghost_side[3], ng = 0;
     for (int k = 0; k < d; k++) {
@@ -615,6 +665,8 @@ static void subcell_value(const or_solver *S, const double *vn, const int *gci, 
             for (int v = 0; v < nv; v++) q[v] = qo[v];
         }
     }
+    for (int k = 0; k < d; k++)
+        if (wall[k]) q[1 + k] = -q[1 + k];
     for (int v = 0; v < nv; v++) out[v] = q[v];
 }
 
@@ -806,6 +858,7 @@ int or_set_state(or_solver *S, const double *u, const double *v_exact) {
         double m[5], M[5];
         for (int v = 0; v < S->nv; v++) { m[v] = S->bmin[v * ncell + c]; M[v] = S->bmax[v * ncell + c]; }
         int bad = detect_cell(S, vs, m, M, &S->margin[c]);
+        if (S->solid && S->solid[c]) { bad = 0; S->margin[c] = INFINITY; }
         if (bad) {
             S->beta[c] = 1;
             count++;
@@ -857,6 +910,7 @@ double or_cfl_dt(const or_solver *S, double cfl) {
     int d = S->d;
     for (long c = 0; c < ncell; c++)
         for (int a = 0; a < S->nn; a++) {
+            if (S->solid && S->solid[c]) break;   /* solid cells take no part in the time step */
             double q[5];
             for (int v = 0; v < S->nv; v++) q[v] = S->u[((long)v * ncell + c) * S->nn + a];
             double cs = sqrt(S->c.gamma * pressure(d, S->c.gamma, q) / q[0]);
@@ -969,6 +1023,9 @@ static void subcell_update(const or_solver *S, const double *vn, long c, double 
         if (nout == 1) {
             int nb = ci[oax] + (oside ? 1 : -1);
             if ((nb < 0 || nb >= S->nc[oax]) && S->c.bc[oax][oside].kind[0] != OR_PERIODIC) continue;
+            int f[3] = {ci[0], ci[1], ci[2]};
+            f[oax] = nb;
+            if (solid_at(S, f)) continue;   /* a wall: no subcells beyond it */
         }
         /* dimension-by-dimension WENO: work array with axes < k reconstructed (size 3,
          * node index) and axes >= k still stencil offsets (size 5). */
@@ -1030,9 +1087,15 @@ static void subcell_update(const or_solver *S, const double *vn, long c, double 
                     else { pL[j] = pR[j] = mp[j2++] + 1; }
                 }
                 int iL = flat(pL, PN, d), iR = flat(pR, PN, d);
-                int bside = -1;
+                int bside = -1, bwall = 0;
                 if (f == 0 && !W->have[iL]) bside = 0;
                 if (f == Ns && !W->have[iR]) bside = 1;
+                if (bside >= 0) {
+                    int fc[3] = {ci[0], ci[1], ci[2]};
+                    fc[k] += bside ? 1 : -1;
+                    const int inside = (fc[k] >= 0 && fc[k] < S->nc[k]) || S->c.bc[k][bside].kind[0] == OR_PERIODIC;
+                    bwall = inside && solid_at(S, fc);
+                }
                 const double *trL = W->tr + (long)iL * trsz + (long)(2 * k + 1) * nv * nfn3 * 3;
                 const double *trR = W->tr + (long)iR * trsz + (long)(2 * k + 0) * nv * nfn3 * 3;
                 /* subcell averages on both sides (halo coordinates) */
@@ -1088,7 +1151,12 @@ static void subcell_update(const or_solver *S, const double *vn, long c, double 
                                 qL[v] = pass ? avL[v] : trL[v * nfn3 * 3 + ap + nfn3 * s];
                                 qR[v] = pass ? avR[v] : trR[v * nfn3 * 3 + ap + nfn3 * s];
                             }
-                            if (bside == 0) bc_ghost(S, k, 0, qR, x, tn, qL);
+                            if (bwall) {   /* reflective wall of the masked geometry */
+                                double *qg = bside ? qR : qL;
+                                const double *qi = bside ? qL : qR;
+                                for (int v = 0; v < nv; v++) qg[v] = qi[v];
+                                qg[1 + k] = -qg[1 + k];
+                            } else if (bside == 0) bc_ghost(S, k, 0, qR, x, tn, qL);
                             else if (bside == 1) bc_ghost(S, k, 1, qL, x, tn, qR);
                             if (!pass && !(all_physical(d, g, qL, 1) && all_physical(d, g, qR, 1))) { ok = 0; break; }
                             /* the scheme's flux on the traces; first-order fallbacks use Rusanov */
@@ -1159,6 +1227,11 @@ int or_step(or_solver *S, double dt) {
         for (long c = 0; c < ncell; c++) {
             for (int v = 0; v < nv; v++)
                 for (int a = 0; a < nn; a++) ucell[v * nn + a] = S->u[((long)v * ncell + c) * nn + a];
+            if (S->solid && S->solid[c]) {   /* solid: state kept, traces never read */
+                for (int v = 0; v < nv; v++)
+                    for (int a = 0; a < nn; a++) ustar[((long)v * ncell + c) * nn + a] = ucell[v * nn + a];
+                continue;
+            }
             predictor(B, d, nv, g, dth, S->c.picard_iters, ucell, q, F, V);
             traces(B, d, nv, q, tr + c * trsz);
             /* volume term of eq. (pde.nc.gw2), divided by the diagonal mass h^d W_a:
@@ -1202,9 +1275,12 @@ int or_step(or_solver *S, double dt) {
                 nb[k] += side ? 1 : -1;
                 int boundary = nb[k] < 0 || nb[k] >= S->nc[k];
                 int periodic = S->c.bc[k][side].kind[0] == OR_PERIODIC;
-                if (side == 1 && !(boundary && !periodic)) continue;
+                if (S->solid && S->solid[c]) continue;
                 if (boundary && periodic) nb[k] = (nb[k] + S->nc[k]) % S->nc[k];
-                long cn = boundary && !periodic ? -1 : cell_index(S, nb);
+                /* a fluid cell's face toward a solid cell is a reflective wall (masked geometry) */
+                const int wall = !(boundary && !periodic) && S->solid && S->solid[cell_index(S, nb)];
+                if (side == 1 && !(boundary && !periodic) && !wall) continue;
+                long cn = (boundary && !periodic) || wall ? -1 : cell_index(S, nb);
                 for (int ap = 0; ap < nfn; ap++) {
                     double acc[5] = {0, 0, 0, 0, 0};
                     int mp[3] = {0, 0, 0};
@@ -1214,7 +1290,10 @@ int or_step(or_solver *S, double dt) {
                         /* trace of c on this face */
                         for (int v = 0; v < nv; v++)
                             qin[v] = tr[c * trsz + ((2 * k + side) * nv + v) * nfn * n + ap + nfn * s];
-                        if (cn < 0) {
+                        if (wall) {
+                            for (int v = 0; v < nv; v++) qout[v] = qin[v];
+                            qout[1 + k] = -qout[1 + k];
+                        } else if (cn < 0) {
                             double x[3];
                             int j2 = 0;
                             for (int j = 0; j < d; j++)
@@ -1247,6 +1326,7 @@ int or_step(or_solver *S, double dt) {
             if (boundary && !periodic) continue;
             if (boundary) nb[k] = 0;
             long cn = cell_index(S, nb);
+            if (S->solid && (S->solid[c] || S->solid[cn])) continue;   /* wall: computed by c itself */
             for (int v = 0; v < nv; v++)
                 for (int ap = 0; ap < nfn; ap++)
                     gbar[c * gsz + ((2 * k + 1) * nv + v) * nfn + ap] = gbar[cn * gsz + ((2 * k + 0) * nv + v) * nfn + ap];
@@ -1256,6 +1336,7 @@ int or_step(or_solver *S, double dt) {
 #pragma omp parallel for schedule(static)
     for (long c = 0; c < ncell; c++)
         for (int a = 0; a < nn; a++) {
+            if (S->solid && S->solid[c]) break;
             int m[3];
             unflat(a, n, d, m);
             for (int k = 0; k < d; k++) {
@@ -1294,6 +1375,7 @@ int or_step(or_solver *S, double dt) {
             for (int v = 0; v < nv; v++) { m[v] = S->bmin[v * ncell + c]; M[v] = S->bmax[v * ncell + c]; }
             int bad = detect_cell(S, vs, m, M, &S->margin[c]);
             bnew[c] = (uint8_t)(bad || S->force[c]);
+            if (S->solid && S->solid[c]) { bnew[c] = 0; S->margin[c] = INFINITY; }
             count += bnew[c];
         }
         free(vs);
@@ -1420,7 +1502,7 @@ int or_step(or_solver *S, double dt) {
             for (int m = 0; m < n; m++) phi3[sg][gq][m] = lagrange(n, B->xi, m, (sg + S->B3.xi[gq]) / Ns);
 #pragma omp parallel for schedule(static)
     for (long c = 0; c < ncell; c++) {
-        if (bnew[c]) continue;
+        if (bnew[c] || (S->solid && S->solid[c])) continue;
         int ci[3];
         cell_coords(S, c, ci);
         for (int k = 0; k < d; k++)

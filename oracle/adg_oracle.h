@@ -67,6 +67,9 @@ void or_get_margin(const or_solver *s, double *margin);
 void or_get_subcells(const or_solver *s, double *v);
 void or_get_bounds(const or_solver *s, double *bmin, double *bmax);
 void or_force_troubled(or_solver *s, const uint8_t *mask);
+/* Masked geometry: mask[c] = 1 marks a solid cell (copied; NULL clears).  Set it before
+ * or_set_state. */
+void or_set_mask(or_solver *s, const uint8_t *mask);
 int or_poison(or_solver *s, long cell, int var, double value);
 /* MOOD layer of the last step: subcells whose WENO3 candidate failed, cells recomputed. */
 void or_mood_stats(const or_solver *s, long *flagged, long *redone);

@@ -52,6 +52,7 @@ def lib():
         L.or_get_subcells.argtypes = [C.c_void_p, dp]
         L.or_get_bounds.argtypes = [C.c_void_p, dp, dp]
         L.or_force_troubled.argtypes = [C.c_void_p, C.POINTER(C.c_uint8)]
+        L.or_set_mask.argtypes = [C.c_void_p, C.POINTER(C.c_uint8)]
         L.or_poison.argtypes = [C.c_void_p, C.c_long, C.c_int, C.c_double]
         L.or_mood_stats.argtypes = [C.c_void_p, C.POINTER(C.c_long), C.POINTER(C.c_long)]
         L.or_numerical_flux.argtypes = [C.c_int, C.c_int, C.c_double, C.c_int, dp, dp, dp]
@@ -215,6 +216,14 @@ class Oracle:
         f, r = C.c_long(), C.c_long()
         lib().or_mood_stats(self.h, C.byref(f), C.byref(r))
         return f.value, r.value
+
+    def set_mask(self, mask: Optional[np.ndarray]):
+        """Masked geometry: mask[c] = 1 marks a solid cell (before set_state)."""
+        if mask is None:
+            lib().or_set_mask(self.h, None)
+        else:
+            m = np.ascontiguousarray(mask, dtype=np.uint8)
+            lib().or_set_mask(self.h, m.ctypes.data_as(C.POINTER(C.c_uint8)))
 
     def force_troubled(self, mask: Optional[np.ndarray]):
         if mask is None:

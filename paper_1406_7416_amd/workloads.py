@@ -12,6 +12,7 @@ Workloads follow the experiments of Sec. 5 of Dumbser, Zanotti, Loubere, Diot (2
   * double_mach                   -- Sec. 5, double Mach reflection (W&C frame)
   * quadrant_batch                -- Sec. 5, 2D Riemann problems (random quadrant states)
   * shock_tube                    -- Sec. 5, Sod and Lax tubes (Table 1)
+  * forward_facing_step           -- Sec. 5, forward-facing step (masked geometry, step_mask)
   * contact_wave                  -- polynomial density advected at constant u, p
 """
 from __future__ import annotations
@@ -304,6 +305,35 @@ def shock_vortex(nx: int = 200, ny: int = 100, N: int = 5) -> Workload:
     out = BC.simple(TRANSMISSIVE)
     return Workload("shock_vortex", 2, N, (nx, ny), (0.0, 0.0), (2.0, 1.0),
                     [(inflow, out), (out, out)], ic, gamma=g, t_end=0.7)
+
+
+# ------------------------------------------------------- forward-facing step
+def forward_facing_step(nx: int = 300, ny: int = 100, N: int = 5, gamma: float = 1.4) -> Workload:
+    """Sec. 5 forward-facing step: a Mach-3 wind tunnel, rho = gamma, p = 1, u = 3, v = 0,
+    on [0,3] x [0,1] without the step [0.6,3] x [0,0.2] (the cells with centres in it are solid,
+    step_mask); inflow of the initial state on the left, outflow (transmissive) on the right,
+    reflective walls at the top, the bottom and on the step.  The paper's mesh size h = 1/100
+    is the default grid; t_end = 4."""
+    state = (gamma, 3.0, 0.0, 1.0)
+
+    def ic(x, t=0.0):
+        X, Y = x[0], x[1]
+        z = 0.0 * X + 0.0 * Y
+        return prim_to_cons(gamma, state[0] + z, [state[1] + z, state[2] + z], state[3] + z)
+
+    wl = Workload("forward_step", 2, N, (nx, ny), (0.0, 0.0), (3.0, 1.0),
+                  [(BC.simple(DIRICHLET, _cons_tuple(gamma, state)), BC.simple(TRANSMISSIVE)),
+                   (BC.simple(REFLECTIVE), BC.simple(REFLECTIVE))], ic, gamma=gamma, t_end=4.0)
+    return wl
+
+
+def step_mask(wl: Workload, x0: float = 0.6, y1: float = 0.2) -> np.ndarray:
+    """Solid cells of the forward-facing step: cell centres in [x0, hi_x] x [lo_y, y1], one byte
+    per cell, x fastest."""
+    nx, ny = wl.ncell[0], wl.ncell[1]
+    xc = wl.lo[0] + (np.arange(nx) + 0.5) * (wl.hi[0] - wl.lo[0]) / nx
+    yc = wl.lo[1] + (np.arange(ny) + 0.5) * (wl.hi[1] - wl.lo[1]) / ny
+    return ((xc[None, :] > x0) & (yc[:, None] < y1)).astype(np.uint8).ravel()
 
 
 # ------------------------------------------------------- four-quadrant RPs

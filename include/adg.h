@@ -140,6 +140,21 @@ int adg_project_samples(const adg_problem *pb, const double *samples, int m, dou
  * (ADG_ECAPACITY otherwise).  Synchronising. */
 int adg_set_state(adg_problem *pb, const double *u, int on_device, const double *v_exact);
 
+/* Masked geometry (Sec. 5, forward-facing step: a rectangle is removed from the domain and
+ * its faces are reflective walls).  mask: host, one byte per cell (x fastest), nonzero =
+ * solid; NULL removes the mask.  A solid cell keeps whatever state adg_set_state gave it,
+ * is never updated, troubled or corrected and takes no part in the time step; a face
+ * between a fluid and a solid cell is a reflective wall for the DG face fluxes and for the
+ * subcell scheme's sub-faces.  Where the subcell halo or the neighbourhood bounds V_i of
+ * eq. (dmp) reach a solid cell, it holds the mirror image of the fluid across its walls:
+ * along each axis with a fluid face neighbour (the lower one if both are fluid) the
+ * neighbour's subcells, reversed along that axis with that axis's momentum negated (at a
+ * convex corner of the obstacle, mirrored along both axes).  Call it before
+ * adg_set_state (whose initial detection uses it); it may be called before or after
+ * adg_bind.  Errors: ADG_EINVAL (every cell solid), ADG_ESTATE (the problem belongs to a
+ * batch), ADG_EDEVICE.  Synchronising when bound. */
+int adg_set_mask(adg_problem *pb, const uint8_t *mask);
+
 /* Copies the DG state out (device pointer if to_device).  Synchronising for host copies. */
 int adg_get_state(const adg_problem *pb, double *u, int to_device);
 

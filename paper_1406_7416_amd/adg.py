@@ -25,7 +25,7 @@ EXPORTS = [
     "adg_profile", "adg_profile_read", "adg_batch_create", "adg_batch_step_cfl", "adg_batch_dt",
     "adg_batch_destroy", "adg_debug_force_troubled", "adg_debug_poison", "adg_get_mood_stats",
     "adg_cfl_dt_static", "adg_state_device_ptr", "adg_batch_workspace_bytes", "adg_batch_bind",
-    "adg_batch_profile", "adg_batch_profile_read", "adg_batch_classes",
+    "adg_batch_profile", "adg_batch_profile_read", "adg_batch_classes", "adg_set_mask",
 ]
 
 BATCH_STAGES = ["dt", "bounds", "predictor", "faces", "corrector_detect", "compact", "subcell", "fluxcorr",
@@ -75,6 +75,7 @@ def load():
     L.adg_axis_points.argtypes = [vp, C.c_int, C.c_int, dp]
     L.adg_project_samples.argtypes = [vp, dp, C.c_int, dp, dp]
     L.adg_set_state.argtypes = [vp, vp, C.c_int, dp]
+    L.adg_set_mask.argtypes = [vp, C.POINTER(C.c_uint8)]
     L.adg_get_state.argtypes = [vp, vp, C.c_int]
     L.adg_cfl_dt.argtypes = [vp, C.c_double, dp]
     L.adg_step.argtypes = [vp, C.c_double]
@@ -241,6 +242,16 @@ class Problem:
 
     def project(self, ic, m: int, t: float = 0.0):
         return _project(self.h, self.wl, ic, m, t, self.Ns)
+
+    def set_mask(self, mask: Optional[np.ndarray]):
+        """Masked geometry: one byte per cell (x fastest), nonzero = solid; None removes it.
+        Call before set_state."""
+        if mask is None:
+            _check(load().adg_set_mask(self.h, None))
+            return
+        m = np.ascontiguousarray(mask, dtype=np.uint8).ravel()
+        assert m.size == self.wl.num_cells
+        _check(load().adg_set_mask(self.h, m.ctypes.data_as(C.POINTER(C.c_uint8))))
 
     def set_state(self, u, v_exact: Optional[np.ndarray] = None):
         ve = None if v_exact is None else np.ascontiguousarray(v_exact, dtype=np.float64)

@@ -71,10 +71,12 @@ struct adg_problem {
     struct Off {
         size_t tab, u0, u1, emin0, emax0, emin1, emax1, trace, gbar, beta0, beta1, force, mflag, margin, tlist, clist,
             slot0,
-            slot1, pool0, pool1, sflux, blk, counts, scal, lampart, ring, halo, Y, strace, fpts, end;
+            slot1, pool0, pool1, sflux, blk, counts, scal, lampart, ring, halo, Y, strace, fpts, mask, end;
     } off;
-    int64_t ring_cap = 0;    // ghost-ring cells of the extended grid
-    int64_t nring = 0;       // of which the detection reads (non-periodic sides)
+    int64_t ring_cap = 0;    // ghost-ring cells of the extended grid (+ every cell, for solid cells)
+    int64_t nring = 0;       // extended cells whose bounds the step computes (ghost ring on
+                             // non-periodic sides, solid cells of the masked geometry)
+    std::vector<uint8_t> mask;   // masked geometry, 1 = solid (empty: no solid cells)
     bool bounds_valid = false;  // interior old-time bounds were written by the previous step
     // bound state
     char *ws = nullptr;
@@ -195,13 +197,14 @@ static void plan(adg_problem *pb) {
     {
         int64_t inner = 1;
         for (int j = 0; j < d; j++) inner *= P.nc[j];
-        pb->ring_cap = next - inner;
+        pb->ring_cap = next - inner + nc;
     }
     f.ring = take(8ull * std::max<int64_t>(1, pb->ring_cap));
     f.halo = take(8ull * chunk * nv * hsz);
     f.Y = take(8ull * chunk * pb->npos * nv * n3);
     f.strace = take(8ull * chunk * pb->npos * 2 * d * nv * nf3 * 3);
     f.fpts = take(8ull * chunk * 2 * d * nv * ipow64(3 * Ns, d - 1));
+    f.mask = take(nc);
     f.end = o;
     pb->ws_bytes = o;
 }
@@ -240,7 +243,46 @@ static void carve(adg_problem *pb) {
     B.Y = (double *)(w + f.Y);
     B.strace = (double *)(w + f.strace);
     B.fpts = (double *)(w + f.fpts);
+    B.mask = pb->mask.empty() ? nullptr : (const uint8_t *)(w + f.mask);
     pb->tab_dev = B.tab;
+}
+
+// The masked geometry (if any) into the workspace, then the extended-grid cells whose
+// old-time bounds each step computes, x fastest: the ghost-ring cells the detection reads
+// (a ring cell whose out-of-range coordinates all lie on non-periodic axes; along a periodic
+// axis the detection wraps to the interior cell instead), then the solid cells (their
+// bounds are those of their mirror image, which the fluid's new data changes every step).
+static int upload_mask_ring(adg_problem *pb) {
+    const Prob &P = pb->P;
+    std::vector<int64_t> ring;
+    ring.reserve(pb->ring_cap);
+    const int64_t ne0 = P.nc[0] + 2, ne1 = P.dim > 1 ? P.nc[1] + 2 : 1, ne2 = P.dim > 2 ? P.nc[2] + 2 : 1;
+    for (int64_t k = 0; k < ne2; k++)
+        for (int64_t j = 0; j < ne1; j++)
+            for (int64_t i = 0; i < ne0; i++) {
+                const int64_t e[3] = {i, j, k}, ne[3] = {ne0, ne1, ne2};
+                bool ghost = false, periodic_image = false;
+                for (int a = 0; a < P.dim; a++)
+                    if (e[a] == 0 || e[a] == ne[a] - 1) {
+                        ghost = true;
+                        if (P.periodic[a]) periodic_image = true;
+                    }
+                if (ghost && !periodic_image) ring.push_back(i + ne0 * (j + ne1 * k));
+            }
+    if (!pb->mask.empty()) {
+        for (int64_t c = 0; c < P.ncell; c++) {
+            if (!pb->mask[c]) continue;
+            const int64_t i = c % P.nc[0], j = P.dim > 1 ? (c / P.nc[0]) % P.nc[1] : 0,
+                          k = P.dim > 2 ? c / ((int64_t)P.nc[0] * P.nc[1]) : 0;
+            ring.push_back((i + 1) + ne0 * ((P.dim > 1 ? j + 1 : 0) + ne1 * (P.dim > 2 ? k + 1 : 0)));
+        }
+        HIPCHK(hipMemcpyAsync(pb->ws + pb->off.mask, pb->mask.data(), P.ncell, hipMemcpyHostToDevice, pb->stream));
+    }
+    if ((int64_t)ring.size() > pb->ring_cap) return fail(ADG_EINVAL, "internal: ghost ring size");
+    pb->nring = (int64_t)ring.size();
+    if (pb->nring) HIPCHK(hipMemcpyAsync(pb->B.ring, ring.data(), 8 * ring.size(), hipMemcpyHostToDevice, pb->stream));
+    HIPCHK(hipStreamSynchronize(pb->stream));
+    return ADG_OK;
 }
 
 static StepCtx ctx(const adg_problem *pb) {
@@ -381,29 +423,8 @@ int adg_bind(adg_problem *pb, void *dev_workspace, size_t bytes, void *hip_strea
     if (!pb->pinned) HIPCHK(hipHostMalloc((void **)&pb->pinned, 64, hipHostMallocDefault));
     HIPCHK(hipMemcpyAsync(pb->tab_dev, &pb->tab_host, sizeof(Tables), hipMemcpyHostToDevice, pb->stream));
     {
-        // extended-grid indices of the ghost-ring cells the detection reads, x fastest: a
-        // ring cell whose out-of-range coordinates all lie on non-periodic axes (along a
-        // periodic axis the detection wraps to the interior cell instead)
-        const Prob &P = pb->P;
-        std::vector<int64_t> ring;
-        ring.reserve(pb->ring_cap);
-        const int64_t ne0 = P.nc[0] + 2, ne1 = P.dim > 1 ? P.nc[1] + 2 : 1, ne2 = P.dim > 2 ? P.nc[2] + 2 : 1;
-        for (int64_t k = 0; k < ne2; k++)
-            for (int64_t j = 0; j < ne1; j++)
-                for (int64_t i = 0; i < ne0; i++) {
-                    const int64_t e[3] = {i, j, k}, ne[3] = {ne0, ne1, ne2};
-                    bool ghost = false, periodic_image = false;
-                    for (int a = 0; a < P.dim; a++)
-                        if (e[a] == 0 || e[a] == ne[a] - 1) {
-                            ghost = true;
-                            if (P.periodic[a]) periodic_image = true;
-                        }
-                    if (ghost && !periodic_image) ring.push_back(i + ne0 * (j + ne1 * k));
-                }
-        if ((int64_t)ring.size() > pb->ring_cap) return fail(ADG_EINVAL, "internal: ghost ring size");
-        pb->nring = (int64_t)ring.size();
-        if (pb->nring)
-            HIPCHK(hipMemcpyAsync(pb->B.ring, ring.data(), 8 * ring.size(), hipMemcpyHostToDevice, pb->stream));
+        const int rc = upload_mask_ring(pb);
+        if (rc != ADG_OK) return rc;
         HIPCHK(hipStreamSynchronize(pb->stream));
     }
     HIPCHK(hipMemsetAsync(pb->B.counts, 0, 32, pb->stream));
@@ -417,6 +438,30 @@ int adg_bind(adg_problem *pb, void *dev_workspace, size_t bytes, void *hip_strea
     pb->has_state = false;
     pb->cur = 0;
     return ADG_OK;
+}
+
+int adg_set_mask(adg_problem *pb, const uint8_t *mask) {
+    if (!pb) return fail(ADG_EINVAL, "null argument");
+    if (pb->batch) return fail(ADG_ESTATE, "the problem belongs to a batch: destroy the batch first");
+    const Prob &P = pb->P;
+    pb->mask.clear();
+    if (mask) {
+        int64_t nsolid = 0;
+        pb->mask.assign(P.ncell, 0);
+        for (int64_t c = 0; c < P.ncell; c++) {
+            pb->mask[c] = mask[c] ? 1 : 0;
+            nsolid += pb->mask[c];
+        }
+        if (nsolid == P.ncell) {
+            pb->mask.clear();
+            return fail(ADG_EINVAL, "every cell is solid");
+        }
+        if (nsolid == 0) pb->mask.clear();
+    }
+    if (!pb->bound) return ADG_OK;
+    pb->B.mask = pb->mask.empty() ? nullptr : (const uint8_t *)(pb->ws + pb->off.mask);
+    pb->bounds_valid = false;   // solid cells' old-time bounds are computed by the next step
+    return upload_mask_ring(pb);
 }
 
 int adg_axis_points(const adg_problem *pb, int axis, int m, double *out) {
@@ -597,6 +642,43 @@ static int initial_detection(adg_problem *pb, std::vector<double> &u, const doub
             }
         }
     };
+    // masked geometry: is the cell at global coordinates g solid (outside a periodic axis it
+    // wraps, outside another it is the interior cell it mirrors)
+    const uint8_t *mask = pb->mask.empty() ? nullptr : pb->mask.data();
+    auto solid_at_host = [&](const int *g) -> bool {
+        if (!mask) return false;
+        int64_t cc = 0;
+        for (int j = d - 1; j >= 0; j--) {
+            const int nk = P.nc[j];
+            int x = g[j];
+            if (x < 0 || x >= nk) x = P.periodic[j] ? ((x % nk) + nk) % nk : (x >= nk ? 2 * nk - 1 - x : -1 - x);
+            cc = cc * nk + x;
+        }
+        return mask[cc] != 0;
+    };
+    // value of one subcell of any cell: a solid cell holds the mirror image of the fluid
+    // across its walls (the lower fluid face neighbour along an axis first, else the upper;
+    // the subcell index reversed and the momentum negated along every mirrored axis)
+    auto sub_value = [&](const int *gci_in, const int *gs_in, double *q) {
+        int gci[3] = {gci_in[0], gci_in[1], gci_in[2]}, gs[3] = {gs_in[0], gs_in[1], gs_in[2]};
+        int istep[3] = {0, 0, 0};
+        if (solid_at_host(gci)) {
+            for (int k = 0; k < d; k++) {
+                int lo[3] = {gci[0], gci[1], gci[2]}, hi[3] = {gci[0], gci[1], gci[2]};
+                lo[k] -= 1;
+                hi[k] += 1;
+                istep[k] = !solid_at_host(lo) ? -1 : (!solid_at_host(hi) ? 1 : 0);
+            }
+            for (int k = 0; k < d; k++)
+                if (istep[k]) {
+                    gci[k] += istep[k];
+                    gs[k] = Ns - 1 - gs[k];
+                }
+        }
+        ghost_value(gci, gs, q);
+        for (int k = 0; k < d; k++)
+            if (istep[k]) q[1 + k] = -q[1 + k];
+    };
     // per-cell extrema of the exact subcell data
     std::vector<double> cmin((size_t)nc * nv), cmax((size_t)nc * nv);
     parallel_for(nc, [&](int64_t c0, int64_t c1) {
@@ -617,6 +699,7 @@ static int initial_detection(adg_problem *pb, std::vector<double> &u, const doub
         std::vector<double> vstar((size_t)nsub), t1, t2;
         std::vector<double> vs((size_t)nv * nsub);
         for (int64_t c = c0; c < c1; c++) {
+            if (mask && mask[c]) continue;   // solid cells are never troubled
             int ci[3] = {(int)(c % P.nc[0]), (int)((c / P.nc[0]) % P.nc[1]), (int)(c / ((int64_t)P.nc[0] * P.nc[1]))};
             double lo[5], hi[5];
             for (int vv = 0; vv < nv; vv++) {
@@ -624,7 +707,7 @@ static int initial_detection(adg_problem *pb, std::vector<double> &u, const doub
                 hi[vv] = -INFINITY;
             }
             // bounds over the 3^d neighbourhood: stored extrema of interior (or periodically
-            // wrapped) cells, subcell by subcell for ghost cells
+            // wrapped) fluid cells, subcell by subcell for ghost and solid cells
             const int nb = (int)ipow64(3, d);
             for (int o = 0; o < nb; o++) {
                 int gci[3] = {ci[0], ci[1], ci[2]};
@@ -639,7 +722,7 @@ static int initial_detection(adg_problem *pb, std::vector<double> &u, const doub
                         else ghost = true;
                     }
                 }
-                if (!ghost) {
+                if (!ghost && !solid_at_host(gci)) {
                     const int64_t cs = src[0] + (int64_t)P.nc[0] * (src[1] + (int64_t)P.nc[1] * src[2]);
                     for (int vv = 0; vv < nv; vv++) {
                         lo[vv] = std::fmin(lo[vv], cmin[(size_t)cs * nv + vv]);
@@ -650,7 +733,7 @@ static int initial_detection(adg_problem *pb, std::vector<double> &u, const doub
                 for (int64_t sg = 0; sg < nsub; sg++) {
                     const int gs[3] = {(int)(sg % Ns), (int)((sg / Ns) % Ns), (int)(sg / (Ns * Ns))};
                     double q[5];
-                    ghost_value(gci, gs, q);
+                    sub_value(gci, gs, q);
                     for (int vv = 0; vv < nv; vv++) {
                         lo[vv] = std::fmin(lo[vv], q[vv]);
                         hi[vv] = std::fmax(hi[vv], q[vv]);

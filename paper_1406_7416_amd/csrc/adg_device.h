@@ -139,4 +139,44 @@ __device__ __forceinline__ void coords_of(const Prob &P, int64_t c, int *ci) {
     ci[2] = (int)(c / ((int64_t)P.nc[0] * P.nc[1]));
 }
 
+// ------------------------------------------------------------- masked geometry
+// 1 if the cell at global coordinates g (possibly outside the domain) is solid: outside a
+// periodic axis it wraps, outside another axis it is the interior cell it mirrors.
+template <int DIM>
+__device__ __forceinline__ bool solid_at(const Prob &P, const uint8_t *mask, int g0, int g1, int g2) {
+    int c[3] = {g0, g1, g2};
+#pragma unroll
+    for (int k = 0; k < DIM; k++) {
+        const int nk = P.nc[k];
+        int x = c[k];
+        if (x < 0 || x >= nk) x = P.periodic[k] ? (x % nk + nk) % nk : (x >= nk ? 2 * nk - 1 - x : -1 - x);
+        c[k] = x;
+    }
+    if (DIM == 2) c[2] = 0;
+    return mask[cell_of(P, c)] != 0;
+}
+
+// The mirror image a solid cell g holds (the fluid across its walls): step[k] = -1 / +1 if
+// its lower / upper face neighbour along k is fluid (the lower one first), 0 if neither; the
+// image is the cell g + step with the subcell index reversed and the momentum negated along
+// every axis with step[k] != 0 (the point reflection at a convex corner of the obstacle).
+template <int DIM>
+__device__ __forceinline__ void solid_image(const Prob &P, const uint8_t *mask, const int *g, int *step) {
+#pragma unroll
+    for (int k = 0; k < 3; k++) step[k] = 0;
+#pragma unroll
+    for (int k = 0; k < DIM; k++) {
+        const int lo0 = g[0] - (k == 0), lo1 = g[1] - (k == 1), lo2 = g[2] - (k == 2);
+        const int hi0 = g[0] + (k == 0), hi1 = g[1] + (k == 1), hi2 = g[2] + (k == 2);
+        step[k] = !solid_at<DIM>(P, mask, lo0, lo1, lo2) ? -1 : (!solid_at<DIM>(P, mask, hi0, hi1, hi2) ? 1 : 0);
+    }
+}
+
+// The reflective wall of the masked geometry: the ghost state across a wall normal to k.
+template <int DIM, typename R>
+__device__ __forceinline__ void wall_ghost(int k, const R *qin, R *qout) {
+#pragma unroll
+    for (int v = 0; v < DIM + 2; v++) qout[v] = (v == 1 + k) ? -qin[v] : qin[v];
+}
+
 }  // namespace adg

@@ -66,6 +66,7 @@ struct Bufs {
     double *gbar;          // [cell][2d][v][nfn]
     uint8_t *beta[2];      // [cell] old / new
     uint8_t *force;        // [cell] forced troubled mask
+    const uint8_t *mask;   // [cell] masked geometry, 1 = solid cell (null: no solid cells)
     uint8_t *mflag;        // [slot][subcell] MOOD flags of the troubled cells' WENO3 results
     float *margin;         // [cell]
     int *tlist, *clist;    // troubled cells, corrected cells

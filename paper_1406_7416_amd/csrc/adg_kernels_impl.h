@@ -36,7 +36,8 @@ struct FaceShape {
 // compile-time constant so that no per-thread array is indexed dynamically.
 template <int DIM, int N, typename R, int K>
 __device__ __forceinline__ void face_axis(const Tables *__restrict__ T, const Prob &P, const R *__restrict__ trace,
-                                          R *__restrict__ gbar, const double *__restrict__ scal, int64_t blk, R *part) {
+                                          R *__restrict__ gbar, const double *__restrict__ scal, int64_t blk, R *part,
+                                          const uint8_t *__restrict__ mask) {
     using FS = FaceShape<DIM, N>;
     constexpr int n = N + 1, NV = DIM + 2, NFN = FS::NFN, PER = FS::PER, FPB = FS::FPB;
     constexpr int k = K;
@@ -49,18 +50,19 @@ __device__ __forceinline__ void face_axis(const Tables *__restrict__ T, const Pr
     const int lf = threadIdx.x / PER, j = threadIdx.x % PER;
     const int s = j / NFN, ap = j % NFN;
     const int64_t fidx = blk * FPB + lf;
-    const bool active = lf < FPB && fidx < nfaces;
+    bool active = lf < FPB && fidx < nfaces;
     int64_t cL = -1, cR = -1;
-    bool hasL = false, hasR = false;
+    bool hasL = false, hasR = false, wall = false;
+    int fk = 0, ci[3] = {0, 0, 0};
     if (active) {
-        const int fk = (int)(fidx % nfk);
+        fk = (int)(fidx % nfk);
         int64_t line = fidx / nfk;
         // cell coordinates, selected per axis with compile-time indices (a runtime index
         // would move the arrays to scratch memory)
         hasL = fk > 0 || P.periodic[k];
         hasR = fk < nk;
         const int fl = fk > 0 ? fk - 1 : fk - 1 + nk;
-        int cl[3] = {0, 0, 0}, cr[3] = {0, 0, 0}, ci[3] = {0, 0, 0};
+        int cl[3] = {0, 0, 0}, cr[3] = {0, 0, 0};
 #pragma unroll
         for (int jj = 0; jj < DIM; jj++) {
             if (jj == k) {
@@ -74,6 +76,15 @@ __device__ __forceinline__ void face_axis(const Tables *__restrict__ T, const Pr
         }
         cL = hasL ? cell_of(P, cl) : -1;
         cR = hasR ? cell_of(P, cr) : -1;
+        if (mask) {
+            // masked geometry: a face toward a solid cell is a reflective wall of the fluid
+            // side; a face with no fluid side carries no flux
+            if (hasL && mask[cL]) { hasL = false; wall = true; }
+            if (hasR && mask[cR]) { hasR = false; wall = true; }
+            if (!hasL && !hasR) active = false;
+        }
+    }
+    if (active) {
         const double dt = scal[0], t0 = scal[1];
         // node position on the face (for boundary states)
         double x[3] = {0, 0, 0};
@@ -98,7 +109,10 @@ __device__ __forceinline__ void face_axis(const Tables *__restrict__ T, const Pr
 #pragma unroll
             for (int v = 0; v < NV; v++) qR[v] = trace[((cR * 2 * DIM + 2 * k) * NV + v) * (NFN * n) + ap + NFN * s];
         }
-        if (!hasL || !hasR) {
+        if (wall) {
+            if (hasL) wall_ghost<DIM, R>(k, qL, qR);
+            else wall_ghost<DIM, R>(k, qR, qL);
+        } else if (!hasL || !hasR) {
             const double ts = t0 + T->xi[s] * dt;
             double qi[NV], qo[NV];
             if (hasL) {
@@ -142,24 +156,24 @@ __device__ __forceinline__ void face_axis(const Tables *__restrict__ T, const Pr
 template <int DIM, int N, typename R>
 __device__ __forceinline__ void face_block(const Tables *__restrict__ T, const Prob &P, const R *__restrict__ trace,
                                            R *__restrict__ gbar, const double *__restrict__ scal, int64_t kb1,
-                                           int64_t kb2, int64_t bid) {
+                                           int64_t kb2, int64_t bid, const uint8_t *__restrict__ mask) {
     // one launch for the faces of every axis: blocks [0, kb1) axis 0, [kb1, kb2) axis 1, then axis 2
     using FS = FaceShape<DIM, N>;
     __shared__ R part[FS::FPB * FS::PER * (DIM + 2)];
     const int k = (bid < kb1) ? 0 : ((bid < kb2) ? 1 : 2);
     const int64_t blk = (int64_t)bid - (k == 0 ? 0 : (k == 1 ? kb1 : kb2));
     switch (k) {
-    case 0: face_axis<DIM, N, R, 0>(T, P, trace, gbar, scal, blk, part); break;
-    case 1: face_axis<DIM, N, R, 1>(T, P, trace, gbar, scal, blk, part); break;
-    default: face_axis<DIM, N, R, DIM - 1>(T, P, trace, gbar, scal, blk, part); break;
+    case 0: face_axis<DIM, N, R, 0>(T, P, trace, gbar, scal, blk, part, mask); break;
+    case 1: face_axis<DIM, N, R, 1>(T, P, trace, gbar, scal, blk, part, mask); break;
+    default: face_axis<DIM, N, R, DIM - 1>(T, P, trace, gbar, scal, blk, part, mask); break;
     }
 }
 template <int DIM, int N, typename R>
 __global__ __launch_bounds__((FaceShape<DIM, N>::BS)) void k_face(const Tables *__restrict__ T, Prob P,
                                                                  const R *__restrict__ trace, R *__restrict__ gbar,
                                                                  const double *__restrict__ scal, int64_t kb1,
-                                                                 int64_t kb2) {
-    face_block<DIM, N, R>(T, P, trace, gbar, scal, kb1, kb2, blockIdx.x);
+                                                                 int64_t kb2, const uint8_t *__restrict__ mask) {
+    face_block<DIM, N, R>(T, P, trace, gbar, scal, kb1, kb2, blockIdx.x, mask);
 }
 
 // Block-wide reduction of per-thread (min, max) pairs of NV variables: wave shuffles,
@@ -329,9 +343,12 @@ __device__ __forceinline__ void corrector_detect_block(const Tables *__restrict_
     const int lc = threadIdx.x / CW, tid = threadIdx.x % CW;
     const int64_t c = (int64_t)bid * CPB + lc;
     const bool live = c < P.ncell;         // every thread stays for the barriers
+    // masked geometry: a solid cell keeps its state and is never troubled
+    const bool solid = live && B.mask && B.mask[c];
     double *us = us_[lc], *vs = vs_[lc], *tmp = tmp_[lc], *red = red_[lc];
     const double dt = B.scal[0];
     double *un = B.u[cur ^ 1];
+    const double *usrc = solid ? B.u[cur] : un;
     // debug poison of one variable of one cell's candidate (armed by the host for one step)
     const bool poisoned = live && B.scal[4] != 0.0 && (int64_t)B.scal[5] == c;
     const int pvar = poisoned ? (int)B.scal[6] : -1;
@@ -375,7 +392,7 @@ __device__ __forceinline__ void corrector_detect_block(const Tables *__restrict_
 #pragma unroll
     for (int e = 0; e < EPT; e++) {
         const int it = tid + e * CW;
-        uv[e] = (live && it < NV * NN) ? un[((int64_t)(it / NN) * P.ncell + c) * NN + it % NN] : 0.0;
+        uv[e] = (live && it < NV * NN) ? usrc[((int64_t)(it / NN) * P.ncell + c) * NN + it % NN] : 0.0;
     }
     __syncthreads();
 #pragma unroll
@@ -387,6 +404,7 @@ __device__ __forceinline__ void corrector_detect_block(const Tables *__restrict_
         double val = uv[e];
 #pragma unroll
         for (int k = 0; k < DIM; k++) {
+            if (solid) break;
             int ap = 0, mul = 1;
             for (int j = 0; j < DIM; j++) {
                 if (j == k) continue;
@@ -497,8 +515,8 @@ __device__ __forceinline__ void corrector_detect_block(const Tables *__restrict_
             bd |= bad_s[lc][ww];
             m = fminf(m, mg_s[lc][ww]);
         }
-        B.beta[1][c] = (uint8_t)((bd || B.force[c]) ? 1 : 0);
-        B.margin[c] = m;
+        B.beta[1][c] = (uint8_t)((!solid && (bd || B.force[c])) ? 1 : 0);
+        B.margin[c] = solid ? INFINITY : m;
     }
     if (tid < 2 * NV) {
         // thread v: min of variable v; thread NV + v: max of variable v
@@ -545,6 +563,14 @@ __device__ __forceinline__ void cell_bounds_block(const Tables *__restrict__ T, 
             ei[j] = (int)(r % ne[j]) - 1;
             r /= ne[j];
         }
+    }
+    // masked geometry: a solid cell holds the mirror image of the fluid across its walls,
+    // whose subcells are those of the image cell (reversed along the mirrored axes, which
+    // leaves the extrema alone) with the mirrored axes' momenta negated
+    int istep[3] = {0, 0, 0};
+    if (B.mask && solid_at<DIM>(P, B.mask, ei[0], ei[1], ei[2])) {
+        solid_image<DIM>(P, B.mask, ei, istep);
+        for (int j = 0; j < DIM; j++) ei[j] += istep[j];
     }
     int src[3] = {0, 0, 0}, mir[3] = {0, 0, 0}, gside[3] = {-1, -1, -1};
     for (int j = 0; j < DIM; j++) {
@@ -616,6 +642,13 @@ __device__ __forceinline__ void cell_bounds_block(const Tables *__restrict__ T, 
     if (tid == 0) {
         int64_t next = 1;
         for (int j = 0; j < DIM; j++) next *= ne[j];
+#pragma unroll
+        for (int j = 0; j < DIM; j++) {
+            if (!istep[j]) continue;
+            const double l = lo[1 + j];
+            lo[1 + j] = -hi[1 + j];
+            hi[1 + j] = -l;
+        }
         for (int v = 0; v < NV; v++) {
             B.ext_min[0][(int64_t)v * next + e] = lo[v];
             B.ext_max[0][(int64_t)v * next + e] = hi[v];
@@ -632,8 +665,8 @@ __global__ __launch_bounds__(128) void k_cell_bounds(const Tables *__restrict__ 
 // Troubled cells and unlimited neighbours of troubled cells, compacted in cell order
 // with wavefront ballots and a block prefix; two passes (count, with the scan of the
 // block counts done by the last block to finish, then scatter).
-__device__ __forceinline__ bool corr_flag(const Prob &P, const uint8_t *beta, int64_t c) {
-    if (beta[c]) return false;
+__device__ __forceinline__ bool corr_flag(const Prob &P, const uint8_t *beta, const uint8_t *mask, int64_t c) {
+    if (beta[c] || (mask && mask[c])) return false;
     int ci[3];
     coords_of(P, c, ci);
     for (int k = 0; k < P.dim; k++)
@@ -658,7 +691,7 @@ __device__ __forceinline__ void compact_count_block(const Prob &P, const Bufs &B
     __shared__ int carry[2];
     const int64_t c = (int64_t)bid * CBS + threadIdx.x;
     const bool t = c < P.ncell && B.beta[1][c];
-    const bool f = c < P.ncell && corr_flag(P, B.beta[1], c);
+    const bool f = c < P.ncell && corr_flag(P, B.beta[1], B.mask, c);
     const uint64_t bt = __ballot(t), bf = __ballot(f);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     if (lane == 0) {
@@ -726,7 +759,7 @@ __device__ __forceinline__ void compact_scatter_block(const Prob &P, const Bufs 
     __shared__ int woff[2][CBS / 64];
     const int64_t c = (int64_t)bid * CBS + threadIdx.x;
     const bool t = c < P.ncell && B.beta[1][c];
-    const bool f = c < P.ncell && corr_flag(P, B.beta[1], c);
+    const bool f = c < P.ncell && corr_flag(P, B.beta[1], B.mask, c);
     const uint64_t bt = __ballot(t), bf = __ballot(f);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -798,11 +831,10 @@ __device__ __forceinline__ void sub_halo_cell(const Tables *__restrict__ T, cons
     int ci[3];
     coords_of(P, c, ci);
     const double t0 = B.scal[1];
-    // source cell of the halo block at offset (o_j - 1) along every axis
-    auto source = [&](const int *off, int *src, int *mir, int *gside, int *gci) {
+    // source cell of the cell at global coordinates gci (possibly outside the domain)
+    auto source = [&](const int *gci, int *src, int *mir, int *gside) {
         for (int j = 0; j < 3; j++) {
-            src[j] = j < DIM ? ci[j] + off[j] : 0;
-            gci[j] = src[j];
+            src[j] = j < DIM ? gci[j] : 0;
             mir[j] = 0;
             gside[j] = -1;
         }
@@ -822,10 +854,10 @@ __device__ __forceinline__ void sub_halo_cell(const Tables *__restrict__ T, cons
     if (nbu) {
         for (int i = threadIdx.x; i < NB * NV * NN; i += blockDim.x) {
             const int o = i / (NV * NN), v = (i / NN) % NV, a = i % NN;
-            int off[3] = {0, 0, 0};
-            for (int j = 0, r = o; j < DIM; j++, r /= 3) off[j] = r % 3 - 1;
-            int src[3], mir[3], gside[3], gci[3];
-            source(off, src, mir, gside, gci);
+            int gci[3] = {0, 0, 0};
+            for (int j = 0, r = o; j < DIM; j++, r /= 3) gci[j] = ci[j] + r % 3 - 1;
+            int src[3], mir[3], gside[3];
+            source(gci, src, mir, gside);
             nbu[i] = B.u[cur][((int64_t)v * P.ncell + cell_of(P, src)) * NN + a];
         }
         __syncthreads();
@@ -838,8 +870,24 @@ __device__ __forceinline__ void sub_halo_cell(const Tables *__restrict__ T, cons
             off[j] = Lj < 0 ? -1 : (Lj >= NS ? 1 : 0);
             gs[j] = Lj - off[j] * NS;
         }
-        int src[3], mir[3], gside[3], gci[3];
-        source(off, src, mir, gside, gci);
+        int gci[3] = {0, 0, 0};
+        for (int j = 0; j < DIM; j++) gci[j] = ci[j] + off[j];
+        // masked geometry: a solid cell holds the mirror image of the fluid across its walls
+        // (the image cell's subcells reversed along the mirrored axes, their momenta negated)
+        int istep[3] = {0, 0, 0};
+        bool staged = nbu != nullptr;
+        if (B.mask && solid_at<DIM>(P, B.mask, gci[0], gci[1], gci[2])) {
+            solid_image<DIM>(P, B.mask, gci, istep);
+#pragma unroll
+            for (int j = 0; j < DIM; j++)
+                if (istep[j]) {
+                    gci[j] += istep[j];
+                    gs[j] = NS - 1 - gs[j];
+                    staged = false;   // the image cell may lie outside the staged block
+                }
+        }
+        int src[3], mir[3], gside[3];
+        source(gci, src, mir, gside);
         for (int j = 0; j < DIM; j++) ss[j] = mir[j] ? NS - 1 - gs[j] : gs[j];
         const int64_t cs = cell_of(P, src);
         int sidx = 0;
@@ -853,6 +901,7 @@ __device__ __forceinline__ void sub_halo_cell(const Tables *__restrict__ T, cons
             // P(u^n) at one subcell: plain tensor sum over the nodes
             int o = 0;
             for (int j = DIM - 1; j >= 0; j--) o = o * 3 + (off[j] + 1);
+            const double *nb = staged ? nbu : nullptr;
 #pragma unroll
             for (int v = 0; v < NV; v++) q[v] = 0.0;
             for (int a = 0; a < NN; a++) {
@@ -861,7 +910,7 @@ __device__ __forceinline__ void sub_halo_cell(const Tables *__restrict__ T, cons
                 for (int j = 0; j < DIM; j++) wgt *= T->P[ss[j]][m[j]];
 #pragma unroll
                 for (int v = 0; v < NV; v++)
-                    q[v] += wgt * (nbu ? nbu[(o * NV + v) * NN + a] : B.u[cur][((int64_t)v * P.ncell + cs) * NN + a]);
+                    q[v] += wgt * (nb ? nb[(o * NV + v) * NN + a] : B.u[cur][((int64_t)v * P.ncell + cs) * NN + a]);
             }
         }
         double x[3] = {0, 0, 0};
@@ -873,6 +922,9 @@ __device__ __forceinline__ void sub_halo_cell(const Tables *__restrict__ T, cons
 #pragma unroll
             for (int v = 0; v < NV; v++) q[v] = qo[v];
         }
+#pragma unroll
+        for (int j = 0; j < DIM; j++)
+            if (istep[j]) q[1 + j] = -q[1 + j];
 #pragma unroll
         for (int v = 0; v < NV; v++) halo[v * HSZ + hidx] = q[v];
     }
@@ -1056,14 +1108,21 @@ __device__ __forceinline__ void sub_update_cell(const Tables *__restrict__ T, co
     const R *tr = reinterpret_cast<const R *>(S.strace) + (int64_t)ch * NPOS * TRS;
     const R gam = (R)P.gamma;
     if (threadIdx.x == 0) badc = 0;
-    // neighbour existence per face of the cell: bit 2k + side
-    int nbex = 0;
+    // neighbour existence per face of the cell: bit 2k + side; a face toward a solid cell
+    // (masked geometry) has no neighbour and is a reflective wall (the same bit of nbwall)
+    int nbex = 0, nbwall = 0;
 #pragma unroll
     for (int k = 0; k < DIM; k++)
 #pragma unroll
         for (int side = 0; side < 2; side++) {
             const int nb = ci[k] + (side ? 1 : -1);
-            if (P.periodic[k] || (nb >= 0 && nb < P.nc[k])) nbex |= 1 << (2 * k + side);
+            if (P.periodic[k] || (nb >= 0 && nb < P.nc[k])) {
+                const int g0 = ci[0] + (k == 0 ? (side ? 1 : -1) : 0);
+                const int g1 = ci[1] + (k == 1 ? (side ? 1 : -1) : 0);
+                const int g2 = ci[2] + (k == 2 ? (side ? 1 : -1) : 0);
+                if (B.mask && solid_at<DIM>(P, B.mask, g0, g1, g2)) nbwall |= 1 << (2 * k + side);
+                else nbex |= 1 << (2 * k + side);
+            }
         }
     // sub-faces of all axes in one range (threads stay busy for small Ns); the body is
     // instantiated per axis (compile-time k: no dynamic indexing of per-thread arrays).
@@ -1166,7 +1225,11 @@ __device__ __forceinline__ void sub_update_cell(const Tables *__restrict__ T, co
                             qL[v] = pass ? (R)avL[v] : trL[v * NF3 * 3 + ap + NF3 * s];
                             qR[v] = pass ? (R)avR[v] : trR[v * NF3 * 3 + ap + NF3 * s];
                         }
-                        if (bside >= 0) {
+                        if (bside >= 0 && ((nbwall >> (2 * k + bside)) & 1)) {
+                            // reflective wall of the masked geometry
+                            if (bside == 0) wall_ghost<DIM, R>(k, qR, qL);
+                            else wall_ghost<DIM, R>(k, qL, qR);
+                        } else if (bside >= 0) {
                             // ghost state of the boundary rule, evaluated in FP64
                             double qi[NV], qo[NV];
                             if (bside == 0) {
@@ -1650,12 +1713,13 @@ __global__ __launch_bounds__(128) void k_fluxcorr(const Tables *__restrict__ T, 
 // ------------------------------------------------------------------ time step
 template <int DIM, int N>
 __device__ __forceinline__ void lambda_block(const Prob &P, const double *__restrict__ u, double *part, int64_t bid,
-                                             int64_t nblk) {
+                                             int64_t nblk, const uint8_t *__restrict__ mask) {
     constexpr int n = N + 1, NV = DIM + 2, NN = cpow(n, DIM);
     __shared__ double red[256];
     double lam = 0.0;
     const int64_t total = P.ncell * NN;
     for (int64_t i = (int64_t)bid * 256 + threadIdx.x; i < total; i += (int64_t)nblk * 256) {
+        if (mask && mask[i / NN]) continue;   // solid cells take no part in the time step
         double q[NV];
 #pragma unroll
         for (int v = 0; v < NV; v++) q[v] = u[(int64_t)v * total + i];
@@ -1672,8 +1736,9 @@ __device__ __forceinline__ void lambda_block(const Prob &P, const double *__rest
     if (threadIdx.x == 0) part[bid] = red[0];
 }
 template <int DIM, int N>
-__global__ __launch_bounds__(256) void k_lambda(Prob P, const double *__restrict__ u, double *part) {
-    lambda_block<DIM, N>(P, u, part, blockIdx.x, gridDim.x);
+__global__ __launch_bounds__(256) void k_lambda(Prob P, const double *__restrict__ u, double *part,
+                                                const uint8_t *__restrict__ mask) {
+    lambda_block<DIM, N>(P, u, part, blockIdx.x, gridDim.x, mask);
 }
 
 __device__ __forceinline__ void dt_final_block(const double *part, int nparts, double *scal, double factor) {
@@ -1711,7 +1776,7 @@ template <int DIM, int N>
 __global__ __launch_bounds__(256) void kb_lambda(const BatchEntry *__restrict__ E, const BTile *__restrict__ tl) {
     const BTile t = tl[blockIdx.x];
     const BatchEntry &e = E[t.p];
-    lambda_block<DIM, N>(e.P, e.B.u[e.cur], e.B.lam_part, t.b, t.n);
+    lambda_block<DIM, N>(e.P, e.B.u[e.cur], e.B.lam_part, t.b, t.n, e.B.mask);
 }
 
 static __global__ __launch_bounds__(256) void kb_dt_final(const BatchEntry *__restrict__ E) {
@@ -1745,7 +1810,7 @@ __global__ __launch_bounds__((FaceShape<DIM, N>::BS)) void kb_face(const BatchEn
     const BTile t = tl[blockIdx.x];
     const BatchEntry &e = E[t.p];
     face_block<DIM, N, R>(e.T, e.P, reinterpret_cast<const R *>(e.B.trace), reinterpret_cast<R *>(e.B.gbar), e.B.scal,
-                          e.kb1, e.kb2, t.b);
+                          e.kb1, e.kb2, t.b, e.B.mask);
 }
 
 // The problem's Prob and Bufs staged in LDS once per workgroup: the corrector's body reads
@@ -1937,7 +2002,7 @@ struct Launch {
         const int64_t kb2 = DIM == 3 ? start[2] : start[DIM];
         hipLaunchKernelGGL((k_face<DIM, N, R>), dim3((unsigned)start[DIM]), dim3(FS::BS), 0, C.stream, C.tab, C.P,
                            reinterpret_cast<const R *>(C.B.trace), reinterpret_cast<R *>(C.B.gbar), C.B.scal,
-                           start[1], kb2);
+                           start[1], kb2, C.B.mask);
     }
     static void faces(const StepCtx &C) {
         if (C.precision == ADG_MIXED) faces_t<float>(C);
@@ -2065,7 +2130,7 @@ struct Launch {
         const int64_t total = C.P.ncell * NN;
         int nb = (int)((total + 255) / 256);
         if (nb > C.lam_blocks) nb = C.lam_blocks;
-        hipLaunchKernelGGL((k_lambda<DIM, N>), dim3(nb), dim3(256), 0, C.stream, C.P, u, C.B.lam_part);
+        hipLaunchKernelGGL((k_lambda<DIM, N>), dim3(nb), dim3(256), 0, C.stream, C.P, u, C.B.lam_part, C.B.mask);
         hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(256), 0, C.stream, C.B.lam_part, nb, C.B.scal, factor);
     }
 };

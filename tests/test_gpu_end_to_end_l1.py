@@ -1,0 +1,167 @@
+"""End-to-end accuracy of both precision forms.
+
+* Against the FP64 oracle (L1 density difference relative to the L1 norm of the oracle's
+  density): the 2D explosion (Sec. 5, 40 x 40 cells, N = 3, initial detection) to t = 0.25 with
+  the oracle's time steps, and the isentropic vortex (N = 9, 16 x 16 cells) to t = 10, the
+  oracle's density stored by tests/golden/make_vortex_oracle_t10.py.  Tolerances: the FP64
+  form differs from the oracle by rounding, amplified where the two take a troubled-cell
+  decision differently at a detection margin below their rounding (the shock of the
+  explosion); the mixed form's FP32 increments (relative rounding 6e-8 of the fluxes,
+  differentiated and summed over the steps) bound its difference.
+* At matched L1 error against an exact solution (the four-quadrant problems of the benchmark
+  batch): away from the central interaction square each quadrant interface is a 1D Riemann
+  problem whose exact solution the oracle's solver gives; the L1 density errors of the two
+  forms against it agree to 1 %: the discretisation error dominates and the mixed form's FP32
+  rounding does not change it.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1406_7416_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "vortex_N9_16x16_t10_oracle_rho.npy")
+
+
+def cell_weights(n, d):
+    w1 = np.polynomial.legendre.leggauss(n)[1] / 2.0
+    w = w1
+    for _ in range(d - 1):
+        w = np.multiply.outer(w1, w).ravel()
+    return w
+
+
+def l1(f, wl):
+    vol = np.prod([(wl.hi[k] - wl.lo[k]) / wl.ncell[k] for k in range(wl.dim)])
+    return float((np.abs(f) @ cell_weights(wl.N + 1, wl.dim)).sum() * vol)
+
+
+def test_explosion_2d_to_t_end_against_oracle():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1406_7416_amd import adg
+    wl = W.explosion_2d(40, 3)
+    o = O.Oracle(wl)
+    u, v = o.project(wl.ic, wl.N + 1)
+    o.set_state(u, v)
+    gs = {}
+    for form, prec in (("fp64", adg.ADG_FP64), ("mixed", adg.ADG_MIXED)):
+        g = adg.Problem(wl, precision=prec)
+        g.set_state(u, v)
+        gs[form] = g
+    steps = 0
+    while o.time < 0.25 * (1 - 1e-14):
+        dt = min(o.cfl_dt(), 0.25 - o.time)
+        o.step(dt)
+        for g in gs.values():
+            g.step(dt)
+        steps += 1
+    ro = o.state()[0]
+    norm = l1(ro, wl)
+    errs = {f: l1(g.state()[0] - ro, wl) / norm for f, g in gs.items()}
+    print(f"explosion 40^2 N=3 to t=0.25 ({steps} steps): relative L1(rho - rho_oracle) fp64 {errs['fp64']:.2e}, "
+          f"mixed {errs['mixed']:.2e}", flush=True)
+    assert errs["fp64"] < 1e-9
+    assert errs["mixed"] < 1e-4
+    for g in gs.values():
+        g.close()
+
+
+@pytest.mark.timeout(600)
+def test_vortex_16x16_to_t10_against_oracle():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1406_7416_amd import adg
+    ro = np.load(GOLDEN)
+    wl = W.vortex(16, 9)
+    norm = l1(ro, wl)
+    out = {}
+    for form, prec in (("fp64", adg.ADG_FP64), ("mixed", adg.ADG_MIXED)):
+        g = adg.Problem(wl, precision=prec)
+        u0, _ = g.project(wl.ic, 0)
+        g.set_state(u0)
+        while g.time < 10.0 * (1 - 1e-14):
+            g.step(min(g.cfl_dt(), 10.0 - g.time))
+        out[form] = l1(g.state()[0] - ro, wl) / norm
+        g.close()
+    print(f"vortex 16^2 N=9 to t=10: relative L1(rho - rho_oracle) fp64 {out['fp64']:.2e}, mixed {out['mixed']:.2e}",
+          flush=True)
+    assert out["fp64"] < 1e-10
+    assert out["mixed"] < 1e-4
+
+
+def quadrant_exact_rho(states, gamma, X, Y, t):
+    """Density of the four 1D Riemann problems at the quadrant interfaces (x = 0 for y > 0 and
+    y < 0; y = 0 for x > 0 and x < 0) at time t, at points outside the central square; NaN
+    inside it.  states: primitive (rho, u, v, p) of quadrants 1..4 (x>0,y>0; x<=0,y>0;
+    x<=0,y<=0; x>0,y<=0)."""
+    q1, q2, q3, q4 = states
+
+    def rp(left, right, normal, xi):
+        L = (left[0], left[1 + normal], left[3])
+        R = (right[0], right[1 + normal], right[3])
+        out, _ = O.exact_riemann(L, R, gamma, xi)
+        return out[:, 0]
+
+    rho = np.full(X.shape, np.nan)
+    # interface y = 0 (normal velocity v), x > 0: q4 below, q1 above; x < 0: q3 below, q2 above
+    for sel, lo_, hi_ in (((X > 0), q4, q1), ((X <= 0), q3, q2)):
+        m = sel & np.isnan(rho)
+        rho[m] = rp(lo_, hi_, 1, Y[m] / t)
+    return rho
+
+
+def test_matched_l1_error_on_quadrant_problems():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1406_7416_amd import adg
+    wls = W.quadrant_batch(256)
+    picked = []
+    for N in (3, 4, 5):
+        picked += [wl for wl in wls if wl.N == N and wl.ncell[0] in (64, 128)][:2]
+    ratios = []
+    for wl in picked:
+        # the quadrant states back from the conserved initial data at the four quadrant centres
+        g = 1.4
+        pts = [(0.25, 0.25), (-0.25, 0.25), (-0.25, -0.25), (0.25, -0.25)]
+        states = []
+        for (x, y) in pts:
+            c = [float(np.asarray(a)) for a in wl.ic([np.array(x), np.array(y)], 0.0)]
+            rho, mu, mv, E = c
+            states.append((rho, mu / rho, mv / rho, (g - 1) * (E - 0.5 * (mu * mu + mv * mv) / rho)))
+        smax = max(abs(s[1]) + abs(s[2]) + math.sqrt(g * s[3] / s[0]) for s in states)
+        t_end = 0.2 * 0.5 / (2.0 * smax)          # waves stay well inside the half-width 0.5
+        h = 1.0 / wl.ncell[0]
+        errs = {}
+        for form, prec in (("fp64", adg.ADG_FP64), ("mixed", adg.ADG_MIXED)):
+            p = adg.Problem(wl, precision=prec)
+            u, _ = p.project(wl.ic, 0)
+            p.set_state(u)
+            while p.time < t_end * (1 - 1e-14):
+                p.step(min(p.cfl_dt(), t_end - p.time))
+            n = wl.N + 1
+            xa = p.axis_points(0, 0).reshape(wl.ncell[0], n)
+            ya = p.axis_points(1, 0).reshape(wl.ncell[1], n)
+            rho = p.state()[0].reshape(wl.ncell[1], wl.ncell[0], n, n)   # [cy][cx][a_y][a_x]
+            X = np.broadcast_to(xa[None, :, None, :], rho.shape)
+            Y = np.broadcast_to(ya[:, None, :, None], rho.shape)
+            # cells entirely outside the central square of half-width 2 smax t + 2h, and away from
+            # the vertical interface x = 0 (only the y = 0 interface problems are compared)
+            cx = (np.arange(wl.ncell[0]) + 0.5) * h - 0.5
+            cy = (np.arange(wl.ncell[1]) + 0.5) * h - 0.5
+            half = 2.0 * smax * t_end + 2.0 * h
+            keep = (np.abs(cx)[None, :] > half) & (np.abs(cy)[:, None] < 0.5 - 2 * h)
+            ex = quadrant_exact_rho(states, g, X[keep], Y[keep], p.time)
+            w = cell_weights(n, 2).reshape(n, n)
+            errs[form] = float((np.abs(rho[keep] - ex) * w).sum() * h * h)
+            p.close()
+        ratios.append(errs["mixed"] / errs["fp64"])
+        print(f"quadrant {wl.name} N={wl.N} {wl.ncell[0]}^2 t={t_end:.4f}: L1 vs exact fp64 {errs['fp64']:.4e}, "
+              f"mixed {errs['mixed']:.4e}, ratio {ratios[-1]:.5f}", flush=True)
+        assert errs["fp64"] > 0
+    assert all(0.99 < r < 1.01 for r in ratios), ratios

@@ -156,9 +156,9 @@ static void plan(adg_problem *pb) {
     const int64_t nblk = (nc + 255) / 256;
     const int64_t hsz = ipow64(Ns + 6, d), n3 = ipow64(3, d), nf3 = ipow64(3, d - 1);
     const int64_t per_chunk_cell = (nv * hsz + pb->npos * nv * n3 + pb->npos * 2 * d * nv * nf3 * 3) * 8;
-    // subcell scratch: one slot per workgroup of the persistent subcell kernel (two per CU
-    // of MI355X, fewer if the pool holds fewer cells)
-    const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(512, pb->cap));
+    // subcell scratch: one slot per workgroup of the persistent subcell kernel (as many as
+    // the 256 CUs of MI355X hold at once, fewer if the pool holds fewer cells)
+    const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(subcell_workgroups(d, P.N), pb->cap));
     (void)per_chunk_cell;
     pb->chunk = (int)chunk;
     pb->lam_blocks = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (nc * nn + 255) / 256));
@@ -1169,11 +1169,12 @@ static void batch_plan(adg_batch *b) {
         for (int t = 0; t < 6; t++) K.off_tiles[t] = take(sizeof(BTile) * K.tiles[t].size());
         K.off_wt = take(4 * (np + 1));
         K.off_wc = take(4 * (np + 1));
-        // subcell scratch: one slot per workgroup of the persistent launch (two per CU)
+        // subcell scratch: one slot per workgroup of the persistent launch (as many as the
+        // chip holds at once)
         const int d = K.dim, nv = d + 2, Ns = 2 * K.N + 1;
         int64_t caps = 0;
         for (int m : K.members) caps += b->ps[m]->cap;
-        K.sub_grid = (int)std::max<int64_t>(1, std::min<int64_t>(512, caps));
+        K.sub_grid = (int)std::max<int64_t>(1, std::min<int64_t>(subcell_workgroups(K.dim, K.N), caps));
         K.fc_grid = 1024;
         const int64_t npos = positions_per_cell(d, K.N), n3 = ipow64(3, d), nf3 = ipow64(3, d - 1);
         const int64_t G = K.sub_grid;
@@ -1229,6 +1230,10 @@ static BatchLaunch batch_launch(const adg_batch *b, const BatchClass &K, int g) 
     char *w = b->ws;
     L.E = (const BatchEntry *)(w + K.off_ents[g]);
     L.np = (int)K.members.size();
+    // every member of a class has the same (d, N) and Ns = 2N+1, so the same tables: the
+    // first member's copy serves the class, passed as a kernel argument (read through
+    // scalar loads, like the per-problem kernels' tables)
+    L.T = b->ps[K.members[0]]->tab_dev;
     const BTile **tp[6] = {&L.t_lambda, &L.t_bounds, &L.t_pred, &L.t_face, &L.t_corr, &L.t_compact};
     int *np_[6] = {&L.n_lambda, &L.n_bounds, &L.n_pred, &L.n_face, &L.n_corr, &L.n_compact};
     for (int t = 0; t < 6; t++) {

@@ -43,6 +43,7 @@ enum {
 
 // One (d, N) class of a batch at one buffer parity (device pointers).
 struct BatchLaunch {
+    const Tables *T;       // the class's operator tables (they depend on (N, Ns) only)
     const BatchEntry *E;
     int np;
     const BTile *t_lambda, *t_bounds, *t_pred, *t_face, *t_corr, *t_compact;
@@ -56,6 +57,8 @@ struct BatchLaunch {
 
 bool supported(int dim, int N);
 int positions_per_cell(int dim, int N);
+// workgroups (= scratch slots) of the persistent subcell launch that fill MI355X's 256 CUs
+int subcell_workgroups(int dim, int N);
 void build_tables(int N, int Ns, Tables *T);
 void gl_nodes(int n, double *x01, double *w01);
 void lagrange_values(int n, const double *xi, double t, double *phi);

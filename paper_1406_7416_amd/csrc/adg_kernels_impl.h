@@ -790,6 +790,14 @@ static __global__ __launch_bounds__(CBS) void k_compact_scatter(Prob P, Bufs B, 
 // ------------------------------------------------------ subcell ADER-WENO3
 constexpr int SUB_BS = 256;   // threads per workgroup of the subcell recompute
 
+// Workgroups of the subcell recompute per CU (= waves per SIMD), the register budget held to
+// it: three for 2D cells up to N = 5 (the batched FP32 kernel at N = 5: 11.3 ms per batch
+// step against 14.0 ms with two; four spill), two for larger cells and in 3D.
+template <int DIM, int N>
+struct SubShape {
+    static constexpr int WPS = (DIM == 2 && N <= 5) ? 3 : 2;
+};
+
 
 // Positions of one troubled cell's subcell scheme: the Ns^d own subcells first, then
 // for each axis k and side the Ns^(d-1) face-adjacent subcells of the neighbour.
@@ -1616,7 +1624,7 @@ __device__ __forceinline__ void subcell_cell(const Tables *__restrict__ T, const
 }
 
 template <int DIM, int N, typename R, bool REDO>
-__global__ __launch_bounds__(SUB_BS, 2) void k_subcell(const Tables *__restrict__ T, Prob P, Bufs B, int cur, int64_t cap,
+__global__ __launch_bounds__(SUB_BS, (SubShape<DIM, N>::WPS)) void k_subcell(const Tables *__restrict__ T, Prob P, Bufs B, int cur, int64_t cap,
                                                  int *nonphys, int flagging) {
     const int count = (int)(B.counts[0] < cap ? B.counts[0] : cap);
     const SubScratch S{B.Y, B.strace, B.halo, B.fpts};
@@ -1785,10 +1793,11 @@ static __global__ __launch_bounds__(256) void kb_dt_final(const BatchEntry *__re
 }
 
 template <int DIM, int N>
-__global__ __launch_bounds__(128) void kb_cell_bounds(const BatchEntry *__restrict__ E, const BTile *__restrict__ tl) {
+__global__ __launch_bounds__(128) void kb_cell_bounds(const Tables *__restrict__ T, const BatchEntry *__restrict__ E,
+                                                      const BTile *__restrict__ tl) {
     const BTile t = tl[blockIdx.x];
     const BatchEntry &e = E[t.p];
-    cell_bounds_block<DIM, N>(e.T, e.P, e.B, e.cur, e.ring, t.b);
+    cell_bounds_block<DIM, N>(T, e.P, e.B, e.cur, e.ring, t.b);
 }
 
 template <typename R> __device__ __forceinline__ const PredArgs<R> &pred_args(const BatchEntry &e);
@@ -1805,11 +1814,12 @@ __global__ __launch_bounds__((PredShape<DIM, N, R>::BS), (sizeof(R) == 4 ? 4 : 2
 }
 
 template <int DIM, int N, typename R>
-__global__ __launch_bounds__((FaceShape<DIM, N>::BS)) void kb_face(const BatchEntry *__restrict__ E,
+__global__ __launch_bounds__((FaceShape<DIM, N>::BS)) void kb_face(const Tables *__restrict__ T,
+                                                                  const BatchEntry *__restrict__ E,
                                                                   const BTile *__restrict__ tl) {
     const BTile t = tl[blockIdx.x];
     const BatchEntry &e = E[t.p];
-    face_block<DIM, N, R>(e.T, e.P, reinterpret_cast<const R *>(e.B.trace), reinterpret_cast<R *>(e.B.gbar), e.B.scal,
+    face_block<DIM, N, R>(T, e.P, reinterpret_cast<const R *>(e.B.trace), reinterpret_cast<R *>(e.B.gbar), e.B.scal,
                           e.kb1, e.kb2, t.b, e.B.mask);
 }
 
@@ -1826,14 +1836,16 @@ __device__ __forceinline__ void stage_entry(const BatchEntry &e, Prob *sP, Bufs 
 }
 
 template <int DIM, int N, typename R>
-__global__ __launch_bounds__((CorrShape<DIM, N>::BS), (CorrShape<DIM, N>::WPS)) void kb_corrector_detect(const BatchEntry *__restrict__ E,
+__global__ __launch_bounds__((CorrShape<DIM, N>::BS), (CorrShape<DIM, N>::WPS)) void kb_corrector_detect(const Tables *__restrict__ T,
+                                                                          const BatchEntry *__restrict__ E,
                                                                           const BTile *__restrict__ tl) {
     __shared__ Prob sP;
     __shared__ Bufs sB;
     const BTile t = tl[blockIdx.x];
     const BatchEntry &e = E[t.p];
+    const int cur = e.cur, limiter = e.limiter;
     stage_entry<CorrShape<DIM, N>::BS>(e, &sP, &sB);
-    corrector_detect_block<DIM, N, R>(e.T, sP, sB, e.cur, e.limiter, t.b);
+    corrector_detect_block<DIM, N, R>(T, sP, sB, cur, limiter, t.b);
 }
 
 static __global__ __launch_bounds__(CBS) void kb_compact_count(const BatchEntry *__restrict__ E, const BTile *__restrict__ tl) {
@@ -1899,24 +1911,24 @@ __device__ __forceinline__ int owner_of(const int *__restrict__ off, int np, int
 // Subcell recompute over one global troubled worklist: the troubled cells of every problem
 // of the class, in problem order, shared out over the persistent grid.
 template <int DIM, int N, typename R, bool REDO>
-__global__ __launch_bounds__(SUB_BS, 2) void kb_subcell(const BatchEntry *__restrict__ E, int np,
-                                                  const int *__restrict__ off, SubScratch S, int flagging) {
+__global__ __launch_bounds__(SUB_BS, (SubShape<DIM, N>::WPS)) void kb_subcell(const Tables *__restrict__ T, const BatchEntry *__restrict__ E,
+                                                        int np, const int *__restrict__ off, SubScratch S, int flagging) {
     const int total = off[np];
     for (int g = blockIdx.x; g < total; g += gridDim.x) {
         const int p = owner_of(off, np, g);
         const BatchEntry &e = E[p];
-        subcell_cell<DIM, N, R, REDO>(e.T, e.P, e.B, e.cur, g - off[p], blockIdx.x, S, e.B.counts + 2, flagging);
+        subcell_cell<DIM, N, R, REDO>(T, e.P, e.B, e.cur, g - off[p], blockIdx.x, S, e.B.counts + 2, flagging);
     }
 }
 
 template <int DIM, int N, typename R>
-__global__ __launch_bounds__(128) void kb_fluxcorr(const BatchEntry *__restrict__ E, int np,
-                                                   const int *__restrict__ off) {
+__global__ __launch_bounds__(128) void kb_fluxcorr(const Tables *__restrict__ T, const BatchEntry *__restrict__ E,
+                                                   int np, const int *__restrict__ off) {
     const int total = off[np];
     for (int g = blockIdx.x; g < total; g += gridDim.x) {
         const int p = owner_of(off, np, g);
         const BatchEntry &e = E[p];
-        fluxcorr_cell<DIM, N, R>(e.T, e.P, e.B, e.cur, g - off[p]);
+        fluxcorr_cell<DIM, N, R>(T, e.P, e.B, e.cur, g - off[p]);
     }
 }
 
@@ -2087,18 +2099,19 @@ struct Launch {
             break;
         case BSTAGE_BOUNDS:
             if (L.n_bounds)
-                hipLaunchKernelGGL((kb_cell_bounds<DIM, N>), dim3(L.n_bounds), dim3(128), 0, st, L.E, L.t_bounds);
+                hipLaunchKernelGGL((kb_cell_bounds<DIM, N>), dim3(L.n_bounds), dim3(128), 0, st, L.T, L.E, L.t_bounds);
             break;
         case BSTAGE_PREDICTOR:
             hipLaunchKernelGGL((kb_predictor<DIM, N, R>), dim3(L.n_pred), dim3(PredShape<DIM, N, R>::BS), 0, st, L.E,
                                L.t_pred);
             break;
         case BSTAGE_FACE:
-            hipLaunchKernelGGL((kb_face<DIM, N, R>), dim3(L.n_face), dim3(FaceShape<DIM, N>::BS), 0, st, L.E, L.t_face);
+            hipLaunchKernelGGL((kb_face<DIM, N, R>), dim3(L.n_face), dim3(FaceShape<DIM, N>::BS), 0, st, L.T, L.E,
+                               L.t_face);
             break;
         case BSTAGE_CORRECTOR:
             hipLaunchKernelGGL((kb_corrector_detect<DIM, N, R>), dim3(L.n_corr), dim3(CorrShape<DIM, N>::BS), 0, st,
-                               L.E, L.t_corr);
+                               L.T, L.E, L.t_corr);
             break;
         case BSTAGE_COMPACT:
             hipLaunchKernelGGL(kb_compact_count, dim3(L.n_compact), dim3(CBS), 0, st, L.E, L.t_compact);
@@ -2106,14 +2119,14 @@ struct Launch {
             hipLaunchKernelGGL(kb_offsets, dim3(1), dim3(1024), 0, st, L.E, L.np, L.off_t, L.off_c);
             break;
         case BSTAGE_SUBCELL:
-            hipLaunchKernelGGL((kb_subcell<DIM, N, R, false>), dim3(L.sub_grid), dim3(SUB_BS), 0, st, L.E, L.np,
+            hipLaunchKernelGGL((kb_subcell<DIM, N, R, false>), dim3(L.sub_grid), dim3(SUB_BS), 0, st, L.T, L.E, L.np,
                                (const int *)L.off_t, L.S, L.mood);
             if (L.mood)
-                hipLaunchKernelGGL((kb_subcell<DIM, N, R, true>), dim3(L.sub_grid), dim3(SUB_BS), 0, st, L.E, L.np,
+                hipLaunchKernelGGL((kb_subcell<DIM, N, R, true>), dim3(L.sub_grid), dim3(SUB_BS), 0, st, L.T, L.E, L.np,
                                    (const int *)L.off_t, L.S, 0);
             break;
         case BSTAGE_FLUXCORR:
-            hipLaunchKernelGGL((kb_fluxcorr<DIM, N, R>), dim3(L.fc_grid), dim3(128), 0, st, L.E, L.np,
+            hipLaunchKernelGGL((kb_fluxcorr<DIM, N, R>), dim3(L.fc_grid), dim3(128), 0, st, L.T, L.E, L.np,
                                (const int *)L.off_c);
             break;
         case BSTAGE_ADVANCE:
@@ -2147,6 +2160,7 @@ struct Ops {
     void (*batched)(int, const BatchLaunch &);
     void (*pred_args)(const StepCtx &, PredArgs<float> *, PredArgs<double> *);
     int npos;
+    int sub_wgs;   // workgroups of the persistent subcell launch that fill the chip
 };
 
 // the (d, N) instantiations, one group per translation unit (null outside the group)
@@ -2160,7 +2174,7 @@ template <int DIM, int N>
 static Ops make_ops() {
     using L = Launch<DIM, N>;
     return Ops{L::predictor, L::faces, L::corrector_detect, L::bounds, L::subcell, L::fluxcorr, L::lambda,
-               L::blocks, L::batched, L::pred_args, L::NPOS};
+               L::blocks, L::batched, L::pred_args, L::NPOS, 256 * SubShape<DIM, N>::WPS};
 }
 
 }  // namespace adg

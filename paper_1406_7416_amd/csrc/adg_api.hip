@@ -158,7 +158,7 @@ static void plan(adg_problem *pb) {
     const int64_t per_chunk_cell = (nv * hsz + pb->npos * nv * n3 + pb->npos * 2 * d * nv * nf3 * 3) * 8;
     // subcell scratch: one slot per workgroup of the persistent subcell kernel (as many as
     // the 256 CUs of MI355X hold at once, fewer if the pool holds fewer cells)
-    const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(subcell_workgroups(d, P.N), pb->cap));
+    const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(subcell_workgroups(d, P.N, pb->prm.precision), pb->cap));
     (void)per_chunk_cell;
     pb->chunk = (int)chunk;
     pb->lam_blocks = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (nc * nn + 255) / 256));
@@ -1174,7 +1174,7 @@ static void batch_plan(adg_batch *b) {
         const int d = K.dim, nv = d + 2, Ns = 2 * K.N + 1;
         int64_t caps = 0;
         for (int m : K.members) caps += b->ps[m]->cap;
-        K.sub_grid = (int)std::max<int64_t>(1, std::min<int64_t>(subcell_workgroups(K.dim, K.N), caps));
+        K.sub_grid = (int)std::max<int64_t>(1, std::min<int64_t>(subcell_workgroups(K.dim, K.N, b->precision), caps));
         K.fc_grid = 1024;
         const int64_t npos = positions_per_cell(d, K.N), n3 = ipow64(3, d), nf3 = ipow64(3, d - 1);
         const int64_t G = K.sub_grid;

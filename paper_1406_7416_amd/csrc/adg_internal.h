@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include "adg.h"
+#include "adg_tune.h"
 
 namespace adg {
 

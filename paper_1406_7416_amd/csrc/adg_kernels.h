@@ -58,7 +58,7 @@ struct BatchLaunch {
 bool supported(int dim, int N);
 int positions_per_cell(int dim, int N);
 // workgroups (= scratch slots) of the persistent subcell launch that fill MI355X's 256 CUs
-int subcell_workgroups(int dim, int N);
+int subcell_workgroups(int dim, int N, int precision);
 void build_tables(int N, int Ns, Tables *T);
 void gl_nodes(int n, double *x01, double *w01);
 void lagrange_values(int n, const double *xi, double t, double *phi);

@@ -305,11 +305,11 @@ __device__ __forceinline__ void tensor_apply(const double *__restrict__ Mbase, c
 // ------------------------------------------- corrector + scatter + detection
 // Threads per cell (one wave while the cell has at most 128 subcells, else two) and cells
 // per workgroup.
-template <int DIM, int N>
+template <int DIM, int N, typename R>
 struct CorrShape {
     static constexpr int NSUB = cpow(2 * N + 1, DIM);
     static constexpr int CW = NSUB <= 128 ? 64 : 128;
-    static constexpr int CPB = (CW == 64) ? 4 : 1;
+    static constexpr int CPB = (CW == 64) ? Tune<DIM, N, sizeof(R) == 4>::corr_cpb : 1;
     static constexpr int BS = CW * CPB;
     static constexpr int NW = CW / 64;   // waves per cell
     // waves per SIMD that the LDS of one workgroup allows (its state, subcell and stage
@@ -326,7 +326,7 @@ struct CorrShape {
 template <int DIM, int N, typename R>
 __device__ __forceinline__ void corrector_detect_block(const Tables *__restrict__ T, const Prob &P, const Bufs &B,
                                                        int cur, int limiter, int64_t bid) {
-    using CS = CorrShape<DIM, N>;
+    using CS = CorrShape<DIM, N, R>;
     constexpr int CW = CS::CW, CPB = CS::CPB, NW = CS::NW;
     const R *gbar = reinterpret_cast<const R *>(B.gbar);
     constexpr int n = N + 1, NV = DIM + 2, NN = cpow(n, DIM), NFN = cpow(n, DIM - 1);
@@ -530,7 +530,7 @@ __device__ __forceinline__ void corrector_detect_block(const Tables *__restrict_
     }
 }
 template <int DIM, int N, typename R>
-__global__ __launch_bounds__((CorrShape<DIM, N>::BS), (CorrShape<DIM, N>::WPS)) void k_corrector_detect(const Tables *__restrict__ T, Prob P,
+__global__ __launch_bounds__((CorrShape<DIM, N, R>::BS), (CorrShape<DIM, N, R>::WPS)) void k_corrector_detect(const Tables *__restrict__ T, Prob P,
                                                                          Bufs B, int cur, int limiter) {
     corrector_detect_block<DIM, N, R>(T, P, B, cur, limiter, blockIdx.x);
 }
@@ -791,11 +791,10 @@ static __global__ __launch_bounds__(CBS) void k_compact_scatter(Prob P, Bufs B, 
 constexpr int SUB_BS = 256;   // threads per workgroup of the subcell recompute
 
 // Workgroups of the subcell recompute per CU (= waves per SIMD), the register budget held to
-// it: three for 2D cells up to N = 5 (the batched FP32 kernel at N = 5: 11.3 ms per batch
-// step against 14.0 ms with two; four spill), two for larger cells and in 3D.
-template <int DIM, int N>
+// it (Tune's sub_wps: by default three for 2D cells up to N = 5, two for larger cells and in 3D).
+template <int DIM, int N, typename R>
 struct SubShape {
-    static constexpr int WPS = (DIM == 2 && N <= 5) ? 3 : 2;
+    static constexpr int WPS = Tune<DIM, N, sizeof(R) == 4>::sub_wps;
 };
 
 
@@ -1624,7 +1623,7 @@ __device__ __forceinline__ void subcell_cell(const Tables *__restrict__ T, const
 }
 
 template <int DIM, int N, typename R, bool REDO>
-__global__ __launch_bounds__(SUB_BS, (SubShape<DIM, N>::WPS)) void k_subcell(const Tables *__restrict__ T, Prob P, Bufs B, int cur, int64_t cap,
+__global__ __launch_bounds__(SUB_BS, (SubShape<DIM, N, R>::WPS)) void k_subcell(const Tables *__restrict__ T, Prob P, Bufs B, int cur, int64_t cap,
                                                  int *nonphys, int flagging) {
     const int count = (int)(B.counts[0] < cap ? B.counts[0] : cap);
     const SubScratch S{B.Y, B.strace, B.halo, B.fpts};
@@ -1805,7 +1804,7 @@ template <> __device__ __forceinline__ const PredArgs<float> &pred_args<float>(c
 template <> __device__ __forceinline__ const PredArgs<double> &pred_args<double>(const BatchEntry &e) { return e.pd; }
 
 template <int DIM, int N, typename R>
-__global__ __launch_bounds__((PredShape<DIM, N, R>::BS), (sizeof(R) == 4 ? 4 : 2)) void kb_predictor(
+__global__ __launch_bounds__((PredShape<DIM, N, R>::BS), (Tune<DIM, N, sizeof(R) == 4>::pred_wps)) void kb_predictor(
     const BatchEntry *__restrict__ E, const BTile *__restrict__ tl) {
     const BTile t = tl[blockIdx.x];
     const BatchEntry &e = E[t.p];
@@ -1836,7 +1835,7 @@ __device__ __forceinline__ void stage_entry(const BatchEntry &e, Prob *sP, Bufs 
 }
 
 template <int DIM, int N, typename R>
-__global__ __launch_bounds__((CorrShape<DIM, N>::BS), (CorrShape<DIM, N>::WPS)) void kb_corrector_detect(const Tables *__restrict__ T,
+__global__ __launch_bounds__((CorrShape<DIM, N, R>::BS), (CorrShape<DIM, N, R>::WPS)) void kb_corrector_detect(const Tables *__restrict__ T,
                                                                           const BatchEntry *__restrict__ E,
                                                                           const BTile *__restrict__ tl) {
     __shared__ Prob sP;
@@ -1844,7 +1843,7 @@ __global__ __launch_bounds__((CorrShape<DIM, N>::BS), (CorrShape<DIM, N>::WPS)) 
     const BTile t = tl[blockIdx.x];
     const BatchEntry &e = E[t.p];
     const int cur = e.cur, limiter = e.limiter;
-    stage_entry<CorrShape<DIM, N>::BS>(e, &sP, &sB);
+    stage_entry<CorrShape<DIM, N, R>::BS>(e, &sP, &sB);
     corrector_detect_block<DIM, N, R>(T, sP, sB, cur, limiter, t.b);
 }
 
@@ -1911,7 +1910,7 @@ __device__ __forceinline__ int owner_of(const int *__restrict__ off, int np, int
 // Subcell recompute over one global troubled worklist: the troubled cells of every problem
 // of the class, in problem order, shared out over the persistent grid.
 template <int DIM, int N, typename R, bool REDO>
-__global__ __launch_bounds__(SUB_BS, (SubShape<DIM, N>::WPS)) void kb_subcell(const Tables *__restrict__ T, const BatchEntry *__restrict__ E,
+__global__ __launch_bounds__(SUB_BS, (SubShape<DIM, N, R>::WPS)) void kb_subcell(const Tables *__restrict__ T, const BatchEntry *__restrict__ E,
                                                         int np, const int *__restrict__ off, SubScratch S, int flagging) {
     const int total = off[np];
     for (int g = blockIdx.x; g < total; g += gridDim.x) {
@@ -2021,13 +2020,14 @@ struct Launch {
         else faces_t<double>(C);
     }
     static void corrector_detect(const StepCtx &C) {
-        using CS = CorrShape<DIM, N>;
-        const unsigned grid = (unsigned)((C.P.ncell + CS::CPB - 1) / CS::CPB);
+        using CF = CorrShape<DIM, N, float>;
+        using CD = CorrShape<DIM, N, double>;
         if (C.precision == ADG_MIXED)
-            hipLaunchKernelGGL((k_corrector_detect<DIM, N, float>), dim3(grid), dim3(CS::BS), 0, C.stream, C.tab, C.P,
-                               C.B, C.cur, C.limiter);
+            hipLaunchKernelGGL((k_corrector_detect<DIM, N, float>), dim3((unsigned)((C.P.ncell + CF::CPB - 1) / CF::CPB)),
+                               dim3(CF::BS), 0, C.stream, C.tab, C.P, C.B, C.cur, C.limiter);
         else
-            hipLaunchKernelGGL((k_corrector_detect<DIM, N, double>), dim3(grid), dim3(CS::BS), 0, C.stream, C.tab, C.P,
+            hipLaunchKernelGGL((k_corrector_detect<DIM, N, double>), dim3((unsigned)((C.P.ncell + CD::CPB - 1) / CD::CPB)),
+                               dim3(CD::BS), 0, C.stream, C.tab, C.P,
                                C.B, C.cur, C.limiter);
     }
     static void bounds(const StepCtx &C) {
@@ -2084,7 +2084,10 @@ struct Launch {
             *kb2 = DIM == 3 ? start[2] : start[DIM];
             return start[DIM];
         }
-        case BSTAGE_CORRECTOR: return (P.ncell + CorrShape<DIM, N>::CPB - 1) / CorrShape<DIM, N>::CPB;
+        case BSTAGE_CORRECTOR: {
+            const int64_t cpb = precision == ADG_MIXED ? CorrShape<DIM, N, float>::CPB : CorrShape<DIM, N, double>::CPB;
+            return (P.ncell + cpb - 1) / cpb;
+        }
         case BSTAGE_COMPACT: return (P.ncell + CBS - 1) / CBS;
         default: return 0;
         }
@@ -2110,7 +2113,7 @@ struct Launch {
                                L.t_face);
             break;
         case BSTAGE_CORRECTOR:
-            hipLaunchKernelGGL((kb_corrector_detect<DIM, N, R>), dim3(L.n_corr), dim3(CorrShape<DIM, N>::BS), 0, st,
+            hipLaunchKernelGGL((kb_corrector_detect<DIM, N, R>), dim3(L.n_corr), dim3(CorrShape<DIM, N, R>::BS), 0, st,
                                L.T, L.E, L.t_corr);
             break;
         case BSTAGE_COMPACT:
@@ -2160,7 +2163,7 @@ struct Ops {
     void (*batched)(int, const BatchLaunch &);
     void (*pred_args)(const StepCtx &, PredArgs<float> *, PredArgs<double> *);
     int npos;
-    int sub_wgs;   // workgroups of the persistent subcell launch that fill the chip
+    int sub_wgs[2];   // workgroups of the persistent subcell launch that fill the chip (FP64, mixed form)
 };
 
 // the (d, N) instantiations, one group per translation unit (null outside the group)
@@ -2174,7 +2177,8 @@ template <int DIM, int N>
 static Ops make_ops() {
     using L = Launch<DIM, N>;
     return Ops{L::predictor, L::faces, L::corrector_detect, L::bounds, L::subcell, L::fluxcorr, L::lambda,
-               L::blocks, L::batched, L::pred_args, L::NPOS, 256 * SubShape<DIM, N>::WPS};
+               L::blocks, L::batched, L::pred_args, L::NPOS,
+               {256 * SubShape<DIM, N, double>::WPS, 256 * SubShape<DIM, N, float>::WPS}};
 }
 
 }  // namespace adg

@@ -15,7 +15,7 @@ namespace adg {
 // and stores them in LDS; "line owner" threads do the length-n spatial contractions
 // (n loads -> n outputs each, in place); the point owner accumulates S over the d axes
 // and applies the time contraction in registers: d + 1 contractions per sweep.
-template <int DIM, int N, typename R = double, int TB = 256>
+template <int DIM, int N, typename R = double, int TB = Tune<DIM, N, sizeof(R) == 4>::pred_tb>
 struct PredShape;
 
 // 1/x: correctly rounded division in FP64; the hardware reciprocal (within 1 ulp) in
@@ -147,7 +147,7 @@ __device__ __forceinline__ void lds_lines(R *X, int k, int nlines_per_var, int l
 }
 
 // Blocks vb = vb0, vb0 + vbs, ... of CPB cells each, out of ncell cells.
-template <int DIM, int N, bool VOL, typename R, int TB = 256>
+template <int DIM, int N, bool VOL, typename R, int TB = Tune<DIM, N, sizeof(R) == 4>::pred_tb>
 __device__ void pred_cells(const PredArgs<R> &A, double gamma_d, int64_t ncell, int64_t vb0, int64_t vbs) {
     using S = PredShape<DIM, N, R, TB>;
     const R gamma = (R)gamma_d;
@@ -385,8 +385,8 @@ __device__ void pred_cells(const PredArgs<R> &A, double gamma_d, int64_t ncell, 
 }
 
 template <int DIM, int N, bool VOL, typename R>
-// FP32: at most 128 registers, four waves per SIMD; FP64: two waves per SIMD
-__global__ __launch_bounds__((PredShape<DIM, N, R>::BS), (sizeof(R) == 4 ? 4 : 2)) void k_predictor(PredArgs<R> A,
+// the register budget held to Tune's waves per SIMD (FP32: four, FP64: two by default)
+__global__ __launch_bounds__((PredShape<DIM, N, R>::BS), (Tune<DIM, N, sizeof(R) == 4>::pred_wps)) void k_predictor(PredArgs<R> A,
                                                                                                    double gamma_d) {
     pred_cells<DIM, N, VOL, R>(A, gamma_d, A.ncell, blockIdx.x, gridDim.x);
 }

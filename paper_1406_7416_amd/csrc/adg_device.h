@@ -139,6 +139,52 @@ __device__ __forceinline__ void coords_of(const Prob &P, int64_t c, int *ci) {
     ci[2] = (int)(c / ((int64_t)P.nc[0] * P.nc[1]));
 }
 
+// ------------------------------------------------------------- wave reductions
+// A 32-bit value moved down by S lanes within each row of 16 lanes (DPP row_shr); a lane
+// whose source lies outside its row keeps its own value (harmless for min, max and or).
+template <int S>
+__device__ __forceinline__ int row_shr(int x) {
+    return __builtin_amdgcn_update_dpp(x, x, 0x110 + S, 0xf, 0xf, false);
+}
+template <int S>
+__device__ __forceinline__ double row_shr(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = row_shr<S>((int)(b & 0xffffffff)), hi = row_shr<S>((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+template <int S>
+__device__ __forceinline__ float row_shr(float x) {
+    return __int_as_float(row_shr<S>(__float_as_int(x)));
+}
+__device__ __forceinline__ double lane_value(double x, int lane) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+__device__ __forceinline__ float lane_value(float x, int lane) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), lane));
+}
+__device__ __forceinline__ int lane_value(int x, int lane) { return __builtin_amdgcn_readlane(x, lane); }
+
+// op over the 64 lanes of a wave (every lane active), the result in every lane: shifts of
+// 1, 2, 4 and 8 lanes leave each row's result in its last lane, then the four row results
+// are combined from scalar registers.  op is associative, commutative and idempotent.
+template <typename T, typename Op>
+__device__ __forceinline__ T wave_reduce(T x, Op op) {
+    x = op(x, row_shr<1>(x));
+    x = op(x, row_shr<2>(x));
+    x = op(x, row_shr<4>(x));
+    x = op(x, row_shr<8>(x));
+    return op(op(lane_value(x, 15), lane_value(x, 31)), op(lane_value(x, 47), lane_value(x, 63)));
+}
+__device__ __forceinline__ double wave_min(double x) {
+    return wave_reduce(x, [](double a, double b) { return fmin(a, b); });
+}
+__device__ __forceinline__ double wave_max(double x) {
+    return wave_reduce(x, [](double a, double b) { return fmax(a, b); });
+}
+
 // ------------------------------------------------------------- masked geometry
 // 1 if the cell at global coordinates g (possibly outside the domain) is solid: outside a
 // periodic axis it wraps, outside another axis it is the interior cell it mirrors.

@@ -181,12 +181,10 @@ __global__ __launch_bounds__((FaceShape<DIM, N>::BS)) void k_face(const Tables *
 template <int NV>
 __device__ __forceinline__ void block_minmax(double *lo, double *hi, int tid, int bs, double *scratch) {
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1)
-#pragma unroll
-        for (int v = 0; v < NV; v++) {
-            lo[v] = fmin(lo[v], __shfl_xor(lo[v], off));
-            hi[v] = fmax(hi[v], __shfl_xor(hi[v], off));
-        }
+    for (int v = 0; v < NV; v++) {
+        lo[v] = wave_min(lo[v]);
+        hi[v] = wave_max(hi[v]);
+    }
     const int w = tid >> 6, lane = tid & 63, nw = bs >> 6;
     if (lane == 0)
 #pragma unroll
@@ -485,15 +483,12 @@ __device__ __forceinline__ void corrector_detect_block(const Tables *__restrict_
         }
         mg = fminf(mg, (float)lmg);
     }
+    bad = wave_reduce(bad, [](int a, int b) { return a | b; });
+    mg = wave_reduce(mg, [](float a, float b) { return fminf(a, b); });
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        bad |= __shfl_xor(bad, off);
-        mg = fminf(mg, __shfl_xor(mg, off));
-#pragma unroll
-        for (int v = 0; v < NV; v++) {
-            lo[v] = fmin(lo[v], __shfl_xor(lo[v], off));
-            hi[v] = fmax(hi[v], __shfl_xor(hi[v], off));
-        }
+    for (int v = 0; v < NV; v++) {
+        lo[v] = wave_min(lo[v]);
+        hi[v] = wave_max(hi[v]);
     }
     const int w = tid >> 6;
     if ((tid & 63) == 0) {

@@ -40,17 +40,20 @@ PEAK_HBM_GBS = 8000.0
 # (launch "stage:N<degree>" -> (bytes per launch, source hash prefix)); copy calibration: a 256 MiB
 # copy reads FETCH_SIZE = 131,084 KiB (factor 2.0) and writes WRITE_SIZE = 262,144 KiB (factor 1.0)
 TRAFFIC = {
-    "subcell:N5": (22312457557, "1db78e76a962899b"),
-    "predictor:N5": (10808884736, "1db78e76a962899b"),
+    "predictor:N5": (10818334208, "ef285853af387acc"),
+    "subcell:N5": (23956235264, "ef285853af387acc"),
+    "corrector_detect:N5": (6559390208, "ef285853af387acc"),
 }
-KERNEL_SOURCES = ("adg_internal.h", "adg_physics.h", "adg_device.h", "adg_predictor.h", "adg_kernels_impl.h")
+# the kernel sources and the tile-parameter table the build compiles them with
+KERNEL_SOURCES = ("csrc/adg_internal.h", "csrc/adg_tune.h", "csrc/adg_physics.h", "csrc/adg_device.h",
+                  "csrc/adg_predictor.h", "csrc/adg_kernels_impl.h", "tuning.json")
 
 
 def kernel_source_hash() -> str:
     import hashlib
     h = hashlib.sha256()
     for name in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_1406_7416_amd", "csrc", name), "rb") as f:
+        with open(os.path.join(ROOT, "paper_1406_7416_amd", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 

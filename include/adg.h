@@ -48,7 +48,17 @@ enum {
 };
 
 enum { ADG_PERIODIC = 0, ADG_TRANSMISSIVE = 1, ADG_REFLECTIVE = 2, ADG_DIRICHLET = 3 };
-enum { ADG_FP64 = 0, ADG_MIXED = 1 };
+/* Precision forms.  ADG_FP64: every operation in FP64.  ADG_MIXED: the predictor, its volume
+ * term and traces, the face fluxes and face increments, and the subcell scheme's
+ * reconstruction, predictor and sub-face fluxes in FP32; the state, the update additions,
+ * projection/reconstruction, detection, time step and the subcell halo and update in FP64.
+ * ADG_MIXED_DEV: as ADG_MIXED, with the predictor, traces and face fluxes carried as
+ * deviations from each cell's reference state (its first nodal value of u^n rounded to FP32)
+ * and the fluxes evaluated as F(c + dq) - F(c) in a form whose terms all have the size of dq,
+ * so that FP32 rounding is relative to the deviation rather than to the state (for smooth
+ * flows, where the mixed form's error would otherwise not fall with the mesh size);
+ * Rusanov flux only. */
+enum { ADG_FP64 = 0, ADG_MIXED = 1, ADG_MIXED_DEV = 2 };
 
 /* One side of one axis.  Where the coordinate along split_axis is below
  * split0 + split_speed * t, (kind[0], state[0]) applies, else (kind[1], state[1]);
@@ -79,7 +89,7 @@ typedef struct {
                              specialised at compile time on Ns = 2N+1, so any other value gives
                              ADG_EINVAL */
     int picard_iters;     /* 0 -> N+1 sweeps of the predictor (reading: fixed count) */
-    int precision;        /* ADG_FP64 or ADG_MIXED */
+    int precision;        /* ADG_FP64, ADG_MIXED or ADG_MIXED_DEV */
     int limiter;          /* 1: subcell limiter on (default), 0: unlimited ADER-DG */
     double eps;           /* eq. (relax) epsilon; 0 -> 1e-3 */
     double delta0;        /* absolute floor of delta; 0 -> 1e-4 (reading: not in the paper) */

@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libadg.so")
 
 ADG_PERIODIC, ADG_TRANSMISSIVE, ADG_REFLECTIVE, ADG_DIRICHLET = 0, 1, 2, 3
-ADG_FP64, ADG_MIXED = 0, 1
+ADG_FP64, ADG_MIXED, ADG_MIXED_DEV = 0, 1, 2
 
 EXPORTS = [
     "adg_last_error", "adg_create", "adg_destroy", "adg_workspace_bytes", "adg_bind", "adg_axis_points",

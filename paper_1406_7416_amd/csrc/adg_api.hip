@@ -324,7 +324,10 @@ int adg_create(const adg_grid_desc *g, int N, double gamma, const adg_params *p,
     if (prm.picard_iters <= 0) prm.picard_iters = N + 1;
     if (prm.eps == 0) prm.eps = 1e-3;
     if (prm.delta0 == 0) prm.delta0 = 1e-4;
-    if (prm.precision != ADG_FP64 && prm.precision != ADG_MIXED) return fail(ADG_EINVAL, "unknown precision mode");
+    if (prm.precision != ADG_FP64 && prm.precision != ADG_MIXED && prm.precision != ADG_MIXED_DEV)
+        return fail(ADG_EINVAL, "unknown precision mode");
+    if (prm.precision == ADG_MIXED_DEV && prm.flux != 0)
+        return fail(ADG_EINVAL, "the deviation form is built for the Rusanov flux only");
     if (prm.mood != 0 && prm.mood != 1) return fail(ADG_EINVAL, "mood must be 0 or 1");
     if (prm.flux != 0 && prm.flux != 1) return fail(ADG_EINVAL, "flux must be 0 (Rusanov) or 1 (Osher-type)");
     adg_problem *pb = new (std::nothrow) adg_problem();

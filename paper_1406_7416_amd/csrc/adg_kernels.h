@@ -14,7 +14,7 @@ struct StepCtx {
     int picard_iters;
     int64_t capacity;      // pool slots
     int lam_blocks;        // blocks of the lambda reduction
-    int precision;         // ADG_FP64 or ADG_MIXED
+    int precision;         // ADG_FP64, ADG_MIXED or ADG_MIXED_DEV
     int ring_only;         // bounds pass over the ghost ring only
     int64_t nring;         // ghost-ring cells
     int subcell_grid;      // workgroups (= scratch slots) of the subcell recompute

@@ -16,7 +16,7 @@ static const Ops *ops_for(int dim, int N) {
 bool supported(int dim, int N) { return ops_for(dim, N) != nullptr; }
 int positions_per_cell(int dim, int N) { return ops_for(dim, N)->npos; }
 int subcell_workgroups(int dim, int N, int precision) {
-    return ops_for(dim, N)->sub_wgs[precision == ADG_MIXED ? 1 : 0];
+    return ops_for(dim, N)->sub_wgs[precision != ADG_FP64 ? 1 : 0];
 }
 
 void launch_bounds(const StepCtx &C) { ops_for(C.P.dim, C.P.N)->bounds(C); }

@@ -32,12 +32,91 @@ struct FaceShape {
     static constexpr int BS = ((FPB * PER + 63) / 64) * 64;
 };
 
+// The Rusanov flux of the deviation form at one face node and time node.  dL / dR: the
+// traces' deviations from the reference states cL / cR of the two cells (first nodal values
+// of u^n in FP32); G receives G - F(c) of the left cell (of the inside cell at a boundary or
+// wall) and dFc the difference F(c_R) - F(c_L) (zero at a boundary or wall).
+template <int DIM, int N, typename R, int K>
+__device__ __forceinline__ void face_flux_dev(const Prob &P, const Tables *__restrict__ T, const double *__restrict__ u,
+                                              int64_t cL, int64_t cR, bool hasL, bool hasR, bool wall, const R *dL,
+                                              const R *dR, const double *x, double ts, R *G, R *dFc) {
+    constexpr int NV = DIM + 2, NN = cpow(N + 1, DIM);
+    constexpr int k = K;
+    const R g = (R)P.gamma;
+    auto ref = [&](int64_t cc) {
+        double c64[NV];
+#pragma unroll
+        for (int v = 0; v < NV; v++) c64[v] = u[((int64_t)v * P.ncell + cc) * NN];
+        return make_devref<DIM, R>(c64, P.gamma);
+    };
+    auto speed = [&](const DevRef<DIM, R> &c, const R *d) {
+        R q[NV];
+#pragma unroll
+        for (int v = 0; v < NV; v++) q[v] = c.q[v] + d[v];
+        return fabs(along<DIM, R>(q, k) / q[0]) + sqrt(g * pressure<DIM, R>(q, g) / q[0]);
+    };
+    auto dflux = [&](const DevRef<DIM, R> &c, const R *d, R *F) {
+        const R ir = R(1) / (c.q[0] + d[0]);
+        dev_flux<DIM, R>(k, c, d, ir, dev_pressure<DIM, R>(c, d, ir, g), F);
+    };
+    R FL[NV], FR[NV];
+    if (hasL && hasR) {
+        const DevRef<DIM, R> rl = ref(cL), rr = ref(cR);
+        double ql[NV], qr[NV], fl[NV], fr[NV];
+#pragma unroll
+        for (int v = 0; v < NV; v++) {
+            ql[v] = (double)rl.q[v];
+            qr[v] = (double)rr.q[v];
+        }
+        euler_flux<DIM, double>(k, ql, fl, P.gamma);
+        euler_flux<DIM, double>(k, qr, fr, P.gamma);
+        dflux(rl, dL, FL);
+        dflux(rr, dR, FR);
+        const R s = fmax(speed(rl, dL), speed(rr, dR));
+#pragma unroll
+        for (int v = 0; v < NV; v++) {
+            dFc[v] = (R)(fr[v] - fl[v]);
+            const R dq = (R)(qr[v] - ql[v]) + (dR[v] - dL[v]);
+            G[v] = R(0.5) * (FL[v] + FR[v] + dFc[v]) - R(0.5) * s * dq;
+        }
+        return;
+    }
+    // one side is a cell, the other the ghost of the boundary rule or the mirror of a wall,
+    // both taken relative to the cell's reference state (the ghost formed in FP64)
+    const bool inL = hasL;
+    const DevRef<DIM, R> rc = ref(inL ? cL : cR);
+    const R *din = inL ? dL : dR;
+    double qi[NV], qo[NV];
+#pragma unroll
+    for (int v = 0; v < NV; v++) qi[v] = (double)rc.q[v] + (double)din[v];
+    if (wall) {
+        wall_ghost<DIM, double>(k, qi, qo);
+    } else {
+        bc_ghost<DIM>(P, k, inL ? 1 : 0, qi, x[0], x[1], x[2], ts, qo);
+    }
+    R dg[NV];
+#pragma unroll
+    for (int v = 0; v < NV; v++) dg[v] = (R)(qo[v] - (double)rc.q[v]);
+    dflux(rc, din, FL);
+    dflux(rc, dg, FR);
+    const R s = fmax(speed(rc, din), speed(rc, dg));
+    // G(q_in, q_ghost) with the inside cell on the left, or G(q_ghost, q_in) with it on the right
+#pragma unroll
+    for (int v = 0; v < NV; v++) {
+        dFc[v] = 0;
+        G[v] = R(0.5) * (FL[v] + FR[v]) - R(0.5) * s * (inL ? dg[v] - din[v] : din[v] - dg[v]);
+    }
+}
+
 // The faces normal to axis K handled by one workgroup (block blk of that axis); K is a
 // compile-time constant so that no per-thread array is indexed dynamically.
-template <int DIM, int N, typename R, int K>
+// DEV: the traces are deviations from each cell's reference state c (its first nodal value of
+// u^n, rounded to FP32); each cell's slot receives G - F(c) of that cell, the Rusanov flux
+// assembled from the deviation fluxes and the FP64 difference of the two references' fluxes.
+template <int DIM, int N, typename R, int K, bool DEV = false>
 __device__ __forceinline__ void face_axis(const Tables *__restrict__ T, const Prob &P, const R *__restrict__ trace,
                                           R *__restrict__ gbar, const double *__restrict__ scal, int64_t blk, R *part,
-                                          const uint8_t *__restrict__ mask) {
+                                          const uint8_t *__restrict__ mask, const double *__restrict__ u) {
     using FS = FaceShape<DIM, N>;
     constexpr int n = N + 1, NV = DIM + 2, NFN = FS::NFN, PER = FS::PER, FPB = FS::FPB;
     constexpr int k = K;
@@ -109,7 +188,10 @@ __device__ __forceinline__ void face_axis(const Tables *__restrict__ T, const Pr
 #pragma unroll
             for (int v = 0; v < NV; v++) qR[v] = trace[((cR * 2 * DIM + 2 * k) * NV + v) * (NFN * n) + ap + NFN * s];
         }
-        if (wall) {
+        if constexpr (DEV) {
+            face_flux_dev<DIM, N, R, K>(P, T, u, cL, cR, hasL, hasR, wall, qL, qR, x, scal[1] + T->xi[s] * scal[0], G,
+                                        part + ((lf * PER + j) * 2 + 1) * NV);
+        } else if (wall) {
             if (hasL) wall_ghost<DIM, R>(k, qL, qR);
             else wall_ghost<DIM, R>(k, qR, qL);
         } else if (!hasL || !hasR) {
@@ -129,51 +211,65 @@ __device__ __forceinline__ void face_axis(const Tables *__restrict__ T, const Pr
                 for (int v = 0; v < NV; v++) qL[v] = (R)qo[v];
             }
         }
-        num_flux<DIM, R>(P, T, k, qL, qR, G);
+        if constexpr (!DEV) num_flux<DIM, R>(P, T, k, qL, qR, G);
         const R ws = std::is_same<R, double>::value ? (R)T->w[s] : (R)T->fw[s];
+        constexpr int PS = DEV ? 2 : 1;   // DEV: [0] the left cell's G - F(c_L), [1] F(c_R) - F(c_L)
 #pragma unroll
-        for (int v = 0; v < NV; v++) part[(lf * PER + j) * NV + v] = ws * G[v];
+        for (int v = 0; v < NV; v++) part[(lf * PER + j) * PS * NV + v] = ws * G[v];
     }
     __syncthreads();
     if (active && s == 0) {
+        constexpr int PS = DEV ? 2 : 1;
         R acc[NV];
 #pragma unroll
         for (int v = 0; v < NV; v++) acc[v] = 0;
         for (int ss = 0; ss < n; ss++)
 #pragma unroll
-            for (int v = 0; v < NV; v++) acc[v] += part[(lf * PER + ap + NFN * ss) * NV + v];
+            for (int v = 0; v < NV; v++) acc[v] += part[(lf * PER + ap + NFN * ss) * PS * NV + v];
         if (hasL) {
 #pragma unroll
             for (int v = 0; v < NV; v++) gbar[((cL * 2 * DIM + 2 * k + 1) * NV + v) * NFN + ap] = acc[v];
         }
         if (hasR) {
+            if constexpr (DEV) {
+                // the right cell's slot: G - F(c_R) = (G - F(c_L)) - (F(c_R) - F(c_L)) times the
+                // time weights' sum (zero unless both sides are cells)
+                if (hasL) {
+                    R wsum = 0;
+                    for (int ss = 0; ss < n; ss++) wsum += (R)T->fw[ss];
+#pragma unroll
+                    for (int v = 0; v < NV; v++) acc[v] -= wsum * part[(lf * PER + ap) * PS * NV + NV + v];
+                }
+            }
 #pragma unroll
             for (int v = 0; v < NV; v++) gbar[((cR * 2 * DIM + 2 * k) * NV + v) * NFN + ap] = acc[v];
         }
     }
 }
 
-template <int DIM, int N, typename R>
+template <int DIM, int N, typename R, bool DEV = false>
 __device__ __forceinline__ void face_block(const Tables *__restrict__ T, const Prob &P, const R *__restrict__ trace,
                                            R *__restrict__ gbar, const double *__restrict__ scal, int64_t kb1,
-                                           int64_t kb2, int64_t bid, const uint8_t *__restrict__ mask) {
+                                           int64_t kb2, int64_t bid, const uint8_t *__restrict__ mask,
+                                           const double *__restrict__ u) {
     // one launch for the faces of every axis: blocks [0, kb1) axis 0, [kb1, kb2) axis 1, then axis 2
     using FS = FaceShape<DIM, N>;
-    __shared__ R part[FS::FPB * FS::PER * (DIM + 2)];
+    __shared__ R part[FS::FPB * FS::PER * (DIM + 2) * (DEV ? 2 : 1)];
     const int k = (bid < kb1) ? 0 : ((bid < kb2) ? 1 : 2);
     const int64_t blk = (int64_t)bid - (k == 0 ? 0 : (k == 1 ? kb1 : kb2));
     switch (k) {
-    case 0: face_axis<DIM, N, R, 0>(T, P, trace, gbar, scal, blk, part, mask); break;
-    case 1: face_axis<DIM, N, R, 1>(T, P, trace, gbar, scal, blk, part, mask); break;
-    default: face_axis<DIM, N, R, DIM - 1>(T, P, trace, gbar, scal, blk, part, mask); break;
+    case 0: face_axis<DIM, N, R, 0, DEV>(T, P, trace, gbar, scal, blk, part, mask, u); break;
+    case 1: face_axis<DIM, N, R, 1, DEV>(T, P, trace, gbar, scal, blk, part, mask, u); break;
+    default: face_axis<DIM, N, R, DIM - 1, DEV>(T, P, trace, gbar, scal, blk, part, mask, u); break;
     }
 }
-template <int DIM, int N, typename R>
+template <int DIM, int N, typename R, bool DEV = false>
 __global__ __launch_bounds__((FaceShape<DIM, N>::BS)) void k_face(const Tables *__restrict__ T, Prob P,
                                                                  const R *__restrict__ trace, R *__restrict__ gbar,
                                                                  const double *__restrict__ scal, int64_t kb1,
-                                                                 int64_t kb2, const uint8_t *__restrict__ mask) {
-    face_block<DIM, N, R>(T, P, trace, gbar, scal, kb1, kb2, blockIdx.x, mask);
+                                                                 int64_t kb2, const uint8_t *__restrict__ mask,
+                                                                 const double *__restrict__ u) {
+    face_block<DIM, N, R, DEV>(T, P, trace, gbar, scal, kb1, kb2, blockIdx.x, mask, u);
 }
 
 // Block-wide reduction of per-thread (min, max) pairs of NV variables: wave shuffles,
@@ -1630,7 +1726,9 @@ __global__ __launch_bounds__(SUB_BS, (SubShape<DIM, N, R>::WPS)) void k_subcell(
 // flux of each face shared with a troubled cell is replaced by the subcell fluxes of
 // that face integrated against the basis (the troubled cell's kernel stores those
 // integrals per tangential node).
-template <int DIM, int N, typename R>
+// DEV: the cell's DG face fluxes are held as G - F(c) (the deviation form); the full flux that
+// the subcell flux replaces is that plus F(c) times the time weights' sum, formed in FP64.
+template <int DIM, int N, typename R, bool DEV = false>
 __device__ __forceinline__ void fluxcorr_cell(const Tables *__restrict__ T, const Prob &P, const Bufs &B, int cur,
                                               int wb) {
     const R *gbar = reinterpret_cast<const R *>(B.gbar);
@@ -1665,6 +1763,24 @@ __device__ __forceinline__ void fluxcorr_cell(const Tables *__restrict__ T, cons
                 nslot[k][side] = B.slot[1][cn];
             }
         }
+    // DEV: F_k(c) of the cell's reference state for every axis, and the time weights' sum
+    __shared__ double fcs[DEV ? 3 * NV : 1];
+    double wsum = 0.0;
+    if constexpr (DEV) {
+        for (int ss = 0; ss < n; ss++) wsum += (double)T->fw[ss];
+        if (threadIdx.x < DIM) {
+            double c64[NV], cq[NV], F[NV];
+#pragma unroll
+            for (int v = 0; v < NV; v++) c64[v] = B.u[cur][((int64_t)v * P.ncell + c) * NN];
+            const DevRef<DIM, float> r = make_devref<DIM, float>(c64, P.gamma);
+#pragma unroll
+            for (int v = 0; v < NV; v++) cq[v] = (double)r.q[v];
+            euler_flux<DIM, double>((int)threadIdx.x, cq, F, P.gamma);
+#pragma unroll
+            for (int v = 0; v < NV; v++) fcs[threadIdx.x * NV + v] = F[v];
+        }
+        __syncthreads();
+    }
     for (int it = threadIdx.x; it < NV * NN; it += 128) {
         const int v = it / NN, a = it % NN;
         int m[3] = {a % n, (a / n) % n, a / (n * n)};
@@ -1684,7 +1800,8 @@ __device__ __forceinline__ void fluxcorr_cell(const Tables *__restrict__ T, cons
                 if (nbc[k][side] < 0) continue;
                 const int slot = nslot[k][side];
                 const double Fsub = B.sflux[(((int64_t)slot * 2 * DIM + 2 * k + (1 - side)) * NV + v) * NFN + ap];
-                const double Gdg = (double)gbar[((c * 2 * DIM + 2 * k + side) * NV + v) * NFN + ap];
+                double Gdg = (double)gbar[((c * 2 * DIM + 2 * k + side) * NV + v) * NFN + ap];
+                if constexpr (DEV) Gdg += wsum * fcs[k * NV + v];
                 val += side ? ck * T->R[ak] * (Gdg - Fsub) : ck * T->L[ak] * (Fsub - Gdg);
             }
         }
@@ -1699,7 +1816,7 @@ __device__ __forceinline__ void fluxcorr_cell(const Tables *__restrict__ T, cons
     }
 }
 
-template <int DIM, int N, typename R>
+template <int DIM, int N, typename R, bool DEV = false>
 __global__ __launch_bounds__(128) void k_fluxcorr(const Tables *__restrict__ T, Prob P, Bufs B, int cur, int count,
                                                   int advance) {
     // the step's last kernel also advances t (no other workgroup reads t here) and ends a
@@ -1709,7 +1826,7 @@ __global__ __launch_bounds__(128) void k_fluxcorr(const Tables *__restrict__ T, 
         B.scal[4] = 0.0;
     }
     if (count < 0) count = B.counts[1];   // device-driven
-    for (int wb = blockIdx.x; wb < count; wb += gridDim.x) fluxcorr_cell<DIM, N, R>(T, P, B, cur, wb);
+    for (int wb = blockIdx.x; wb < count; wb += gridDim.x) fluxcorr_cell<DIM, N, R, DEV>(T, P, B, cur, wb);
 }
 
 // ------------------------------------------------------------------ time step
@@ -1798,23 +1915,23 @@ template <typename R> __device__ __forceinline__ const PredArgs<R> &pred_args(co
 template <> __device__ __forceinline__ const PredArgs<float> &pred_args<float>(const BatchEntry &e) { return e.pf; }
 template <> __device__ __forceinline__ const PredArgs<double> &pred_args<double>(const BatchEntry &e) { return e.pd; }
 
-template <int DIM, int N, typename R>
+template <int DIM, int N, typename R, bool DEV = false>
 __global__ __launch_bounds__((PredShape<DIM, N, R>::BS), (Tune<DIM, N, sizeof(R) == 4>::pred_wps)) void kb_predictor(
     const BatchEntry *__restrict__ E, const BTile *__restrict__ tl) {
     const BTile t = tl[blockIdx.x];
     const BatchEntry &e = E[t.p];
     const PredArgs<R> &A = pred_args<R>(e);
-    pred_cells<DIM, N, true, R>(A, e.P.gamma, A.ncell, t.b, A.ncell);
+    pred_cells<DIM, N, true, R, DEV>(A, e.P.gamma, A.ncell, t.b, A.ncell);
 }
 
-template <int DIM, int N, typename R>
+template <int DIM, int N, typename R, bool DEV = false>
 __global__ __launch_bounds__((FaceShape<DIM, N>::BS)) void kb_face(const Tables *__restrict__ T,
                                                                   const BatchEntry *__restrict__ E,
                                                                   const BTile *__restrict__ tl) {
     const BTile t = tl[blockIdx.x];
     const BatchEntry &e = E[t.p];
-    face_block<DIM, N, R>(T, e.P, reinterpret_cast<const R *>(e.B.trace), reinterpret_cast<R *>(e.B.gbar), e.B.scal,
-                          e.kb1, e.kb2, t.b, e.B.mask);
+    face_block<DIM, N, R, DEV>(T, e.P, reinterpret_cast<const R *>(e.B.trace), reinterpret_cast<R *>(e.B.gbar),
+                               e.B.scal, e.kb1, e.kb2, t.b, e.B.mask, e.B.u[e.cur]);
 }
 
 // The problem's Prob and Bufs staged in LDS once per workgroup: the corrector's body reads
@@ -1915,14 +2032,14 @@ __global__ __launch_bounds__(SUB_BS, (SubShape<DIM, N, R>::WPS)) void kb_subcell
     }
 }
 
-template <int DIM, int N, typename R>
+template <int DIM, int N, typename R, bool DEV = false>
 __global__ __launch_bounds__(128) void kb_fluxcorr(const Tables *__restrict__ T, const BatchEntry *__restrict__ E,
                                                    int np, const int *__restrict__ off) {
     const int total = off[np];
     for (int g = blockIdx.x; g < total; g += gridDim.x) {
         const int p = owner_of(off, np, g);
         const BatchEntry &e = E[p];
-        fluxcorr_cell<DIM, N, R>(T, e.P, e.B, e.cur, g - off[p]);
+        fluxcorr_cell<DIM, N, R, DEV>(T, e.P, e.B, e.cur, g - off[p]);
     }
 }
 
@@ -1941,13 +2058,13 @@ struct Launch {
     static constexpr int n = N + 1, NV = DIM + 2, NN = cpow(n, DIM), NS = 2 * N + 1;
     static constexpr int NPOS = cpow(NS, DIM) + 2 * DIM * cpow(NS, DIM - 1);
 
-    template <typename R>
+    template <typename R, bool DEV = false>
     static void predictor_t(const StepCtx &C) {
         using S = PredShape<DIM, N, R>;
         PredArgs<R> A;
         fill_pred_args<R>(C, A);
         const int64_t grid = (C.P.ncell + S::CPB - 1) / S::CPB;
-        hipLaunchKernelGGL((k_predictor<DIM, N, true, R>), dim3((unsigned)grid), dim3(S::BS), 0, C.stream, A,
+        hipLaunchKernelGGL((k_predictor<DIM, N, true, R, DEV>), dim3((unsigned)grid), dim3(S::BS), 0, C.stream, A,
                            C.P.gamma);
     }
     template <typename R>
@@ -1990,10 +2107,11 @@ struct Launch {
         fill_pred_args<double>(C, *pd);
     }
     static void predictor(const StepCtx &C) {
-        if (C.precision == ADG_MIXED) predictor_t<float>(C);
+        if (C.precision == ADG_MIXED_DEV) predictor_t<float, true>(C);
+        else if (C.precision == ADG_MIXED) predictor_t<float>(C);
         else predictor_t<double>(C);
     }
-    template <typename R>
+    template <typename R, bool DEV = false>
     static void faces_t(const StepCtx &C) {
         using FS = FaceShape<DIM, N>;
         int64_t start[4] = {0, 0, 0, 0};   // first block of each axis
@@ -2006,18 +2124,19 @@ struct Launch {
             start[k + 1] = start[k] + (nfaces + FS::FPB - 1) / FS::FPB;
         }
         const int64_t kb2 = DIM == 3 ? start[2] : start[DIM];
-        hipLaunchKernelGGL((k_face<DIM, N, R>), dim3((unsigned)start[DIM]), dim3(FS::BS), 0, C.stream, C.tab, C.P,
+        hipLaunchKernelGGL((k_face<DIM, N, R, DEV>), dim3((unsigned)start[DIM]), dim3(FS::BS), 0, C.stream, C.tab, C.P,
                            reinterpret_cast<const R *>(C.B.trace), reinterpret_cast<R *>(C.B.gbar), C.B.scal,
-                           start[1], kb2, C.B.mask);
+                           start[1], kb2, C.B.mask, (const double *)C.B.u[C.cur]);
     }
     static void faces(const StepCtx &C) {
-        if (C.precision == ADG_MIXED) faces_t<float>(C);
+        if (C.precision == ADG_MIXED_DEV) faces_t<float, true>(C);
+        else if (C.precision == ADG_MIXED) faces_t<float>(C);
         else faces_t<double>(C);
     }
     static void corrector_detect(const StepCtx &C) {
         using CF = CorrShape<DIM, N, float>;
         using CD = CorrShape<DIM, N, double>;
-        if (C.precision == ADG_MIXED)
+        if (C.precision != ADG_FP64)
             hipLaunchKernelGGL((k_corrector_detect<DIM, N, float>), dim3((unsigned)((C.P.ncell + CF::CPB - 1) / CF::CPB)),
                                dim3(CF::BS), 0, C.stream, C.tab, C.P, C.B, C.cur, C.limiter);
         else
@@ -2046,12 +2165,15 @@ struct Launch {
     // redo = 0: the subcell scheme (flagging its result when the MOOD layer is on); 1: the
     // MOOD layer's recompute
     static void subcell(const StepCtx &C, int redo) {
-        if (C.precision == ADG_MIXED) subcell_t<float>(C, redo);
+        if (C.precision != ADG_FP64) subcell_t<float>(C, redo);
         else subcell_t<double>(C, redo);
     }
     static void fluxcorr(const StepCtx &C, int count, int advance) {
         const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(count >= 0 ? count : C.P.ncell, 512));
-        if (C.precision == ADG_MIXED)
+        if (C.precision == ADG_MIXED_DEV)
+            hipLaunchKernelGGL((k_fluxcorr<DIM, N, float, true>), dim3(g), dim3(128), 0, C.stream, C.tab, C.P, C.B,
+                               C.cur, count, advance);
+        else if (C.precision == ADG_MIXED)
             hipLaunchKernelGGL((k_fluxcorr<DIM, N, float>), dim3(g), dim3(128), 0, C.stream, C.tab, C.P, C.B, C.cur,
                                count, advance);
         else
@@ -2062,7 +2184,7 @@ struct Launch {
     static int64_t blocks(int stage, const Prob &P, int precision, int64_t *kb1, int64_t *kb2) {
         switch (stage) {
         case BSTAGE_PREDICTOR: {
-            const int64_t cpb = precision == ADG_MIXED ? PredShape<DIM, N, float>::CPB : PredShape<DIM, N, double>::CPB;
+            const int64_t cpb = precision != ADG_FP64 ? PredShape<DIM, N, float>::CPB : PredShape<DIM, N, double>::CPB;
             return (P.ncell + cpb - 1) / cpb;
         }
         case BSTAGE_FACE: {
@@ -2080,14 +2202,14 @@ struct Launch {
             return start[DIM];
         }
         case BSTAGE_CORRECTOR: {
-            const int64_t cpb = precision == ADG_MIXED ? CorrShape<DIM, N, float>::CPB : CorrShape<DIM, N, double>::CPB;
+            const int64_t cpb = precision != ADG_FP64 ? CorrShape<DIM, N, float>::CPB : CorrShape<DIM, N, double>::CPB;
             return (P.ncell + cpb - 1) / cpb;
         }
         case BSTAGE_COMPACT: return (P.ncell + CBS - 1) / CBS;
         default: return 0;
         }
     }
-    template <typename R>
+    template <typename R, bool DEV = false>
     static void batched_t(int stage, const BatchLaunch &L) {
         const hipStream_t st = L.stream;
         switch (stage) {
@@ -2100,11 +2222,11 @@ struct Launch {
                 hipLaunchKernelGGL((kb_cell_bounds<DIM, N>), dim3(L.n_bounds), dim3(128), 0, st, L.T, L.E, L.t_bounds);
             break;
         case BSTAGE_PREDICTOR:
-            hipLaunchKernelGGL((kb_predictor<DIM, N, R>), dim3(L.n_pred), dim3(PredShape<DIM, N, R>::BS), 0, st, L.E,
+            hipLaunchKernelGGL((kb_predictor<DIM, N, R, DEV>), dim3(L.n_pred), dim3(PredShape<DIM, N, R>::BS), 0, st, L.E,
                                L.t_pred);
             break;
         case BSTAGE_FACE:
-            hipLaunchKernelGGL((kb_face<DIM, N, R>), dim3(L.n_face), dim3(FaceShape<DIM, N>::BS), 0, st, L.T, L.E,
+            hipLaunchKernelGGL((kb_face<DIM, N, R, DEV>), dim3(L.n_face), dim3(FaceShape<DIM, N>::BS), 0, st, L.T, L.E,
                                L.t_face);
             break;
         case BSTAGE_CORRECTOR:
@@ -2124,7 +2246,7 @@ struct Launch {
                                    (const int *)L.off_t, L.S, 0);
             break;
         case BSTAGE_FLUXCORR:
-            hipLaunchKernelGGL((kb_fluxcorr<DIM, N, R>), dim3(L.fc_grid), dim3(128), 0, st, L.T, L.E, L.np,
+            hipLaunchKernelGGL((kb_fluxcorr<DIM, N, R, DEV>), dim3(L.fc_grid), dim3(128), 0, st, L.T, L.E, L.np,
                                (const int *)L.off_c);
             break;
         case BSTAGE_ADVANCE:
@@ -2134,7 +2256,8 @@ struct Launch {
         }
     }
     static void batched(int stage, const BatchLaunch &L) {
-        if (L.precision == ADG_MIXED) batched_t<float>(stage, L);
+        if (L.precision == ADG_MIXED_DEV) batched_t<float, true>(stage, L);
+        else if (L.precision == ADG_MIXED) batched_t<float>(stage, L);
         else batched_t<double>(stage, L);
     }
     static void lambda(const StepCtx &C, const double *u, double factor) {

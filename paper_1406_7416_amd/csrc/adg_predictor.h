@@ -147,8 +147,14 @@ __device__ __forceinline__ void lds_lines(R *X, int k, int nlines_per_var, int l
 }
 
 // Blocks vb = vb0, vb0 + vbs, ... of CPB cells each, out of ncell cells.
-template <int DIM, int N, bool VOL, typename R, int TB = Tune<DIM, N, sizeof(R) == 4>::pred_tb>
+// DEV (FP32 working precision only): the pencils carry the deviation dq = q - c from the cell's
+// reference state c (its first nodal value rounded to FP32) and the fluxes are evaluated as
+// F(c + dq) - F(c) in the expanded form of dev_flux; the derivative matrix annihilates the
+// constant F(c), so the Picard iteration, the volume term and the traces are those of the
+// deviations, and FP32 rounding is relative to the deviation instead of the state.
+template <int DIM, int N, bool VOL, typename R, bool DEV = false, int TB = Tune<DIM, N, sizeof(R) == 4>::pred_tb>
 __device__ void pred_cells(const PredArgs<R> &A, double gamma_d, int64_t ncell, int64_t vb0, int64_t vbs) {
+    static_assert(!DEV || sizeof(R) == 4, "the deviation form is an FP32 form");
     using S = PredShape<DIM, N, R, TB>;
     const R gamma = (R)gamma_d;
     constexpr int n = S::n, NV = S::NV, NN = S::NN, NST = S::NST, NFN = S::NFN, CPB = S::CPB, VC = S::VC;
@@ -185,14 +191,31 @@ __device__ void pred_cells(const PredArgs<R> &A, double gamma_d, int64_t ncell, 
     const bool owner = (tid < S::ACT) && (c < ncell);
 
     R u0[NV], q[NV][n], Sacc[NV][n];
+    DevRef<DIM, R> cref;
     if (owner) {
+        if constexpr (DEV) {
+            double c64[NV];
 #pragma unroll
-        for (int v = 0; v < NV; v++) u0[v] = (R)A.in[c * A.in_cstride + v * A.in_vstride + a];
+            for (int v = 0; v < NV; v++) c64[v] = A.in[c * A.in_cstride + v * A.in_vstride];
+            cref = make_devref<DIM, R>(c64, gamma_d);
+#pragma unroll
+            for (int v = 0; v < NV; v++) u0[v] = (R)(A.in[c * A.in_cstride + v * A.in_vstride + a] - (double)cref.q[v]);
+        } else {
+#pragma unroll
+            for (int v = 0; v < NV; v++) u0[v] = (R)A.in[c * A.in_cstride + v * A.in_vstride + a];
+        }
     } else {
         // idle lanes carry a valid constant state so that they never produce NaN
 #pragma unroll
-        for (int v = 0; v < NV; v++) u0[v] = (v == 0) ? R(1) : R(0);
-        u0[NV - 1] = R(2.5);
+        for (int v = 0; v < NV; v++) u0[v] = (v == 0 && !DEV) ? R(1) : R(0);
+        if constexpr (!DEV) u0[NV - 1] = R(2.5);
+        if constexpr (DEV) {
+            double c64[NV];
+#pragma unroll
+            for (int v = 0; v < NV; v++) c64[v] = (v == 0) ? 1.0 : 0.0;
+            c64[NV - 1] = 2.5;
+            cref = make_devref<DIM, R>(c64, gamma_d);
+        }
     }
 #pragma unroll
     for (int v = 0; v < NV; v++)
@@ -213,11 +236,20 @@ __device__ void pred_cells(const PredArgs<R> &A, double gamma_d, int64_t ncell, 
         if constexpr (CACHE_IRHO) {
 #pragma unroll
             for (int t = 0; t < NT; t++) {
-                irho[t] = recip(q[0][t]);
-                R ke = 0;
+                if constexpr (DEV) {
+                    // deviation form: 1/rho of the full state and the pressure's deviation
+                    R dq[NV];
 #pragma unroll
-                for (int j = 0; j < DIM; j++) ke += q[1 + j][t] * q[1 + j][t];
-                pr[t] = (gamma - R(1)) * (q[NV - 1][t] - R(0.5) * ke * irho[t]);
+                    for (int v = 0; v < NV; v++) dq[v] = q[v][t];
+                    irho[t] = recip(cref.q[0] + dq[0]);
+                    pr[t] = dev_pressure<DIM, R>(cref, dq, irho[t], gamma);
+                } else {
+                    irho[t] = recip(q[0][t]);
+                    R ke = 0;
+#pragma unroll
+                    for (int j = 0; j < DIM; j++) ke += q[1 + j][t] * q[1 + j][t];
+                    pr[t] = (gamma - R(1)) * (q[NV - 1][t] - R(0.5) * ke * irho[t]);
+                }
             }
         }
 #pragma unroll
@@ -241,10 +273,17 @@ __device__ void pred_cells(const PredArgs<R> &A, double gamma_d, int64_t ncell, 
                             prt = (gamma - R(1)) * (q[NV - 1][t] - R(0.5) * ke * ir);
                         }
                         R F[NV];
-                        F[0] = q[1 + k][t];
+                        if constexpr (DEV) {
+                            R dq[NV];
 #pragma unroll
-                        for (int j = 0; j < DIM; j++) F[1 + j] = q[1 + j][t] * un + (j == k ? prt : R(0));
-                        F[NV - 1] = un * (q[NV - 1][t] + prt);
+                            for (int v = 0; v < NV; v++) dq[v] = q[v][t];
+                            dev_flux<DIM, R>(k, cref, dq, ir, prt, F);
+                        } else {
+                            F[0] = q[1 + k][t];
+#pragma unroll
+                            for (int j = 0; j < DIM; j++) F[1 + j] = q[1 + j][t] * un + (j == k ? prt : R(0));
+                            F[NV - 1] = un * (q[NV - 1][t] + prt);
+                        }
 #pragma unroll
                         for (int vv = 0; vv < VC; vv++)
                             if (v0 + vv < NV) X[(lc * VC + vv) * NST + a + NN * t] = F[v0 + vv];
@@ -311,7 +350,12 @@ __device__ void pred_cells(const PredArgs<R> &A, double gamma_d, int64_t ncell, 
                 R qt[NV], F[NV];
 #pragma unroll
                 for (int v = 0; v < NV; v++) qt[v] = q[v][t];
-                euler_flux<DIM, R>(k, qt, F, gamma);
+                if constexpr (DEV) {
+                    const R ir = recip(cref.q[0] + qt[0]);
+                    dev_flux<DIM, R>(k, cref, qt, ir, dev_pressure<DIM, R>(cref, qt, ir, gamma), F);
+                } else {
+                    euler_flux<DIM, R>(k, qt, F, gamma);
+                }
 #pragma unroll
                 for (int v = 0; v < NV; v++) Fi[v] += A.w[t] * F[v];
             }
@@ -384,11 +428,11 @@ __device__ void pred_cells(const PredArgs<R> &A, double gamma_d, int64_t ncell, 
     }  // persistent loop
 }
 
-template <int DIM, int N, bool VOL, typename R>
+template <int DIM, int N, bool VOL, typename R, bool DEV = false>
 // the register budget held to Tune's waves per SIMD (FP32: four, FP64: two by default)
 __global__ __launch_bounds__((PredShape<DIM, N, R>::BS), (Tune<DIM, N, sizeof(R) == 4>::pred_wps)) void k_predictor(PredArgs<R> A,
                                                                                                    double gamma_d) {
-    pred_cells<DIM, N, VOL, R>(A, gamma_d, A.ncell, blockIdx.x, gridDim.x);
+    pred_cells<DIM, N, VOL, R, DEV>(A, gamma_d, A.ncell, blockIdx.x, gridDim.x);
 }
 
 }  // namespace adg

@@ -1222,16 +1222,20 @@ __device__ __forceinline__ void sub_update_cell(const Tables *__restrict__ T, co
                 else nbex |= 1 << (2 * k + side);
             }
         }
-    // sub-faces of all axes in one range (threads stay busy for small Ns); the body is
-    // instantiated per axis (compile-time k: no dynamic indexing of per-thread arrays).
-    // Each axis's range is padded to whole waves (no wave runs two axes' bodies) unless
-    // that would take more rounds of the workgroup.
-    constexpr int PA = (NS + 1) * NSF, PA64 = (PA + 63) / 64 * 64;
-    constexpr int STRIDE = (DIM * PA64 + SUB_BS - 1) / SUB_BS <= (DIM * PA + SUB_BS - 1) / SUB_BS ? PA64 : PA;
-    for (int i0 = threadIdx.x; i0 < DIM * STRIDE; i0 += SUB_BS) {
-        const int kk = i0 / STRIDE, it2 = i0 % STRIDE;
-        if (it2 >= PA) continue;
-        const int it = kk * PA + it2;   // sub-face index: axis-major, then face, then tangential
+    // Sub-face fluxes.  A sub-face is handled by NF3 consecutive lanes of one wave, one per
+    // tangential quadrature point (64 / NF3 sub-faces per wave); a wave takes a run of
+    // sub-faces of one axis, so the body is instantiated per axis (compile-time k: no dynamic
+    // indexing of per-thread arrays).  The lanes of a sub-face agree on the positivity
+    // fallback by a ballot and the first of them sums the tangential points in order.
+    constexpr int SPW = 64 / NF3;
+    constexpr int PA = (NS + 1) * NSF, WPA = (PA + SPW - 1) / SPW;   // sub-faces, waves per axis
+    const int lane = threadIdx.x & 63, sfl = lane / NF3, ap = lane % NF3;
+    for (int wt = threadIdx.x >> 6; wt < DIM * WPA; wt += SUB_BS / 64) {
+        const int kk = wt / WPA;
+        const int it2r = (wt % WPA) * SPW + sfl;
+        const bool valid = sfl < SPW && it2r < PA;
+        const int it2 = valid ? it2r : 0;   // idle lanes work on an in-range sub-face, store nothing
+        const int it = kk * PA + it2;       // sub-face index: axis-major, then face, then tangential
         auto subface = [&](auto kc) {
             constexpr int k = decltype(kc)::value;
             const int f = it2 / NSF;
@@ -1284,89 +1288,98 @@ __device__ __forceinline__ void sub_update_cell(const Tables *__restrict__ T, co
                     avR[v] = halo[v * HSZ + hR];
                 }
             }
-            // Positivity safeguard: if any predictor trace on either side is not a physical
-            // state, the sub-face takes the first-order flux of the two subcell averages.
-            // A sub-face on the cell's own face also keeps its time-averaged flux at each
-            // tangential quadrature point for the flux correction of the neighbour.
-            R Fbar[NV];
-            const bool own_face = (f == 0 || f == NS);
-            double *fp = S.fpts + ((int64_t)ch * 2 * DIM + 2 * k + (f == NS ? 1 : 0)) * NV * QF;
-            for (int pass = low; pass < 2; pass++) {
-                bool ok = true;
+            // this lane's tangential quadrature point: position and weight
+            const int ma0 = ap % 3, ma1 = ap / 3;
+            double wtan = 1.0;
+            double x[3] = {0, 0, 0};
 #pragma unroll
-                for (int v = 0; v < NV; v++) Fbar[v] = 0;
-                for (int ap = 0; ap < NF3 && ok; ap++) {
-                    const int ma0 = ap % 3, ma1 = ap / 3;
-                    double wtan = 1.0;
-                    double x[3] = {0, 0, 0};
-#pragma unroll
-                    for (int j = 0; j < DIM; j++) {
-                        if (j == k) {
-                            x[j] = P.lo[j] + P.h[j] * (ci[j] + (double)f / NS);
-                        } else {
-                            const bool first = (j < k ? j : j - 1) == 0;
-                            const int ma = first ? ma0 : ma1;
-                            wtan *= T->w3[ma];
-                            x[j] = P.lo[j] + P.h[j] * (ci[j] + ((first ? mp0 : mp1) + T->xi3[ma]) / NS);
-                        }
-                    }
-                    R Gt[NV];
-#pragma unroll
-                    for (int v = 0; v < NV; v++) Gt[v] = 0;
-                    for (int s = 0; s < 3; s++) {
-                        R qL[NV], qR[NV], G[NV];
-                        const double ts = t0 + T->xi3[s] * dt;
-                        const R *trL = tr + (int64_t)pL * TRS + (2 * k + 1) * NV * NF3 * 3;
-                        const R *trR = tr + (int64_t)pR * TRS + (2 * k + 0) * NV * NF3 * 3;
-#pragma unroll
-                        for (int v = 0; v < NV; v++) {
-                            qL[v] = pass ? (R)avL[v] : trL[v * NF3 * 3 + ap + NF3 * s];
-                            qR[v] = pass ? (R)avR[v] : trR[v * NF3 * 3 + ap + NF3 * s];
-                        }
-                        if (bside >= 0 && ((nbwall >> (2 * k + bside)) & 1)) {
-                            // reflective wall of the masked geometry
-                            if (bside == 0) wall_ghost<DIM, R>(k, qR, qL);
-                            else wall_ghost<DIM, R>(k, qL, qR);
-                        } else if (bside >= 0) {
-                            // ghost state of the boundary rule, evaluated in FP64
-                            double qi[NV], qo[NV];
-                            if (bside == 0) {
-#pragma unroll
-                                for (int v = 0; v < NV; v++) qi[v] = (double)qR[v];
-                                bc_ghost<DIM>(P, k, 0, qi, x[0], x[1], x[2], ts, qo);
-#pragma unroll
-                                for (int v = 0; v < NV; v++) qL[v] = (R)qo[v];
-                            } else {
-#pragma unroll
-                                for (int v = 0; v < NV; v++) qi[v] = (double)qL[v];
-                                bc_ghost<DIM>(P, k, 1, qi, x[0], x[1], x[2], ts, qo);
-#pragma unroll
-                                for (int v = 0; v < NV; v++) qR[v] = (R)qo[v];
-                            }
-                        }
-                        if (!pass && !(physical<DIM, R>(qL, gam) && physical<DIM, R>(qR, gam))) {
-                            ok = false;
-                            break;
-                        }
-                        // the scheme's flux on the traces; the first-order fallback uses Rusanov
-                        if (pass) rusanov<DIM, R>(k, qL, qR, G, gam);
-                        else num_flux<DIM, R>(P, T, k, qL, qR, G);
-#pragma unroll
-                        for (int v = 0; v < NV; v++) Gt[v] += (R)T->w3[s] * G[v];
-                    }
-                    if (!ok) break;
-#pragma unroll
-                    for (int v = 0; v < NV; v++) Fbar[v] += (R)wtan * Gt[v];
-                    if (own_face) {
-                        const int q = (mp0 * 3 + ma0) + 3 * NS * (mp1 * 3 + ma1);
-#pragma unroll
-                        for (int v = 0; v < NV; v++) fp[v * QF + q] = (double)Gt[v];
-                    }
+            for (int j = 0; j < DIM; j++) {
+                if (j == k) {
+                    x[j] = P.lo[j] + P.h[j] * (ci[j] + (double)f / NS);
+                } else {
+                    const bool first = (j < k ? j : j - 1) == 0;
+                    const int ma = first ? ma0 : ma1;
+                    wtan *= T->w3[ma];
+                    x[j] = P.lo[j] + P.h[j] * (ci[j] + ((first ? mp0 : mp1) + T->xi3[ma]) / NS);
                 }
-                if (ok) break;
             }
+            // the time-averaged flux at the point: on the predictor's traces (pass 0) or, the
+            // positivity fallback, the first-order Rusanov flux of the two subcell averages
+            R Gt[NV];
+            auto point_flux = [&](int pass) -> bool {
 #pragma unroll
-            for (int v = 0; v < NV; v++) Fb[it * NV + v] = Fbar[v];
+                for (int v = 0; v < NV; v++) Gt[v] = 0;
+                for (int s = 0; s < 3; s++) {
+                    R qL[NV], qR[NV], G[NV];
+                    const double ts = t0 + T->xi3[s] * dt;
+                    const R *trL = tr + (int64_t)pL * TRS + (2 * k + 1) * NV * NF3 * 3;
+                    const R *trR = tr + (int64_t)pR * TRS + (2 * k + 0) * NV * NF3 * 3;
+#pragma unroll
+                    for (int v = 0; v < NV; v++) {
+                        qL[v] = pass ? (R)avL[v] : trL[v * NF3 * 3 + ap + NF3 * s];
+                        qR[v] = pass ? (R)avR[v] : trR[v * NF3 * 3 + ap + NF3 * s];
+                    }
+                    if (bside >= 0 && ((nbwall >> (2 * k + bside)) & 1)) {
+                        // reflective wall of the masked geometry
+                        if (bside == 0) wall_ghost<DIM, R>(k, qR, qL);
+                        else wall_ghost<DIM, R>(k, qL, qR);
+                    } else if (bside >= 0) {
+                        // ghost state of the boundary rule, evaluated in FP64
+                        double qi[NV], qo[NV];
+                        if (bside == 0) {
+#pragma unroll
+                            for (int v = 0; v < NV; v++) qi[v] = (double)qR[v];
+                            bc_ghost<DIM>(P, k, 0, qi, x[0], x[1], x[2], ts, qo);
+#pragma unroll
+                            for (int v = 0; v < NV; v++) qL[v] = (R)qo[v];
+                        } else {
+#pragma unroll
+                            for (int v = 0; v < NV; v++) qi[v] = (double)qL[v];
+                            bc_ghost<DIM>(P, k, 1, qi, x[0], x[1], x[2], ts, qo);
+#pragma unroll
+                            for (int v = 0; v < NV; v++) qR[v] = (R)qo[v];
+                        }
+                    }
+                    if (!pass && !(physical<DIM, R>(qL, gam) && physical<DIM, R>(qR, gam))) return false;
+                    // the scheme's flux on the traces; the first-order fallback uses Rusanov
+                    if (pass) rusanov<DIM, R>(k, qL, qR, G, gam);
+                    else num_flux<DIM, R>(P, T, k, qL, qR, G);
+#pragma unroll
+                    for (int v = 0; v < NV; v++) Gt[v] += (R)T->w3[s] * G[v];
+                }
+                return true;
+            };
+            // Positivity safeguard: if any predictor trace on either side of the sub-face is
+            // not a physical state, the whole sub-face takes the first-order flux.
+            const bool ok = low ? false : point_flux(0);
+            const uint64_t badm = __ballot(valid && !ok);
+            const bool fallback = ((badm >> (sfl * NF3)) & ((1ull << NF3) - 1ull)) != 0ull;
+            if (fallback) point_flux(1);
+            // a sub-face on the cell's own face keeps its time-averaged flux at each tangential
+            // quadrature point for the flux correction of the neighbour
+            if (valid && (f == 0 || f == NS)) {
+                double *fp = S.fpts + ((int64_t)ch * 2 * DIM + 2 * k + (f == NS ? 1 : 0)) * NV * QF;
+                const int q = (mp0 * 3 + ma0) + 3 * NS * (mp1 * 3 + ma1);
+#pragma unroll
+                for (int v = 0; v < NV; v++) fp[v * QF + q] = (double)Gt[v];
+            }
+            // the sub-face flux: the tangential points' fluxes times their weights, summed in
+            // order by the sub-face's first lane
+            R Fbar[NV];
+#pragma unroll
+            for (int v = 0; v < NV; v++) Fbar[v] = 0;
+            const R wl = (R)wtan;
+#pragma unroll
+            for (int a2 = 0; a2 < NF3; a2++) {
+                const int src = min(sfl * NF3 + a2, 63);
+                const R w2 = __shfl(wl, src);
+#pragma unroll
+                for (int v = 0; v < NV; v++) Fbar[v] += w2 * __shfl(Gt[v], src);
+            }
+            if (valid && ap == 0) {
+#pragma unroll
+                for (int v = 0; v < NV; v++) Fb[it * NV + v] = Fbar[v];
+            }
         };
         if (kk == 0) subface(std::integral_constant<int, 0>{});
         else if (kk == 1) subface(std::integral_constant<int, 1>{});

@@ -4,13 +4,15 @@ build turns into the header <adg_tuning.h>.
 
     python -m paper_1406_7416_amd.tune build   [--dir D]   # CPU: builds one library per variant
     python -m paper_1406_7416_amd.tune measure [--dir D]   # GPU: times every variant, writes tuning.json
+    python -m paper_1406_7416_amd.tune choose              # re-derive the choice from the stored times
 
 The parameters act on different stages of the step (predictor: pred_tb, pred_wps;
 corrector + detection: corr_cpb; subcell recompute: sub_wps), every variant computes the
 same step, and the batch's stage timing gives each (stage, class) launch its own time.  So
 variant i takes option i of every parameter's list for every class at once, and each
 parameter is then chosen per class from its own stage's times: five builds sweep five
-options of every parameter.
+options of every parameter.  A variant replaces the defaults only when it is faster by more
+than the run-to-run spread of the stage times.
 """
 from __future__ import annotations
 
@@ -35,6 +37,9 @@ PRED = {"fp32": [(256, 4), (128, 4), (512, 4), (256, 3), (256, 5)],
 CORR_CPB = [4, 2, 1, 8, 4]          # 8 only where the workgroup's LDS allows it (N = 3)
 SUB_WPS = {"fp32": [3, 2, 4, 3, 3], "fp64": [3, 2, 2, 3, 3]}
 NVAR = 5
+# a variant replaces the defaults (option 0) only when it is faster by more than the
+# run-to-run spread of the stage times (about 2 %)
+MARGIN = 1.03
 
 
 def variant_table(i: int) -> dict:
@@ -105,24 +110,41 @@ def cmd_measure(dirname: str) -> None:
         times.append(json.loads(r.stdout.strip().splitlines()[-1]))
         print("  " + " ".join(f"{k}={v:.2f}" for k, v in sorted(times[-1]["fp32"].items())
                                if k.split(":")[0] in ("predictor", "corrector_detect", "subcell")), flush=True)
-    chosen, measured = {}, {}
+    measured = {}
     for d, N, prec in CLASSES:
         key = f"{d},{N},{prec}"
         tables = [variant_table(i)["classes"][key] for i in range(NVAR)]
-        pick = {}
-        for group, names in (("predictor", ("pred_tb", "pred_wps")), ("corrector_detect", ("corr_cpb",)),
-                             ("subcell", ("sub_wps",))):
+        for group, names in GROUPS:
             ms = [times[i][prec].get(f"{group}:N{N}", float("inf")) for i in range(NVAR)]
-            best = min(range(NVAR), key=lambda i: ms[i])
-            for name in names:
-                pick[name] = tables[best][name]
             measured[f"{key}:{group}"] = {"ms_per_step": [round(x, 4) for x in ms],
                                          "options": [[tables[i][n] for n in names] for i in range(NVAR)]}
-        chosen[key] = pick
-    table = {"classes": chosen,
+    write_table(measured)
+
+
+GROUPS = (("predictor", ("pred_tb", "pred_wps")), ("corrector_detect", ("corr_cpb",)), ("subcell", ("sub_wps",)))
+
+
+def choose(measured: dict) -> dict:
+    """Per class and parameter group: the fastest option, unless the defaults (option 0)
+    are within MARGIN of it."""
+    chosen = {}
+    for key, m in measured.items():
+        cls, group = key.rsplit(":", 1)
+        ms = m["ms_per_step"]
+        best = min(range(len(ms)), key=lambda i: ms[i])
+        if ms[0] <= MARGIN * ms[best]:
+            best = 0
+        names = dict(GROUPS)[group]
+        for name, val in zip(names, m["options"][best]):
+            chosen.setdefault(cls, {})[name] = val
+    return chosen
+
+
+def write_table(measured: dict) -> None:
+    table = {"classes": choose(measured),
              "measured": measured,
              "workload": "batch of 256 four-quadrant problems (d = 2, N = 3..5), stage times per batch step",
-             "variants": NVAR}
+             "variants": NVAR, "margin": MARGIN}
     path = os.path.join(PKG, "tuning.json")
     with open(path, "w") as f:
         json.dump(table, f, indent=1, sort_keys=True)
@@ -131,7 +153,7 @@ def cmd_measure(dirname: str) -> None:
 
 def main() -> None:
     ap = argparse.ArgumentParser()
-    ap.add_argument("cmd", choices=["build", "measure", "_child"])
+    ap.add_argument("cmd", choices=["build", "measure", "choose", "_child"])
     ap.add_argument("lib", nargs="?")
     ap.add_argument("--dir", default=DEFAULT_DIR)
     a = ap.parse_args()
@@ -139,6 +161,10 @@ def main() -> None:
         cmd_build(a.dir)
     elif a.cmd == "measure":
         cmd_measure(a.dir)
+    elif a.cmd == "choose":
+        # re-derive the chosen values from the times already in tuning.json
+        with open(os.path.join(PKG, "tuning.json")) as f:
+            write_table(json.load(f)["measured"])
     else:
         print(json.dumps(measure_variant(a.lib)), flush=True)
 

@@ -161,7 +161,13 @@ def main():
     ap.add_argument("--batch-only", action="store_true",
                     help="only the mixed batched form of the batch: no FP64 forms, MOOD run, CPU leg or extras "
                          "(profiling runs)")
+    ap.add_argument("--explosion3d-only", action="store_true",
+                    help="only the 3D explosion at its full size, both forms (profiling runs)")
     args = ap.parse_args()
+
+    if args.explosion3d_only:
+        print(json.dumps(explosion3d_measurement(args.steps_3d, warmup=2)))
+        return
 
     if args.convergence:
         print(json.dumps(vortex_convergence(args.N)))

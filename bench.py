@@ -163,10 +163,15 @@ def main():
                          "(profiling runs)")
     ap.add_argument("--explosion3d-only", action="store_true",
                     help="only the 3D explosion at its full size, both forms (profiling runs)")
+    ap.add_argument("--vortex-only", action="store_true",
+                    help="only the vortex measurement (degree --N on --grid^2 cells), every form (profiling runs)")
     args = ap.parse_args()
 
     if args.explosion3d_only:
         print(json.dumps(explosion3d_measurement(args.steps_3d, warmup=2)))
+        return
+    if args.vortex_only:
+        print(json.dumps(vortex_measurement(args.grid, args.N, args.vortex_steps)))
         return
 
     if args.convergence:

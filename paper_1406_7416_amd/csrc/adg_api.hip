@@ -71,7 +71,7 @@ struct adg_problem {
     struct Off {
         size_t tab, u0, u1, emin0, emax0, emin1, emax1, trace, gbar, beta0, beta1, force, mflag, margin, tlist, clist,
             slot0,
-            slot1, pool0, pool1, sflux, blk, counts, scal, lampart, ring, halo, Y, strace, fpts, mask, end;
+            slot1, pool0, pool1, sflux, blk, counts, scal, lampart, ring, halo, Y, strace, fpts, mask, big, end;
     } off;
     int64_t ring_cap = 0;    // ghost-ring cells of the extended grid (+ every cell, for solid cells)
     int64_t nring = 0;       // extended cells whose bounds the step computes (ghost ring on
@@ -158,7 +158,8 @@ static void plan(adg_problem *pb) {
     const int64_t per_chunk_cell = (nv * hsz + pb->npos * nv * n3 + pb->npos * 2 * d * nv * nf3 * 3) * 8;
     // subcell scratch: one slot per workgroup of the persistent subcell kernel (as many as
     // the 256 CUs of MI355X hold at once, fewer if the pool holds fewer cells)
-    const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(subcell_workgroups(d, P.N, pb->prm.precision), pb->cap));
+    int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(subcell_workgroups(d, P.N, pb->prm.precision), pb->cap));
+    if (big_slot_doubles(d, P.N) > 0) chunk = std::min<int64_t>(chunk, BIG_WG);   // one global slot per workgroup
     (void)per_chunk_cell;
     pb->chunk = (int)chunk;
     pb->lam_blocks = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (nc * nn + 255) / 256));
@@ -205,6 +206,9 @@ static void plan(adg_problem *pb) {
     f.strace = take(8ull * chunk * pb->npos * 2 * d * nv * nf3 * 3);
     f.fpts = take(8ull * chunk * 2 * d * nv * ipow64(3 * Ns, d - 1));
     f.mask = take(nc);
+    // large cells: one global slot per workgroup of their corrector, bounds, subcell and
+    // flux-correction launches
+    f.big = take(8ull * BIG_WG * std::max<int64_t>(1, big_slot_doubles(d, P.N)));
     f.end = o;
     pb->ws_bytes = o;
 }
@@ -244,6 +248,7 @@ static void carve(adg_problem *pb) {
     B.strace = (double *)(w + f.strace);
     B.fpts = (double *)(w + f.fpts);
     B.mask = pb->mask.empty() ? nullptr : (const uint8_t *)(w + f.mask);
+    B.big = (double *)(w + f.big);
     pb->tab_dev = B.tab;
 }
 
@@ -1347,6 +1352,9 @@ int adg_batch_create(adg_problem *const *ps, int count, adg_batch **out) {
         const adg_params &a = ps[0]->prm, &c = pb->prm;
         if (c.precision != a.precision || c.limiter != a.limiter || c.mood != a.mood)
             return fail(ADG_EINVAL, "problem %d: the problems of a batch share precision, limiter and MOOD layer", i);
+        if (big_slot_doubles(pb->P.dim, pb->P.N) > 0)
+            return fail(ADG_EINVAL, "problem %d: 3D problems of degree %d are stepped one by one, not in a batch", i,
+                        pb->P.N);
     }
     adg_batch *b = new (std::nothrow) adg_batch();
     if (!b) return fail(ADG_ENOMEM, "host allocation failed");

@@ -86,6 +86,8 @@ struct Bufs {
     double *halo;          // [chunk][v][(Ns+6)^d]
     double *Y;             // [chunk][pos][v][3^d] reconstructed nodal values (float in the mixed form)
     double *strace;        // [chunk][pos][2d][v][3^(d-1)*3]
+    // large cells (3D, N = 9): per-workgroup slots of the arrays that exceed LDS
+    double *big;           // [BIG_WG][BigCell slot]
 };
 
 // Arguments of one launch of the space-time predictor.

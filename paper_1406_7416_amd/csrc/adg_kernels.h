@@ -25,7 +25,12 @@ struct StepCtx {
 // predictor traces, the 3D halo and the per-point boundary fluxes.
 struct SubScratch {
     double *Y, *strace, *halo, *fpts;
+    double *big;           // large cells: slots of the update's sub-face fluxes and subcell arrays
 };
+
+// Workgroups (= global scratch slots) of the kernels of large cells, whose per-cell arrays
+// exceed the LDS of a CU and live in a slot of global memory instead (3D, N = 9).
+constexpr int BIG_WG = 512;
 
 // Stages of one step in a batch, each one batched launch (or a few) per (d, N) class.
 enum {
@@ -56,6 +61,8 @@ struct BatchLaunch {
 };
 
 bool supported(int dim, int N);
+// doubles per global scratch slot of a large-cell class (0: the class works in LDS)
+int64_t big_slot_doubles(int dim, int N);
 int positions_per_cell(int dim, int N);
 // workgroups (= scratch slots) of the persistent subcell launch that fill MI355X's 256 CUs
 int subcell_workgroups(int dim, int N, int precision);

@@ -10,10 +10,12 @@ static const Ops *ops_for(int dim, int N) {
     if (dim == 2 && N >= 6 && N <= 7) return ops_2d_c(N);
     if (dim == 2 && N >= 8 && N <= 9) return ops_2d_d(N);
     if (dim == 3 && N >= 1 && N <= 3) return ops_3d(N);
+    if (dim == 3 && N == 9) return ops_3d_9(N);
     return nullptr;
 }
 
 bool supported(int dim, int N) { return ops_for(dim, N) != nullptr; }
+int64_t big_slot_doubles(int dim, int N) { return ops_for(dim, N)->big_slot; }
 int positions_per_cell(int dim, int N) { return ops_for(dim, N)->npos; }
 int subcell_workgroups(int dim, int N, int precision) {
     return ops_for(dim, N)->sub_wgs[precision != ADG_FP64 ? 1 : 0];

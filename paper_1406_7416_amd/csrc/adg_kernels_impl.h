@@ -21,6 +21,32 @@
 
 namespace adg {
 
+// ------------------------------------------------------------------- large cells
+// 3D cells of degree N = 9 carry 19^3 subcells and 10^3 nodes per variable: the candidate's
+// subcell averages, the stages of the sum-factorised projection P and gather R and the
+// subcell update's sub-face fluxes (0.4-1.4 MB per cell) exceed the 160 KB of LDS of a CU.
+// Those arrays live in a slot of global memory per workgroup (reused cell after cell, so it
+// stays in the L2 / Infinity Cache) and the kernels loop over their cells with a grid of at
+// most BIG_WG workgroups; the nodal state of the cell stays in LDS.
+template <int DIM, int N>
+struct BigCell {
+    static constexpr bool on = DIM == 3 && N >= 9;
+    static constexpr int n = N + 1, NV = DIM + 2, NN = cpow(n, DIM), NS = 2 * N + 1, NSUB = cpow(NS, DIM);
+    static constexpr int NSF = cpow(NS, DIM - 1), BIGN = NSUB > NN ? NSUB : NN;
+    // corrector: subcell averages + the stage-1 intermediate of P
+    static constexpr int64_t CORR = (int64_t)NV * NSUB + (int64_t)NV * NS * NS * n;
+    // bounds and flux correction: subcell averages + intermediate, both NV x max(NSUB, NN)
+    static constexpr int64_t BND = 2ll * NV * BIGN;
+    // subcell update: sub-face fluxes (FP64 at most) or the gather's intermediate, then the
+    // new subcell averages and the gathered nodal values
+    static constexpr int64_t FB = (int64_t)DIM * (NS + 1) * NSF * NV, TM = (int64_t)NV * BIGN;
+    static constexpr int64_t SUB = (FB > TM ? FB : TM) + 2ll * NV * BIGN;
+    static constexpr int64_t M1 = CORR > BND ? CORR : BND, M2 = M1 > SUB ? M1 : SUB;
+    static constexpr int64_t SLOT = on ? ((M2 + 31) / 32) * 32 : 0;   // doubles, 256-byte aligned
+    // the slot's regions in the subcell update
+    static constexpr int64_t SUB_VN = FB > TM ? FB : TM, SUB_UG = SUB_VN + (int64_t)NV * BIGN;
+};
+
 // ------------------------------------------------------------------- face fluxes
 // One thread per (face, tangential node, time node): Rusanov flux weighted by the time
 // quadrature weight; the time sum is then taken in LDS in fixed order and written into
@@ -402,7 +428,8 @@ __device__ __forceinline__ void tensor_apply(const double *__restrict__ Mbase, c
 template <int DIM, int N, typename R>
 struct CorrShape {
     static constexpr int NSUB = cpow(2 * N + 1, DIM);
-    static constexpr int CW = NSUB <= 128 ? 64 : 128;
+    static constexpr bool BIG = BigCell<DIM, N>::on;
+    static constexpr int CW = BIG ? 256 : (NSUB <= 128 ? 64 : 128);
     static constexpr int CPB = (CW == 64) ? Tune<DIM, N, sizeof(R) == 4>::corr_cpb : 1;
     static constexpr int BS = CW * CPB;
     static constexpr int NW = CW / 64;   // waves per cell
@@ -410,7 +437,9 @@ struct CorrShape {
     // arrays); the register budget is held to it so that registers do not limit further
     static constexpr int NN = cpow(N + 1, DIM), NV = DIM + 2;
     static constexpr int TMPN = (DIM == 2) ? (2 * N + 1) * (N + 1) : (2 * N + 1) * (2 * N + 1) * (N + 1);
-    static constexpr int LDSB = CPB * NV * (NN + NSUB + TMPN) * 8 + CPB * (2 * NW + 2) * NV * 8 + 2048;
+    // (large cells: the nodal state and the face fluxes in LDS, the rest in the global slot)
+    static constexpr int LDSB = BIG ? NV * NN * 8 + 2 * DIM * NV * cpow(N + 1, DIM - 1) * 8 + (2 * NW + 2) * NV * 8 + 2048
+                                    : CPB * NV * (NN + NSUB + TMPN) * 8 + CPB * (2 * NW + 2) * NV * 8 + 2048;
     static constexpr int WPS0 = (163840 / LDSB) * (BS / 64) / 4;
     static constexpr int WPS = WPS0 < 1 ? 1 : (WPS0 > 6 ? 6 : WPS0);
 };
@@ -428,8 +457,6 @@ __device__ __forceinline__ void corrector_detect_block(const Tables *__restrict_
     // intermediate of the sum-factorised P: stage 0 (2D) or stage 1 (3D) output
     constexpr int TMP = (DIM == 2) ? NS * n : NS * NS * n;
     __shared__ double us_[CPB][NV * NN];
-    __shared__ double vs_[CPB][NV * NSUB];
-    __shared__ double tmp_[CPB][NV * TMP];
     __shared__ double red_[CPB][NW * 2 * NV];
     __shared__ int bad_s[CPB][NW];
     __shared__ float mg_s[CPB][NW];
@@ -439,7 +466,16 @@ __device__ __forceinline__ void corrector_detect_block(const Tables *__restrict_
     const bool live = c < P.ncell;         // every thread stays for the barriers
     // masked geometry: a solid cell keeps its state and is never troubled
     const bool solid = live && B.mask && B.mask[c];
-    double *us = us_[lc], *vs = vs_[lc], *tmp = tmp_[lc], *red = red_[lc];
+    double *us = us_[lc], *red = red_[lc], *vs, *tmp;
+    if constexpr (CS::BIG) {
+        vs = B.big + (int64_t)blockIdx.x * BigCell<DIM, N>::SLOT;
+        tmp = vs + NV * NSUB;
+    } else {
+        __shared__ double vs_[CPB][NV * NSUB];
+        __shared__ double tmp_[CPB][NV * TMP];
+        vs = vs_[lc];
+        tmp = tmp_[lc];
+    }
     const double dt = B.scal[0];
     double *un = B.u[cur ^ 1];
     const double *usrc = solid ? B.u[cur] : un;
@@ -623,7 +659,15 @@ __device__ __forceinline__ void corrector_detect_block(const Tables *__restrict_
 template <int DIM, int N, typename R>
 __global__ __launch_bounds__((CorrShape<DIM, N, R>::BS), (CorrShape<DIM, N, R>::WPS)) void k_corrector_detect(const Tables *__restrict__ T, Prob P,
                                                                          Bufs B, int cur, int limiter) {
-    corrector_detect_block<DIM, N, R>(T, P, B, cur, limiter, blockIdx.x);
+    if constexpr (BigCell<DIM, N>::on) {
+        // large cells: one cell per iteration on the workgroup's global slot
+        for (int64_t c = blockIdx.x; c < P.ncell; c += gridDim.x) {
+            corrector_detect_block<DIM, N, R>(T, P, B, cur, limiter, c);
+            __syncthreads();
+        }
+    } else {
+        corrector_detect_block<DIM, N, R>(T, P, B, cur, limiter, blockIdx.x);
+    }
 }
 
 // --------------------------------------------------------- old-time bounds
@@ -639,9 +683,17 @@ __device__ __forceinline__ void cell_bounds_block(const Tables *__restrict__ T, 
     constexpr int NS = 2 * N + 1, NSUB = cpow(NS, DIM);
     constexpr int BIG = NSUB > NN ? NSUB : NN;
     __shared__ double us[NV * NN];
-    __shared__ double vs[NV * BIG];
-    __shared__ double tmp[NV * BIG];
     __shared__ double red[2 * NV * 2];
+    double *vs, *tmp;
+    if constexpr (BigCell<DIM, N>::on) {
+        vs = B.big + (int64_t)blockIdx.x * BigCell<DIM, N>::SLOT;
+        tmp = vs + NV * BIG;
+    } else {
+        __shared__ double vs_[NV * BIG];
+        __shared__ double tmp_[NV * BIG];
+        vs = vs_;
+        tmp = tmp_;
+    }
     const int tid = threadIdx.x;
     // all extended cells, or only the ghost ring (interior bounds then come from the
     // kernels of the previous step that produced each cell's new subcell data)
@@ -746,10 +798,18 @@ __device__ __forceinline__ void cell_bounds_block(const Tables *__restrict__ T, 
         }
     }
 }
+// nblk: extended cells of the launch (large cells: the grid loops over them)
 template <int DIM, int N>
 __global__ __launch_bounds__(128) void k_cell_bounds(const Tables *__restrict__ T, Prob P, Bufs B, int cur,
-                                                     const int64_t *__restrict__ ring) {
-    cell_bounds_block<DIM, N>(T, P, B, cur, ring, blockIdx.x);
+                                                     const int64_t *__restrict__ ring, int64_t nblk) {
+    if constexpr (BigCell<DIM, N>::on) {
+        for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
+            cell_bounds_block<DIM, N>(T, P, B, cur, ring, b);
+            __syncthreads();
+        }
+    } else {
+        cell_bounds_block<DIM, N>(T, P, B, cur, ring, blockIdx.x);
+    }
 }
 
 // ------------------------------------------------------------------ compaction
@@ -1191,11 +1251,25 @@ __device__ __forceinline__ void sub_update_cell(const Tables *__restrict__ T, co
     constexpr int NFN = cpow(n, DIM - 1);
     // sub-face fluxes (working precision), later the gather's intermediate stage
     constexpr int FBB = DIM * (NS + 1) * NSF * NV * (int)sizeof(R), TMB = NV * BIG * 8;
-    __shared__ __align__(16) unsigned char fbt[FBB > TMB ? FBB : TMB];
-    R *Fb = reinterpret_cast<R *>(fbt);
-    double *tmp = reinterpret_cast<double *>(fbt);
-    __shared__ double vn[NV * BIG];
-    __shared__ double ug[NV * BIG];
+    R *Fb;
+    double *tmp, *vn, *ug;
+    if constexpr (BigCell<DIM, N>::on) {
+        // large cells: the workgroup's global slot
+        using BC = BigCell<DIM, N>;
+        double *slot = S.big + (int64_t)sidx * BC::SLOT;
+        Fb = reinterpret_cast<R *>(slot);
+        tmp = slot;
+        vn = slot + BC::SUB_VN;
+        ug = slot + BC::SUB_UG;
+    } else {
+        __shared__ __align__(16) unsigned char fbt[FBB > TMB ? FBB : TMB];
+        __shared__ double vn_[NV * BIG];
+        __shared__ double ug_[NV * BIG];
+        Fb = reinterpret_cast<R *>(fbt);
+        tmp = reinterpret_cast<double *>(fbt);
+        vn = vn_;
+        ug = ug_;
+    }
     __shared__ double red[2 * NV * (SUB_BS / 64)];
     __shared__ int badc;
     const int ch = sidx;
@@ -1730,7 +1804,7 @@ template <int DIM, int N, typename R, bool REDO>
 __global__ __launch_bounds__(SUB_BS, (SubShape<DIM, N, R>::WPS)) void k_subcell(const Tables *__restrict__ T, Prob P, Bufs B, int cur, int64_t cap,
                                                  int *nonphys, int flagging) {
     const int count = (int)(B.counts[0] < cap ? B.counts[0] : cap);
-    const SubScratch S{B.Y, B.strace, B.halo, B.fpts};
+    const SubScratch S{B.Y, B.strace, B.halo, B.fpts, B.big};
     for (int w = blockIdx.x; w < count; w += gridDim.x)
         subcell_cell<DIM, N, R, REDO>(T, P, B, cur, w, blockIdx.x, S, nonphys, flagging);
 }
@@ -1748,9 +1822,17 @@ __device__ __forceinline__ void fluxcorr_cell(const Tables *__restrict__ T, cons
     constexpr int NS_ = 2 * N + 1, NSUB_ = cpow(NS_, DIM), NN_ = cpow(N + 1, DIM), NV_ = DIM + 2;
     constexpr int TMP_ = (DIM == 2) ? NS_ * (N + 1) : NS_ * NS_ * (N + 1);
     __shared__ double us[NV_ * NN_];
-    __shared__ double vs[NV_ * NSUB_];
-    __shared__ double tmp[NV_ * TMP_];
     __shared__ double red[2 * NV_ * 2];
+    double *vs, *tmp;
+    if constexpr (BigCell<DIM, N>::on) {
+        vs = B.big + (int64_t)blockIdx.x * BigCell<DIM, N>::SLOT;
+        tmp = vs + NV_ * NSUB_;
+    } else {
+        __shared__ double vs_[NV_ * NSUB_];
+        __shared__ double tmp_[NV_ * TMP_];
+        vs = vs_;
+        tmp = tmp_;
+    }
     constexpr int n = N + 1, NV = DIM + 2, NN = cpow(n, DIM), NFN = cpow(n, DIM - 1);
     constexpr int NS = 2 * N + 1;
     {
@@ -2149,21 +2231,26 @@ struct Launch {
     static void corrector_detect(const StepCtx &C) {
         using CF = CorrShape<DIM, N, float>;
         using CD = CorrShape<DIM, N, double>;
+        // large cells: a grid of at most BIG_WG workgroups (one global slot each) loops over the cells
+        auto grid = [&](int64_t cpb) {
+            const int64_t nb = (C.P.ncell + cpb - 1) / cpb;
+            return (unsigned)(BigCell<DIM, N>::on ? std::min<int64_t>(nb, BIG_WG) : nb);
+        };
         if (C.precision != ADG_FP64)
-            hipLaunchKernelGGL((k_corrector_detect<DIM, N, float>), dim3((unsigned)((C.P.ncell + CF::CPB - 1) / CF::CPB)),
-                               dim3(CF::BS), 0, C.stream, C.tab, C.P, C.B, C.cur, C.limiter);
+            hipLaunchKernelGGL((k_corrector_detect<DIM, N, float>), dim3(grid(CF::CPB)), dim3(CF::BS), 0, C.stream,
+                               C.tab, C.P, C.B, C.cur, C.limiter);
         else
-            hipLaunchKernelGGL((k_corrector_detect<DIM, N, double>), dim3((unsigned)((C.P.ncell + CD::CPB - 1) / CD::CPB)),
-                               dim3(CD::BS), 0, C.stream, C.tab, C.P,
-                               C.B, C.cur, C.limiter);
+            hipLaunchKernelGGL((k_corrector_detect<DIM, N, double>), dim3(grid(CD::CPB)), dim3(CD::BS), 0, C.stream,
+                               C.tab, C.P, C.B, C.cur, C.limiter);
     }
     static void bounds(const StepCtx &C) {
         int64_t next = 1;
         for (int j = 0; j < DIM; j++) next *= C.P.nc[j] + 2;
         const int64_t nblk = C.ring_only ? C.nring : next;
+        const int64_t grid = BigCell<DIM, N>::on ? std::min<int64_t>(nblk, BIG_WG) : nblk;
         if (nblk > 0)
-            hipLaunchKernelGGL((k_cell_bounds<DIM, N>), dim3((unsigned)nblk), dim3(128), 0, C.stream, C.tab, C.P, C.B,
-                               C.cur, C.ring_only ? C.B.ring : (const int64_t *)nullptr);
+            hipLaunchKernelGGL((k_cell_bounds<DIM, N>), dim3((unsigned)grid), dim3(128), 0, C.stream, C.tab, C.P, C.B,
+                               C.cur, C.ring_only ? C.B.ring : (const int64_t *)nullptr, nblk);
     }
     template <typename R>
     static void subcell_t(const StepCtx &C, int redo) {
@@ -2182,6 +2269,7 @@ struct Launch {
         else subcell_t<double>(C, redo);
     }
     static void fluxcorr(const StepCtx &C, int count, int advance) {
+        static_assert(BIG_WG >= 512, "the flux correction's grid must fit the large-cell slots");
         const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(count >= 0 ? count : C.P.ncell, 512));
         if (C.precision == ADG_MIXED_DEV)
             hipLaunchKernelGGL((k_fluxcorr<DIM, N, float, true>), dim3(g), dim3(128), 0, C.stream, C.tab, C.P, C.B,
@@ -2224,6 +2312,11 @@ struct Launch {
     }
     template <typename R, bool DEV = false>
     static void batched_t(int stage, const BatchLaunch &L) {
+        // large cells are stepped problem by problem (a batch refuses them)
+        if constexpr (!BigCell<DIM, N>::on) batched_body<R, DEV>(stage, L);
+    }
+    template <typename R, bool DEV>
+    static void batched_body(int stage, const BatchLaunch &L) {
         const hipStream_t st = L.stream;
         switch (stage) {
         case BSTAGE_DT:
@@ -2295,6 +2388,7 @@ struct Ops {
     void (*pred_args)(const StepCtx &, PredArgs<float> *, PredArgs<double> *);
     int npos;
     int sub_wgs[2];   // workgroups of the persistent subcell launch that fill the chip (FP64, mixed form)
+    int64_t big_slot; // doubles per global scratch slot of large cells (0: the class works in LDS)
 };
 
 // the (d, N) instantiations, one group per translation unit (null outside the group)
@@ -2303,13 +2397,14 @@ const Ops *ops_2d_b(int N);   // d = 2, N = 4..5
 const Ops *ops_2d_c(int N);   // d = 2, N = 6..7
 const Ops *ops_2d_d(int N);   // d = 2, N = 8..9
 const Ops *ops_3d(int N);     // d = 3, N = 1..3
+const Ops *ops_3d_9(int N);   // d = 3, N = 9 (large cells)
 
 template <int DIM, int N>
 static Ops make_ops() {
     using L = Launch<DIM, N>;
     return Ops{L::predictor, L::faces, L::corrector_detect, L::bounds, L::subcell, L::fluxcorr, L::lambda,
                L::blocks, L::batched, L::pred_args, L::NPOS,
-               {256 * SubShape<DIM, N, double>::WPS, 256 * SubShape<DIM, N, float>::WPS}};
+               {256 * SubShape<DIM, N, double>::WPS, 256 * SubShape<DIM, N, float>::WPS}, BigCell<DIM, N>::SLOT};
 }
 
 }  // namespace adg

@@ -163,6 +163,9 @@ def main():
                          "(profiling runs)")
     ap.add_argument("--explosion3d-only", action="store_true",
                     help="only the 3D explosion at its full size, both forms (profiling runs)")
+    ap.add_argument("--explosion3d-p9-only", action="store_true",
+                    help="only the 3D explosion at N = 9 on 50^3 cells, both forms (profiling runs)")
+    ap.add_argument("--no-p9", action="store_true", help="skip the 3D explosion at N = 9 (50^3 cells)")
     ap.add_argument("--vortex-only", action="store_true",
                     help="only the vortex measurement (degree --N on --grid^2 cells), every form (profiling runs)")
     args = ap.parse_args()
@@ -172,6 +175,9 @@ def main():
         return
     if args.vortex_only:
         print(json.dumps(vortex_measurement(args.grid, args.N, args.vortex_steps)))
+        return
+    if args.explosion3d_p9_only:
+        print(json.dumps(explosion3d_p9_measurement()))
         return
 
     if args.convergence:
@@ -237,6 +243,8 @@ def main():
         out["vortex"] = vortex_measurement(args.grid, args.N, args.vortex_steps)
         if not args.no_3d:
             out["explosion3d"] = explosion3d_measurement(args.steps_3d)
+        if not args.no_p9:
+            out["explosion3d_p9"] = explosion3d_p9_measurement()
         # the other 2D workloads: the 2D explosion (40 x 40, N = 3), the double Mach reflection
         # at its full size (400 x 100, N = 5) and the shock-vortex interaction (200 x 100, N = 5)
         out["explosion2d"] = form_pair_measurement(W.explosion_2d(40, 3), 4, steps=50)
@@ -352,26 +360,28 @@ def form_pair_measurement(wl, m, steps, warmup=3):
     return res
 
 
-def explosion3d_measurement(steps, warmup=2, breakdown=2, ncell=128, N=3):
-    """The 3D explosion at its full size (128^3 cells on [-1,1]^3, N = 3): both precision
-    forms stepped at the CFL time step from the initial data (nodal interpolant, initial
-    detection against the subcell-centre values), `warmup` untimed steps, then `steps`
-    timed steps."""
+def explosion3d_measurement(steps, warmup=2, breakdown=2, ncell=128, N=3, detect=True, pool_div=8, note=""):
+    """The 3D explosion (cube [-1,1]^3, ncell^3 cells, degree N; by default its full size
+    128^3 at N = 3): both precision forms stepped at the CFL time step from the initial data
+    (nodal interpolant; with detect, the initial detection against the subcell-centre values,
+    else the first step's detection finds the cells the sphere cuts), `warmup` untimed steps,
+    then `steps` timed steps."""
     import torch
     from paper_1406_7416_amd import adg
     from paper_1406_7416_amd import workloads as W
     wl = W.explosion_3d(ncell, N)
     t0 = time.perf_counter()
     u0 = adg.project(wl, 0)[0]
-    v0 = adg.project(wl, 1)[1]
+    v0 = adg.project(wl, 1)[1] if detect else None
     t_init = time.perf_counter() - t0
     print(f"# explosion3d {ncell}^3 N={N}: initial data {t_init:.1f} s", file=sys.stderr, flush=True)
     st_dof = wl.st_dof_per_step()
     res = {"workload": f"3D explosion (Sec. 5), N={N}, {ncell}^3 cells on [-1,1]^3, transmissive, "
-                       f"CFL factor {wl.cfl}, Ns={2 * N + 1}",
+                       f"CFL factor {wl.cfl}, Ns={2 * N + 1}{note}",
            "cells": wl.num_cells, "st_dof_per_step": st_dof, "steps": steps, "warmup": warmup}
     for form, prec in (("fp64", adg.ADG_FP64), ("mixed", adg.ADG_MIXED)):
-        prob = adg.Problem(wl, precision=prec, pool_capacity=wl.num_cells // 8)
+        prob = adg.Problem(wl, precision=prec, pool_capacity=wl.num_cells // pool_div)
+        res["workspace_gb"] = prob.workspace_bytes / 1e9
         prob.set_state(u0, v0)
         troubled0 = int(prob.troubled().sum())
         for _ in range(warmup):
@@ -408,10 +418,22 @@ def explosion3d_measurement(steps, warmup=2, breakdown=2, ncell=128, N=3):
         prob.close()
         del prob
         torch.cuda.empty_cache()
-        print(f"# explosion3d {form}: {res[form]['value']:.3e} st-dof/s, {res[form]['ms_per_step']:.2f} ms/step, "
+        print(f"# explosion3d {ncell}^3 N={N} {form}: {res[form]['value']:.3e} st-dof/s, "
+              f"{res[form]['ms_per_step']:.2f} ms/step, "
               f"troubled {res[form]['troubled_last_step']}", file=sys.stderr, flush=True)
     res["speedup_mixed_vs_fp64"] = res["mixed"]["value"] / res["fp64"]["value"]
     return res
+
+
+def explosion3d_p9_measurement(steps=2, warmup=1, breakdown=1):
+    """The 3D explosion at N = 9 (Sec. 5's P9 run: 10^4 space-time nodes per cell and
+    variable, N_s = 19) on 50^3 cells: one eighth of the paper's 100^3-cell run, the share of
+    one GPU of eight under a Cartesian split.  Both precision forms, from the nodal initial
+    data with the initial detection against the subcell-centre values (at degree 9 the nodal
+    interpolant of the discontinuity oscillates too strongly for P(u) to be a usable start of
+    the subcell scheme in the cells the sphere cuts)."""
+    return explosion3d_measurement(steps, warmup=warmup, breakdown=breakdown, ncell=50, N=9, pool_div=4,
+                                   note="; one eighth of the 100^3-cell P9 run (one GPU's share of eight)")
 
 
 def copy_bandwidth_gbs(nbytes=1 << 30, reps=5):

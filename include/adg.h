@@ -108,8 +108,11 @@ typedef struct adg_problem adg_problem;
 
 const char *adg_last_error(void);
 
-/* Creates a problem (host side only).  N in 1..9; gamma > 1.  p may be NULL for
- * defaults.  Errors: ADG_EINVAL. */
+/* Creates a problem (host side only).  N in 1..9 for dim 2; 1..3 and 9 for dim 3 (the
+ * degrees of the paper's 3D runs; at N = 9, 19^3 subcells per cell, the per-cell arrays of the
+ * corrector, bounds, subcell and flux-correction kernels live in 512 per-workgroup slots of
+ * about 1.4 MB of the workspace instead of LDS); gamma > 1.  p may be NULL for defaults.
+ * Errors: ADG_EINVAL (other degrees included). */
 int adg_create(const adg_grid_desc *g, int N, double gamma, const adg_params *p, adg_problem **out);
 int adg_destroy(adg_problem *pb);
 
@@ -229,8 +232,9 @@ int adg_profile_read(adg_problem *pb, double *ms, int64_t *launches, int ngroups
 /* Batching of independent problems (not in the paper): the problems (each created and
  * bound as above, with a state set, all on the current device, none in another batch,
  * sharing precision, limiter and MOOD layer; grids, degrees, boundaries, flux and Picard
- * sweeps may differ) advance together; while the batch exists they are not stepped or
- * set on their own (adg_step, adg_step_cfl, adg_set_state return ADG_ESTATE).
+ * sweeps may differ; 3D problems of degree 9 are refused with ADG_EINVAL: they are stepped
+ * one by one) advance together; while the batch exists they are not stepped or set on their
+ * own (adg_step, adg_step_cfl, adg_set_state return ADG_ESTATE).
  * The problems are grouped into classes of equal (dim, N).  Every stage of the step is one
  * launch per class over all its problems: a tile table maps each workgroup to (problem,
  * block of that problem's own grid) for the time step, ghost-ring bounds, predictor, face

@@ -1088,6 +1088,149 @@ __device__ __forceinline__ void sub_halo_cell(const Tables *__restrict__ T, cons
     }
 }
 
+// S1 in 3D: the halo region by region.  The halo's 3^3 regions are the parts of the 3x3x3 block
+// of cells around the troubled cell that lie within three subcells of it (the cell itself,
+// three-subcell slabs of its face neighbours, bars of the edge neighbours, cubes of the corner
+// neighbours).  Each region has one source cell (the neighbour, its periodic image, the
+// interior cell a boundary ghost mirrors, or the fluid image of a solid cell), whose subcells
+// the region needs on a box; P(u^n) (eq. (subcell.p)) is sum-factorised over that box axis by
+// axis (x, then y, then z) instead of summed over the n^3 nodes at every halo point.  A source
+// cell troubled at the previous step gives its stored subcell data instead.  st: scratch of
+// NV (NS n^2 + NS^2 n) doubles for the first two stages.
+template <int N>
+__device__ __forceinline__ void sub_halo_cell3(const Tables *__restrict__ T, const Prob &P, const Bufs &B, int cur, int w,
+                                               double *halo, double *st) {
+    constexpr int DIM = 3, n = N + 1, NV = 5, NN = n * n * n;
+    constexpr int NS = 2 * N + 1, NSUB = NS * NS * NS, HN = NS + 6, HSZ = HN * HN * HN;
+    double *st1 = st, *st2 = st + NV * NS * n * n;
+    const int64_t c = B.tlist[w];
+    int ci[3];
+    coords_of(P, c, ci);
+    const double t0 = B.scal[1];
+    const double *u = B.u[cur];
+    for (int o = 0; o < 27; o++) {
+        const int off[3] = {o % 3 - 1, (o / 3) % 3 - 1, o / 9 - 1};
+        // the region's box of local subcell coordinates gs: the last three subcells of a
+        // neighbour below, all of the cell itself, the first three of a neighbour above
+        int glo[3], gn[3], gci[3], istep[3] = {0, 0, 0};
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            glo[j] = off[j] < 0 ? NS - 3 : 0;
+            gn[j] = off[j] == 0 ? NS : 3;
+            gci[j] = ci[j] + off[j];
+        }
+        // masked geometry: a solid cell holds the mirror image of the fluid across its walls
+        // (the image cell's subcells reversed along the mirrored axes, their momenta negated)
+        if (B.mask && solid_at<DIM>(P, B.mask, gci[0], gci[1], gci[2])) {
+            solid_image<DIM>(P, B.mask, gci, istep);
+#pragma unroll
+            for (int j = 0; j < 3; j++) gci[j] += istep[j];
+        }
+        // source cell; a non-periodic boundary mirrors the interior cell (gside: its side)
+        int src[3], mir[3], gside[3];
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            src[j] = gci[j];
+            mir[j] = 0;
+            gside[j] = -1;
+            if (gci[j] < 0 || gci[j] >= P.nc[j]) {
+                const int side = gci[j] >= P.nc[j];
+                if (P.periodic[j]) {
+                    src[j] = (gci[j] + P.nc[j]) % P.nc[j];
+                } else {
+                    src[j] = side ? 2 * P.nc[j] - 1 - gci[j] : -1 - gci[j];
+                    mir[j] = 1;
+                    gside[j] = side;
+                }
+            }
+        }
+        // source subcell ss = gs, reversed along an axis where exactly one of the image and the
+        // boundary mirror reverses it; the box of ss the region needs starts at sslo
+        int flip[3], sslo[3];
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            flip[j] = (istep[j] != 0) != (mir[j] != 0);
+            sslo[j] = flip[j] ? NS - glo[j] - gn[j] : glo[j];
+        }
+        const int64_t cs = cell_of(P, src);
+        const int slot = B.slot[0][cs];
+        const bool pooled = B.beta[0][cs] && slot >= 0;
+        if (!pooled) {
+            // stage 1 (x): st1[v][i0][a2][a1] = sum_a0 P[sslo0 + i0][a0] u[v][a0, a1, a2]
+            const int n1 = NV * gn[0] * n * n;
+            for (int it = threadIdx.x; it < n1; it += blockDim.x) {
+                const int a12 = it % (n * n), i0 = (it / (n * n)) % gn[0], v = it / (n * n * gn[0]);
+                const double *x = u + ((int64_t)v * P.ncell + cs) * NN + a12 * n;
+                const double *pr = T->P[sslo[0] + i0];
+                double acc = 0.0;
+#pragma unroll
+                for (int a0 = 0; a0 < n; a0++) acc += pr[a0] * x[a0];
+                st1[it] = acc;
+            }
+            __syncthreads();
+            // stage 2 (y): st2[v][i0][i1][a2] = sum_a1 P[sslo1 + i1][a1] st1[v][i0][a2][a1]
+            const int n2 = NV * gn[0] * gn[1] * n;
+            for (int it = threadIdx.x; it < n2; it += blockDim.x) {
+                const int a2 = it % n, i1 = (it / n) % gn[1], vi0 = it / (n * gn[1]);   // vi0 = v * gn0 + i0
+                const double *x = st1 + ((int64_t)vi0 * n + a2) * n;     // st1[v][i0][a2][a1], a1 fastest
+                const double *pr = T->P[sslo[1] + i1];
+                double acc = 0.0;
+#pragma unroll
+                for (int a1 = 0; a1 < n; a1++) acc += pr[a1] * x[a1];
+                st2[it] = acc;
+            }
+            __syncthreads();
+        }
+        // stage 3 (z) per halo point of the region, all variables, then the boundary rules
+        const int np = gn[0] * gn[1] * gn[2];
+        for (int it = threadIdx.x; it < np; it += blockDim.x) {
+            const int i[3] = {it % gn[0], (it / gn[0]) % gn[1], it / (gn[0] * gn[1])};
+            int ss[3], gsI[3], hl[3];
+#pragma unroll
+            for (int j = 0; j < 3; j++) {
+                ss[j] = sslo[j] + i[j];
+                gsI[j] = mir[j] ? NS - 1 - ss[j] : ss[j];                 // local coordinate in the (image) cell
+                const int gs0 = istep[j] ? NS - 1 - gsI[j] : gsI[j];      // in the halo's own cell
+                hl[j] = gs0 + off[j] * NS + 3;
+            }
+            double q[NV];
+            if (pooled) {
+                const int sidx = ss[0] + NS * (ss[1] + NS * ss[2]);
+#pragma unroll
+                for (int v = 0; v < NV; v++) q[v] = B.pool[0][((int64_t)slot * NV + v) * NSUB + sidx];
+            } else {
+                const double *pr = T->P[ss[2]];
+#pragma unroll
+                for (int v = 0; v < NV; v++) {
+                    const double *x = st2 + (((int64_t)v * gn[0] + i[0]) * gn[1] + i[1]) * n;
+                    double acc = 0.0;
+#pragma unroll
+                    for (int a2 = 0; a2 < n; a2++) acc += pr[a2] * x[a2];
+                    q[v] = acc;
+                }
+            }
+            double x[3];
+#pragma unroll
+            for (int j = 0; j < 3; j++) x[j] = P.lo[j] + P.h[j] * (gci[j] + (gsI[j] + 0.5) / NS);
+#pragma unroll
+            for (int j = 0; j < 3; j++) {
+                if (gside[j] < 0) continue;
+                double qo[NV];
+                bc_ghost<DIM>(P, j, gside[j], q, x[0], x[1], x[2], t0, qo);
+#pragma unroll
+                for (int v = 0; v < NV; v++) q[v] = qo[v];
+            }
+#pragma unroll
+            for (int j = 0; j < 3; j++)
+                if (istep[j]) q[1 + j] = -q[1 + j];
+            const int hidx = hl[0] + HN * (hl[1] + HN * hl[2]);
+#pragma unroll
+            for (int v = 0; v < NV; v++) halo[v * HSZ + hidx] = q[v];
+        }
+        __syncthreads();   // the stage buffers are reused by the next region
+    }
+}
+
 // One-dimensional WENO3 (degree 2, three stencils, lambda = 1, 1e5, 1, eps 1e-14, r 8):
 // five averages at offsets -2..2 -> values at the three GL nodes of the central subcell.
 __device__ __forceinline__ void weno3(const Tables *__restrict__ T, const double *a, double *out) {
@@ -1241,7 +1384,8 @@ template <int DIM, int N, typename R, bool REDO>
 __device__ __forceinline__ void sub_update_cell(const Tables *__restrict__ T, const Prob &P, const Bufs &B, int cur,
                                                 int w, int sidx, const SubScratch &S, int *nonphys, const double *halo,
                                                 int flagging,
-                                                const double (*mb)[DIM + 2], const int (*nslot)[2]) {
+                                                const double (*mb)[DIM + 2], const int (*nslot)[2],
+                                                unsigned char *fbt) {
     constexpr int n = N + 1, NV = DIM + 2, NN = cpow(n, DIM);
     constexpr int NS = 2 * N + 1, NSUB = cpow(NS, DIM), NSF = cpow(NS, DIM - 1), HN = NS + 6, HSZ = cpow(HN, DIM);
     constexpr int NPOS = NSUB + 2 * DIM * NSF, NF3 = cpow(3, DIM - 1);
@@ -1262,7 +1406,7 @@ __device__ __forceinline__ void sub_update_cell(const Tables *__restrict__ T, co
         vn = slot + BC::SUB_VN;
         ug = slot + BC::SUB_UG;
     } else {
-        __shared__ __align__(16) unsigned char fbt[FBB > TMB ? FBB : TMB];
+        // fbt: LDS of FBB > TMB ? FBB : TMB bytes (declared by the caller)
         __shared__ double vn_[NV * BIG];
         __shared__ double ug_[NV * BIG];
         Fb = reinterpret_cast<R *>(fbt);
@@ -1509,21 +1653,46 @@ __device__ __forceinline__ void sub_update_cell(const Tables *__restrict__ T, co
     // node a of the DG basis, the integral of the subcell flux times phi_a over the face,
     // divided by the face weight w_a, from the per-point fluxes (3 Gauss-Legendre points per
     // sub-face and tangential axis; Pq[s*3+g][a] = (w3_g / Ns) phi_a((s + xi3_g) / Ns) / w_a).
-    for (int it = threadIdx.x; it < 2 * DIM * NV * NFN; it += SUB_BS) {
-        const int face = it / (NV * NFN), v = (it / NFN) % NV, a = it % NFN;
-        const int a0 = a % n, a1 = a / n;
-        const double *fq = S.fpts + ((int64_t)ch * 2 * DIM + face) * NV * QF + v * QF;
-        double acc = 0.0;
-        for (int ms1 = 0; ms1 < (DIM == 3 ? NS : 1); ms1++)
-            for (int ms0 = 0; ms0 < NS; ms0++)
-                for (int g1 = 0; g1 < (DIM == 3 ? 3 : 1); g1++)
-                    for (int g0 = 0; g0 < 3; g0++) {
-                        const int q0 = ms0 * 3 + g0, q1 = ms1 * 3 + g1;
-                        double wgt = T->Pq[q0][a0];
-                        if (DIM == 3) wgt *= T->Pq[q1][a1];
-                        acc += wgt * fq[q0 + 3 * NS * q1];
-                    }
-        B.sflux[(int64_t)slot * 2 * DIM * NV * NFN + it] = acc;
+    // For large cells the double sum over the face's (3 Ns)^2 = 3249 points is sum-factorised
+    // (first along the first tangential axis for every node a0 and point row q1, then along the
+    // second; 8.5x fewer operations), its intermediate in the slot's sub-face flux region, which
+    // the FV update has read.  (At N = 3 the 441-point sums cost less than the extra barriers.)
+    constexpr int QS = 3 * NS, FCT = 2 * DIM * NV * n * QS;
+    if constexpr (BigCell<DIM, N>::on) {
+        static_assert(FCT <= BigCell<DIM, N>::SUB_VN, "the stage must fit the sub-face flux region");
+        __syncthreads();
+        for (int it = threadIdx.x; it < FCT; it += SUB_BS) {
+            const int a0 = it % n, q1 = (it / n) % QS, fv = it / (n * QS);   // fv = face * NV + v
+            const double *fq = S.fpts + ((int64_t)ch * 2 * DIM * NV + fv) * QF + QS * q1;
+            double acc = 0.0;
+            for (int q0 = 0; q0 < QS; q0++) acc += T->Pq[q0][a0] * fq[q0];
+            tmp[((int64_t)fv * n + a0) * QS + q1] = acc;
+        }
+        __syncthreads();
+        for (int it = threadIdx.x; it < 2 * DIM * NV * NFN; it += SUB_BS) {
+            const int fv = it / NFN, a = it % NFN, a0 = a % n, a1 = a / n;
+            const double *x = tmp + ((int64_t)fv * n + a0) * QS;
+            double acc = 0.0;
+            for (int q1 = 0; q1 < QS; q1++) acc += T->Pq[q1][a1] * x[q1];
+            B.sflux[(int64_t)slot * 2 * DIM * NV * NFN + it] = acc;
+        }
+    } else {
+        for (int it = threadIdx.x; it < 2 * DIM * NV * NFN; it += SUB_BS) {
+            const int face = it / (NV * NFN), v = (it / NFN) % NV, a = it % NFN;
+            const int a0 = a % n, a1 = a / n;
+            const double *fq = S.fpts + ((int64_t)ch * 2 * DIM + face) * NV * QF + v * QF;
+            double acc = 0.0;
+            for (int ms1 = 0; ms1 < (DIM == 3 ? NS : 1); ms1++)
+                for (int ms0 = 0; ms0 < NS; ms0++)
+                    for (int g1 = 0; g1 < (DIM == 3 ? 3 : 1); g1++)
+                        for (int g0 = 0; g0 < 3; g0++) {
+                            const int q0 = ms0 * 3 + g0, q1 = ms1 * 3 + g1;
+                            double wgt = T->Pq[q0][a0];
+                            if (DIM == 3) wgt *= T->Pq[q1][a1];
+                            acc += wgt * fq[q0 + 3 * NS * q1];
+                        }
+            B.sflux[(int64_t)slot * 2 * DIM * NV * NFN + it] = acc;
+        }
     }
     __syncthreads();
     store_cell_bounds<NV>(P, B, c, vn, NSUB, threadIdx.x, SUB_BS, red);
@@ -1717,6 +1886,17 @@ __device__ __forceinline__ void subcell_cell(const Tables *__restrict__ T, const
     __shared__ int nslot[3][2];       // pool slots of troubled face neighbours (MOOD recompute)
     double *halo = (DIM == 2) ? halo_s : S.halo + (int64_t)sidx * NV * HSZ;
     double *nbu = (DIM == 2) ? nbu_s : nullptr;
+    // LDS of the update's sub-face fluxes and of the gather's intermediate stage (large cells:
+    // their global slot); in 3D the halo's sum-factorisation stages use it first
+    constexpr int n = N + 1, NN = cpow(n, DIM), BIGN = NSUB > NN ? NSUB : NN;
+    constexpr int FBB = DIM * (NS + 1) * NSF * NV * (int)sizeof(R), TMB = NV * BIGN * 8;
+    constexpr int FBT = FBB > TMB ? FBB : TMB;
+    __shared__ __align__(16) unsigned char fbt[BigCell<DIM, N>::on ? 16 : FBT];
+    static_assert(DIM == 2 || BigCell<DIM, N>::on || (NV * NS * n * n + NV * NS * NS * n) * 8 <= FBT,
+                  "the 3D halo's stage buffers must fit the sub-face flux LDS");
+    static_assert(!BigCell<DIM, N>::on || NV * NS * n * n + NV * NS * NS * n <= BigCell<DIM, N>::SUB_VN,
+                  "the 3D halo's stage buffers must fit the slot's sub-face flux region");
+    double *hst = BigCell<DIM, N>::on ? S.big + (int64_t)sidx * BigCell<DIM, N>::SLOT : reinterpret_cast<double *>(fbt);
     {
         const int64_t c = B.tlist[w];
         if (!REDO && flagging) {
@@ -1790,13 +1970,14 @@ __device__ __forceinline__ void subcell_cell(const Tables *__restrict__ T, const
             if (!__syncthreads_or(any)) return;
             if (threadIdx.x == 0) atomicAdd(&B.counts[6], 1);
         }
-        sub_halo_cell<DIM, N>(T, P, B, cur, w, halo, nbu);
+        if constexpr (DIM == 3) sub_halo_cell3<N>(T, P, B, cur, w, halo, hst);
+        else sub_halo_cell<DIM, N>(T, P, B, cur, w, halo, nbu);
         __syncthreads();
         sub_recon_cell<DIM, N, R>(T, S.Y, sidx, halo);
         __syncthreads();
         sub_predictor<DIM, R>(T, Ys, trs, NPOS, NSUB, NSF, dt, dth, P.gamma);
         __syncthreads();
-        sub_update_cell<DIM, N, R, REDO>(T, P, B, cur, w, sidx, S, nonphys, halo, REDO ? 0 : flagging, mb, nslot);
+        sub_update_cell<DIM, N, R, REDO>(T, P, B, cur, w, sidx, S, nonphys, halo, REDO ? 0 : flagging, mb, nslot, fbt);
     }
 }
 

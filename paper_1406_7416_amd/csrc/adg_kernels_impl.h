@@ -1757,13 +1757,18 @@ __device__ void sub_predictor(const Tables *__restrict__ T, const R *__restrict_
         for (int v = 0; v < NV; v++)
 #pragma unroll
             for (int s = 0; s < 3; s++) q[v][s] = u0[v];
+        // Three Picard sweeps.  The first starts from u^n at every time node, so its fluxes and
+        // their derivatives are the same on the three time slices: slice 0 is computed and
+        // copied (nt: time slices computed, uniform over the wave).
         for (int r = 0; r < 3; r++) {
+            const int nt = r == 0 ? 1 : 3;
             R S[NV][3];
 #pragma unroll
             for (int k = 0; k < DIM; k++) {
                 R F[NV][3];
 #pragma unroll
                 for (int t = 0; t < 3; t++) {
+                    if (t >= nt) break;
                     const R ir = recip(q[0][t]);
                     const R un = q[1 + k][t] * ir;
                     R ke = 0;
@@ -1779,20 +1784,27 @@ __device__ void sub_predictor(const Tables *__restrict__ T, const R *__restrict_
                 // all lane permutations of the axis first (independent, in flight together)
                 R g1[NV][3], g2[NV][3], x[NV][3];
 #pragma unroll
-                for (int v = 0; v < NV; v++)
+                for (int t = 0; t < 3; t++) {
+                    if (t >= nt) break;
 #pragma unroll
-                    for (int t = 0; t < 3; t++) {
+                    for (int v = 0; v < NV; v++) {
                         g1[v][t] = __shfl(F[v][t], src1[k]);
                         g2[v][t] = __shfl(F[v][t], src2[k]);
                     }
+                }
 #pragma unroll
-                for (int v = 0; v < NV; v++)
+                for (int t = 0; t < 3; t++) {
+                    if (t >= nt) break;
 #pragma unroll
-                    for (int t = 0; t < 3; t++) x[v][t] = Dk[k][0] * F[v][t] + Dk[k][1] * g1[v][t] + Dk[k][2] * g2[v][t];
+                    for (int v = 0; v < NV; v++) {
+                        x[v][t] = Dk[k][0] * F[v][t] + Dk[k][1] * g1[v][t] + Dk[k][2] * g2[v][t];
+                        S[v][t] = (k == 0) ? ck[k] * x[v][t] : S[v][t] + ck[k] * x[v][t];
+                    }
+                }
+            }
+            if (nt == 1) {
 #pragma unroll
-                for (int v = 0; v < NV; v++)
-#pragma unroll
-                    for (int t = 0; t < 3; t++) S[v][t] = (k == 0) ? ck[k] * x[v][t] : S[v][t] + ck[k] * x[v][t];
+                for (int v = 0; v < NV; v++) S[v][1] = S[v][2] = S[v][0];
             }
             // time contraction K1^{-1} diag(w)
 #pragma unroll

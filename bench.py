@@ -40,9 +40,9 @@ PEAK_HBM_GBS = 8000.0
 # (launch "stage:N<degree>" -> (bytes per launch, source hash prefix)); copy calibration: a 256 MiB
 # copy reads FETCH_SIZE = 131,084 KiB (factor 2.0) and writes WRITE_SIZE = 262,144 KiB (factor 1.0)
 TRAFFIC = {
-    "predictor:N5": (10799367680, "8fbf60372f9de7c1"),
-    "subcell:N5": (22144924672, "8fbf60372f9de7c1"),
-    "corrector_detect:N5": (6559392768, "8fbf60372f9de7c1"),
+    "predictor:N5": (10796308480, "a2e6916de4558d2d"),
+    "subcell:N5": (22127721920, "a2e6916de4558d2d"),
+    "corrector_detect:N5": (6559404032, "a2e6916de4558d2d"),
 }
 # the kernel sources and the tile-parameter table the build compiles them with
 KERNEL_SOURCES = ("csrc/adg_internal.h", "csrc/adg_tune.h", "csrc/adg_physics.h", "csrc/adg_device.h",

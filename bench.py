@@ -244,7 +244,7 @@ def main():
         if not args.no_3d:
             out["explosion3d"] = explosion3d_measurement(args.steps_3d)
         if not args.no_p9:
-            out["explosion3d_p9"] = explosion3d_p9_measurement()
+            out["explosion3d_p9"] = explosion3d_p9_measurement(cpu=not args.no_cpu_baseline)
         # the other 2D workloads: the 2D explosion (40 x 40, N = 3), the double Mach reflection
         # at its full size (400 x 100, N = 5) and the shock-vortex interaction (200 x 100, N = 5)
         out["explosion2d"] = form_pair_measurement(W.explosion_2d(40, 3), 4, steps=50)
@@ -425,15 +425,42 @@ def explosion3d_measurement(steps, warmup=2, breakdown=2, ncell=128, N=3, detect
     return res
 
 
-def explosion3d_p9_measurement(steps=2, warmup=1, breakdown=1):
+def explosion3d_p9_measurement(steps=2, warmup=1, breakdown=1, cpu=False):
     """The 3D explosion at N = 9 (Sec. 5's P9 run: 10^4 space-time nodes per cell and
     variable, N_s = 19) on 50^3 cells: one eighth of the paper's 100^3-cell run, the share of
     one GPU of eight under a Cartesian split.  Both precision forms, from the nodal initial
     data with the initial detection against the subcell-centre values (at degree 9 the nodal
     interpolant of the discontinuity oscillates too strongly for P(u) to be a usable start of
     the subcell scheme in the cells the sphere cuts)."""
-    return explosion3d_measurement(steps, warmup=warmup, breakdown=breakdown, ncell=50, N=9, pool_div=4,
-                                   note="; one eighth of the 100^3-cell P9 run (one GPU's share of eight)")
+    res = explosion3d_measurement(steps, warmup=warmup, breakdown=breakdown, ncell=50, N=9, pool_div=4,
+                                  note="; one eighth of the 100^3-cell P9 run (one GPU's share of eight)")
+    if cpu:
+        res["cpu_oracle"] = p9_oracle_sample()
+    return res
+
+
+def p9_oracle_sample(nw=5, origin=(35, 22, 22)):
+    """The FP64 CPU oracle on a sample of the 50^3, N = 9 explosion: one step of an nw^3-cell
+    window of the same grid cut on the sphere (same h and initial data, initial detection,
+    transmissive sides), all host threads."""
+    from oracle import oracle as O
+    from paper_1406_7416_amd import workloads as W
+    h = 2.0 / 50
+    lo = tuple(-1.0 + i * h for i in origin)
+    hi = tuple(l + nw * h for l in lo)
+    bc = (W.BC.simple(W.TRANSMISSIVE), W.BC.simple(W.TRANSMISSIVE))
+    ww = W.Workload("explosion3d-window", 3, 9, (nw,) * 3, lo, hi, [bc] * 3, W.explosion_ic(3))
+    o = O.Oracle(ww)
+    u, v = o.project(ww.ic, 0)[0], o.project(ww.ic, 1)[1]
+    o.set_state(u, v)
+    t0 = time.perf_counter()
+    o.step(o.cfl_dt())
+    el = time.perf_counter() - t0
+    threads = O.get_threads()
+    return {"value": ww.st_dof_per_step() / el, "unit": "st-dof/s", "cores": threads, "kind": "oracle",
+            "sample": f"one step of a {nw}^3-cell window of the 50^3 grid on the sphere (cells {origin} on), "
+                      f"{int(o.troubled().sum())} of {nw ** 3} cells troubled after it; {el:.1f} s, "
+                      f"OpenMP threads={threads}"}
 
 
 def copy_bandwidth_gbs(nbytes=1 << 30, reps=5):

@@ -407,6 +407,9 @@ def explosion3d_measurement(steps, warmup=2, breakdown=2, ncell=128, N=3, detect
             "ms_per_step": 1e3 * elapsed / steps,
             "predictor_avg_us": 1e6 * pred_s,
             "predictor_tflops": predictor_flops_per_cell(3, N) * wl.num_cells / pred_s / 1e12,
+            # against the published peak of the form's working precision (FP32 157.3, FP64 78.6 TFLOP/s)
+            "predictor_frac": predictor_flops_per_cell(3, N) * wl.num_cells / pred_s / 1e12
+                              / (157.3 if prec == adg.ADG_MIXED else 78.6),
             "kernels": {g: {"ms_total": round(ms, 4), "launches": n, "avg_us": round(1e3 * ms / n, 3) if n else None}
                         for g, (ms, n) in prof.items()},
             "face_kernel_gbs": (wl.num_cells * 2 * 3 * 5 * ((N + 1) ** 3 + (N + 1) ** 2) * (4 if prec == adg.ADG_MIXED else 8)

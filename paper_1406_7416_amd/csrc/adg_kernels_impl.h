@@ -1308,16 +1308,18 @@ __device__ __forceinline__ void weno3(const Tables *__restrict__ T, const float 
 // the 3^d GL points of the subcell (x sweep on the averages, then y (then z) sweeps on
 // the nodal values of the previous sweep).  One work item per (position, variable).
 template <int DIM, int N, typename R>
-__device__ __forceinline__ void sub_recon_cell(const Tables *__restrict__ T, double *Yscratch, int sidx, const double *halo) {
+__device__ __forceinline__ void sub_recon_cell(const Tables *__restrict__ T, double *Yscratch, int sidx, const double *halo,
+                                               R *stg) {
     constexpr int NV = DIM + 2, NS = 2 * N + 1, HN = NS + 6, HSZ = cpow(HN, DIM);
     constexpr int NPOS = cpow(NS, DIM) + 2 * DIM * cpow(NS, DIM - 1), N3 = cpow(3, DIM);
-    for (int item = threadIdx.x; item < NPOS * NV; item += blockDim.x) {
-        const int v = item / NPOS, pos = item % NPOS;
-        int L[3];
-        position_coords<DIM>(pos, NS, L);
-        const double *h = halo + v * HSZ;
-        R *Y = reinterpret_cast<R *>(Yscratch) + ((int64_t)sidx * NPOS + pos) * NV * N3 + v * N3;
-        if constexpr (DIM == 2) {
+    if constexpr (DIM == 2) {
+        (void)stg;
+        for (int item = threadIdx.x; item < NPOS * NV; item += blockDim.x) {
+            const int v = item / NPOS, pos = item % NPOS;
+            int L[3];
+            position_coords<DIM>(pos, NS, L);
+            const double *h = halo + v * HSZ;
+            R *Y = reinterpret_cast<R *>(Yscratch) + ((int64_t)sidx * NPOS + pos) * NV * N3 + v * N3;
             // x sweep on the five rows of the 5 x 5 stencil, then y sweep per x node
             R w1[5][3];
 #pragma unroll
@@ -1336,41 +1338,55 @@ __device__ __forceinline__ void sub_recon_cell(const Tables *__restrict__ T, dou
 #pragma unroll
                 for (int qy = 0; qy < 3; qy++) Y[qy * 3 + qx] = o3[qy];
             }
-        } else {
-            // plane by plane in z: x sweep on the five rows of the plane, y sweep per x node;
-            // then the z sweep per (y node, x node)
-            R w2[5][3][3];   // [z][qy][qx]
+        }
+    } else {
+        // 3D: the sweeps are shared between positions.  x sweep of every halo row at the x
+        // coordinates of the positions (-1 .. Ns), then the y sweep per x node at their (x, y)
+        // coordinates, both into stg; then per position the z sweep per (y, x) node.  The same
+        // WENO3 evaluations on the same values as one position at a time (three times fewer).
+        constexpr int NI = NS + 2;
+        static_assert((int64_t)NV * NI * HN * HN * 3 + (int64_t)NV * NI * NI * HN * 9 <=
+                          (int64_t)NPOS * 2 * DIM * NV * cpow(3, DIM - 1) * 3,
+                      "the sweeps' intermediates must fit the slot's trace storage");
+        R *vx = stg;                                           // [v][i][kh][jh][qx]
+        R *vxy = stg + (int64_t)NV * NI * HN * HN * 3;         // [v][i][j][kh][qy][qx]
+        for (int it = threadIdx.x; it < NV * NI * HN * HN; it += blockDim.x) {
+            const int jh = it % HN, kh = (it / HN) % HN, i = (it / (HN * HN)) % NI, v = it / (HN * HN * NI);
+            const double *h = halo + (int64_t)v * HSZ + (kh * HN + jh) * HN + i;
+            R a5[5], o3[3];
 #pragma unroll
-            for (int z = 0; z < 5; z++) {
-                R w1[5][3];
+            for (int o = 0; o < 5; o++) a5[o] = (R)h[o];
+            weno3(T, a5, o3);
 #pragma unroll
-                for (int y = 0; y < 5; y++) {
-                    R a5[5];
+            for (int q = 0; q < 3; q++) vx[(int64_t)it * 3 + q] = o3[q];
+        }
+        __syncthreads();
+        for (int it = threadIdx.x; it < NV * NI * NI * HN * 3; it += blockDim.x) {
+            const int qx = it % 3, kh = (it / 3) % HN, j = (it / (3 * HN)) % NI;
+            const int i = (it / (3 * HN * NI)) % NI, v = it / (3 * HN * NI * NI);
+            const R *src = vx + ((((int64_t)v * NI + i) * HN + kh) * HN + j) * 3 + qx;
+            R a5[5], o3[3];
 #pragma unroll
-                    for (int o = 0; o < 5; o++) a5[o] = (R)h[((L[2] + z + 1) * HN + (L[1] + y + 1)) * HN + (L[0] + o + 1)];
-                    weno3(T, a5, w1[y]);
-                }
+            for (int y = 0; y < 5; y++) a5[y] = src[y * 3];
+            weno3(T, a5, o3);
+            R *dst = vxy + ((((int64_t)v * NI + i) * NI + j) * HN + kh) * 9 + qx;
 #pragma unroll
-                for (int qx = 0; qx < 3; qx++) {
-                    R a5[5], o3[3];
+            for (int qy = 0; qy < 3; qy++) dst[qy * 3] = o3[qy];
+        }
+        __syncthreads();
+        for (int it = threadIdx.x; it < NPOS * NV * 9; it += blockDim.x) {
+            const int qq = it % 9, item = it / 9;
+            const int v = item / NPOS, pos = item % NPOS;
+            int L[3];
+            position_coords<DIM>(pos, NS, L);
+            const R *src = vxy + ((((int64_t)v * NI + (L[0] + 1)) * NI + (L[1] + 1)) * HN + (L[2] + 1)) * 9 + qq;
+            R a5[5], o3[3];
 #pragma unroll
-                    for (int y = 0; y < 5; y++) a5[y] = w1[y][qx];
-                    weno3(T, a5, o3);
+            for (int z = 0; z < 5; z++) a5[z] = src[z * 9];
+            weno3(T, a5, o3);
+            R *Y = reinterpret_cast<R *>(Yscratch) + ((int64_t)sidx * NPOS + pos) * NV * N3 + v * N3 + qq;
 #pragma unroll
-                    for (int qy = 0; qy < 3; qy++) w2[z][qy][qx] = o3[qy];
-                }
-            }
-#pragma unroll
-            for (int qy = 0; qy < 3; qy++)
-#pragma unroll
-                for (int qx = 0; qx < 3; qx++) {
-                    R a5[5], o3[3];
-#pragma unroll
-                    for (int z = 0; z < 5; z++) a5[z] = w2[z][qy][qx];
-                    weno3(T, a5, o3);
-#pragma unroll
-                    for (int qz = 0; qz < 3; qz++) Y[(qz * 3 + qy) * 3 + qx] = o3[qz];
-                }
+            for (int qz = 0; qz < 3; qz++) Y[qz * 9] = o3[qz];
         }
     }
 }
@@ -1985,7 +2001,7 @@ __device__ __forceinline__ void subcell_cell(const Tables *__restrict__ T, const
         if constexpr (DIM == 3) sub_halo_cell3<N>(T, P, B, cur, w, halo, hst);
         else sub_halo_cell<DIM, N>(T, P, B, cur, w, halo, nbu);
         __syncthreads();
-        sub_recon_cell<DIM, N, R>(T, S.Y, sidx, halo);
+        sub_recon_cell<DIM, N, R>(T, S.Y, sidx, halo, trs);
         __syncthreads();
         sub_predictor<DIM, R>(T, Ys, trs, NPOS, NSUB, NSF, dt, dth, P.gamma);
         __syncthreads();

@@ -40,9 +40,9 @@ PEAK_HBM_GBS = 8000.0
 # (launch "stage:N<degree>" -> (bytes per launch, source hash prefix)); copy calibration: a 256 MiB
 # copy reads FETCH_SIZE = 131,084 KiB (factor 2.0) and writes WRITE_SIZE = 262,144 KiB (factor 1.0)
 TRAFFIC = {
-    "predictor:N5": (10796308480, "a2e6916de4558d2d"),
-    "subcell:N5": (22127721920, "a2e6916de4558d2d"),
-    "corrector_detect:N5": (6559404032, "a2e6916de4558d2d"),
+    "predictor:N5": (10797208064, "e097ea857da0de8b"),
+    "subcell:N5": (22133512533, "e097ea857da0de8b"),
+    "corrector_detect:N5": (6559403520, "e097ea857da0de8b"),
 }
 # the kernel sources and the tile-parameter table the build compiles them with
 KERNEL_SOURCES = ("csrc/adg_internal.h", "csrc/adg_tune.h", "csrc/adg_physics.h", "csrc/adg_device.h",

@@ -1729,9 +1729,10 @@ __device__ __forceinline__ void sub_update_cell(const Tables *__restrict__ T, co
 // the line by lane permutation, so the waves work without LDS or workgroup barriers.
 // Output: the face traces of every position, [pos][2d][v][3^(d-1) tangential x 3 time],
 // in the working precision R (FP32 in the mixed form).
-template <int DIM, typename R>
+template <int DIM, typename R, bool XCH = false>
 __device__ void sub_predictor(const Tables *__restrict__ T, const R *__restrict__ Y, R *__restrict__ tr,
-                              int npos, int nsub, int nsf, double dt, const double *dth, double gamma_d) {
+                              int npos, int nsub, int nsf, double dt, const double *dth, double gamma_d,
+                              R *xch = nullptr) {
     constexpr int NV = DIM + 2, NN = cpow(3, DIM), NF = cpow(3, DIM - 1), PPW = 64 / NN;
     constexpr int TRS = 2 * DIM * NV * NF * 3;
     constexpr int ST[3] = {1, 3, 9};
@@ -1797,15 +1798,44 @@ __device__ void sub_predictor(const Tables *__restrict__ T, const R *__restrict_
                     F[NV - 1][t] = un * (q[NV - 1][t] + prt);
                 }
                 // sum_b D[a_k][b] F(node b of the line): own node, then (ia + 1) % 3, (ia + 2) % 3
-                // all lane permutations of the axis first (independent, in flight together)
+                // all lane permutations of the axis first (independent, in flight together); with an
+                // exchange buffer (3D), through the wave's own LDS rows instead: each lane writes its
+                // fluxes once and reads those of its two line neighbours
                 R g1[NV][3], g2[NV][3], x[NV][3];
+                if constexpr (XCH) {
+                    R *xw = xch + (int64_t)wv * 64 * NV * 3;
 #pragma unroll
-                for (int t = 0; t < 3; t++) {
-                    if (t >= nt) break;
+                    for (int v = 0; v < NV; v++)
 #pragma unroll
-                    for (int v = 0; v < NV; v++) {
-                        g1[v][t] = __shfl(F[v][t], src1[k]);
-                        g2[v][t] = __shfl(F[v][t], src2[k]);
+                        for (int t = 0; t < 3; t++)
+                            if (t < nt) xw[lane * (NV * 3) + v * 3 + t] = F[v][t];
+                    // lanes of one wave only: order the writes before the reads at wave scope
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+                    for (int v = 0; v < NV; v++)
+#pragma unroll
+                        for (int t = 0; t < 3; t++)
+                            if (t < nt) {
+                                // (source lanes taken mod 64 as a lane permutation takes them: the
+                                // idle lanes past the last position stay within the wave's rows)
+                                g1[v][t] = xw[(src1[k] & 63) * (NV * 3) + v * 3 + t];
+                                g2[v][t] = xw[(src2[k] & 63) * (NV * 3) + v * 3 + t];
+                            }
+                    // the next axis overwrites the rows only after every lane has read them
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                } else {
+#pragma unroll
+                    for (int t = 0; t < 3; t++) {
+                        if (t >= nt) break;
+#pragma unroll
+                        for (int v = 0; v < NV; v++) {
+                            g1[v][t] = __shfl(F[v][t], src1[k]);
+                            g2[v][t] = __shfl(F[v][t], src2[k]);
+                        }
                     }
                 }
 #pragma unroll
@@ -2003,7 +2033,10 @@ __device__ __forceinline__ void subcell_cell(const Tables *__restrict__ T, const
         __syncthreads();
         sub_recon_cell<DIM, N, R>(T, S.Y, sidx, halo, trs);
         __syncthreads();
-        sub_predictor<DIM, R>(T, Ys, trs, NPOS, NSUB, NSF, dt, dth, P.gamma);
+        // 3D (not large cells, where the rows fit): the line exchange of the predictor through the
+        // flux LDS, free in this phase
+        constexpr bool XCH = DIM == 3 && !BigCell<DIM, N>::on && (SUB_BS / 64) * 64 * NV * 3 * (int)sizeof(R) <= FBT;
+        sub_predictor<DIM, R, XCH>(T, Ys, trs, NPOS, NSUB, NSF, dt, dth, P.gamma, reinterpret_cast<R *>(fbt));
         __syncthreads();
         sub_update_cell<DIM, N, R, REDO>(T, P, B, cur, w, sidx, S, nonphys, halo, REDO ? 0 : flagging, mb, nslot, fbt);
     }

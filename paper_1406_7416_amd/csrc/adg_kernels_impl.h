@@ -1869,7 +1869,18 @@ __device__ void sub_predictor(const Tables *__restrict__ T, const R *__restrict_
             }
         }
         // face traces: the lane at the low end of a line writes the xi_k = 0 trace, the lane
-        // at the high end the xi_k = 1 trace
+        // at the high end the xi_k = 1 trace (with the exchange buffer, the pencils are written
+        // once for the three axes)
+        R *xq = xch + (int64_t)wv * 64 * NV * 3;
+        if constexpr (XCH) {
+#pragma unroll
+            for (int v = 0; v < NV; v++)
+#pragma unroll
+                for (int s = 0; s < 3; s++) xq[lane * (NV * 3) + v * 3 + s] = q[v][s];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
 #pragma unroll
         for (int k = 0; k < DIM; k++) {
             // the line's three nodes in this lane's order: own, (ia + 1) % 3, (ia + 2) % 3
@@ -1879,8 +1890,13 @@ __device__ void sub_predictor(const Tables *__restrict__ T, const R *__restrict_
 #pragma unroll
                 for (int s = 0; s < 3; s++) {
                     qb[0][v][s] = q[v][s];
-                    qb[1][v][s] = __shfl(q[v][s], src1[k]);
-                    qb[2][v][s] = __shfl(q[v][s], src2[k]);
+                    if constexpr (XCH) {
+                        qb[1][v][s] = xq[(src1[k] & 63) * (NV * 3) + v * 3 + s];
+                        qb[2][v][s] = xq[(src2[k] & 63) * (NV * 3) + v * 3 + s];
+                    } else {
+                        qb[1][v][s] = __shfl(q[v][s], src1[k]);
+                        qb[2][v][s] = __shfl(q[v][s], src2[k]);
+                    }
                 }
             // a neighbour-layer position (pos >= nsub) only needs the trace on its face toward
             // the cell: the + face of the low layer, the - face of the high layer
@@ -1911,6 +1927,12 @@ __device__ void sub_predictor(const Tables *__restrict__ T, const R *__restrict_
                         o[v * NF * 3 + ap + NF * s] = acc;
                     }
             }
+        }
+        if constexpr (XCH) {
+            // the next positions' sweep overwrites the rows only after every lane has read them
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
     }
 }

@@ -1961,7 +1961,9 @@ __device__ __forceinline__ void subcell_cell(const Tables *__restrict__ T, const
     // 2D: the halo and the source cells' coefficients live in LDS; 3D: halo in HBM scratch
     constexpr int HSZ = cpow(NS + 6, DIM), NNS = cpow(N + 1, DIM);
     __shared__ double halo_s[DIM == 2 ? NV * HSZ : 1];
-    __shared__ double nbu_s[DIM == 2 ? 9 * NV * NNS : 1];
+    // 2D: the source cells' coefficients of the halo, later the predictor's line-exchange rows
+    constexpr int XROWS = (SUB_BS / 64) * 64 * NV * 3 * (int)sizeof(R) / 8;   // doubles
+    __shared__ double nbu_s[DIM == 2 ? (9 * NV * NNS > XROWS ? 9 * NV * NNS : XROWS) : 1];
     __shared__ double mb[2][NV];      // m_i, M_i of eq. (dmp) (MOOD flags)
     __shared__ int nslot[3][2];       // pool slots of troubled face neighbours (MOOD recompute)
     double *halo = (DIM == 2) ? halo_s : S.halo + (int64_t)sidx * NV * HSZ;
@@ -2055,10 +2057,11 @@ __device__ __forceinline__ void subcell_cell(const Tables *__restrict__ T, const
         __syncthreads();
         sub_recon_cell<DIM, N, R>(T, S.Y, sidx, halo, trs);
         __syncthreads();
-        // 3D (not large cells, where the rows fit): the line exchange of the predictor through the
-        // flux LDS, free in this phase
-        constexpr bool XCH = DIM == 3 && !BigCell<DIM, N>::on && (SUB_BS / 64) * 64 * NV * 3 * (int)sizeof(R) <= FBT;
-        sub_predictor<DIM, R, XCH>(T, Ys, trs, NPOS, NSUB, NSF, dt, dth, P.gamma, reinterpret_cast<R *>(fbt));
+        // the line exchange of the predictor through LDS rows (free in this phase): in 2D the halo's
+        // staging LDS, in 3D the flux LDS where the rows fit (not for large cells)
+        constexpr bool XCH = DIM == 2 || (!BigCell<DIM, N>::on && (SUB_BS / 64) * 64 * NV * 3 * (int)sizeof(R) <= FBT);
+        R *xrows = DIM == 2 ? reinterpret_cast<R *>(nbu_s) : reinterpret_cast<R *>(fbt);
+        sub_predictor<DIM, R, XCH>(T, Ys, trs, NPOS, NSUB, NSF, dt, dth, P.gamma, xrows);
         __syncthreads();
         sub_update_cell<DIM, N, R, REDO>(T, P, B, cur, w, sidx, S, nonphys, halo, REDO ? 0 : flagging, mb, nslot, fbt);
     }

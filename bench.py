@@ -40,9 +40,9 @@ PEAK_HBM_GBS = 8000.0
 # (launch "stage:N<degree>" -> (bytes per launch, source hash prefix)); copy calibration: a 256 MiB
 # copy reads FETCH_SIZE = 131,084 KiB (factor 2.0) and writes WRITE_SIZE = 262,144 KiB (factor 1.0)
 TRAFFIC = {
-    "predictor:N5": (10797208064, "e097ea857da0de8b"),
-    "subcell:N5": (22133512533, "e097ea857da0de8b"),
-    "corrector_detect:N5": (6559403520, "e097ea857da0de8b"),
+    "predictor:N5": (10796879296, "7856a18f536122a0"),
+    "subcell:N5": (22236328917, "7856a18f536122a0"),
+    "corrector_detect:N5": (6559405568, "7856a18f536122a0"),
 }
 # the kernel sources and the tile-parameter table the build compiles them with
 KERNEL_SOURCES = ("csrc/adg_internal.h", "csrc/adg_tune.h", "csrc/adg_physics.h", "csrc/adg_device.h",

@@ -81,3 +81,46 @@ def test_library_projection_matches_oracle_projection():
             if m:
                 assert np.abs(v - vo).max() < 1e-13 * max(1, np.abs(vo).max())
         L.adg_destroy(h)
+
+
+def test_degrees_built_per_dimension_and_large_cell_workspace():
+    """3D is built for N = 1..3 and 9 (2D for 1..9); other 3D degrees are refused with the
+    reason.  A 3D problem of degree 9 plans the large-cell slots (512 per-workgroup slots of
+    the arrays that exceed LDS) on top of its state, traces and pool."""
+    from paper_1406_7416_amd import workloads as W
+    L = adg.load()
+
+    def create(wl, N, cap=0):
+        g = adg._grid(wl)
+        prm = adg._Params()
+        prm.limiter = 1
+        prm.Ns = 2 * N + 1
+        prm.pool_capacity = cap
+        h = ctypes.c_void_p()
+        rc = L.adg_create(ctypes.byref(g), N, 1.4, ctypes.byref(prm), ctypes.byref(h))
+        return rc, h
+
+    for N in (1, 2, 3, 9):
+        rc, h = create(W.explosion_3d(2, N), N)
+        assert rc == 0, N
+        L.adg_destroy(h)
+    for N in (4, 5, 8):
+        rc, _ = create(W.explosion_3d(2, N), N)
+        assert rc == -1 and b"not built" in L.adg_last_error(), N
+    # 4^3 cells of degree 9, pool for every cell: the state (2 copies), the traces and face
+    # fluxes, two pools of 19^3 subcells, the subcell chunk scratch and the large-cell slots
+    rc, h = create(W.explosion_3d(4, 9), 9)
+    assert rc == 0
+    nb = L.adg_workspace_bytes(h)
+    L.adg_destroy(h)
+    nc, nv, n, ns = 64, 5, 10, 19
+    state = 2 * 8 * nv * nc * n ** 3
+    pools = 2 * 8 * nc * nv * ns ** 3
+    slots = 8 * 512 * 176896
+    assert nb > state + pools + slots
+    # and the slots are the difference a smaller pool does not remove
+    rc, h = create(W.explosion_3d(4, 9), 9, cap=8)
+    assert rc == 0
+    nb8 = L.adg_workspace_bytes(h)
+    L.adg_destroy(h)
+    assert nb8 > slots and nb - nb8 >= 2 * 8 * (nc - 8) * nv * ns ** 3
